@@ -1,0 +1,472 @@
+"""Pins for the FP64 oracle: each check ties an oracle function to
+something other than itself (numpy's Philox, enumeration, dense Hamiltonians,
+closed forms, finite differences, the push-through identity)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import hamiltonian as ham_mod
+from oracle import jacobian, minsr, model, philox
+from tests import refs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def golden(name):
+    with open(os.path.join(HERE, "golden", "paper_values.txt")) as f:
+        for line in f:
+            if line.startswith(name + " "):
+                return float(line.split()[1])
+    raise KeyError(name)
+
+
+def scaled_theta(spec, seed, scale):
+    """Glorot init with weights scaled up so that conditionals are far from
+    uniform (a stronger test than the near-uniform initial state), plus
+    non-zero biases."""
+    th = model.glorot_init(spec, seed) * scale
+    rng = np.random.default_rng(seed)
+    off = 0
+    for name, shape in model.layout(spec):
+        n = int(np.prod(shape))
+        if len(shape) == 1:
+            th[off:off + n] = rng.uniform(-0.5, 0.5, n)
+        off += n
+    return th
+
+
+# --------------------------------------------------------------------- RNG
+
+@pytest.mark.parametrize("key,ctr", [(0, 0), (5, 10), (2**63 + 12345, 2**40 + 7), (2**64 - 1, 2**64 - 2)])
+def test_philox_matches_numpy(key, ctr):
+    # numpy's Philox (4x64-10) increments its 256-bit counter before each
+    # block: its block for counter c is philox4x64(c + 1).
+    bg = np.random.Philox(key=np.array([key, 99], dtype=np.uint64),
+                          counter=np.array([ctr, 3, 4, 5], dtype=np.uint64))
+    raw = bg.random_raw(4)
+    c0 = (ctr + 1) % 2**64
+    c1 = 3 + (1 if ctr + 1 == 2**64 else 0)
+    mine = philox.philox4x64((c0, c1, 4, 5), (key, 99))
+    assert [int(x) for x in raw] == list(mine)
+
+
+def test_uniform_grid():
+    u = philox.uniforms(7, 3, 16, 10)
+    assert u.shape == (16, 10)
+    assert np.all(u >= 0) and np.all(u < 1)
+    assert np.all(u * 2.0**53 == np.floor(u * 2.0**53))
+
+
+# ------------------------------------------------------------ layout/init
+
+@pytest.mark.parametrize("dim,H,cplx,expected", [
+    (1, 16, False, 962), (1, 64, False, 13058), (1, 128, False, 50690),
+    (1, 128, True, 50948), (2, 128, False, 84226), (2, 128, True, 84484),
+    (2, 10, False, 682), (2, 10, True, 704)])
+def test_param_counts(dim, H, cplx, expected):
+    # App. A cell sizes: 1D 3H^2 + 4*2H + 4H + 2 (+2H+2 for the phase head);
+    # 2D adds U1, U2 and doubles the spin input width.
+    spec = model.Spec(Lx=4, Ly=4 if dim == 2 else 1, dim=dim, H=H, complex_head=cplx)
+    assert model.num_params(spec) == expected
+
+
+def test_glorot_bounds_and_stats():
+    spec = model.Spec(Lx=10, H=64)
+    th = model.glorot_init(spec, 2002)
+    P = model.unpack(spec, th)
+    for name, shape in model.layout(spec):
+        if len(shape) == 1:
+            assert np.all(P[name] == 0.0)
+        else:
+            a = math.sqrt(6.0 / (shape[0] + shape[1]))
+            w = P[name].ravel()
+            assert np.all(np.abs(w) <= a)
+            if w.size > 1000:   # uniform(-a, a): mean 0, variance a^2/3
+                assert abs(w.mean()) < 0.1 * a
+                assert abs(w.var() / (a * a / 3) - 1) < 0.1
+
+
+def test_path_zigzag():
+    spec = model.Spec(Lx=3, Ly=3, dim=2, H=4)
+    assert model.path_coords(spec) == [(0, 0), (1, 0), (2, 0), (2, 1), (1, 1), (0, 1), (0, 2), (1, 2), (2, 2)]
+    nb = model.neighbours_2d(spec)
+    # site (1,1) at k=4: horizontal neighbour (2,1) (k=3), vertical (1,0) (k=1)
+    assert nb[4] == (3, 1)
+    assert nb[0] == (-1, -1)
+
+
+# ------------------------------------------------------------ normalisation
+
+SPECS_SMALL = [
+    model.Spec(Lx=8, H=6),
+    model.Spec(Lx=8, H=6, complex_head=True),
+    model.Spec(Lx=3, Ly=3, dim=2, H=5),
+    model.Spec(Lx=3, Ly=3, dim=2, H=5, complex_head=True, marshall=True),
+]
+
+
+@pytest.mark.parametrize("spec", SPECS_SMALL)
+def test_probabilities_sum_to_one(spec):
+    th = scaled_theta(spec, 11, 2.0)
+    s = refs.all_configs(spec.N)
+    lp = model.log_psi(spec, th, s)
+    assert abs(np.sum(np.exp(2 * lp.real)) - 1.0) < 1e-12
+
+
+def test_zero_mag_mask_normalised_in_sector():
+    spec = model.Spec(Lx=4, Ly=2, dim=2, H=5, zero_mag=True, marshall=True)
+    th = scaled_theta(spec, 12, 2.0)
+    s = refs.all_configs(spec.N)
+    P = np.exp(2 * model.log_psi(spec, th, s).real)
+    in_sector = s.sum(axis=1) == spec.N // 2
+    assert abs(P[in_sector].sum() - 1.0) < 1e-12
+    assert np.all(P[~in_sector] == 0.0)
+
+
+def test_config1_enumeration_normalised():
+    spec = model.Spec(Lx=10, H=16)
+    th = model.glorot_init(spec, 2001)
+    lp = model.log_psi(spec, th, refs.all_configs(10))
+    assert abs(np.sum(np.exp(2 * lp.real)) - 1.0) < 1e-12
+
+
+# ------------------------------------------------------------ sampling
+
+def test_sampling_matches_exact_distribution():
+    spec = model.Spec(Lx=5, H=4)
+    th = scaled_theta(spec, 3, 3.0)
+    u = philox.uniforms(77, 0, 20000, spec.N)
+    sig, lp = model.sample(spec, th, u)
+    # returned log Psi is the log Psi of the returned configuration
+    lp2 = model.log_psi(spec, th, sig)
+    assert np.max(np.abs(lp - lp2)) < 1e-13
+    allc = refs.all_configs(5)
+    P = np.exp(2 * model.log_psi(spec, th, allc).real)
+    idx = sig @ (1 << np.arange(4, -1, -1))
+    counts = np.bincount(idx, minlength=32)
+    expct = P * len(idx)
+    chi2 = np.sum((counts - expct) ** 2 / expct)
+    # 31 degrees of freedom: chi2 < 70 fails with probability ~1e-4
+    assert chi2 < 70.0
+
+
+def test_sampling_respects_zero_mag():
+    spec = model.Spec(Lx=4, Ly=4, dim=2, H=4, zero_mag=True)
+    th = scaled_theta(spec, 5, 3.0)
+    sig, lp = model.sample(spec, th, philox.uniforms(1, 2, 300, spec.N))
+    assert np.all(sig.sum(axis=1) == 8)
+    assert np.all(np.isfinite(lp))
+
+
+# ------------------------------------------------------------ Hamiltonians
+
+def test_tfim_free_fermion_matches_paper_table2():
+    e = refs.tfim_obc_free_fermion(200) / 200
+    assert abs(e - golden("tfim_obc_N200_exact_E_per_site")) < 5e-11
+
+
+def test_dense_hamiltonians_exact_energies():
+    e = np.linalg.eigvalsh(refs.dense_tfim(10, 1, 1, False))[0]
+    assert abs(e - refs.tfim_obc_free_fermion(10)) < 1e-10
+    assert abs(e - (-12.381489999654756)) < 1e-10
+    e = np.linalg.eigvalsh(refs.dense_tfim(8, 1, 1, True))[0]
+    assert abs(e - refs.tfim_pbc_critical(8)) < 1e-10
+    e = np.linalg.eigvalsh(refs.dense_cluster_pbc(8))[0]
+    assert abs(e / 8 - golden("cluster_exact_E_per_site")) < 1e-12
+
+
+def _eloc_vs_dense(spec, ham, Hd, seed, scale=2.0):
+    th = scaled_theta(spec, seed, scale)
+    s = refs.all_configs(spec.N)
+    lp = model.log_psi(spec, th, s)
+    psi = np.exp(lp)
+    eps = ham_mod.local_energy(spec, th, ham, s, lp)
+    ok = np.abs(psi) > 0
+    ref = (Hd @ psi)[ok] / psi[ok]
+    assert np.max(np.abs(eps[ok] - ref)) < 1e-9 * max(1.0, np.max(np.abs(ref)))
+    # variational principle for the normalised state
+    E = np.sum(np.abs(psi[ok]) ** 2 * eps[ok]).real
+    assert E >= np.linalg.eigvalsh(Hd)[0] - 1e-10
+    return th
+
+
+@pytest.mark.parametrize("pbc", [False, True])
+def test_eloc_tfim_dense(pbc):
+    spec = model.Spec(Lx=8, H=6)
+    _eloc_vs_dense(spec, ham_mod.Ham("tfim", J=1.0, h=0.7, pbc=pbc), refs.dense_tfim(8, 1.0, 0.7, pbc), 21)
+
+
+def test_eloc_cluster_dense_complex():
+    spec = model.Spec(Lx=8, H=6, complex_head=True)
+    _eloc_vs_dense(spec, ham_mod.Ham("cluster"), refs.dense_cluster_pbc(8), 22)
+
+
+@pytest.mark.parametrize("J2,cplx", [(0.0, False), (0.5, True)])
+def test_eloc_j1j2_dense_marshall(J2, cplx):
+    spec = model.Spec(Lx=3, Ly=3, dim=2, H=5, complex_head=cplx, marshall=True)
+    _eloc_vs_dense(spec, ham_mod.Ham("j1j2", J=1.0, J2=J2), refs.dense_j1j2(3, 3, 1.0, J2), 23)
+
+
+def test_eloc_j1j2_dense_zero_mag():
+    spec = model.Spec(Lx=4, Ly=2, dim=2, H=5, marshall=True, zero_mag=True)
+    _eloc_vs_dense(spec, ham_mod.Ham("j1j2", J=1.0, J2=0.0), refs.dense_j1j2(4, 2, 1.0, 0.0), 24)
+
+
+def test_eloc_product_state_closed_form():
+    # U = 0, c = 0: every conditional is (1/2, 1/2), Psi uniform, so the
+    # off-diagonal TFIM ratios are all 1: eps = -J sum zz - h N exactly.
+    spec = model.Spec(Lx=10, H=16)
+    th = model.glorot_init(spec, 2001)
+    P = model.unpack(spec, th)
+    P["U"][:] = 0.0
+    P["c"][:] = 0.0
+    s = refs.all_configs(10)[::7]
+    eps = ham_mod.local_energy(spec, th, ham_mod.Ham("tfim", J=1.0, h=1.0), s)
+    z = 1 - 2 * s
+    expect = -np.sum(z[:, :-1] * z[:, 1:], axis=1) - 10.0
+    assert np.all(eps == expect)
+
+
+def test_marshall_makes_heisenberg_ground_state_positive():
+    # With the Marshall sign (-1)^{sigma_A}, the Heisenberg ground state
+    # times the sign is non-negative: the sign structure the oracle applies
+    # is the exact one at J2 = 0.
+    spec = model.Spec(Lx=3, Ly=2, dim=2, H=3, marshall=True)
+    Hd = refs.dense_j1j2(3, 2, 1.0, 0.0)
+    w, V = np.linalg.eigh(Hd)
+    v = V[:, 0]
+    s = refs.all_configs(6)
+    sign = np.exp(1j * model.marshall_phase(spec, s)).real
+    w2 = (v * sign)
+    w2 = w2 / w2[np.argmax(np.abs(w2))]
+    assert np.min(w2.real) > -1e-10
+
+
+# ------------------------------------------------------------ Jacobian
+
+def _fd_check(spec, seed, ns=3, h=1e-6):
+    th = scaled_theta(spec, seed, 1.5)
+    u = philox.uniforms(seed, 0, ns, spec.N)
+    sig, _ = model.sample(spec, th, u)
+    D = jacobian.log_derivatives(spec, th, sig)
+    Dfd = np.zeros_like(D)
+    for k in range(th.size):
+        tp = th.copy(); tp[k] += h
+        tm = th.copy(); tm[k] -= h
+        Dfd[:, k] = (model.log_psi(spec, tp, sig) - model.log_psi(spec, tm, sig)) / (2 * h) \
+            if np.iscomplexobj(D) else \
+            (model.log_psi(spec, tp, sig).real - model.log_psi(spec, tm, sig).real) / (2 * h)
+    assert np.max(np.abs(D - Dfd)) < 1e-7 * max(1.0, np.max(np.abs(D)))
+
+
+@pytest.mark.parametrize("spec", [
+    model.Spec(Lx=6, H=4),
+    model.Spec(Lx=6, H=4, complex_head=True),
+    model.Spec(Lx=3, Ly=3, dim=2, H=3, marshall=True),
+    model.Spec(Lx=3, Ly=2, dim=2, H=3, complex_head=True, marshall=True),
+    model.Spec(Lx=2, Ly=4, dim=2, H=3, zero_mag=True),
+])
+def test_jacobian_central_fd(spec):
+    _fd_check(spec, 31)
+
+
+@pytest.mark.parametrize("spec", [model.Spec(Lx=7, H=5), model.Spec(Lx=7, H=5, complex_head=True)])
+def test_score_has_zero_mean(spec):
+    # sum_sigma P(sigma) d log Psi = 0 for the real part (normalised P); the
+    # phase derivative has no such constraint.
+    th = scaled_theta(spec, 41, 2.0)
+    s = refs.all_configs(spec.N)
+    P = np.exp(2 * model.log_psi(spec, th, s).real)
+    D = jacobian.log_derivatives(spec, th, s)
+    assert np.max(np.abs(P @ D.real)) < 1e-12
+    if spec.complex_head:
+        assert np.max(np.abs(P @ D.imag)) > 1e-3
+
+
+@pytest.mark.parametrize("spec,ham,Hd", [
+    (model.Spec(Lx=6, H=4), ham_mod.Ham("tfim", J=1.0, h=0.8, pbc=True), refs.dense_tfim(6, 1.0, 0.8, True)),
+    (model.Spec(Lx=6, H=4, complex_head=True), ham_mod.Ham("cluster"), refs.dense_cluster_pbc(6)),
+])
+def test_energy_gradient_by_enumeration(spec, ham, Hd):
+    # d<H>/dtheta from central differences of the exactly enumerated energy
+    # equals 2 Re sum_sigma P (d log Psi)^* (eps - <H>)  (Sec. 2.3).
+    th = scaled_theta(spec, 51, 1.5)
+    s = refs.all_configs(spec.N)
+
+    def energy(t):
+        psi = np.exp(model.log_psi(spec, t, s))
+        return (np.conj(psi) @ (Hd @ psi)).real
+
+    lp = model.log_psi(spec, th, s)
+    P = np.exp(2 * lp.real)
+    eps = ham_mod.local_energy(spec, th, ham, s, lp)
+    E = P @ eps
+    D = jacobian.log_derivatives(spec, th, s)
+    grad = 2 * np.real(np.conj(D).T @ (P * (eps - E)))
+    h = 1e-6
+    for k in range(0, th.size, 7):
+        tp = th.copy(); tp[k] += h
+        tm = th.copy(); tm[k] -= h
+        fd = (energy(tp) - energy(tm)) / (2 * h)
+        assert abs(fd - grad[k]) < 1e-7 * max(1.0, abs(grad[k]))
+
+
+# ------------------------------------------------------------ minSR algebra
+
+def _config1_inputs(cplx=False, ns=64):
+    spec = model.Spec(Lx=10, H=16, complex_head=cplx)
+    th = scaled_theta(spec, 2001, 1.0)
+    sig, lp = model.sample(spec, th, philox.uniforms(1001, 0, ns, 10))
+    ham = ham_mod.Ham("tfim", J=1.0, h=1.0) if not cplx else ham_mod.Ham("cluster")
+    eps = ham_mod.local_energy(spec, th, ham, sig, lp)
+    D = jacobian.log_derivatives(spec, th, sig)
+    return spec, th, D, eps
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_T_symmetric_psd_and_centred(cplx):
+    _, _, D, eps = _config1_inputs(cplx)
+    r = minsr.update(D, eps, 0.01, 1e-3)
+    T = r["T"]
+    n = T.shape[0]
+    assert n == (128 if cplx else 64)
+    assert np.max(np.abs(T - T.T)) == 0.0
+    w = np.linalg.eigvalsh(T)
+    assert w[0] > -n * 1e-15 * w[-1]
+    ones = np.ones(64)
+    for blk in range(n // 64):
+        v = np.zeros(n); v[blk * 64:(blk + 1) * 64] = ones
+        assert np.max(np.abs(T @ v)) < 1e-12 * w[-1]
+    # T and S = O' O'^T share their non-zero spectrum (App. E)
+    S = r["Op"] @ r["Op"].T
+    ws = np.linalg.eigvalsh(S)[-n:]
+    big = w > 1e-8 * w[-1]
+    assert np.allclose(np.sort(ws)[-big.sum():], w[big], rtol=1e-9, atol=1e-12 * w[-1])
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_push_through_identity(cplx):
+    # minSR (sample space) equals SR (parameter space): Eq. SR vs Eq. minsrR.
+    _, _, D, eps = _config1_inputs(cplx)
+    eta, lam = 0.01, 1e-3
+    r = minsr.update(D, eps, eta, lam)
+    Op, ep = r["Op"], r["ep"]
+    S = Op @ Op.T
+    sr = eta * np.linalg.solve(S + lam * np.eye(S.shape[0]), Op @ ep)
+    assert np.max(np.abs(sr - r["dtheta"])) < 1e-9 * np.max(np.abs(sr))
+
+
+def test_sgd_limit():
+    # lambda >> ||S||: dtheta -> (eta/lambda) * 2 Re[Obar ebar], the
+    # centred SGD step of Eq. SGD_update, here written from D and eps.
+    _, _, D, eps = _config1_inputs(True)
+    eta, lam = 0.01, 1e9
+    r = minsr.update(D, eps, eta, lam)
+    Ns = D.shape[0]
+    grad = 2 * np.real((D - D.mean(axis=0)).T @ np.conj(eps - eps.mean())) / Ns
+    assert np.max(np.abs(r["dtheta"] * lam / eta - grad)) < 1e-6 * np.max(np.abs(grad))
+
+
+def test_pseudo_inverse_branch():
+    _, _, D, eps = _config1_inputs(False)
+    r = minsr.update(D, eps, 1.0, 0.0, pinv_cutoff=1e-8)
+    T = r["T"]
+    x_ref = np.linalg.pinv(T, rcond=1e-8, hermitian=True) @ r["ep"]
+    assert np.max(np.abs(r["x"] - x_ref)) < 1e-8 * np.max(np.abs(x_ref))
+    assert abs(np.sum(r["x"])) < 1e-8 * np.max(np.abs(r["x"]))
+
+
+def test_full_step_config1():
+    spec = model.Spec(Lx=10, H=16)
+    th = model.glorot_init(spec, 2001)
+    res = minsr.step(spec, th, np.zeros_like(th), ham_mod.Ham("tfim"), 64, 0.01, 1e-3, 0.0, 1001, 0)
+    assert np.all(np.isfinite(res["dtheta"]))
+    assert np.array_equal(res["theta"], th - res["dtheta"])
+    # the energy estimate lies above the exact ground energy by a margin
+    # far larger than its statistical error at initialisation
+    assert res["E"].real > -12.381489999654756
+
+
+# ------------------------------------------------------------ cell formulas
+
+def _torch_cell_from_paper(P, H, ds):
+    """torch.nn.GRUCell whose output equals the App. A cell: torch's update
+    gate z plays the role of 1 - u (so its pre-activation is -W_u x - b_u),
+    its reset gate is r, and its candidate is tanh(W_in x + b_in +
+    r * (W_h h + b_h))."""
+    import torch
+    cell = torch.nn.GRUCell(ds, H, bias=True).double()
+    Wu, Wr = P["Wu"], P["Wr"]
+    w_ih = np.concatenate([Wr[:, H:], -Wu[:, H:], P["Win"]], axis=0)
+    w_hh = np.concatenate([Wr[:, :H], -Wu[:, :H], P["Wh"]], axis=0)
+    b_ih = np.concatenate([P["br"], -P["bu"], P["bin"]])
+    b_hh = np.concatenate([np.zeros(H), np.zeros(H), P["bh"]])
+    with torch.no_grad():
+        cell.weight_ih.copy_(torch.from_numpy(w_ih))
+        cell.weight_hh.copy_(torch.from_numpy(w_hh))
+        cell.bias_ih.copy_(torch.from_numpy(b_ih))
+        cell.bias_hh.copy_(torch.from_numpy(b_hh))
+    return cell
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_gru_cell_matches_torch_grucell(dim):
+    import torch
+    spec = model.Spec(Lx=4, Ly=4 if dim == 2 else 1, dim=dim, H=7)
+    th = scaled_theta(spec, 61, 2.0)
+    P = model.unpack(spec, th)
+    ds = 2 if dim == 1 else 4
+    rng = np.random.default_rng(0)
+    hprev = rng.normal(size=(9, 7))
+    xs = rng.integers(0, 2, size=(9, ds)).astype(float)
+    h, _ = model.gru_cell(P, hprev, xs)
+    cell = _torch_cell_from_paper(P, 7, ds)
+    with torch.no_grad():
+        ref = cell(torch.from_numpy(xs), torch.from_numpy(hprev)).numpy()
+    assert np.max(np.abs(h - ref)) < 1e-14
+
+
+def test_1d_log_p_matches_torch_recurrence():
+    # whole 1D recurrence: torch GRUCell + log_softmax head, zero initial
+    # state and zero first input (Sec. 2, vanilla-cell paragraph)
+    import torch
+    spec = model.Spec(Lx=9, H=6)
+    th = scaled_theta(spec, 62, 2.0)
+    P = model.unpack(spec, th)
+    cell = _torch_cell_from_paper(P, 6, 2)
+    sig = refs.all_configs(9)[::5]
+    with torch.no_grad():
+        h = torch.zeros(len(sig), 6, dtype=torch.float64)
+        x = torch.zeros(len(sig), 2, dtype=torch.float64)
+        tot = torch.zeros(len(sig), dtype=torch.float64)
+        for k in range(9):
+            h = cell(x, h)
+            z = h @ torch.from_numpy(P["U"]).T + torch.from_numpy(P["c"])
+            lsm = torch.log_softmax(z, dim=1)
+            s = torch.from_numpy(sig[:, k])
+            tot += lsm[torch.arange(len(sig)), s]
+            x = torch.nn.functional.one_hot(s, 2).double()
+    lp = model.log_psi(spec, th, sig)
+    assert np.max(np.abs(2 * lp.real - tot.numpy())) < 1e-12
+
+
+def test_head_closed_forms():
+    # U = 0, U_phi = 0: conditionals are softmax(c) and phases
+    # pi*softsign(c_phi) at every site, independent of the history.
+    spec = model.Spec(Lx=6, H=4, complex_head=True)
+    th = scaled_theta(spec, 63, 1.0)
+    P = model.unpack(spec, th)
+    P["U"][:] = 0.0
+    P["Uphi"][:] = 0.0
+    P["c"][:] = [0.3, -1.1]
+    P["cphi"][:] = [0.7, -2.0]
+    s = refs.all_configs(6)
+    lp = model.log_psi(spec, th, s)
+    n0 = np.sum(s == 0, axis=1)
+    n1 = 6 - n0
+    lse = np.log(np.exp(0.3) + np.exp(-1.1))
+    assert np.allclose(2 * lp.real, n0 * (0.3 - lse) + n1 * (-1.1 - lse), rtol=0, atol=1e-13)
+    ph = n0 * math.pi * 0.7 / 1.7 + n1 * math.pi * (-2.0) / 3.0
+    assert np.allclose(lp.imag, ph, rtol=0, atol=1e-13)
