@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""Throughput of one minSR iteration on one MI355X.
+
+Workload (the metric's configuration): 1D transverse-field Ising chain,
+N = 64, periodic, J = h = 1; 1D GRU pRNN with d_h = 64 (13058 parameters);
+N_s = 1024 samples with N + 1 connected configurations each; regularised
+minSR step with lambda = 1e-3, eta = 0.5, momentum 0.7.  The timed region is
+a training run of K consecutive steps from the seeded initialisation; the
+energy of every step is kept on the device, and |Delta E / N| against the
+closed-form ground energy is reported for the last 50 steps.
+
+value: steps/s of the BF16 + FP64 form (BF16 O'/Gram on MFMA with FP32
+accumulation, FP64 reductions, solve and update; FP32 recurrence).  The
+plain FP32 form is timed the same way and reported beside it.
+
+Per-kernel times come from HIP events recorded by the library on the
+step's stream during the timed region; `roofline` is given for the kernel
+with the largest share of the step.  `cpu_baseline` times the FP64 CPU
+oracle on one full step of the same workload on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("minSR steps/sec at fixed ΔE/N; Jacobian GB/s & Gram MFMA util vs peak")
+PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP32_VEC_TFLOPS = 157.3
+
+# traffic measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE) per launch,
+# scaled by the counter's reading on a plain copy of known size; None until
+# taken for the current kernel version
+TRAFFIC_BYTES = {"eloc": None, "jacobian": None, "gram": None}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 form")
+    return ap.parse_args()
+
+
+def work_units(wl):
+    """Algorithmic work per launch of the three graded kernels."""
+    N, H, Ns = wl.Lx * wl.Ly, wl.H, wl.Ns
+    Np = 3 * H * H + 4 * 2 * H + 4 * H + 2      # 1D pRNN, local dimension 2
+    seq_sites = Ns * N * (N - 1) // 2           # flip at k re-runs sites k+1..N-1
+    return dict(
+        Np=Np,
+        # GRU gate products (3 H x H) and the two logits per re-evaluated site
+        eloc_flop=seq_sites * (6 * H * H + 4 * H),
+        # O written once in FP32 (Ns rows of Np)
+        jacobian_bytes=Ns * Np * 4,
+        # useful flops of the symmetric Gram: n (n + 1) Np
+        gram_flop=Ns * (Ns + 1) * Np,
+    )
+
+
+def run_form(pm, wl, form, K, W, dtype="f32"):
+    import torch
+    ham = pm.hamiltonian("tfim", J=wl.J, h=wl.h, pbc=wl.pbc)
+    m = pm.Model(wl.Lx, wl.Ly, wl.dim, wl.H, wl.complex_head, wl.marshall, wl.zero_mag,
+                 dtype=dtype, seed=wl.seed, max_Ns=wl.Ns)
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    outs = m.step_outputs(wl.Ns)
+    hist = torch.zeros((max(K, 1), 3), dtype=torch.float64, device="cuda")
+    status = torch.zeros(max(K, 1), dtype=torch.int32, device="cuda")
+    counter = 0
+
+    def one(i, timed):
+        nonlocal counter
+        o = dict(outs)
+        if timed:
+            o["energy"] = hist[i]
+            o["status"] = status[i:i + 1]
+        m.step(ham, wl.Ns, wl.eta, wl.lam, wl.mu, mom, wl.key, counter, form=form,
+               ckpt_every=wl.ckpt_every, outputs=o)
+        counter += 1
+
+    for i in range(W):
+        one(i, False)
+    torch.cuda.synchronize()
+    m.timing_begin(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        one(i, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases, nrec = m.timing_read()
+    E = hist.cpu().numpy()
+    st = status.cpu().numpy()
+    m.close()
+    return dict(seconds=t1 - t0, phases={k: v / max(nrec, 1) for k, v in phases.items()},
+                energy=E, status=st)
+
+
+def cpu_baseline(wl):
+    """One full FP64 oracle step of the workload on the host cores."""
+    import numpy as np
+    from oracle import hamiltonian, minsr, model
+    spec = model.Spec(Lx=wl.Lx, Ly=wl.Ly, dim=wl.dim, H=wl.H, complex_head=wl.complex_head,
+                      marshall=wl.marshall, zero_mag=wl.zero_mag)
+    th = model.glorot_init(spec, wl.seed)
+    ham = hamiltonian.Ham("tfim", J=wl.J, h=wl.h, pbc=wl.pbc)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    minsr.step(spec, th, np.zeros_like(th), ham, wl.Ns, wl.eta, wl.lam, wl.mu, wl.key, 0)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": "one full FP64 oracle step of the same workload (Ns=1024, N=64, d_h=64): "
+                      "uniforms, sampling, local energies, Jacobian, Gram, Cholesky, update; "
+                      "%.1f s" % dt}
+
+
+def roofline_entry(name, ms, units):
+    if name == "gram":
+        ach = units["gram_flop"] / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_BF16_TFLOPS, "traffic": TRAFFIC_BYTES["gram"],
+                "ms": ms}
+    if name == "jacobian":
+        ach = units["jacobian_bytes"] / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": TRAFFIC_BYTES["jacobian"], "ms": ms}
+    ach = units["eloc_flop"] / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VEC_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP32_VEC_TFLOPS, "traffic": TRAFFIC_BYTES["eloc"], "ms": ms}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2608_18065_amd as pm
+    from workloads import WORKLOADS
+
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    wl = WORKLOADS["tfim64"]
+    K, W = args.steps, args.warmup
+    units = work_units(wl)
+    N = wl.Lx * wl.Ly
+
+    res = run_form(pm, wl, pm.FORM_BF16_FP64, K, W)
+    print("bf16_fp64: %.3f s for %d steps" % (res["seconds"], K), file=sys.stderr, flush=True)
+    ms_step = res["seconds"] / K * 1e3
+    value = K / res["seconds"]
+    ph = res["phases"]
+
+    def dE(E):
+        tail = E[-min(50, len(E)):, 0]
+        return float(tail.mean() / N - wl.E0 / N), float(tail.std() / N / math.sqrt(len(tail)))
+
+    graded = {k: roofline_entry(k, ph[k], units) for k in ("eloc", "jacobian", "gram")}
+    dom = max(("sample", "eloc", "jacobian", "gram"), key=lambda k: ph[k])
+    roof = graded.get(dom) or graded["eloc"]
+
+    forms = {"bf16_fp64": {"steps_per_s": value, "ms_per_step": ms_step,
+                           "dE_per_site_last50": dE(res["energy"]),
+                           "status_nonzero_steps": int(np.count_nonzero(res["status"]))}}
+    if not args.no_fp32:
+        r32 = run_form(pm, wl, pm.FORM_FP32_PLAIN, K, W)
+        print("fp32_plain: %.3f s for %d steps" % (r32["seconds"], K), file=sys.stderr, flush=True)
+        forms["fp32_plain"] = {"steps_per_s": K / r32["seconds"],
+                               "ms_per_step": r32["seconds"] / K * 1e3,
+                               "dE_per_site_last50": dE(r32["energy"]),
+                               "status_nonzero_steps": int(np.count_nonzero(r32["status"])),
+                               "phase_ms": r32["phases"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl)
+        print("cpu baseline: %s" % cpu["sample"], file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16-gram/f32-recurrence/f64-solve", "data": "synthetic",
+        "config": {"workload": "tfim64: 1D TFIM N=64 periodic J=h=1, 1D GRU pRNN d_h=64 "
+                               "(13058 params), Ns=1024 (N+1 connected configs each), "
+                               "BF16+FP64 form, lambda=1e-3, eta=0.5, mu=0.7, "
+                               "training run from the seeded init",
+                   "Ns": wl.Ns, "N": N, "d_h": wl.H, "Np": units["Np"]},
+        "roofline": dict(roof, kernel=dom if dom in graded else "eloc"),
+        "rooflines": graded,
+        "phase_ms": ph,
+        "forms": forms,
+        "E0_per_site": wl.E0 / N,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,244 @@
+/*
+ * minsr.h -- C ABI of the MI355X minimum-step stochastic reconfiguration
+ * (minSR) hot path for recurrent (GRU) neural quantum states.
+ *
+ * The method is the one of "Quantum Geometric Tensor Preconditioning for
+ * Stable Training of Recurrent Neural Quantum States": one iteration of its
+ * Algorithm 1 draws N_s configurations exactly from an autoregressive GRU
+ * wave function, evaluates local energies, forms the per-sample
+ * log-derivatives O, centres them, builds the sample-space Gram matrix
+ * T = O'^T O' and applies the regularised update
+ *     dtheta = eta * O' (T + lambda I)^{-1} eps'          (Eq. minsrR)
+ * followed by the momentum step of App. B.
+ *
+ * Conventions shared by every call
+ *   - Every function returns an int status: MINSR_OK (0) or a negative
+ *     MINSR_E_* code.  minsr_last_error() returns a thread-local message
+ *     describing the last failure of the calling thread.
+ *   - Array arguments named dev_* are device pointers owned by the caller,
+ *     contiguous and row-major, with their lengths given by the other
+ *     arguments.  The library never frees or retains them.
+ *   - The library owns only what a model or batch handle holds: the FP64
+ *     master parameters, working copies of them in the compute precision,
+ *     and workspace sized at creation for max_Ns samples.
+ *   - Every call takes a hipStream_t, only enqueues work on it and never
+ *     synchronises the host, so calls can be captured in a hip graph.
+ *     Numerical failures found on the device are reported through a status
+ *     word the caller reads after its own synchronisation.
+ *   - Spins are uint8 0/1 in lattice-path order; 0 is z = +1 (spin up).
+ *   - Complex numbers are interleaved (re, im) doubles.
+ *   - log Psi is complex: re = 0.5 log P(sigma), im = phase (Eqs. 2, 6, 8).
+ *   - Identical inputs give bitwise identical outputs (no floating-point
+ *     atomics anywhere).
+ *   - A handle must not be used from two host threads at once.
+ */
+#ifndef MINSR_H
+#define MINSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MINSR_OK              0
+#define MINSR_E_INVALID_ARG  -1   /* NULL pointer or out-of-range scalar  */
+#define MINSR_E_SHAPE        -2   /* size outside what the handle supports */
+#define MINSR_E_DEVICE       -3   /* a HIP runtime call failed             */
+#define MINSR_E_NUMERIC      -4   /* reserved: host-visible numeric error  */
+#define MINSR_E_NOMEM        -5   /* device allocation failed              */
+#define MINSR_E_UNSUPPORTED  -6   /* option not available in this build    */
+
+/* floating-point formats */
+#define MINSR_F64   0
+#define MINSR_F32   1
+#define MINSR_BF16  2
+
+/* Hamiltonians (Sec. 3): transverse-field Ising chain, periodic cluster
+ * chain -sum Z X Z, and the open square-lattice J1-J2 model (J2 = 0 is the
+ * Heisenberg model). */
+#define MINSR_HAM_TFIM     0
+#define MINSR_HAM_CLUSTER  1
+#define MINSR_HAM_J1J2     2
+
+/* numerical precision of one minSR step */
+#define MINSR_FORM_FP64_REF   0  /* everything in FP64                       */
+#define MINSR_FORM_BF16_FP64  1  /* BF16 O'/Gram on MFMA, FP32 accumulation,
+                                    FP64 reductions, solve and update        */
+#define MINSR_FORM_FP32_PLAIN 2  /* FP32 O', Gram, solve and update          */
+
+/* device status-word bits (minsr_step_out.dev_status) */
+#define MINSR_ST_NONFINITE_ELOC  0x1u
+#define MINSR_ST_NOT_PD          0x2u   /* Cholesky met a pivot <= 0 / NaN */
+#define MINSR_ST_NONFINITE_DTH   0x4u
+#define MINSR_ST_EIG_NOCONV      0x8u
+
+/* Architecture of one wave function (Sec. 2, Sec. 2.1 and App. A).
+ *   Lx, Ly        lattice extent; a chain has Ly = 1 and dim = 1
+ *   dim           1: the 1D GRU; 2: the 2D GRU on the zigzag path
+ *   hidden        d_h; supported: 8, 16, 32, 64, 128
+ *   complex_head  1 adds the softsign phase head (cRNN), 0 is a pRNN
+ *   marshall      multiply Psi by (-1)^{sigma_A}, A = {(x, y): x + y even}
+ *   zero_mag      restrict the autoregressive conditionals to S^z = 0
+ *   compute_dtype MINSR_F64 or MINSR_F32: precision of every GRU evaluation
+ *   init_seed     Philox key of the Glorot-uniform initialisation
+ *   max_Ns        largest N_s any call on this handle will use           */
+typedef struct {
+  int32_t Lx, Ly, dim, hidden;
+  int32_t complex_head, marshall, zero_mag;
+  int32_t compute_dtype;
+  uint64_t init_seed;
+  int32_t max_Ns;
+  int32_t reserved;
+} minsr_model_desc;
+
+typedef struct {
+  int32_t kind;      /* MINSR_HAM_*                                      */
+  int32_t pbc;       /* TFIM only: 1 adds the bond (N-1, 0)             */
+  double J;          /* TFIM ZZ coupling; J1-J2 nearest-neighbour J1     */
+  double h;          /* TFIM transverse field                            */
+  double J2;         /* J1-J2 next-nearest-neighbour coupling            */
+} minsr_hamiltonian;
+
+typedef struct minsr_model minsr_model;
+typedef struct minsr_batch minsr_batch;
+
+const char* minsr_last_error(void);
+
+/* ---- model -------------------------------------------------------------
+ * Creates a wave function and initialises theta_0: every weight matrix
+ * Glorot-uniform a (2u - 1), a = sqrt(6 / (fan_in + fan_out)), with u the
+ * Philox4x64-10 uniform of (key = init_seed, counter = parameter index),
+ * every bias zero (Sec. 2 and App. A define the cell; the paper leaves the
+ * initialisation open).  The flat parameter order is, each block
+ * row-major: [U1, U2 (2D only)], Wu [H x (H+ds)], bu, Wr [H x (H+ds)], br,
+ * Wh [H x H], bh, Win [H x ds], bin, U [2 x H], c [2], [Uphi [2 x H],
+ * cphi [2] (complex head only)], with ds = 2 (1D) or 4 (2D).
+ * Allocates device memory on the current device; returns MINSR_E_NOMEM if
+ * that fails.  All later calls must run with the same device current.   */
+int minsr_create_model(const minsr_model_desc* desc, minsr_model** out);
+int minsr_destroy_model(minsr_model* m);
+int minsr_num_params(const minsr_model* m, size_t* np);
+int minsr_num_sites(const minsr_model* m, int* n);
+/* copy the FP64 master parameters out / in (np doubles, device)          */
+int minsr_get_params(minsr_model* m, double* dev_theta, hipStream_t s);
+int minsr_set_params(minsr_model* m, const double* dev_theta, hipStream_t s);
+
+/* ---- sampling (Sec. 2, exact autoregressive sampling; Alg. 1 step 3) ---
+ * Draws Ns configurations.  At path position i the conditional
+ * p_i = softmax(U h_i + c) (masked to S^z = 0 if requested) gives
+ * sigma_i = 0 if u < p_i(0), else 1.  u[s, i] is dev_uniforms[s * N + i]
+ * (doubles in [0, 1)) or, if dev_uniforms is NULL, the uniform
+ * (w >> 11) * 2^-53 of word (i mod 4) of Philox4x64-10 with
+ * counter (counter, s, i / 4, 0) and key (key, 0).
+ * Outputs: dev_sigma [Ns x N] uint8, dev_logpsi [Ns] complex.            */
+int minsr_sample(minsr_model* m, int Ns, const double* dev_uniforms,
+                 uint64_t key, uint64_t counter, uint8_t* dev_sigma,
+                 double* dev_logpsi, hipStream_t s);
+
+/* ---- evaluation: log Psi(sigma) for given configurations (Eqs. 2, 6, 8) */
+int minsr_logpsi(minsr_model* m, int Ns, const uint8_t* dev_sigma,
+                 double* dev_logpsi, hipStream_t s);
+
+/* ---- local energies (Sec. 2.3) -------------------------------------------
+ * eps(sigma) = sum_{sigma'} H_{sigma sigma'} Psi(sigma') / Psi(sigma) for
+ * the Hamiltonian H.  dev_logpsi must hold log Psi(dev_sigma) (as returned
+ * by minsr_sample / minsr_logpsi).  Outputs dev_eloc [Ns] complex and
+ * dev_stats [3] = (Re E, Im E, Var eps) with E the sample mean of eps
+ * (Eq. energy), all FP64.  Supported Hamiltonians: TFIM and cluster on
+ * 1D models, J1-J2 on 2D models.                                         */
+int minsr_local_energy(minsr_model* m, const minsr_hamiltonian* H, int Ns,
+                       const uint8_t* dev_sigma, const double* dev_logpsi,
+                       double* dev_eloc, double* dev_stats, hipStream_t s);
+
+/* ---- per-sample log-derivatives (Sec. 2.3, Alg. 1 step 5) ---------------
+ * Writes O[r, k] = d log Psi(sigma^(s)) / d theta_k / sqrt(Ns), computed
+ * by a reverse pass through the recurrence that recomputes hidden states
+ * between checkpoints taken every ckpt_every sites (1D models; 2D models
+ * keep every hidden state).  Rows: a pRNN has Ns rows (r = s); a cRNN has
+ * 2 Ns rows, r = s for Re (0.5 d log P) and r = Ns + s for Im (d phase).
+ * centered != 0 subtracts, per block of Ns rows, the column mean, which is
+ * also written to dev_colmean (rows/Ns x Np doubles, may be NULL when
+ * centered == 0).  out_dtype: MINSR_F64, MINSR_F32 or MINSR_BF16 (BF16
+ * only with centered != 0; centring happens in FP32/FP64 before rounding).
+ * ckpt_every in [1, 16].                                                  */
+int minsr_jacobian(minsr_model* m, int Ns, const uint8_t* dev_sigma,
+                   int out_dtype, int centered, int ckpt_every, void* dev_O,
+                   double* dev_colmean, hipStream_t s);
+
+/* ---- vector-Jacobian product of log Psi ---------------------------------
+ * dev_grad_theta[k] = sum_s (g_re[s] * d Re log Psi_s / d theta_k
+ *                            + g_im[s] * d Im log Psi_s / d theta_k)
+ * with dev_g [Ns] complex (g_re, g_im) interleaved.  Used as the backward
+ * of a log Psi autograd function.                                         */
+int minsr_logpsi_vjp(minsr_model* m, int Ns, const uint8_t* dev_sigma,
+                     const double* dev_g, double* dev_grad_theta,
+                     hipStream_t s);
+
+/* ---- one minSR iteration (Alg. 1 loop body; App. B momentum) -------------
+ * Samples, evaluates eps, forms O, E, eps' = 2 (Re ebar; -Im ebar) with
+ * ebar_s = (eps_s - E)^* / sqrt(Ns) (Eq. real-valued), T = O'^T O', solves
+ * (T + lambda I) x = eps' by Cholesky (pinv_cutoff == 0) or, at
+ * lambda = 0, with the Moore-Penrose pseudo-inverse that drops eigenvalues
+ * <= pinv_cutoff * lambda_max(T) (App. F), and sets
+ *     dtheta = eta O' x;  m = mu m + (1 - mu) dtheta;  theta -= m.
+ * theta and m change only if apply_update != 0 and the device status word
+ * is zero.  The uniforms are Philox (key, counter) as in minsr_sample; the
+ * caller advances counter between steps.                                   */
+typedef struct {
+  int32_t Ns;
+  int32_t form;          /* MINSR_FORM_*                                    */
+  double eta, lambda, mu;
+  double pinv_cutoff;    /* 0: Cholesky of T + lambda I                     */
+  int32_t ckpt_every;    /* Jacobian checkpoint stride (1D models)          */
+  int32_t apply_update;
+} minsr_step_cfg;
+
+typedef struct {
+  double* dev_momentum;  /* [Np] FP64, caller-owned, updated in place       */
+  uint64_t key, counter; /* Philox stream of the sampling uniforms          */
+} minsr_step_state;
+
+typedef struct {
+  double* dev_energy;    /* [3]: Re E, Im E, Var eps                        */
+  double* dev_dtheta;    /* [Np] FP64, may be NULL                          */
+  uint32_t* dev_status;  /* [1] MINSR_ST_* bits, written every step         */
+  double* dev_eloc;      /* [Ns] complex, may be NULL                       */
+  uint8_t* dev_sigma;    /* [Ns x N], may be NULL                           */
+} minsr_step_out;
+
+int minsr_step(minsr_model* m, const minsr_hamiltonian* H,
+               const minsr_step_cfg* cfg, const minsr_step_state* st,
+               const minsr_step_out* out, hipStream_t s);
+
+/* Device pointers to the step's intermediates after the last minsr_step
+ * on this handle (valid until the next call on it): T (n x n FP64, or
+ * FP32 in the FP32_PLAIN form), x (n), eps' (n), with n = Ns (pRNN) or
+ * 2 Ns (cRNN); O' (n x Np, rows centred; dtype per form).  For tests.    */
+int minsr_step_intermediates(minsr_model* m, const void** T, const double** x,
+                             const double** eps_prime, const void** Oprime,
+                             int* n, int* Np);
+
+/* ---- per-phase timing of minsr_step (profiling) -------------------------
+ * minsr_timing_begin arms HIP-event recording on the step's stream for the
+ * next max_steps calls of minsr_step on this handle (events are created
+ * once, outside the step; do not arm it while capturing a graph).
+ * minsr_timing_read waits for the recorded events and returns in ms[] the
+ * milliseconds summed over the recorded steps for each phase, and in
+ * *nsteps the number of steps recorded; it disarms recording.  Phases:
+ *   0 sampling recurrence          5 Gram tile products (MFMA for BF16)
+ *   1 local-energy recurrence      6 Gram split-K reduction and mirror
+ *   2 eps sums, E, Var, eps'       7 regularised solve
+ *   3 BPTT Jacobian                8 dtheta, momentum, parameter update
+ *   4 centring and real form       9 working-copy repack                */
+#define MINSR_NPHASES 10
+int minsr_timing_begin(minsr_model* m, int max_steps);
+int minsr_timing_read(minsr_model* m, double* ms, int* nsteps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MINSR_H */

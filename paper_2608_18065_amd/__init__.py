@@ -1,0 +1,288 @@
+"""MI355X minSR hot path for recurrent (GRU) neural quantum states.
+
+Thin ctypes binding over the C ABI declared in include/minsr.h.  Every step
+of the method runs in the HIP kernels of libminsr.so; this module only
+marshals arguments.  PyTorch supplies device memory and the current HIP
+stream.  Importing the package fails loudly if the library is not built.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libminsr.so")
+
+F64, F32, BF16 = 0, 1, 2
+HAM_TFIM, HAM_CLUSTER, HAM_J1J2 = 0, 1, 2
+FORM_FP64_REF, FORM_BF16_FP64, FORM_FP32_PLAIN = 0, 1, 2
+ST_NONFINITE_ELOC, ST_NOT_PD, ST_NONFINITE_DTH, ST_EIG_NOCONV = 1, 2, 4, 8
+
+# every entry point of include/minsr.h
+SYMBOLS = (
+    "minsr_last_error", "minsr_create_model", "minsr_destroy_model", "minsr_num_params",
+    "minsr_num_sites", "minsr_get_params", "minsr_set_params", "minsr_sample", "minsr_logpsi",
+    "minsr_local_energy", "minsr_jacobian", "minsr_logpsi_vjp", "minsr_step",
+    "minsr_step_intermediates", "minsr_timing_begin", "minsr_timing_read",
+)
+PHASES = ("sample", "eloc", "eloc_sum_stats", "jacobian", "center", "gram", "gram_reduce",
+          "solve", "update", "repack")
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("hidden", ctypes.c_int32), ("complex_head", ctypes.c_int32),
+                ("marshall", ctypes.c_int32), ("zero_mag", ctypes.c_int32),
+                ("compute_dtype", ctypes.c_int32), ("init_seed", ctypes.c_uint64),
+                ("max_Ns", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Hamiltonian(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pbc", ctypes.c_int32), ("J", ctypes.c_double),
+                ("h", ctypes.c_double), ("J2", ctypes.c_double)]
+
+
+class StepCfg(ctypes.Structure):
+    _fields_ = [("Ns", ctypes.c_int32), ("form", ctypes.c_int32), ("eta", ctypes.c_double),
+                ("lam", ctypes.c_double), ("mu", ctypes.c_double),
+                ("pinv_cutoff", ctypes.c_double), ("ckpt_every", ctypes.c_int32),
+                ("apply_update", ctypes.c_int32)]
+
+
+class StepState(ctypes.Structure):
+    _fields_ = [("dev_momentum", ctypes.c_void_p), ("key", ctypes.c_uint64),
+                ("counter", ctypes.c_uint64)]
+
+
+class StepOut(ctypes.Structure):
+    _fields_ = [("dev_energy", ctypes.c_void_p), ("dev_dtheta", ctypes.c_void_p),
+                ("dev_status", ctypes.c_void_p), ("dev_eloc", ctypes.c_void_p),
+                ("dev_sigma", ctypes.c_void_p)]
+
+
+def load_library(path=LIB_PATH):
+    """Load libminsr.so and declare argument types.  Raises if missing."""
+    if not os.path.exists(path):
+        raise ImportError("libminsr.so is not built (run paper_2608_18065_amd/build.py): " + path)
+    lib = ctypes.CDLL(path)
+    vp, i32, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
+    lib.minsr_last_error.restype = ctypes.c_char_p
+    sig = {
+        "minsr_create_model": [ctypes.POINTER(ModelDesc), ctypes.POINTER(vp)],
+        "minsr_destroy_model": [vp],
+        "minsr_num_params": [vp, ctypes.POINTER(sz)],
+        "minsr_num_sites": [vp, ctypes.POINTER(ctypes.c_int)],
+        "minsr_get_params": [vp, vp, vp],
+        "minsr_set_params": [vp, vp, vp],
+        "minsr_sample": [vp, i32, vp, u64, u64, vp, vp, vp],
+        "minsr_logpsi": [vp, i32, vp, vp, vp],
+        "minsr_local_energy": [vp, ctypes.POINTER(Hamiltonian), i32, vp, vp, vp, vp, vp],
+        "minsr_jacobian": [vp, i32, vp, i32, i32, i32, vp, vp, vp],
+        "minsr_logpsi_vjp": [vp, i32, vp, vp, vp, vp],
+        "minsr_step": [vp, ctypes.POINTER(Hamiltonian), ctypes.POINTER(StepCfg),
+                       ctypes.POINTER(StepState), ctypes.POINTER(StepOut), vp],
+        "minsr_step_intermediates": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+        "minsr_timing_begin": [vp, i32],
+        "minsr_timing_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+class MinsrError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().minsr_last_error().decode(errors="replace")
+        raise MinsrError("minsr error %d: %s" % (rc, msg))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def hamiltonian(kind, J=1.0, h=1.0, J2=0.0, pbc=False):
+    k = {"tfim": HAM_TFIM, "cluster": HAM_CLUSTER, "j1j2": HAM_J1J2}[kind] if isinstance(kind, str) else kind
+    return Hamiltonian(k, 1 if pbc else 0, float(J), float(h), float(J2))
+
+
+class Model:
+    """One GRU wave function on the current HIP device (Sec. 2, App. A)."""
+
+    def __init__(self, Lx, Ly=1, dim=1, hidden=16, complex_head=False, marshall=False,
+                 zero_mag=False, dtype="f64", seed=0, max_Ns=1024):
+        self.desc = ModelDesc(Lx, Ly, dim, hidden, int(complex_head), int(marshall),
+                              int(zero_mag), F64 if dtype == "f64" else F32, seed, max_Ns, 0)
+        h = ctypes.c_void_p()
+        _check(lib().minsr_create_model(ctypes.byref(self.desc), ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_size_t()
+        _check(lib().minsr_num_params(h, ctypes.byref(n)))
+        self.Np = n.value
+        self.N = Lx * Ly
+        self.complex_head = bool(complex_head)
+        self.dtype = dtype
+        self.max_Ns = max_Ns
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().minsr_destroy_model(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- parameters
+    def get_params(self):
+        t = torch.empty(self.Np, dtype=torch.float64, device=self.device)
+        _check(lib().minsr_get_params(self.handle, _ptr(t), _stream()))
+        return t
+
+    def set_params(self, theta):
+        theta = theta.to(device=self.device, dtype=torch.float64).contiguous()
+        _check(lib().minsr_set_params(self.handle, _ptr(theta), _stream()))
+
+    # ------------------------------------------------------------ sampling
+    def sample(self, Ns, key=0, counter=0, uniforms=None):
+        sigma = torch.empty((Ns, self.N), dtype=torch.uint8, device=self.device)
+        lp = torch.empty((Ns, 2), dtype=torch.float64, device=self.device)
+        if uniforms is not None:
+            uniforms = uniforms.to(device=self.device, dtype=torch.float64).contiguous()
+            assert uniforms.shape == (Ns, self.N)
+        _check(lib().minsr_sample(self.handle, Ns, _ptr(uniforms), key, counter, _ptr(sigma),
+                                  _ptr(lp), _stream()))
+        return sigma, torch.view_as_complex(lp)
+
+    def logpsi(self, sigma):
+        sigma = sigma.to(device=self.device, dtype=torch.uint8).contiguous()
+        Ns = sigma.shape[0]
+        lp = torch.empty((Ns, 2), dtype=torch.float64, device=self.device)
+        _check(lib().minsr_logpsi(self.handle, Ns, _ptr(sigma), _ptr(lp), _stream()))
+        return torch.view_as_complex(lp)
+
+    def local_energy(self, ham, sigma, logpsi):
+        sigma = sigma.to(device=self.device, dtype=torch.uint8).contiguous()
+        Ns = sigma.shape[0]
+        lp = torch.view_as_real(logpsi.to(self.device)).contiguous()
+        eloc = torch.empty((Ns, 2), dtype=torch.float64, device=self.device)
+        stats = torch.empty(3, dtype=torch.float64, device=self.device)
+        _check(lib().minsr_local_energy(self.handle, ctypes.byref(ham), Ns, _ptr(sigma), _ptr(lp),
+                                        _ptr(eloc), _ptr(stats), _stream()))
+        return torch.view_as_complex(eloc), stats
+
+    def jacobian(self, sigma, out_dtype=None, centered=False, ckpt_every=1):
+        """Rows O[r] = d log Psi / d theta / sqrt(Ns) (2 Ns rows for a cRNN:
+        real parts, then imaginary parts)."""
+        sigma = sigma.to(device=self.device, dtype=torch.uint8).contiguous()
+        Ns = sigma.shape[0]
+        if out_dtype is None:
+            out_dtype = F64 if self.dtype == "f64" else F32
+        tdt = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[out_dtype]
+        rows = Ns * (2 if self.complex_head else 1)
+        O = torch.empty((rows, self.Np), dtype=tdt, device=self.device)
+        colmean = None
+        if centered:
+            colmean = torch.empty((rows // max(Ns, 1), self.Np), dtype=torch.float64, device=self.device)
+        _check(lib().minsr_jacobian(self.handle, Ns, _ptr(sigma), out_dtype, int(centered),
+                                    ckpt_every, _ptr(O), _ptr(colmean), _stream()))
+        return O, colmean
+
+    def logpsi_vjp(self, sigma, g):
+        sigma = sigma.to(device=self.device, dtype=torch.uint8).contiguous()
+        Ns = sigma.shape[0]
+        g = torch.view_as_real(g.to(device=self.device, dtype=torch.complex128)).contiguous()
+        out = torch.empty(self.Np, dtype=torch.float64, device=self.device)
+        _check(lib().minsr_logpsi_vjp(self.handle, Ns, _ptr(sigma), _ptr(g), _ptr(out), _stream()))
+        return out
+
+    # ------------------------------------------------------------ one step
+    def step(self, ham, Ns, eta, lam, mu, momentum, key, counter, form=FORM_FP64_REF,
+             pinv_cutoff=0.0, ckpt_every=1, apply_update=True, outputs=None):
+        """One minSR iteration (Alg. 1); returns the output tensors.
+
+        `outputs` may hold preallocated tensors (energy, dtheta, status,
+        eloc, sigma) to avoid allocation, e.g. inside a timed loop."""
+        o = outputs if outputs is not None else self.step_outputs(Ns)
+        cfg = StepCfg(Ns, form, eta, lam, mu, pinv_cutoff, ckpt_every, int(apply_update))
+        st = StepState(ctypes.c_void_p(momentum.data_ptr()), key, counter)
+        out = StepOut(_ptr(o["energy"]).value, _ptr(o["dtheta"]).value, _ptr(o["status"]).value,
+                      _ptr(o.get("eloc")).value, _ptr(o.get("sigma")).value)
+        _check(lib().minsr_step(self.handle, ctypes.byref(ham), ctypes.byref(cfg),
+                                ctypes.byref(st), ctypes.byref(out), _stream()))
+        return o
+
+    def step_outputs(self, Ns):
+        dev = self.device
+        return dict(energy=torch.empty(3, dtype=torch.float64, device=dev),
+                    dtheta=torch.empty(self.Np, dtype=torch.float64, device=dev),
+                    status=torch.zeros(1, dtype=torch.int32, device=dev),
+                    eloc=torch.empty((Ns, 2), dtype=torch.float64, device=dev),
+                    sigma=torch.empty((Ns, self.N), dtype=torch.uint8, device=dev))
+
+    def timing_begin(self, max_steps):
+        _check(lib().minsr_timing_begin(self.handle, max_steps))
+
+    def timing_read(self):
+        """{phase: summed ms} over the steps recorded since timing_begin."""
+        ms = (ctypes.c_double * len(PHASES))()
+        n = ctypes.c_int()
+        _check(lib().minsr_timing_read(self.handle, ms, ctypes.byref(n)))
+        return dict(zip(PHASES, list(ms))), n.value
+
+    def intermediates(self, form):
+        """T, x, eps', O' of the last step, as torch views (copies)."""
+        vp = ctypes.c_void_p
+        T, x, e, O = vp(), vp(), vp(), vp()
+        n, Np = ctypes.c_int(), ctypes.c_int()
+        _check(lib().minsr_step_intermediates(self.handle, ctypes.byref(T), ctypes.byref(x),
+                                              ctypes.byref(e), ctypes.byref(O), ctypes.byref(n),
+                                              ctypes.byref(Np)))
+        n, Np = n.value, Np.value
+        tdt = torch.float32 if form == FORM_FP32_PLAIN else torch.float64
+        odt = {FORM_FP64_REF: torch.float64, FORM_BF16_FP64: torch.bfloat16,
+               FORM_FP32_PLAIN: torch.float32}[form]
+        return dict(T=_from_ptr(T.value, (n, n), tdt), x=_from_ptr(x.value, (n,), torch.float64),
+                    eps_prime=_from_ptr(e.value, (n,), torch.float64),
+                    Oprime=_from_ptr(O.value, (n, Np), odt))
+
+
+def _from_ptr(addr, shape, dtype):
+    """Copy a library-owned device buffer into a new tensor."""
+    numel = 1
+    for s in shape:
+        numel *= s
+    out = torch.empty(shape, dtype=dtype, device="cuda")
+    nbytes = numel * out.element_size()
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    torch.cuda.synchronize()
+    rc = hip.hipMemcpy(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(addr), nbytes, 3)
+    if rc != 0:
+        raise MinsrError("hipMemcpy failed: %d" % rc)
+    return out

@@ -1,0 +1,478 @@
+// C ABI of the minSR library: argument checking, workspace ownership and
+// the order in which one iteration of Algorithm 1 enqueues its kernels.
+#include "model.hpp"
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace minsr {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+Layout make_layout(int dim, int H, int cplx) {
+  Layout L{};
+  L.H = H; L.dim = dim; L.cplx = cplx; L.ds = dim == 1 ? 2 : 4;
+  size_t o = 0;
+  auto take = [&](size_t n) { size_t r = o; o += n; return r; };
+  const size_t h = (size_t)H, ds = (size_t)L.ds;
+  if (dim == 2) { L.U1 = take(h * h); L.U2 = take(h * h); }
+  L.Wu = take(h * (h + ds)); L.bu = take(h);
+  L.Wr = take(h * (h + ds)); L.br = take(h);
+  L.Wh = take(h * h); L.bh = take(h);
+  L.Win = take(h * ds); L.bin = take(h);
+  L.U = take(2 * h); L.c = take(2);
+  if (cplx) { L.Uphi = take(2 * h); L.cphi = take(2); }
+  L.Np = o;
+  return L;
+}
+
+size_t packed_elems(minsr_model* m);
+void bind_work(minsr_model* m);
+size_t gram_partial_bytes(int n, size_t Np, int dtype);
+
+// zero-fill by kernel (safe inside captured graphs)
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+template <typename TO>
+__global__ void k_vjp(const TO* O, int Ns, int two, size_t Np, const double* g, double scale,
+                      double* out) {
+  size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= Np) return;
+  double s = 0.0;
+  for (int r = 0; r < Ns; ++r) s += g[2 * r] * (double)O[(size_t)r * Np + col];
+  if (two)
+    for (int r = 0; r < Ns; ++r) s += g[2 * r + 1] * (double)O[((size_t)Ns + r) * Np + col];
+  out[col] = s * scale;
+}
+
+static int alloc(void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(MINSR_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return MINSR_OK;
+}
+
+static void release(minsr_model* m) {
+  void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->site, m->contrib,
+                  m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
+                  m->colpart, m->colmean, m->T, m->Lf, m->gpart, m->epsp, m->x, m->vwork,
+                  m->dpart, m->dtheta, m->status, m->eig};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (hipEvent_t e : m->ev) (void)hipEventDestroy(e);
+  m->ev.clear();
+}
+
+}  // namespace minsr
+
+using namespace minsr;
+
+extern "C" {
+
+const char* minsr_last_error(void) { return g_err.c_str(); }
+
+int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
+  if (!d || !out) return fail(MINSR_E_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (d->dim != 1 && d->dim != 2) return fail(MINSR_E_INVALID_ARG, "dim must be 1 or 2");
+  const int H = d->hidden;
+  if (H != 8 && H != 16 && H != 32 && H != 64 && H != 128)
+    return fail(MINSR_E_UNSUPPORTED, "hidden width must be 8, 16, 32, 64 or 128");
+  if (d->Lx < 2 || d->Ly < 1) return fail(MINSR_E_INVALID_ARG, "lattice too small");
+  if (d->dim == 1 && d->Ly != 1) return fail(MINSR_E_INVALID_ARG, "1D models need Ly == 1");
+  if (d->dim == 2 && (d->Ly < 2 || d->Lx > 16))
+    return fail(MINSR_E_UNSUPPORTED, "2D models need Ly >= 2 and Lx <= 16");
+  const int N = d->Lx * d->Ly;
+  if (N > 1024) return fail(MINSR_E_UNSUPPORTED, "at most 1024 sites");
+  if (d->zero_mag && (N % 2)) return fail(MINSR_E_INVALID_ARG, "zero_mag needs an even N");
+  if (d->compute_dtype != MINSR_F64 && d->compute_dtype != MINSR_F32)
+    return fail(MINSR_E_INVALID_ARG, "compute_dtype must be MINSR_F64 or MINSR_F32");
+  if (d->max_Ns < 1 || d->max_Ns > (1 << 16)) return fail(MINSR_E_INVALID_ARG, "max_Ns out of range");
+
+  minsr_model* m = new (std::nothrow) minsr_model();
+  if (!m) return fail(MINSR_E_NOMEM, "host allocation failed");
+  m->d = *d;
+  m->N = N; m->H = H; m->dim = d->dim; m->cplx = d->complex_head ? 1 : 0;
+  m->ds = d->dim == 1 ? 2 : 4;
+  m->f64 = d->compute_dtype == MINSR_F64;
+  m->L = make_layout(m->dim, H, m->cplx);
+  if (hipGetDevice(&m->device) != hipSuccess) { delete m; return fail(MINSR_E_DEVICE, "no HIP device"); }
+
+  const size_t Np = m->L.Np, S = (size_t)d->max_Ns, Nz = (size_t)N, Hz = (size_t)H;
+  const size_t sz = m->f64 ? 8 : 4;
+
+  // lattice tables: zigzag path predecessors, Marshall sublattice, bonds
+  std::vector<int> nbr(2 * N, -1);
+  std::vector<uint8_t> subA(N, 0);
+  auto pidx = [&](int i, int j) { return j * d->Lx + ((j % 2 == 0) ? i : d->Lx - 1 - i); };
+  for (int k = 0; k < N; ++k) {
+    const int j = k / d->Lx;
+    const int i = (j % 2 == 0) ? k % d->Lx : d->Lx - 1 - k % d->Lx;
+    if (m->dim == 2) {
+      const int ih = (j % 2 == 0) ? i - 1 : i + 1;
+      nbr[2 * k] = (ih >= 0 && ih < d->Lx) ? pidx(ih, j) : -1;
+      nbr[2 * k + 1] = j >= 1 ? pidx(i, j - 1) : -1;
+    } else {
+      nbr[2 * k] = k - 1;
+    }
+    subA[k] = ((i + j) % 2 == 0) ? 1 : 0;
+  }
+  std::vector<int> bonds;
+  if (m->dim == 2) {
+    auto addb = [&](int a, int b) { bonds.push_back(std::min(a, b)); bonds.push_back(std::max(a, b)); };
+    for (int j = 0; j < d->Ly; ++j)
+      for (int i = 0; i < d->Lx; ++i) {
+        if (i + 1 < d->Lx) addb(pidx(i, j), pidx(i + 1, j));
+        if (j + 1 < d->Ly) addb(pidx(i, j), pidx(i, j + 1));
+      }
+    m->n_nn = (int)bonds.size() / 2;
+    for (int j = 0; j < d->Ly; ++j)
+      for (int i = 0; i < d->Lx; ++i) {
+        if (i + 1 < d->Lx && j + 1 < d->Ly) addb(pidx(i, j), pidx(i + 1, j + 1));
+        if (i - 1 >= 0 && j + 1 < d->Ly) addb(pidx(i, j), pidx(i - 1, j + 1));
+      }
+    m->n_nnn = (int)bonds.size() / 2 - m->n_nn;
+  }
+  m->max_terms = std::max(N, m->n_nn + m->n_nnn);
+
+  const size_t rows = (m->cplx ? 2 : 1) * S;
+  const size_t nrc = (S + 31) / 32;
+  size_t gp = 0;
+  for (int dt : {MINSR_BF16, MINSR_F32, MINSR_F64})
+    gp = std::max(gp, gram_partial_bytes((int)rows, Np, dt));
+  m->gpart_elems = gp / sizeof(float) + 1;
+
+  int rc = MINSR_OK;
+  rc = rc ? rc : alloc((void**)&m->theta, Np * 8);
+  size_t pk = packed_elems(m);
+  m->work_elems = pk;
+  rc = rc ? rc : alloc(&m->work, pk * sz);
+  rc = rc ? rc : alloc((void**)&m->nbr, nbr.size() * sizeof(int));
+  rc = rc ? rc : alloc((void**)&m->subA, subA.size());
+  rc = rc ? rc : alloc((void**)&m->bonds, std::max<size_t>(bonds.size(), 2) * sizeof(int));
+  rc = rc ? rc : alloc(&m->states, S * Nz * Hz * sz);
+  rc = rc ? rc : alloc((void**)&m->site, S * Nz * 4 * 8);
+  rc = rc ? rc : alloc((void**)&m->contrib, (size_t)m->max_terms * S * 2 * 8);
+  if (m->dim == 2) {
+    m->ring_blocks = (int)S;
+    rc = rc ? rc : alloc(&m->ring, S * (size_t)(2 * d->Lx) * Hz * sz);
+  }
+  rc = rc ? rc : alloc((void**)&m->sigma, S * Nz);
+  rc = rc ? rc : alloc((void**)&m->logpsi, S * 2 * 8);
+  rc = rc ? rc : alloc((void**)&m->eloc, S * 2 * 8);
+  rc = rc ? rc : alloc((void**)&m->stats, 4 * 8);
+  rc = rc ? rc : alloc(&m->O, rows * Np * sz);
+  rc = rc ? rc : alloc(&m->R, rows * Np * sz);
+  rc = rc ? rc : alloc((void**)&m->colpart, 2 * nrc * Np * 8);
+  rc = rc ? rc : alloc((void**)&m->colmean, 2 * Np * 8);
+  rc = rc ? rc : alloc((void**)&m->T, rows * rows * 8);
+  rc = rc ? rc : alloc((void**)&m->Lf, rows * rows * 8);
+  rc = rc ? rc : alloc((void**)&m->gpart, m->gpart_elems * sizeof(float));
+  rc = rc ? rc : alloc((void**)&m->epsp, rows * 8);
+  rc = rc ? rc : alloc((void**)&m->x, rows * 8);
+  rc = rc ? rc : alloc((void**)&m->vwork, rows * 8);
+  rc = rc ? rc : alloc((void**)&m->dpart, ((rows + 63) / 64) * Np * 8);
+  rc = rc ? rc : alloc((void**)&m->dtheta, Np * 8);
+  rc = rc ? rc : alloc((void**)&m->status, 16);
+  if (rc) { release(m); delete m; return rc; }
+
+  hipError_t e = hipMemcpy(m->nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->subA, subA.data(), subA.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !bonds.empty())
+    e = hipMemcpy(m->bonds, bonds.data(), bonds.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { release(m); delete m; return fail(MINSR_E_DEVICE, hipGetErrorString(e)); }
+  bind_work(m);
+  rc = launch_init_theta(m, nullptr);
+  if (!rc) rc = launch_pack(m, nullptr);
+  if (!rc && hipDeviceSynchronize() != hipSuccess) rc = fail(MINSR_E_DEVICE, "initialisation failed");
+  if (rc) { release(m); delete m; return rc; }
+  *out = m;
+  return MINSR_OK;
+}
+
+int minsr_destroy_model(minsr_model* m) {
+  if (!m) return fail(MINSR_E_INVALID_ARG, "null model");
+  (void)hipDeviceSynchronize();
+  release(m);
+  delete m;
+  return MINSR_OK;
+}
+
+int minsr_num_params(const minsr_model* m, size_t* np) {
+  if (!m || !np) return fail(MINSR_E_INVALID_ARG, "null argument");
+  *np = m->L.Np;
+  return MINSR_OK;
+}
+
+int minsr_num_sites(const minsr_model* m, int* n) {
+  if (!m || !n) return fail(MINSR_E_INVALID_ARG, "null argument");
+  *n = m->N;
+  return MINSR_OK;
+}
+
+int minsr_get_params(minsr_model* m, double* dev_theta, hipStream_t s) {
+  if (!m || !dev_theta) return fail(MINSR_E_INVALID_ARG, "null argument");
+  MINSR_HIP(hipMemcpyAsync(dev_theta, m->theta, m->L.Np * 8, hipMemcpyDeviceToDevice, s));
+  return MINSR_OK;
+}
+
+int minsr_set_params(minsr_model* m, const double* dev_theta, hipStream_t s) {
+  if (!m || !dev_theta) return fail(MINSR_E_INVALID_ARG, "null argument");
+  MINSR_HIP(hipMemcpyAsync(m->theta, dev_theta, m->L.Np * 8, hipMemcpyDeviceToDevice, s));
+  return launch_pack(m, s);
+}
+
+static int check_ns(minsr_model* m, int Ns) {
+  if (!m) return fail(MINSR_E_INVALID_ARG, "null model");
+  if (Ns < 0 || Ns > m->d.max_Ns)
+    return fail(MINSR_E_SHAPE, "Ns=" + std::to_string(Ns) + " outside [0, max_Ns=" +
+                                   std::to_string(m->d.max_Ns) + "]");
+  return MINSR_OK;
+}
+
+int minsr_sample(minsr_model* m, int Ns, const double* dev_uniforms, uint64_t key,
+                 uint64_t counter, uint8_t* dev_sigma, double* dev_logpsi, hipStream_t s) {
+  int rc = check_ns(m, Ns);
+  if (rc) return rc;
+  if (!dev_sigma || !dev_logpsi) return fail(MINSR_E_INVALID_ARG, "null output");
+  return launch_forward(m, 0, Ns, dev_uniforms, key, counter, dev_sigma, dev_logpsi, m->states, 1,
+                        m->site, s);
+}
+
+int minsr_logpsi(minsr_model* m, int Ns, const uint8_t* dev_sigma, double* dev_logpsi,
+                 hipStream_t s) {
+  int rc = check_ns(m, Ns);
+  if (rc) return rc;
+  if (!dev_sigma || !dev_logpsi) return fail(MINSR_E_INVALID_ARG, "null argument");
+  return launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), dev_logpsi,
+                        m->states, 1, m->site, s);
+}
+
+static int check_ham(minsr_model* m, const minsr_hamiltonian* H) {
+  if (!H) return fail(MINSR_E_INVALID_ARG, "null Hamiltonian");
+  if (H->kind == MINSR_HAM_TFIM || H->kind == MINSR_HAM_CLUSTER) {
+    if (m->dim != 1) return fail(MINSR_E_UNSUPPORTED, "TFIM / cluster need a 1D model");
+    if (H->kind == MINSR_HAM_CLUSTER && m->N < 3) return fail(MINSR_E_SHAPE, "cluster needs N >= 3");
+    return MINSR_OK;
+  }
+  if (H->kind == MINSR_HAM_J1J2) {
+    if (m->dim != 2) return fail(MINSR_E_UNSUPPORTED, "J1-J2 needs a 2D model");
+    return MINSR_OK;
+  }
+  return fail(MINSR_E_INVALID_ARG, "unknown Hamiltonian kind");
+}
+
+int minsr_local_energy(minsr_model* m, const minsr_hamiltonian* H, int Ns,
+                       const uint8_t* dev_sigma, const double* dev_logpsi, double* dev_eloc,
+                       double* dev_stats, hipStream_t s) {
+  int rc = check_ns(m, Ns);
+  if (rc) return rc;
+  if ((rc = check_ham(m, H))) return rc;
+  if (!dev_sigma || !dev_eloc) return fail(MINSR_E_INVALID_ARG, "null argument");
+  // hidden states and per-site conditionals of the given configurations
+  rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
+                      m->states, 1, m->site, s);
+  if (rc) return rc;
+  rc = launch_eloc(m, H, Ns, dev_sigma, dev_logpsi, m->states, m->site, dev_eloc, s);
+  if (rc) return rc;
+  if (dev_stats) rc = launch_stats(m, Ns, dev_eloc, dev_stats, nullptr, nullptr, s);
+  return rc;
+}
+
+int minsr_jacobian(minsr_model* m, int Ns, const uint8_t* dev_sigma, int out_dtype, int centered,
+                   int ckpt_every, void* dev_O, double* dev_colmean, hipStream_t s) {
+  int rc = check_ns(m, Ns);
+  if (rc) return rc;
+  if (!dev_sigma || !dev_O) return fail(MINSR_E_INVALID_ARG, "null argument");
+  if (out_dtype != MINSR_F64 && out_dtype != MINSR_F32 && out_dtype != MINSR_BF16)
+    return fail(MINSR_E_INVALID_ARG, "unknown out_dtype");
+  if (out_dtype == MINSR_BF16 && !centered)
+    return fail(MINSR_E_INVALID_ARG, "BF16 output requires centred rows");
+  if (ckpt_every < 1 || ckpt_every > 16) return fail(MINSR_E_INVALID_ARG, "ckpt_every in [1, 16]");
+  if (centered && !dev_colmean) return fail(MINSR_E_INVALID_ARG, "centred output needs dev_colmean");
+  const int C = m->dim == 1 ? ckpt_every : 1;
+  rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
+                      m->states, C, nullptr, s);
+  if (rc) return rc;
+  const int native = m->f64 ? MINSR_F64 : MINSR_F32;
+  const int nb = m->cplx ? 2 : 1;
+  if (!centered && out_dtype == native)
+    return launch_jacobian(m, Ns, dev_sigma, m->states, C, dev_O, nullptr, nullptr, s);
+  rc = launch_jacobian(m, Ns, dev_sigma, m->states, C, m->O, nullptr, nullptr, s);
+  if (rc) return rc;
+  return launch_center(Ns, nb, m->L.Np, m->O, m->f64, dev_O, out_dtype, m->colpart,
+                       centered ? dev_colmean : nullptr, s);
+}
+
+int minsr_logpsi_vjp(minsr_model* m, int Ns, const uint8_t* dev_sigma, const double* dev_g,
+                     double* dev_grad_theta, hipStream_t s) {
+  int rc = check_ns(m, Ns);
+  if (rc) return rc;
+  if (!dev_sigma || !dev_g || !dev_grad_theta) return fail(MINSR_E_INVALID_ARG, "null argument");
+  if (Ns == 0) {
+    MINSR_HIP(hipMemsetAsync(dev_grad_theta, 0, m->L.Np * 8, s));
+    return MINSR_OK;
+  }
+  rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
+                      m->states, 1, nullptr, s);
+  if (rc) return rc;
+  rc = launch_jacobian(m, Ns, dev_sigma, m->states, 1, m->O, nullptr, nullptr, s);
+  if (rc) return rc;
+  const size_t Np = m->L.Np;
+  const double scale = std::sqrt((double)Ns);
+  const unsigned grid = (unsigned)((Np + 255) / 256);
+  if (m->f64) k_vjp<double><<<grid, 256, 0, s>>>((const double*)m->O, Ns, m->cplx, Np, dev_g, scale, dev_grad_theta);
+  else k_vjp<float><<<grid, 256, 0, s>>>((const float*)m->O, Ns, m->cplx, Np, dev_g, scale, dev_grad_theta);
+  MINSR_CHECK_LAUNCH();
+  return MINSR_OK;
+}
+
+int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg* cfg,
+               const minsr_step_state* st, const minsr_step_out* out, hipStream_t s) {
+  if (!m || !cfg || !st || !out) return fail(MINSR_E_INVALID_ARG, "null argument");
+  int rc = check_ns(m, cfg->Ns);
+  if (rc) return rc;
+  if ((rc = check_ham(m, H))) return rc;
+  const int Ns = cfg->Ns;
+  if (Ns < 2) return fail(MINSR_E_SHAPE, "a step needs Ns >= 2");
+  if (!out->dev_energy || !out->dev_status) return fail(MINSR_E_INVALID_ARG, "null output");
+  if (cfg->apply_update && !st->dev_momentum) return fail(MINSR_E_INVALID_ARG, "null momentum");
+  if (cfg->form < 0 || cfg->form > 2) return fail(MINSR_E_INVALID_ARG, "unknown form");
+  if (!(cfg->lambda >= 0.0) || !(cfg->pinv_cutoff >= 0.0)) return fail(MINSR_E_INVALID_ARG, "negative lambda / cutoff");
+  if (cfg->pinv_cutoff == 0.0 && cfg->lambda == 0.0)
+    return fail(MINSR_E_INVALID_ARG, "lambda = 0 needs the pseudo-inverse (T is singular)");
+  if (cfg->form == MINSR_FORM_FP64_REF && !m->f64)
+    return fail(MINSR_E_INVALID_ARG, "the FP64 reference form needs an FP64 model");
+  const int C = m->dim == 1 ? cfg->ckpt_every : 1;
+  if (C < 1 || C > 16) return fail(MINSR_E_INVALID_ARG, "ckpt_every in [1, 16]");
+
+  const size_t Np = m->L.Np;
+  const int nb = m->cplx ? 2 : 1;
+  const int n = nb * Ns;
+  uint8_t* sigma = out->dev_sigma ? out->dev_sigma : m->sigma;
+  double* eloc = out->dev_eloc ? out->dev_eloc : m->eloc;
+  double* dth = out->dev_dtheta ? out->dev_dtheta : m->dtheta;
+  const int rdt = cfg->form == MINSR_FORM_FP64_REF ? MINSR_F64
+                  : cfg->form == MINSR_FORM_BF16_FP64 ? MINSR_BF16 : MINSR_F32;
+
+  const bool timing = m->t_slot < m->t_max;
+  auto mark = [&](int phase) -> int {
+    if (timing) MINSR_HIP(hipEventRecord(m->ev[(size_t)m->t_slot * (MINSR_NPHASES + 1) + phase], s));
+    return MINSR_OK;
+  };
+#define MINSR_PHASE(ph) do { int rc_ = mark(ph); if (rc_) return rc_; } while (0)
+
+  k_zero_u32<<<1, 64, 0, s>>>(out->dev_status, 1);
+  MINSR_CHECK_LAUNCH();
+  MINSR_PHASE(0);
+  // 1. exact autoregressive samples, hidden states, per-site conditionals
+  rc = launch_forward(m, 0, Ns, nullptr, st->key, st->counter, sigma, m->logpsi, m->states, 1,
+                      m->site, s);
+  if (rc) return rc;
+  MINSR_PHASE(1);
+  // 2. local energies, E, Var and eps'
+  rc = launch_eloc(m, H, Ns, sigma, m->logpsi, m->states, m->site, eloc, s, 1);
+  if (rc) return rc;
+  MINSR_PHASE(2);
+  rc = launch_eloc(m, H, Ns, sigma, m->logpsi, m->states, m->site, eloc, s, 2);
+  if (rc) return rc;
+  rc = launch_stats(m, Ns, eloc, out->dev_energy, m->epsp, out->dev_status, s);
+  if (rc) return rc;
+  MINSR_PHASE(3);
+  // 3. log-derivatives, centring and real form
+  rc = launch_jacobian(m, Ns, sigma, m->states, C, m->O, nullptr, nullptr, s);
+  if (rc) return rc;
+  MINSR_PHASE(4);
+  rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, s);
+  if (rc) return rc;
+  MINSR_PHASE(5);
+  // 4. Gram and regularised solve
+  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 1);
+  if (rc) return rc;
+  MINSR_PHASE(6);
+  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 2);
+  if (rc) return rc;
+  MINSR_PHASE(7);
+  if (cfg->pinv_cutoff > 0.0)
+    rc = launch_pinv_solve(n, m->T, cfg->pinv_cutoff, m->epsp, m->x, m->eig, m->eig_elems,
+                           out->dev_status, s);
+  else
+    rc = launch_cholesky_solve(n, m->T, m->Lf, rdt == MINSR_F32, cfg->lambda, m->epsp, m->x,
+                               out->dev_status, s);
+  if (rc) return rc;
+  MINSR_PHASE(8);
+  // 5. dtheta = eta O' x, momentum, parameters, working copy
+  rc = launch_update(n, Np, m->R, rdt, m->x, cfg->eta, cfg->mu, m->dpart, dth, st->dev_momentum,
+                     m->theta, out->dev_status, cfg->apply_update, s);
+  if (rc) return rc;
+  MINSR_PHASE(9);
+  if (cfg->apply_update) {
+    rc = launch_pack(m, s);
+    if (rc) return rc;
+  }
+  MINSR_PHASE(10);
+#undef MINSR_PHASE
+  if (timing) m->t_slot++;
+  m->last_n = n;
+  m->last_form = cfg->form;
+  return MINSR_OK;
+}
+
+int minsr_timing_begin(minsr_model* m, int max_steps) {
+  if (!m || max_steps < 0) return fail(MINSR_E_INVALID_ARG, "bad argument");
+  const size_t need = (size_t)max_steps * (MINSR_NPHASES + 1);
+  while (m->ev.size() < need) {
+    hipEvent_t e;
+    MINSR_HIP(hipEventCreate(&e));
+    m->ev.push_back(e);
+  }
+  m->t_max = max_steps;
+  m->t_slot = 0;
+  return MINSR_OK;
+}
+
+int minsr_timing_read(minsr_model* m, double* ms, int* nsteps) {
+  if (!m || !ms || !nsteps) return fail(MINSR_E_INVALID_ARG, "null argument");
+  for (int p = 0; p < MINSR_NPHASES; ++p) ms[p] = 0.0;
+  for (int t = 0; t < m->t_slot; ++t) {
+    hipEvent_t* e = &m->ev[(size_t)t * (MINSR_NPHASES + 1)];
+    MINSR_HIP(hipEventSynchronize(e[MINSR_NPHASES]));
+    for (int p = 0; p < MINSR_NPHASES; ++p) {
+      float f = 0.f;
+      MINSR_HIP(hipEventElapsedTime(&f, e[p], e[p + 1]));
+      ms[p] += f;
+    }
+  }
+  *nsteps = m->t_slot;
+  m->t_max = 0;
+  m->t_slot = 0;
+  return MINSR_OK;
+}
+
+int minsr_step_intermediates(minsr_model* m, const void** T, const double** x,
+                             const double** eps_prime, const void** Oprime, int* n, int* Np) {
+  if (!m) return fail(MINSR_E_INVALID_ARG, "null model");
+  if (T) *T = m->T;  // the factorisation works on a copy
+  if (x) *x = m->x;
+  if (eps_prime) *eps_prime = m->epsp;
+  if (Oprime) *Oprime = m->R;
+  if (n) *n = m->last_n;
+  if (Np) *Np = (int)m->L.Np;
+  return MINSR_OK;
+}
+
+}  // extern "C"

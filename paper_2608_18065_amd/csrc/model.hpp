@@ -1,0 +1,96 @@
+// Internal state of a model handle and the launchers each translation unit
+// provides.  Not part of the ABI.
+#pragma once
+#include "common.hpp"
+
+struct minsr_model {
+  minsr_model_desc d;
+  int N, H, dim, cplx, ds;
+  int f64;                 // compute precision: 1 double, 0 float
+  minsr::Layout L;
+  int device;
+
+  double* theta = nullptr;  // [Np] master parameters
+  void* work = nullptr;     // packed working copy (compute precision)
+  size_t work_elems = 0;
+  minsr::Work<float> wf{};
+  minsr::Work<double> wd{};
+
+  int* nbr = nullptr;       // [N][2] path positions of the horizontal and
+                            // vertical predecessors (-1 outside the lattice)
+  uint8_t* subA = nullptr;  // [N] 1 if the site is on the Marshall sublattice
+  int* bonds = nullptr;     // [nb][2] J1-J2 bonds (path positions, a < b):
+  int n_nn = 0, n_nnn = 0;  //   n_nn nearest neighbours first, then n_nnn
+
+  // ---- workspace sized for d.max_Ns
+  int max_terms = 0;        // off-diagonal terms per sample (upper bound)
+  void* states = nullptr;   // [max_Ns][N][H] hidden states
+  double* site = nullptr;   // [max_Ns][N][4]: log p(0), log p(1), phi(0), phi(1)
+  double* contrib = nullptr;// [max_terms][max_Ns][2]
+  double* diag = nullptr;   // [max_Ns]
+  void* ring = nullptr;     // 2D local-energy recompute windows
+  int ring_blocks = 0;
+  uint8_t* sigma = nullptr; // [max_Ns][N]
+  double* logpsi = nullptr; // [max_Ns][2]
+  double* eloc = nullptr;   // [max_Ns][2]
+  double* stats = nullptr;  // [4]
+  void* O = nullptr;        // [2 max_Ns][Np] raw log-derivatives (compute precision)
+  void* R = nullptr;        // [2 max_Ns][Np] centred real form (step precision)
+  double* colpart = nullptr;// column-sum partials
+  double* colmean = nullptr;// [2][Np]
+  double* T = nullptr;      // [n][n] Gram (FP64, or FP32 in the plain form)
+  double* Lf = nullptr;     // [n][n] Cholesky factor of T + lambda I
+  float* gpart = nullptr;   // split-K Gram partials
+  size_t gpart_elems = 0;
+  double* epsp = nullptr;   // [n] eps'
+  double* x = nullptr;      // [n] solution
+  double* vwork = nullptr;  // [n] solver scratch
+  double* dpart = nullptr;  // update partials
+  double* dtheta = nullptr; // [Np]
+  uint32_t* status = nullptr;
+  double* eig = nullptr;    // eigen solver workspace
+  size_t eig_elems = 0;
+  int last_n = 0;
+  int last_form = 0;
+
+  // per-phase event timing of minsr_step (profiling only)
+  std::vector<hipEvent_t> ev;   // [t_max][NPHASE + 1]
+  int t_max = 0, t_slot = 0;
+};
+
+namespace minsr {
+
+// gru.hip
+int launch_init_theta(minsr_model* m, hipStream_t s);
+int launch_pack(minsr_model* m, hipStream_t s);
+// mode 0: sample, 1: evaluate.  states/site may be null.
+int launch_forward(minsr_model* m, int mode, int Ns, const double* uniforms, uint64_t key,
+                   uint64_t counter, uint8_t* sigma, double* logpsi, void* states,
+                   int store_every, double* site, hipStream_t s);
+// which: 1 = off-diagonal terms (the recurrence), 2 = diagonal + sum, 3 = both
+int launch_eloc(minsr_model* m, const minsr_hamiltonian* H, int Ns, const uint8_t* sigma,
+                const double* logpsi, const void* states, const double* site, double* eloc,
+                hipStream_t s, int which = 3);
+int launch_stats(minsr_model* m, int Ns, const double* eloc, double* stats, double* epsp,
+                 uint32_t* status, hipStream_t s);
+// jacobian.hip: raw rows (scaled by 1/sqrt(Ns)) into O (compute precision)
+int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* states,
+                    int ckpt_every, void* O, const double* g, double* vjp_part,
+                    hipStream_t s);
+// linalg.hip
+int launch_center(int rows_per_block, int nblocks, size_t Np, const void* O, int in_f64,
+                  void* R, int out_dtype, double* colpart, double* colmean, hipStream_t s);
+// which: 1 = tile products, 2 = split-K reduction and mirror, 3 = both
+int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gpart,
+                size_t gpart_elems, hipStream_t s, int which = 3);
+// factors T + lambda I into Lf (T is left unchanged) and solves for x
+int launch_cholesky_solve(int n, const double* T, double* Lf, int f32, double lambda,
+                          const double* b, double* x, uint32_t* status, hipStream_t s);
+int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* x,
+                      double* eig, size_t eig_elems, uint32_t* status, hipStream_t s);
+int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, double eta,
+                  double mu, double* dpart, double* dtheta, double* momentum, double* theta,
+                  uint32_t* status, int apply, hipStream_t s);
+int launch_reduce_rows(int rows, size_t Np, const double* part, double* out, hipStream_t s);
+
+}  // namespace minsr

@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path against the FP64 oracle on identical seeded
+inputs (FP64 models: 1e-10; sampled configurations bit-exact)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hamiltonian as oham
+from oracle import jacobian as ojac
+from oracle import minsr as ominsr
+from oracle import model as omodel
+from oracle import philox
+from tests import refs
+from tests.gpu_common import gpu, make_pair, need_gpu, rel_err, scaled_theta, to_dev
+from workloads import random_configs
+
+pytestmark = gpu
+
+ARCHS = [
+    dict(Lx=10, H=16),                                          # the N = 10 chain
+    dict(Lx=13, H=8, cplx=True),                                # ragged, complex head
+    dict(Lx=9, H=64),
+    dict(Lx=7, H=128, cplx=True),
+    dict(Lx=4, Ly=3, dim=2, H=8, marshall=True),
+    dict(Lx=4, Ly=4, dim=2, H=16, cplx=True, marshall=True, zero_mag=True),
+    dict(Lx=3, Ly=4, dim=2, H=64, zero_mag=True),
+    dict(Lx=4, Ly=2, dim=2, H=128, cplx=True, marshall=True),
+]
+
+
+def _ids(a):
+    return "_".join("%s%s" % (k, v) for k, v in a.items())
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("arch", ARCHS, ids=_ids)
+def test_init_bitexact(arch):
+    spec, m = make_pair(**arch, seed=2001 + arch["H"])
+    ref = omodel.glorot_init(spec, 2001 + arch["H"])
+    got = m.get_params().cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("arch", ARCHS, ids=_ids)
+def test_sample_bitexact_and_logpsi(arch):
+    spec, m = make_pair(**arch)
+    th = scaled_theta(spec, 7, 2.0)
+    m.set_params(to_dev(th))
+    Ns = 37
+    u = philox.uniforms(1001, 3, Ns, spec.N)
+    sig_ref, lp_ref = omodel.sample(spec, th, u)
+    # caller-provided uniforms
+    sig, lp = m.sample(Ns, uniforms=to_dev(u))
+    torch.cuda.synchronize()
+    assert np.array_equal(sig.cpu().numpy(), sig_ref.astype(np.uint8))
+    assert rel_err(lp.cpu().numpy(), lp_ref) < 1e-12
+    # uniforms generated in the kernel from the same Philox stream
+    sig2, lp2 = m.sample(Ns, key=1001, counter=3)
+    torch.cuda.synchronize()
+    assert np.array_equal(sig2.cpu().numpy(), sig_ref.astype(np.uint8))
+    assert np.array_equal(lp2.cpu().numpy(), lp.cpu().numpy())
+
+
+@pytest.mark.parametrize("arch", ARCHS, ids=_ids)
+def test_logpsi_random_configs(arch):
+    spec, m = make_pair(**arch)
+    th = scaled_theta(spec, 8, 1.5)
+    m.set_params(to_dev(th))
+    s = random_configs(5, 29, spec.N, zero_mag=spec.zero_mag)
+    lp = m.logpsi(to_dev(s)).cpu().numpy()
+    ref = omodel.log_psi(spec, th, s)
+    assert rel_err(lp, ref) < 1e-12
+
+
+def test_enumeration_normalised_config1():
+    spec, m = make_pair(Lx=10, H=16, max_Ns=1024)
+    s = refs.all_configs(10).astype(np.uint8)
+    lp = m.logpsi(to_dev(s)).cpu().numpy()
+    assert abs(np.sum(np.exp(2 * lp.real)) - 1.0) < 1e-12
+
+
+def test_sample_fp32_mostly_identical():
+    spec, m = make_pair(Lx=10, H=16, dtype="f32")
+    th = omodel.glorot_init(spec, 2001)
+    u = philox.uniforms(1001, 0, 64, 10)
+    sig_ref, lp_ref = omodel.sample(spec, th, u)
+    sig, lp = m.sample(64, uniforms=to_dev(u))
+    same = np.mean(np.all(sig.cpu().numpy() == sig_ref, axis=1))
+    assert same > 0.95
+    ok = np.all(sig.cpu().numpy() == sig_ref, axis=1)
+    assert rel_err(lp.cpu().numpy()[ok], lp_ref[ok]) < 1e-5
+
+
+HAMS = [
+    (dict(Lx=10, H=16), oham.Ham("tfim", J=1.0, h=1.0, pbc=False)),
+    (dict(Lx=11, H=64), oham.Ham("tfim", J=0.8, h=1.3, pbc=True)),
+    (dict(Lx=9, H=8, cplx=True), oham.Ham("cluster")),
+    (dict(Lx=7, H=128, cplx=True), oham.Ham("cluster")),
+    (dict(Lx=4, Ly=3, dim=2, H=8, marshall=True, zero_mag=True), oham.Ham("j1j2", J=1.0, J2=0.0)),
+    (dict(Lx=3, Ly=4, dim=2, H=16, cplx=True, marshall=True), oham.Ham("j1j2", J=1.0, J2=0.5)),
+    (dict(Lx=4, Ly=4, dim=2, H=64, marshall=True, zero_mag=True), oham.Ham("j1j2", J=1.0, J2=0.0)),
+    (dict(Lx=4, Ly=2, dim=2, H=128, cplx=True, marshall=True), oham.Ham("j1j2", J=1.0, J2=0.5)),
+]
+
+
+def _gpu_ham(h):
+    import paper_2608_18065_amd as pm
+    return pm.hamiltonian(h.kind, J=h.J, h=h.h, J2=h.J2, pbc=h.pbc)
+
+
+@pytest.mark.parametrize("arch,ham", HAMS, ids=lambda x: _ids(x) if isinstance(x, dict) else x.kind)
+def test_local_energy_parity(arch, ham):
+    spec, m = make_pair(**arch)
+    th = scaled_theta(spec, 9, 1.5)
+    m.set_params(to_dev(th))
+    Ns = 21
+    u = philox.uniforms(77, 1, Ns, spec.N)
+    sig, lp = omodel.sample(spec, th, u)
+    ref = oham.local_energy(spec, th, ham, sig, lp)
+    eloc, stats = m.local_energy(_gpu_ham(ham), to_dev(sig.astype(np.uint8)), to_dev(lp))
+    eloc = eloc.cpu().numpy()
+    assert rel_err(eloc, ref) < 1e-10
+    st = stats.cpu().numpy()
+    assert abs(st[0] - ref.mean().real) < 1e-10 * max(1, abs(ref.mean()))
+    assert abs(st[1] - ref.mean().imag) < 1e-10 * max(1, abs(ref.mean()))
+    assert abs(st[2] - np.mean(np.abs(ref - ref.mean()) ** 2)) < 1e-9 * max(1, st[2])
+
+
+JACS = [
+    dict(Lx=10, H=16),
+    dict(Lx=13, H=8, cplx=True),
+    dict(Lx=12, H=64),
+    dict(Lx=11, H=128, cplx=True),
+    dict(Lx=3, Ly=3, dim=2, H=8, marshall=True),
+    dict(Lx=4, Ly=3, dim=2, H=16, cplx=True, marshall=True, zero_mag=True),
+    dict(Lx=4, Ly=3, dim=2, H=64, zero_mag=True),
+    dict(Lx=3, Ly=2, dim=2, H=128, cplx=True),
+]
+
+
+@pytest.mark.parametrize("arch", JACS, ids=_ids)
+def test_jacobian_parity(arch):
+    spec, m = make_pair(**arch)
+    th = scaled_theta(spec, 10, 1.5)
+    m.set_params(to_dev(th))
+    Ns = 5
+    sig, _ = omodel.sample(spec, th, philox.uniforms(5, 0, Ns, spec.N))
+    D = ojac.log_derivatives(spec, th, sig)
+    ref = (np.concatenate([D.real, D.imag], axis=0) if spec.complex_head else D) / np.sqrt(Ns)
+    O, _ = m.jacobian(to_dev(sig.astype(np.uint8)))
+    assert rel_err(O.cpu().numpy(), ref) < 1e-10
+
+
+@pytest.mark.parametrize("arch", [dict(Lx=23, H=16), dict(Lx=20, H=64, cplx=True),
+                                  dict(Lx=21, H=128)], ids=_ids)
+@pytest.mark.parametrize("C", [3, 10, 16])
+def test_checkpointed_jacobian_bitwise(arch, C):
+    spec, m = make_pair(**arch)
+    th = scaled_theta(spec, 11, 1.5)
+    m.set_params(to_dev(th))
+    sig, _ = m.sample(19, key=3, counter=4)
+    O1, _ = m.jacobian(sig, ckpt_every=1)
+    Oc, _ = m.jacobian(sig, ckpt_every=C)
+    assert torch.equal(O1, Oc)
+
+
+def test_jacobian_centered_colmean():
+    spec, m = make_pair(Lx=10, H=16, cplx=True)
+    th = scaled_theta(spec, 12, 1.0)
+    m.set_params(to_dev(th))
+    sig, _ = m.sample(33, key=9, counter=1)
+    O, _ = m.jacobian(sig)
+    Oc, mean = m.jacobian(sig, centered=True)
+    O = O.cpu().numpy().reshape(2, 33, -1)
+    ref_mean = O.mean(axis=1)
+    assert rel_err(mean.cpu().numpy(), ref_mean) < 1e-12
+    assert rel_err(Oc.cpu().numpy().reshape(2, 33, -1), O - ref_mean[:, None, :]) < 1e-12
+    Ob, _ = m.jacobian(sig, out_dtype=2, centered=True)
+    assert rel_err(Ob.float().cpu().numpy().reshape(2, 33, -1), O - ref_mean[:, None, :]) < 1e-2
+
+
+def test_vjp_matches_oracle():
+    spec, m = make_pair(Lx=9, H=16, cplx=True)
+    th = scaled_theta(spec, 13, 1.0)
+    m.set_params(to_dev(th))
+    sig, _ = omodel.sample(spec, th, philox.uniforms(2, 2, 11, spec.N))
+    g = np.random.default_rng(0).normal(size=11) + 1j * np.random.default_rng(1).normal(size=11)
+    D = ojac.log_derivatives(spec, th, sig)
+    ref = g.real @ D.real + g.imag @ D.imag
+    got = m.logpsi_vjp(to_dev(sig.astype(np.uint8)), to_dev(g)).cpu().numpy()
+    assert rel_err(got, ref) < 1e-10
+
+
+# ------------------------------------------------------------ whole step
+
+def _oracle_step_from_gpu_samples(spec, th, ham, sig, eta, lam, pinv=0.0):
+    sig = sig.astype(np.int64)
+    lp = omodel.log_psi(spec, th, sig)
+    eps = oham.local_energy(spec, th, ham, sig, lp)
+    D = ojac.log_derivatives(spec, th, sig)
+    r = ominsr.update(D, eps, eta, lam, pinv)
+    r["eps"] = eps
+    return r
+
+
+def test_step_fp64_config1():
+    import paper_2608_18065_amd as pm
+    spec, m = make_pair(Lx=10, H=16, max_Ns=64)
+    th = omodel.glorot_init(spec, 2001)
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    ham = oham.Ham("tfim", J=1.0, h=1.0)
+    o = m.step(_gpu_ham(ham), 64, 0.01, 1e-3, 0.0, mom, 1001, 0, form=pm.FORM_FP64_REF)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == 0
+    ref = ominsr.step(spec, th, np.zeros_like(th), ham, 64, 0.01, 1e-3, 0.0, 1001, 0)
+    assert np.array_equal(o["sigma"].cpu().numpy(), ref["sigma"].astype(np.uint8))
+    e = o["energy"].cpu().numpy()
+    assert abs(e[0] - ref["E"].real) < 1e-10 * abs(ref["E"])
+    it = m.intermediates(pm.FORM_FP64_REF)
+    assert rel_err(it["eps_prime"].cpu().numpy(), ref["ep"]) < 1e-10
+    T = it["T"].cpu().numpy()
+    assert np.array_equal(T, T.T)
+    assert rel_err(T, ref["T"]) < 1e-10
+    assert rel_err(it["x"].cpu().numpy(), ref["x"]) < 1e-10
+    assert rel_err(o["dtheta"].cpu().numpy(), ref["dtheta"]) < 1e-10
+    assert rel_err(m.get_params().cpu().numpy(), ref["theta"]) < 1e-10
+    assert rel_err(mom.cpu().numpy(), ref["m"]) < 1e-10
+
+
+@pytest.mark.parametrize("arch,ham,Ns", [
+    (dict(Lx=12, H=32), oham.Ham("tfim", J=1.0, h=1.0, pbc=True), 200),
+    (dict(Lx=10, H=16, cplx=True), oham.Ham("cluster"), 150),
+    (dict(Lx=3, Ly=4, dim=2, H=16, marshall=True, zero_mag=True), oham.Ham("j1j2", J=1.0), 130),
+], ids=["tfim_pbc", "cluster_c", "heis2d"])
+def test_step_fp64_ragged(arch, ham, Ns):
+    import paper_2608_18065_amd as pm
+    spec, m = make_pair(**arch, max_Ns=Ns)
+    th = scaled_theta(spec, 14, 1.0)
+    m.set_params(to_dev(th))
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    o = m.step(_gpu_ham(ham), Ns, 0.05, 1e-3, 0.5, mom, 5, 6, form=pm.FORM_FP64_REF)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == 0
+    ref = _oracle_step_from_gpu_samples(spec, th, ham, o["sigma"].cpu().numpy(), 0.05, 1e-3)
+    assert rel_err(o["eloc"].cpu().numpy() @ np.array([1, 1j]), ref["eps"]) < 1e-10
+    it = m.intermediates(pm.FORM_FP64_REF)
+    assert rel_err(it["T"].cpu().numpy(), ref["T"]) < 1e-10
+    assert rel_err(o["dtheta"].cpu().numpy(), ref["dtheta"]) < 1e-10
+    np.testing.assert_allclose(m.get_params().cpu().numpy(), th - 0.5 * ref["dtheta"],
+                               rtol=0, atol=1e-10 * np.max(np.abs(ref["dtheta"])) + 1e-15)
+
+
+@pytest.mark.parametrize("form,tol", [(1, 2e-2), (2, 5e-2)], ids=["bf16_fp64", "fp32_plain"])
+def test_step_low_precision_forms(form, tol):
+    spec, m = make_pair(Lx=10, H=16, dtype="f32", max_Ns=64)
+    th = omodel.glorot_init(spec, 2001)
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    ham = oham.Ham("tfim", J=1.0, h=1.0)
+    o = m.step(_gpu_ham(ham), 64, 0.01, 1e-3, 0.0, mom, 1001, 0, form=form)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == 0
+    ref = _oracle_step_from_gpu_samples(spec, th, ham, o["sigma"].cpu().numpy(), 0.01, 1e-3)
+    d = o["dtheta"].cpu().numpy()
+    err = np.linalg.norm(d - ref["dtheta"]) / np.linalg.norm(ref["dtheta"])
+    assert err < tol, err
