@@ -217,7 +217,9 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H,
 /* Device pointers to the step's intermediates after the last minsr_step
  * on this handle (valid until the next call on it): T (n x n FP64, or
  * FP32 in the FP32_PLAIN form), x (n), eps' (n), with n = Ns (pRNN) or
- * 2 Ns (cRNN); O' (n x Np, rows centred; dtype per form).  For tests.    */
+ * 2 Ns (cRNN); O' (n rows, centred; dtype per form) whose row stride is
+ * returned in *Np (the parameter count rounded up to a multiple of 64,
+ * zero padded).  For tests.                                              */
 int minsr_step_intermediates(minsr_model* m, const void** T, const double** x,
                              const double** eps_prime, const void** Oprime,
                              int* n, int* Np);

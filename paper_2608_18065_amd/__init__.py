@@ -263,13 +263,13 @@ class Model:
         _check(lib().minsr_step_intermediates(self.handle, ctypes.byref(T), ctypes.byref(x),
                                               ctypes.byref(e), ctypes.byref(O), ctypes.byref(n),
                                               ctypes.byref(Np)))
-        n, Np = n.value, Np.value
+        n, Np = n.value, Np.value     # Np: padded row stride of O'
         tdt = torch.float32 if form == FORM_FP32_PLAIN else torch.float64
         odt = {FORM_FP64_REF: torch.float64, FORM_BF16_FP64: torch.bfloat16,
                FORM_FP32_PLAIN: torch.float32}[form]
         return dict(T=_from_ptr(T.value, (n, n), tdt), x=_from_ptr(x.value, (n,), torch.float64),
                     eps_prime=_from_ptr(e.value, (n,), torch.float64),
-                    Oprime=_from_ptr(O.value, (n, Np), odt))
+                    Oprime=_from_ptr(O.value, (n, Np), odt)[:, :self.Np])
 
 
 def _from_ptr(addr, shape, dtype):

@@ -69,7 +69,7 @@ static int alloc(void** p, size_t bytes) {
 static void release(minsr_model* m) {
   void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->site, m->contrib,
                   m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
-                  m->colpart, m->colmean, m->T, m->Lf, m->gpart, m->epsp, m->x, m->vwork,
+                  m->colpart, m->colmean, m->T, m->Lf, m->Dinv, m->gpart, m->epsp, m->x, m->vwork,
                   m->dpart, m->dtheta, m->status, m->eig};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -168,19 +168,22 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   rc = rc ? rc : alloc((void**)&m->site, S * Nz * 4 * 8);
   rc = rc ? rc : alloc((void**)&m->contrib, (size_t)m->max_terms * S * 2 * 8);
   if (m->dim == 2) {
-    m->ring_blocks = (int)S;
-    rc = rc ? rc : alloc(&m->ring, S * (size_t)(2 * d->Lx) * Hz * sz);
+    // recompute windows: one per sample (sampling) or per in-flight
+    // local-energy sequence (persistent grid of up to 512 x 32 sequences)
+    m->ring_blocks = (int)std::max<size_t>(S, 512 * 32);
+    rc = rc ? rc : alloc(&m->ring, (size_t)m->ring_blocks * (size_t)(2 * d->Lx) * Hz * sz);
   }
   rc = rc ? rc : alloc((void**)&m->sigma, S * Nz);
   rc = rc ? rc : alloc((void**)&m->logpsi, S * 2 * 8);
   rc = rc ? rc : alloc((void**)&m->eloc, S * 2 * 8);
   rc = rc ? rc : alloc((void**)&m->stats, 4 * 8);
   rc = rc ? rc : alloc(&m->O, rows * Np * sz);
-  rc = rc ? rc : alloc(&m->R, rows * Np * sz);
+  rc = rc ? rc : alloc(&m->R, rows * padded_ld(Np) * sz);
   rc = rc ? rc : alloc((void**)&m->colpart, 2 * nrc * Np * 8);
   rc = rc ? rc : alloc((void**)&m->colmean, 2 * Np * 8);
   rc = rc ? rc : alloc((void**)&m->T, rows * rows * 8);
   rc = rc ? rc : alloc((void**)&m->Lf, rows * rows * 8);
+  rc = rc ? rc : alloc((void**)&m->Dinv, chol_dinv_elems((int)rows) * 8);
   rc = rc ? rc : alloc((void**)&m->gpart, m->gpart_elems * sizeof(float));
   rc = rc ? rc : alloc((void**)&m->epsp, rows * 8);
   rc = rc ? rc : alloc((void**)&m->x, rows * 8);
@@ -315,7 +318,7 @@ int minsr_jacobian(minsr_model* m, int Ns, const uint8_t* dev_sigma, int out_dty
   rc = launch_jacobian(m, Ns, dev_sigma, m->states, C, m->O, nullptr, nullptr, s);
   if (rc) return rc;
   return launch_center(Ns, nb, m->L.Np, m->O, m->f64, dev_O, out_dtype, m->colpart,
-                       centered ? dev_colmean : nullptr, s);
+                       centered ? dev_colmean : nullptr, m->L.Np, s);
 }
 
 int minsr_logpsi_vjp(minsr_model* m, int Ns, const uint8_t* dev_sigma, const double* dev_g,
@@ -397,7 +400,7 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   rc = launch_jacobian(m, Ns, sigma, m->states, C, m->O, nullptr, nullptr, s);
   if (rc) return rc;
   MINSR_PHASE(4);
-  rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, s);
+  rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, padded_ld(Np), s);
   if (rc) return rc;
   MINSR_PHASE(5);
   // 4. Gram and regularised solve
@@ -411,8 +414,8 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
     rc = launch_pinv_solve(n, m->T, cfg->pinv_cutoff, m->epsp, m->x, m->eig, m->eig_elems,
                            out->dev_status, s);
   else
-    rc = launch_cholesky_solve(n, m->T, m->Lf, rdt == MINSR_F32, cfg->lambda, m->epsp, m->x,
-                               out->dev_status, s);
+    rc = launch_cholesky_solve(n, m->T, m->Lf, m->Dinv, rdt == MINSR_F32, cfg->lambda, m->epsp,
+                               m->x, out->dev_status, s);
   if (rc) return rc;
   MINSR_PHASE(8);
   // 5. dtheta = eta O' x, momentum, parameters, working copy
@@ -471,7 +474,7 @@ int minsr_step_intermediates(minsr_model* m, const void** T, const double** x,
   if (eps_prime) *eps_prime = m->epsp;
   if (Oprime) *Oprime = m->R;
   if (n) *n = m->last_n;
-  if (Np) *Np = (int)m->L.Np;
+  if (Np) *Np = (int)padded_ld(m->L.Np);   // row stride of O' (zero padded)
   return MINSR_OK;
 }
 

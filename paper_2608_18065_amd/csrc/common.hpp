@@ -81,8 +81,11 @@ Layout make_layout(int dim, int H, int cplx);
 //   xc   : per unit: Wu[j][H+c], Wr[j][H+c], Win[j][c] for c < ds as
 //          [3][ds][H]; then bu, br, bh, bin as [4][H]
 //   head : U [2][H], Uphi [2][H], c[2], cphi[2]
+//   mw   : FP32 models: MFMA B-operand fragments of the gate weights for the
+//          local-energy kernel, [wave][step][64 lanes] (see gru_mfma.hip)
+//   m2   : FP32 2D models: the same for [U1 | U2]
 template <typename T> struct Work {
-  T* fw; T* bw; T* f2; T* b2; T* xc; T* bias; T* head; T* headb;
+  T* fw; T* bw; T* f2; T* b2; T* xc; T* bias; T* head; T* headb; T* mw; T* m2;
 };
 
 }  // namespace minsr

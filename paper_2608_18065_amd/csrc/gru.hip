@@ -75,7 +75,8 @@ struct PackArgs {
   const double* th;
   int H, ds, dim, cplx, V;
   long long Wu, bu, Wr, br, Wh, bh, Win, bin, U, c, Uphi, cphi, U1, U2;
-  long long o_fw, o_bw, o_f2, o_b2, o_xc, o_bias, o_head, o_headb, total;
+  long long o_fw, o_bw, o_f2, o_b2, o_xc, o_bias, o_head, o_headb, o_mw, o_m2, total;
+  int ks, kx, nstep;   // MFMA fragments: h steps, one-hot steps, steps per wave
 };
 
 template <typename T>
@@ -134,10 +135,37 @@ __global__ void k_pack(T* out, PackArgs p) {
     int j = (int)(r % H); int q = (int)(r / H);
     if (q < 2) v = th[p.U + (long long)q * H + j];
     else v = p.cplx ? th[p.Uphi + (long long)(q - 2) * H + j] : 0.0;
-  } else {                                // headb [4]
+  } else if (e < p.o_mw) {                // headb [4]
     int q = (int)(e - p.o_headb);
     if (q < 2) v = th[p.c + q];
     else v = p.cplx ? th[p.cphi + q - 2] : 0.0;
+  } else if (e < p.o_m2) {                // mw [wave][step][lane]
+    long long r = e - p.o_mw;
+    const int lane = (int)(r % 64); r /= 64;
+    const int step = (int)(r % p.nstep); const int w = (int)(r / p.nstep);
+    const int unit = 32 * w + (lane & 31), half = lane >> 5;
+    const int KS = p.ks, KX = p.kx;
+    // steps: u (KS + KX), r (KS + KX), g (KS), i (KX); the h part pairs
+    // input k = s + half * KS, the one-hot part column c = 2 x + half
+    int q, st;
+    if (step < KS + KX) { q = 0; st = step; }
+    else if (step < 2 * (KS + KX)) { q = 1; st = step - (KS + KX); }
+    else if (step < 2 * (KS + KX) + KS) { q = 2; st = step - 2 * (KS + KX); }
+    else { q = 3; st = step - 2 * (KS + KX); }
+    if (q < 3 && st < KS) {
+      v = gate(q, unit, st + half * KS);
+    } else {
+      const int c = 2 * (st - KS) + half;
+      if (q == 0) v = th[p.Wu + (long long)unit * (H + ds) + H + c];
+      else if (q == 1) v = th[p.Wr + (long long)unit * (H + ds) + H + c];
+      else v = th[p.Win + (long long)unit * ds + c];
+    }
+  } else {                                // m2 [wave][s][lane]: U1 (half 0), U2 (half 1)
+    long long r = e - p.o_m2;
+    const int lane = (int)(r % 64); r /= 64;
+    const int st = (int)(r % H); const int w = (int)(r / H);
+    const int unit = 32 * w + (lane & 31), half = lane >> 5;
+    v = u12(half, unit, st);
   }
   out[e] = (T)v;
 }
@@ -160,7 +188,13 @@ static PackArgs pack_args(minsr_model* m) {
   p.o_bias = p.o_xc + 3 * L.ds * H;
   p.o_head = p.o_bias + 4 * H;
   p.o_headb = p.o_head + 4 * H;
-  p.total = p.o_headb + 4;
+  p.o_mw = p.o_headb + 4;
+  const bool mf = !m->f64 && H >= 32;
+  p.ks = (int)H / 2;
+  p.kx = L.dim == 1 ? 1 : 2;
+  p.nstep = 3 * p.ks + 3 * p.kx;
+  p.o_m2 = p.o_mw + (mf ? (H / 32) * p.nstep * 64 : 0);
+  p.total = p.o_m2 + (mf && L.dim == 2 ? (H / 32) * H * 64 : 0);
   return p;
 }
 
@@ -171,6 +205,8 @@ static void set_work(Work<T>& w, T* base, const PackArgs& p) {
   w.fw = base + p.o_fw; w.bw = base + p.o_bw; w.f2 = base + p.o_f2; w.b2 = base + p.o_b2;
   w.xc = base + p.o_xc; w.bias = base + p.o_bias; w.head = base + p.o_head;
   w.headb = base + p.o_headb;
+  w.mw = base + p.o_mw;
+  w.m2 = base + p.o_m2;
 }
 
 void bind_work(minsr_model* m) {
@@ -374,6 +410,7 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
         T acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = (T)0;
+#pragma unroll 2
         for (int k4 = 0; k4 < H / V; ++k4) {
           const VT w1 = f2[(k4 * H + j) * 2 + 0];
           const VT w2 = f2[(k4 * H + j) * 2 + 1];
@@ -426,6 +463,7 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
           }
         }
       }
+#pragma unroll 2
       for (int k4 = 0; k4 < H / V; ++k4) {
         const VT wu = fw[(k4 * H + j) * 3 + 0];
         const VT wr = fw[(k4 * H + j) * 3 + 1];
@@ -712,7 +750,11 @@ static int eloc_t(minsr_model* m, const Work<T>& w, const minsr_hamiltonian* H, 
     if ((int)grid > cap) grid = (unsigned)cap;
   }
   if (a.n_items > 0 && (which & 1)) {
-    int rc = dispatch_dim<T, 4>(m, a, grid, s);
+    int rc;
+    if (!m->f64 && !m->force_vector && eloc_mfma_supported(m))
+      rc = launch_eloc_mfma(m, H, Ns, sigma, states, site, M, s);
+    else
+      rc = dispatch_dim<T, 4>(m, a, grid, s);
     if (rc) return rc;
   }
   if (!(which & 2)) return MINSR_OK;

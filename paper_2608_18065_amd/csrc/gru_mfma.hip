@@ -1,0 +1,308 @@
+// Local energies of FP32 models on the matrix cores (Sec. 2.3, local
+// energy; App. A, GRU cells).
+//
+// A workgroup re-evaluates 32 connected configurations that share their
+// first flipped site (one term of the Hamiltonian for 32 samples), so all
+// 32 recurrences restart at the same site and advance in lockstep.  At
+// every site the gate pre-activations of the 32 sequences are one
+// [32 x (H + ds)] x [(H + ds) x 3H] product on v_mfma_f32_32x32x2_f32:
+// wave w owns hidden units 32w..32w+31 and keeps its B-operand fragments of
+// W_u, W_r, W_h and of the one-hot input columns in registers for the whole
+// kernel, so the only per-site operand traffic is the 32 x H hidden state
+// read from LDS.  The input vector is [h; onehot(sigma)], exactly the
+// paper's x = [h; sigma]; its one-hot columns enter as extra K-steps.  The
+// elementwise GRU update runs in the accumulator layout (lane l holds unit
+// l mod 32 of 16 sequences), the new state goes back to LDS, and each lane
+// then reduces the output head for its own sequence.  2D models form
+// h' = U1 h_horizontal + U2 h_vertical with one more MFMA product per site
+// (B fragments streamed from L2) before the cell.
+#include "model.hpp"
+
+namespace minsr {
+
+typedef __attribute__((ext_vector_type(16))) float f32x16_m;
+
+struct ElocMArgs {
+  const float* mw;
+  const float* m2;
+  const float* bias;
+  const float* head;
+  const float* headb;
+  int N, Ns, zero_mag, cplx, marshall, nchunks, n_items, W;
+  const int* nbr;
+  const uint8_t* subA;
+  const uint8_t* sigma;
+  const float* states;
+  const double* site;
+  const int* bonds;
+  int n_nn, ham_kind;
+  double hx, J1, J2;
+  double* contrib;
+  float* ring;
+};
+
+__device__ inline f32x16_m mfma_f32(float a, float b, f32x16_m c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+template <int H, int DIM>
+__global__ __launch_bounds__(64 * (H / 32)) void k_eloc_mfma(ElocMArgs a) {
+  constexpr int S = 32;
+  constexpr int HP = H + 4;
+  constexpr int KS = H / 2;
+  constexpr int KX = DIM == 1 ? 1 : 2;
+  constexpr int NSTEP = 3 * KS + 3 * KX;
+  __shared__ __align__(16) float hA[2][S][HP];
+  __shared__ __align__(16) float hx[DIM == 2 ? S : 1][2 * H + 4];
+  __shared__ __align__(16) float hw[4][H];
+  __shared__ float hb[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int half = lane >> 5, col = lane & 31;
+  const int unit = 32 * w + col;
+  const int N = a.N;
+  const int NT = blockDim.x;
+
+  float Wu[KS + KX], Wr[KS + KX], Wg[KS], Wi[KX];
+  {
+    const float* base = a.mw + (size_t)w * NSTEP * 64 + lane;
+#pragma unroll
+    for (int s = 0; s < KS + KX; ++s) Wu[s] = base[(size_t)s * 64];
+#pragma unroll
+    for (int s = 0; s < KS + KX; ++s) Wr[s] = base[(size_t)(KS + KX + s) * 64];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) Wg[s] = base[(size_t)(2 * (KS + KX) + s) * 64];
+#pragma unroll
+    for (int s = 0; s < KX; ++s) Wi[s] = base[(size_t)(2 * (KS + KX) + KS + s) * 64];
+  }
+  const float bu = a.bias[unit], br = a.bias[H + unit], bh = a.bias[2 * H + unit];
+  const float bi = a.bias[3 * H + unit];
+  for (int i = tid; i < 4 * H; i += NT) hw[i / H][i % H] = a.head[i];
+  if (tid < 4) hb[tid] = a.headb[tid];
+  __syncthreads();
+  const float PI = 3.14159265358979323846f;
+
+  for (int item = blockIdx.x; item < a.n_items; item += gridDim.x) {
+    const int t = item / a.nchunks, chunk = item % a.nchunks;
+    int f1, f2p = -1;
+    double Jt = 0.0;
+    if (a.ham_kind == MINSR_HAM_J1J2) {
+      f1 = a.bonds[2 * t]; f2p = a.bonds[2 * t + 1];
+      Jt = t < a.n_nn ? a.J1 : a.J2;
+    } else {
+      f1 = t;
+    }
+    const int k0 = f1;
+    const int s = chunk * S + col;      // this lane's sequence (both halves)
+    const bool act = s < a.Ns;
+    const int sid = act ? s : 0;
+    const uint8_t* sg = a.sigma + (size_t)sid * N;
+    const double* st = a.site + (size_t)sid * N * 4;
+    int nup = 0, ndn = 0, dA = 0;
+    double oldlp = 0.0, oldph = 0.0;
+    for (int k = 0; k <= k0; ++k) {
+      int v = sg[k];
+      if (k == f1) v ^= 1;
+      nup += v == 0; ndn += v == 1;
+    }
+    for (int k = k0; k < N; ++k) {
+      const int v = sg[k];
+      oldlp += st[4 * k + v];
+      oldph += st[4 * k + 2 + v];
+    }
+    const int vflip = sg[k0] ^ 1;
+    double lp = st[4 * k0 + vflip];
+    double ph = st[4 * k0 + 2 + vflip];
+    int sprev = vflip;
+    double mel;
+    if (a.ham_kind == MINSR_HAM_TFIM) {
+      mel = -a.hx;
+    } else if (a.ham_kind == MINSR_HAM_CLUSTER) {
+      const double zl = 1.0 - 2.0 * sg[(f1 - 1 + N) % N];
+      const double zr = 1.0 - 2.0 * sg[(f1 + 1) % N];
+      mel = -zl * zr;
+    } else {
+      mel = sg[f1] != sg[f2p] ? 0.5 * Jt : 0.0;
+    }
+    if (a.marshall) {
+      if (a.subA[f1]) dA += 1 - 2 * sg[f1];
+      if (f2p >= 0 && a.subA[f2p]) dA += 1 - 2 * sg[f2p];
+    }
+    if (DIM == 1 && k0 + 1 < N) {
+      for (int i = tid; i < S * H; i += NT) {
+        const int q = i / H, u = i % H;
+        int sq = chunk * S + q;
+        sq = sq < a.Ns ? sq : 0;
+        hA[(k0 + 1) & 1][q][u] = a.states[((size_t)sq * N + k0) * H + u];
+      }
+    }
+    __syncthreads();
+
+    for (int k = k0 + 1; k < N; ++k) {
+      const int cb = k & 1, nb = cb ^ 1;
+      f32x16_m hin;
+      int sh = -1, sv = -1;
+      if (DIM == 2) {
+        const int kh = a.nbr[2 * k], kv = a.nbr[2 * k + 1];
+        if (kh >= 0) { sh = sg[kh]; if (kh == f1 || kh == f2p) sh ^= 1; }
+        if (kv >= 0) { sv = sg[kv]; if (kv == f1 || kv == f2p) sv ^= 1; }
+        for (int i = tid; i < S * 2 * H; i += NT) {
+          const int q = i / (2 * H), r = i % (2 * H);
+          const int pos = r < H ? kh : kv;
+          const int u = r < H ? r : r - H;
+          float v = 0.f;
+          if (pos >= 0) {
+            int sq = chunk * S + q;
+            sq = sq < a.Ns ? sq : 0;
+            if (pos <= k0) v = a.states[((size_t)sq * N + pos) * H + u];
+            else v = a.ring[(((size_t)blockIdx.x * S + q) * a.W + pos % a.W) * H + u];
+          }
+          hx[q][r] = v;
+        }
+        __syncthreads();
+        f32x16_m acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+        const float* m2 = a.m2 + (size_t)w * H * 64 + lane;
+#pragma unroll 4
+        for (int s4 = 0; s4 < H; s4 += 4) {
+          const float4 av = *reinterpret_cast<const float4*>(&hx[col][s4 + half * H]);
+          acc = mfma_f32(av.x, m2[(size_t)(s4 + 0) * 64], acc);
+          acc = mfma_f32(av.y, m2[(size_t)(s4 + 1) * 64], acc);
+          acc = mfma_f32(av.z, m2[(size_t)(s4 + 2) * 64], acc);
+          acc = mfma_f32(av.w, m2[(size_t)(s4 + 3) * 64], acc);
+        }
+        hin = acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) hA[cb][(e / 4) * 8 + half * 4 + (e % 4)][unit] = hin[e];
+        __syncthreads();
+      }
+      // gate pre-activations of the 32 sequences for this wave's units
+      f32x16_m au, ar, ag, ai;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { au[e] = bu; ar[e] = br; ag[e] = bh; ai[e] = bi; }
+#pragma unroll
+      for (int s4 = 0; s4 < KS; s4 += 4) {
+        const float4 av = *reinterpret_cast<const float4*>(&hA[cb][col][s4 + half * KS]);
+        au = mfma_f32(av.x, Wu[s4 + 0], au); ar = mfma_f32(av.x, Wr[s4 + 0], ar); ag = mfma_f32(av.x, Wg[s4 + 0], ag);
+        au = mfma_f32(av.y, Wu[s4 + 1], au); ar = mfma_f32(av.y, Wr[s4 + 1], ar); ag = mfma_f32(av.y, Wg[s4 + 1], ag);
+        au = mfma_f32(av.z, Wu[s4 + 2], au); ar = mfma_f32(av.z, Wr[s4 + 2], ar); ag = mfma_f32(av.z, Wg[s4 + 2], ag);
+        au = mfma_f32(av.w, Wu[s4 + 3], au); ar = mfma_f32(av.w, Wr[s4 + 3], ar); ag = mfma_f32(av.w, Wg[s4 + 3], ag);
+      }
+      // one-hot spin inputs: this lane supplies column c = 2x + half
+      if (DIM == 1) {
+        const float o = sprev == half ? 1.f : 0.f;
+        au = mfma_f32(o, Wu[KS], au); ar = mfma_f32(o, Wr[KS], ar); ai = mfma_f32(o, Wi[0], ai);
+      } else {
+        const float o0 = sh == half ? 1.f : 0.f;
+        const float o1 = sv == half ? 1.f : 0.f;
+        au = mfma_f32(o0, Wu[KS], au); ar = mfma_f32(o0, Wr[KS], ar); ai = mfma_f32(o0, Wi[0], ai);
+        au = mfma_f32(o1, Wu[KS + 1], au); ar = mfma_f32(o1, Wr[KS + 1], ar); ai = mfma_f32(o1, Wi[1], ai);
+      }
+      // GRU update in the accumulator layout: element e is sequence
+      // (e / 4) * 8 + half * 4 + e % 4, unit `unit`
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = (e / 4) * 8 + half * 4 + (e % 4);
+        const float hp = DIM == 1 ? hA[cb][row][unit] : hin[e];
+        const float u = 1.f / (1.f + expf(-au[e]));
+        const float rr = 1.f / (1.f + expf(-ar[e]));
+        const float ht = tanhf(rr * ag[e] + ai[e]);
+        const float hn = (1.f - u) * hp + u * ht;
+        hA[nb][row][unit] = hn;
+        if (DIM == 2) a.ring[(((size_t)blockIdx.x * S + row) * a.W + k % a.W) * H + unit] = hn;
+      }
+      __syncthreads();
+      // output head of this lane's sequence over units [half H/2, (half+1) H/2)
+      float z0 = 0.f, z1 = 0.f, q0 = 0.f, q1 = 0.f;
+#pragma unroll 4
+      for (int u4 = 0; u4 < H / 2; u4 += 4) {
+        const int u0 = half * (H / 2) + u4;
+        const float4 h4 = *reinterpret_cast<const float4*>(&hA[nb][col][u0]);
+        const float4 w0 = *reinterpret_cast<const float4*>(&hw[0][u0]);
+        const float4 w1 = *reinterpret_cast<const float4*>(&hw[1][u0]);
+        z0 = fmaf(w0.x, h4.x, z0); z0 = fmaf(w0.y, h4.y, z0); z0 = fmaf(w0.z, h4.z, z0); z0 = fmaf(w0.w, h4.w, z0);
+        z1 = fmaf(w1.x, h4.x, z1); z1 = fmaf(w1.y, h4.y, z1); z1 = fmaf(w1.z, h4.z, z1); z1 = fmaf(w1.w, h4.w, z1);
+        if (a.cplx) {
+          const float4 p0 = *reinterpret_cast<const float4*>(&hw[2][u0]);
+          const float4 p1 = *reinterpret_cast<const float4*>(&hw[3][u0]);
+          q0 = fmaf(p0.x, h4.x, q0); q0 = fmaf(p0.y, h4.y, q0); q0 = fmaf(p0.z, h4.z, q0); q0 = fmaf(p0.w, h4.w, q0);
+          q1 = fmaf(p1.x, h4.x, q1); q1 = fmaf(p1.y, h4.y, q1); q1 = fmaf(p1.z, h4.z, q1); q1 = fmaf(p1.w, h4.w, q1);
+        }
+      }
+      z0 += __shfl_xor(z0, 32, 64);
+      z1 += __shfl_xor(z1, 32, 64);
+      q0 += __shfl_xor(q0, 32, 64);
+      q1 += __shfl_xor(q1, 32, 64);
+      const float zz0 = z0 + hb[0], zz1 = z1 + hb[1];
+      const float mx = zz0 > zz1 ? zz0 : zz1;
+      const float d = zz0 > zz1 ? zz1 - zz0 : zz0 - zz1;
+      const float lse = mx + log1pf(expf(d));
+      float lp0 = zz0 - lse, lp1 = zz1 - lse;
+      if (a.zero_mag) {
+        if (nup >= N / 2) { lp0 = -INFINITY; lp1 = 0.f; }
+        else if (ndn >= N / 2) { lp0 = 0.f; lp1 = -INFINITY; }
+      }
+      int v = sg[k];
+      if (k == f2p) v ^= 1;
+      lp += (double)(v == 0 ? lp0 : lp1);
+      if (a.cplx) {
+        const float aa = v == 0 ? q0 + hb[2] : q1 + hb[3];
+        ph += (double)(PI * aa / (1.f + fabsf(aa)));
+      }
+      nup += v == 0; ndn += v == 1;
+      sprev = v;
+    }
+    if (w == 0 && half == 0 && act) {
+      const double dre = 0.5 * (lp - oldlp);
+      const double dim_ = (ph - oldph) + 3.14159265358979323846 * (double)dA;
+      const double e = mel == 0.0 ? 0.0 : exp(dre);
+      double* o = a.contrib + ((size_t)t * a.Ns + s) * 2;
+      o[0] = mel * e * cos(dim_);
+      o[1] = mel * e * sin(dim_);
+    }
+    __syncthreads();
+  }
+}
+
+bool eloc_mfma_supported(minsr_model* m) {
+  return !m->f64 && (m->H == 32 || m->H == 64 || m->H == 128);
+}
+
+int launch_eloc_mfma(minsr_model* m, const minsr_hamiltonian* H, int Ns, const uint8_t* sigma,
+                     const void* states, const double* site, int M, hipStream_t s) {
+  ElocMArgs a{};
+  const Work<float>& w = m->wf;
+  a.mw = w.mw; a.m2 = w.m2; a.bias = w.bias; a.head = w.head; a.headb = w.headb;
+  a.N = m->N; a.Ns = Ns; a.zero_mag = m->d.zero_mag; a.cplx = m->cplx;
+  a.marshall = m->d.marshall;
+  a.nchunks = (Ns + 31) / 32;
+  a.n_items = a.nchunks * M;
+  a.W = 2 * m->d.Lx;
+  a.nbr = m->nbr; a.subA = m->subA; a.sigma = sigma; a.states = (const float*)states;
+  a.site = site; a.bonds = m->bonds; a.n_nn = m->n_nn; a.ham_kind = H->kind;
+  a.hx = H->h; a.J1 = H->J; a.J2 = H->J2; a.contrib = m->contrib; a.ring = (float*)m->ring;
+  if (a.n_items == 0) return MINSR_OK;
+  unsigned grid = (unsigned)a.n_items;
+  if (m->dim == 2) {
+    const int cap = m->ring_blocks / 32;
+    if (cap < 1) return fail(MINSR_E_SHAPE, "recompute window too small");
+    grid = std::min<unsigned>(grid, (unsigned)cap);
+  }
+  const unsigned nt = 64u * (unsigned)(m->H / 32);
+#define MINSR_ELOC_MFMA(HH, DD) k_eloc_mfma<HH, DD><<<grid, nt, 0, s>>>(a)
+  if (m->dim == 1) {
+    if (m->H == 32) MINSR_ELOC_MFMA(32, 1);
+    else if (m->H == 64) MINSR_ELOC_MFMA(64, 1);
+    else MINSR_ELOC_MFMA(128, 1);
+  } else {
+    if (m->H == 32) MINSR_ELOC_MFMA(32, 2);
+    else if (m->H == 64) MINSR_ELOC_MFMA(64, 2);
+    else MINSR_ELOC_MFMA(128, 2);
+  }
+#undef MINSR_ELOC_MFMA
+  MINSR_CHECK_LAUNCH();
+  return MINSR_OK;
+}
+
+}  // namespace minsr

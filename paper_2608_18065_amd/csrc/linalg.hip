@@ -7,6 +7,7 @@
 // Every reduction runs in a fixed order: results are bitwise reproducible.
 #include "model.hpp"
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 namespace minsr {
@@ -49,23 +50,28 @@ template <> __device__ inline __hip_bfloat16 cvt_out<__hip_bfloat16>(double v) {
 // against the FP64 mean rounded to FP32), then rounded to the output type
 template <typename TI, typename TO>
 __global__ void k_center(const TI* O, int rows_per_block, int RC, size_t Np, const double* mean,
-                         TO* R) {
+                         TO* R, size_t ldo) {
   size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= Np) return;
+  if (col >= ldo) return;
   const int blk = blockIdx.z, chunk = blockIdx.y;
   const int r0 = chunk * RC;
   const int r1 = min(rows_per_block, r0 + RC);
+  const size_t oo = ((size_t)blk * rows_per_block) * ldo + col;
+  if (col >= Np) {   // zero padding of the output rows
+    for (int r = r0; r < r1; ++r) R[oo + (size_t)r * ldo] = cvt_out<TO>(0.0);
+    return;
+  }
   const TI mu = mean ? (TI)mean[(size_t)blk * Np + col] : (TI)0;
   const size_t off = ((size_t)blk * rows_per_block) * Np + col;
   for (int r = r0; r < r1; ++r) {
     const TI v = O[off + (size_t)r * Np] - mu;
-    R[off + (size_t)r * Np] = cvt_out<TO>((double)v);
+    R[oo + (size_t)r * ldo] = cvt_out<TO>((double)v);
   }
 }
 
 template <typename TI>
 static int center_t(int rows_per_block, int nblocks, size_t Np, const TI* O, void* R,
-                    int out_dtype, double* colpart, double* colmean, hipStream_t s) {
+                    int out_dtype, double* colpart, double* colmean, size_t ldo, hipStream_t s) {
   const int RC = 32;
   const int nrc = (rows_per_block + RC - 1) / RC;
   dim3 grid((unsigned)((Np + 255) / 256), (unsigned)nrc, (unsigned)nblocks);
@@ -76,16 +82,17 @@ static int center_t(int rows_per_block, int nblocks, size_t Np, const TI* O, voi
                                                           Np, colmean);
     MINSR_CHECK_LAUNCH();
   }
+  dim3 ogrid((unsigned)((ldo + 255) / 256), (unsigned)nrc, (unsigned)nblocks);
   switch (out_dtype) {
     case MINSR_F64:
-      k_center<TI, double><<<grid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean, (double*)R);
+      k_center<TI, double><<<ogrid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean, (double*)R, ldo);
       break;
     case MINSR_F32:
-      k_center<TI, float><<<grid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean, (float*)R);
+      k_center<TI, float><<<ogrid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean, (float*)R, ldo);
       break;
     case MINSR_BF16:
-      k_center<TI, __hip_bfloat16><<<grid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean,
-                                                         (__hip_bfloat16*)R);
+      k_center<TI, __hip_bfloat16><<<ogrid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean,
+                                                          (__hip_bfloat16*)R, ldo);
       break;
     default:
       return fail(MINSR_E_INVALID_ARG, "unknown output dtype");
@@ -95,13 +102,13 @@ static int center_t(int rows_per_block, int nblocks, size_t Np, const TI* O, voi
 }
 
 int launch_center(int rows_per_block, int nblocks, size_t Np, const void* O, int in_f64, void* R,
-                  int out_dtype, double* colpart, double* colmean, hipStream_t s) {
+                  int out_dtype, double* colpart, double* colmean, size_t ldo, hipStream_t s) {
   if (rows_per_block == 0 || Np == 0) return MINSR_OK;
   if (in_f64)
     return center_t<double>(rows_per_block, nblocks, Np, (const double*)O, R, out_dtype, colpart,
-                            colmean, s);
+                            colmean, ldo, s);
   return center_t<float>(rows_per_block, nblocks, Np, (const float*)O, R, out_dtype, colpart,
-                         colmean, s);
+                         colmean, ldo, s);
 }
 
 // ================================================================== Gram
@@ -120,18 +127,20 @@ typedef __attribute__((ext_vector_type(16))) float f32x16_t;
 
 // BF16 MFMA tile kernel: 128 x 128 output tile per workgroup (4 waves,
 // 64 x 64 each as 2 x 2 blocks of v_mfma_f32_32x32x16_bf16), K staged
-// through LDS 64 columns at a time.
+// through two LDS buffers 64 columns at a time: the next stage's global
+// loads are in flight while the current stage feeds the matrix cores.
+// Rows of R have a stride ld that is a multiple of 64, zero-padded past Np.
 constexpr int GT = 128, GK = 64, GKP = GK + 8;
 
-__global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R, int n, size_t Np,
+__global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R, int n, size_t ld,
                                                    size_t kchunk, float* part) {
-  __shared__ __align__(16) __hip_bfloat16 As[GT][GKP];
-  __shared__ __align__(16) __hip_bfloat16 Bs[GT][GKP];
+  __shared__ __align__(16) __hip_bfloat16 As[2][GT][GKP];
+  __shared__ __align__(16) __hip_bfloat16 Bs[2][GT][GKP];
   int ti, tj;
   pair_decode(blockIdx.x, ti, tj);
   const int split = blockIdx.y;
   const size_t k0 = (size_t)split * kchunk;
-  const size_t k1 = min(Np, k0 + kchunk);
+  const size_t k1 = min(ld, k0 + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   f32x16_t acc[2][2];
@@ -143,48 +152,53 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R, int 
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
 
   const int arow0 = ti * GT, brow0 = tj * GT;
-  const bool vec_ok = (Np % 8) == 0;
-  for (size_t kk = k0; kk < k1; kk += GK) {
-    // stage: 128 rows x 64 bf16 per operand = 1024 chunks of 8
-    for (int c = tid; c < GT * (GK / 8); c += 256) {
-      const int r = c / (GK / 8), q = (c % (GK / 8)) * 8;
-      const size_t col = kk + q;
-      __hip_bfloat16 va[8], vb[8];
-      const int ra = arow0 + r, rb = brow0 + r;
-      if (vec_ok && col + 8 <= k1) {
-        uint4 xa = make_uint4(0, 0, 0, 0), xb = make_uint4(0, 0, 0, 0);
-        if (ra < n) xa = *reinterpret_cast<const uint4*>(R + (size_t)ra * Np + col);
-        if (rb < n) xb = *reinterpret_cast<const uint4*>(R + (size_t)rb * Np + col);
-        *reinterpret_cast<uint4*>(&As[r][q]) = xa;
-        *reinterpret_cast<uint4*>(&Bs[r][q]) = xb;
-      } else {
+  // this thread's four 16-byte chunks of each operand per stage
+  constexpr int CPT = GT * (GK / 8) / 256;
+  uint4 ra[CPT], rb[CPT];
+  auto load = [&](size_t kk) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const bool ok = col + e < k1;
-          va[e] = (ok && ra < n) ? R[(size_t)ra * Np + col + e] : __float2bfloat16(0.f);
-          vb[e] = (ok && rb < n) ? R[(size_t)rb * Np + col + e] : __float2bfloat16(0.f);
-          As[r][q + e] = va[e];
-          Bs[r][q + e] = vb[e];
-        }
-      }
+    for (int i = 0; i < CPT; ++i) {
+      const int c = tid + 256 * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
+      const int xa = arow0 + r, xb = brow0 + r;
+      ra[i] = xa < n ? *reinterpret_cast<const uint4*>(R + (size_t)xa * ld + kk + q) : make_uint4(0, 0, 0, 0);
+      rb[i] = xb < n ? *reinterpret_cast<const uint4*>(R + (size_t)xb * ld + kk + q) : make_uint4(0, 0, 0, 0);
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int c = tid + 256 * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
+      *reinterpret_cast<uint4*>(&As[buf][r][q]) = ra[i];
+      *reinterpret_cast<uint4*>(&Bs[buf][r][q]) = rb[i];
+    }
+  };
+  if (k0 < k1) {
+    load(k0);
+    store(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (size_t kk = k0; kk < k1; kk += GK) {
+    const bool more = kk + GK < k1;
+    if (more) load(kk + GK);
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 16) {
       bf16x8_t fa[2], fb[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
-        fa[a] = *reinterpret_cast<const bf16x8_t*>(&As[wm + a * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
+        fa[a] = *reinterpret_cast<const bf16x8_t*>(&As[cur][wm + a * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
 #pragma unroll
       for (int b = 0; b < 2; ++b)
-        fb[b] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn + b * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
+        fb[b] = *reinterpret_cast<const bf16x8_t*>(&Bs[cur][wn + b * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
+    if (more) store(cur ^ 1);
     __syncthreads();
+    cur ^= 1;
   }
   // write the partial tile: acc element e of lane l is row
   // (e / 4) * 8 + (l / 32) * 4 + e % 4, column l % 32 of its 32 x 32 block
@@ -224,12 +238,20 @@ __global__ __launch_bounds__(256) void k_gram_vec(const TI* R, int n, size_t Np,
     for (int b = 0; b < 4; ++b) acc[a][b] = (TA)0;
   const int arow0 = ti * VT_, brow0 = tj * VT_;
   for (size_t kk = k0; kk < k1; kk += VK) {
-    for (int e = tid; e < VT_ * VK; e += 256) {
-      const int r = e / VK, q = e % VK;
+    TA va[VT_ * VK / 256], vb[VT_ * VK / 256];
+#pragma unroll
+    for (int i = 0; i < VT_ * VK / 256; ++i) {
+      const int e = tid + 256 * i, r = e / VK, q = e % VK;
       const size_t col = kk + q;
       const int ra = arow0 + r, rb = brow0 + r;
-      As[q][r] = (col < k1 && ra < n) ? (TA)R[(size_t)ra * Np + col] : (TA)0;
-      Bs[q][r] = (col < k1 && rb < n) ? (TA)R[(size_t)rb * Np + col] : (TA)0;
+      va[i] = (col < k1 && ra < n) ? (TA)R[(size_t)ra * Np + col] : (TA)0;
+      vb[i] = (col < k1 && rb < n) ? (TA)R[(size_t)rb * Np + col] : (TA)0;
+    }
+#pragma unroll
+    for (int i = 0; i < VT_ * VK / 256; ++i) {
+      const int e = tid + 256 * i, r = e / VK, q = e % VK;
+      As[q][r] = va[i];
+      Bs[q][r] = vb[i];
     }
     __syncthreads();
 #pragma unroll
@@ -289,13 +311,15 @@ size_t gram_partial_bytes(int n, size_t Np, int dtype) {
 
 int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gpart,
                 size_t gpart_elems, hipStream_t s, int which) {
+  // R rows have the padded stride ld = round_up(Np, 64); the padding is zero
+  const size_t ld = (Np + 63) / 64 * 64;
   if (n == 0) return MINSR_OK;
   const int tile = dtype == MINSR_BF16 ? GT : VT_;
   const int nt = (n + tile - 1) / tile;
   const int npairs = nt * (nt + 1) / 2;
   const int S = pick_split(npairs, Np, 0);
   const size_t kgran = dtype == MINSR_BF16 ? GK : VK;
-  size_t kchunk = (Np + S - 1) / S;
+  size_t kchunk = (ld + S - 1) / S;
   kchunk = (kchunk + kgran - 1) / kgran * kgran;
   const size_t need = gram_partial_bytes(n, Np, dtype);
   if (need > gpart_elems * sizeof(float)) return fail(MINSR_E_SHAPE, "Gram workspace too small");
@@ -303,20 +327,20 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
   dim3 rgrid((unsigned)((tile * tile + 255) / 256), (unsigned)npairs);
   if (dtype == MINSR_BF16) {
     if (which & 1) {
-      k_gram_bf16<<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, n, Np, kchunk, gpart);
+      k_gram_bf16<<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, n, ld, kchunk, gpart);
       MINSR_CHECK_LAUNCH();
     }
     if (which & 2) k_gram_reduce<float, double><<<rgrid, 256, 0, s>>>(gpart, npairs, S, tile, n, T);
   } else if (dtype == MINSR_F32) {
     if (which & 1) {
-      k_gram_vec<float, float><<<grid, 256, 0, s>>>((const float*)R, n, Np, kchunk, gpart);
+      k_gram_vec<float, float><<<grid, 256, 0, s>>>((const float*)R, n, ld, kchunk, gpart);
       MINSR_CHECK_LAUNCH();
     }
     if (which & 2) k_gram_reduce<float, float><<<rgrid, 256, 0, s>>>(gpart, npairs, S, tile, n, (float*)T);
   } else {
     double* dp = reinterpret_cast<double*>(gpart);
     if (which & 1) {
-      k_gram_vec<double, double><<<grid, 256, 0, s>>>((const double*)R, n, Np, kchunk, dp);
+      k_gram_vec<double, double><<<grid, 256, 0, s>>>((const double*)R, n, ld, kchunk, dp);
       MINSR_CHECK_LAUNCH();
     }
     if (which & 2) k_gram_reduce<double, double><<<rgrid, 256, 0, s>>>(dp, npairs, S, tile, n, T);
@@ -326,82 +350,166 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
 }
 
 // ============================================================= Cholesky
-// Right-looking blocked Cholesky of A = T + lambda I (lower, in place,
-// row-major), block 64: factor the diagonal block, solve the panel below
-// it, update the trailing lower triangle.
+// Right-looking blocked Cholesky of A = T + lambda I (lower, row-major,
+// block 64) into a separate buffer, so T survives.  Each diagonal block is
+// factored by one wavefront (lane r holds row r), which also forms the
+// block's inverse; panels below are multiplied by that inverse (a small
+// GEMM instead of a sequential substitution); the trailing update of the
+// lower tiles also factors the next diagonal block.  The triangular solves
+// reuse the stored block inverses.
 constexpr int CB = 64;
 
+// factor the 64 x 64 tile held in LDS (rows < nb valid; the lower triangle
+// is read), write L to A and inv(L) to Dinv.  Executed by the first
+// wavefront of a workgroup only: lane r keeps row r in registers; at column
+// c the pivot column is published through LDS, read back by every lane in
+// one batch of 16-byte loads, and applied as a rank-1 update to its row.
 template <typename TT>
-__global__ __launch_bounds__(256) void k_potrf_diag(TT* A, int n, int kb, uint32_t* status) {
-  __shared__ TT L[CB][CB + 1];
-  const int k0 = kb * CB;
-  const int nb = min(CB, n - k0);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int r = e / CB, c = e % CB;
-    L[r][c] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * n + k0 + c] : (TT)0;
-  }
-  __syncthreads();
-  __shared__ int bad;
-  if (tid == 0) bad = 0;
-  __syncthreads();
-  for (int c = 0; c < nb; ++c) {
-    if (tid == 0) {
-      TT d = L[c][c];
-      if (!(d > (TT)0)) { bad = 1; d = (TT)1; }
-      L[c][c] = sqrt(d);
-    }
-    __syncthreads();
-    const TT piv = L[c][c];
-    for (int r = c + 1 + tid; r < nb; r += 256) L[r][c] /= piv;
-    __syncthreads();
-    // rank-1 update of the remaining lower triangle
-    for (int e = tid; e < CB * CB; e += 256) {
-      const int r = e / CB, q = e % CB;
-      if (r > c && q > c && q <= r && r < nb) L[r][q] -= L[r][c] * L[q][c];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int r = e / CB, c = e % CB;
-    if (r < nb && c <= r) A[(size_t)(k0 + r) * n + k0 + c] = L[r][c];
-  }
-  if (tid == 0 && bad && status) atomicOr(status, MINSR_ST_NOT_PD);
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// panel rows below the diagonal block: X L_kk^T = A_ik, one row per thread
 template <typename TT>
-__global__ __launch_bounds__(64) void k_trsm_panel(TT* A, int n, int kb) {
-  __shared__ TT L[CB][CB + 1];
-  const int k0 = kb * CB;
-  const int nb = min(CB, n - k0);
-  for (int e = threadIdx.x; e < CB * CB; e += 64) {
-    const int r = e / CB, c = e % CB;
-    L[r][c] = (r < nb && c <= r) ? A[(size_t)(k0 + r) * n + k0 + c] : (TT)0;
-  }
-  __syncthreads();
-  const int row = k0 + nb + blockIdx.x * 64 + threadIdx.x;
-  if (row >= n) return;
-  TT x[CB];
-  TT* a = A + (size_t)row * n + k0;
+__device__ __forceinline__ void factor_tile(TT (*Ls)[CB + 1], int nb, TT* A, int n, int k0,
+                                            TT* Dinv, uint32_t* status) {
+  const int r = threadIdx.x;   // 0..63
+  __shared__ __align__(16) TT colc[CB];
+  __shared__ __align__(16) TT Lrow[CB][CB];
+  TT a[CB];
 #pragma unroll
-  for (int c = 0; c < CB; ++c) x[c] = c < nb ? a[c] : (TT)0;
+  for (int q = 0; q < CB; ++q) a[q] = (q <= r && r < nb) ? Ls[r][q] : (r == q ? (TT)1 : (TT)0);
+  bool bad = false;
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
     if (c < nb) {
-      TT v = x[c];
+      TT d = __shfl(a[c], c, 64);
+      if (!(d > (TT)0)) { bad = true; d = (TT)1; }
+      const TT piv = sqrt(d);
+      const TT rp = (TT)1 / piv;
+      if (r == c) a[c] = piv;
+      else if (r > c) a[c] = a[c] * rp;
+      colc[r] = a[c];
+      wave_sync_lds<TT>();
+      const int Q0 = ((c + 1) / 2) * 2;   // even start: 16-byte aligned reads
+      TT cv[CB];
 #pragma unroll
-      for (int m = 0; m < c; ++m) v -= x[m] * L[c][m];
-      x[c] = v / L[c][c];
+      for (int q = Q0; q < CB; q += 2) {
+        const auto v2 = *reinterpret_cast<const typename std::conditional<sizeof(TT) == 8, double2, float2>::type*>(&colc[q]);
+        cv[q] = v2.x; cv[q + 1] = v2.y;
+      }
+      if (r > c) {
+        const TT nl = -a[c];
+#pragma unroll
+        for (int q = c + 1; q < CB; ++q) a[q] = fma(nl, cv[q], a[q]);
+      }
+      wave_sync_lds<TT>();
     }
   }
+  if (bad && r == 0 && status) atomicOr(status, MINSR_ST_NOT_PD);
+  // write L and publish its rows for the inverse
 #pragma unroll
-  for (int c = 0; c < CB; ++c) if (c < nb) a[c] = x[c];
+  for (int q = 0; q < CB; ++q) {
+    const TT v = (q <= r && r < nb) ? a[q] : (r == q ? (TT)1 : (TT)0);
+    Lrow[r][q] = v;
+    if (q <= r && r < nb) A[(size_t)(k0 + r) * n + k0 + q] = v;
+  }
+  wave_sync_lds<TT>();
+  // inv(L): lane c solves L z = e_c (z_i = 0 for i < c); row i of L is
+  // read in one batch, the dot product uses four partial sums
+  const int c = r;
+  TT z[CB];
+#pragma unroll
+  for (int i = 0; i < CB; ++i) {
+    TT li[CB];
+#pragma unroll
+    for (int q = 0; q < i + 1; q += 2) {
+      const auto v2 = *reinterpret_cast<const typename std::conditional<sizeof(TT) == 8, double2, float2>::type*>(&Lrow[i][q]);
+      li[q] = v2.x; li[q + 1] = v2.y;
+    }
+    TT p0 = (i == c) ? (TT)1 : (TT)0, p1 = 0, p2 = 0, p3 = 0;
+#pragma unroll
+    for (int q = 0; q < i; ++q) {
+      const TT t = -li[q] * z[q];
+      if ((q & 3) == 0) p0 += t; else if ((q & 3) == 1) p1 += t;
+      else if ((q & 3) == 2) p2 += t; else p3 += t;
+    }
+    z[i] = ((p0 + p1) + (p2 + p3)) / li[i];
+  }
+#pragma unroll
+  for (int i = 0; i < CB; ++i) Dinv[(size_t)i * CB + c] = (i < nb && c < nb) ? z[i] : (TT)0;
 }
 
-// trailing update A_ij -= L_ik L_jk^T for the lower tiles i >= j > k
 template <typename TT>
-__global__ __launch_bounds__(256) void k_syrk_trail(TT* A, int n, int kb) {
+__global__ __launch_bounds__(64) void k_chol_diag(TT* A, int n, int kb, TT* Dinv, uint32_t* status) {
+  __shared__ TT Ls[CB][CB + 1];
+  const int k0 = kb * CB, nb = min(CB, n - k0);
+  {
+    // lane q reads column q of every row: 64 independent coalesced loads
+    const int q = threadIdx.x;
+    TT v[CB];
+#pragma unroll
+    for (int r = 0; r < CB; ++r) v[r] = (r < nb && q < nb) ? A[(size_t)(k0 + r) * n + k0 + q] : (TT)0;
+#pragma unroll
+    for (int r = 0; r < CB; ++r) Ls[r][q] = v[r];
+  }
+  __syncthreads();
+  factor_tile<TT>(Ls, nb, A, n, k0, Dinv + (size_t)kb * CB * CB, status);
+}
+
+// panel rows below the diagonal block: A_ik <- A_ik inv(L_kk)^T
+template <typename TT>
+__global__ __launch_bounds__(256) void k_chol_panel(TT* A, int n, int kb, const TT* Dinv) {
+  __shared__ TT As[CB][CB + 1];
+  __shared__ TT Is[CB][CB + 1];
+  const int k0 = kb * CB, nb = min(CB, n - k0);
+  const int r0 = k0 + nb + blockIdx.x * CB;
+  const TT* Di = Dinv + (size_t)kb * CB * CB;
+  const int tid = threadIdx.x;
+  {
+    TT va[CB * CB / 256], vi[CB * CB / 256];
+#pragma unroll
+    for (int i = 0; i < CB * CB / 256; ++i) {
+      const int e = tid + 256 * i, r = e / CB, q = e % CB;
+      va[i] = (r0 + r < n && q < nb) ? A[(size_t)(r0 + r) * n + k0 + q] : (TT)0;
+      vi[i] = Di[e];
+    }
+#pragma unroll
+    for (int i = 0; i < CB * CB / 256; ++i) {
+      const int e = tid + 256 * i, r = e / CB, q = e % CB;
+      As[r][q] = va[i];
+      Is[r][q] = vi[i];
+    }
+  }
+  __syncthreads();
+  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+  TT acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (TT)0;
+#pragma unroll 4
+  for (int q = 0; q < CB; ++q) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(As[tr + a][q], Is[tc + b][q], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = r0 + tr + a, c = tc + b;
+      if (r < n && c < nb) A[(size_t)r * n + k0 + c] = acc[a][b];
+    }
+}
+
+// trailing update A_ij -= L_ik L_jk^T for the lower tiles i >= j > k; the
+// workgroup of the first diagonal tile then factors it
+template <typename TT>
+__global__ __launch_bounds__(256) void k_syrk_trail(TT* A, int n, int kb, TT* Dinv,
+                                                    uint32_t* status) {
   __shared__ TT Li[CB][CB + 1];
   __shared__ TT Lj[CB][CB + 1];
   const int k0 = kb * CB;
@@ -412,10 +520,20 @@ __global__ __launch_bounds__(256) void k_syrk_trail(TT* A, int n, int kb) {
   ti += base; tj += base;
   const int r0 = ti * CB, c0 = tj * CB;
   const int tid = threadIdx.x;
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int r = e / CB, q = e % CB;
-    Li[r][q] = (r0 + r < n && q < nb) ? A[(size_t)(r0 + r) * n + k0 + q] : (TT)0;
-    Lj[r][q] = (c0 + r < n && q < nb) ? A[(size_t)(c0 + r) * n + k0 + q] : (TT)0;
+  {
+    TT vi[CB * CB / 256], vj[CB * CB / 256];
+#pragma unroll
+    for (int i = 0; i < CB * CB / 256; ++i) {
+      const int e = tid + 256 * i, r = e / CB, q = e % CB;
+      vi[i] = (r0 + r < n && q < nb) ? A[(size_t)(r0 + r) * n + k0 + q] : (TT)0;
+      vj[i] = (c0 + r < n && q < nb) ? A[(size_t)(c0 + r) * n + k0 + q] : (TT)0;
+    }
+#pragma unroll
+    for (int i = 0; i < CB * CB / 256; ++i) {
+      const int e = tid + 256 * i, r = e / CB, q = e % CB;
+      Li[r][q] = vi[i];
+      Lj[r][q] = vj[i];
+    }
   }
   __syncthreads();
   const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
@@ -424,82 +542,122 @@ __global__ __launch_bounds__(256) void k_syrk_trail(TT* A, int n, int kb) {
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = (TT)0;
+#pragma unroll 4
   for (int q = 0; q < CB; ++q) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = fma(Li[tr + a][q], Lj[tc + b][q], acc[a][b]);
   }
+  // the current values of this block's tile, read before the barrier
+  TT cur[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int r = r0 + tr + a, c = c0 + tc + b;
-      if (r < n && c < n && (ti != tj || c <= r)) A[(size_t)r * n + c] -= acc[a][b];
+      cur[a][b] = (r < n && c < n && (ti != tj || c <= r)) ? A[(size_t)r * n + c] : (TT)0;
     }
+  const bool diag_next = blockIdx.x == 0;   // tile (kb+1, kb+1)
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = r0 + tr + a, c = c0 + tc + b;
+      if (r < n && c < n && (ti != tj || c <= r)) {
+        const TT v = cur[a][b] - acc[a][b];
+        A[(size_t)r * n + c] = v;
+        if (diag_next) Li[tr + a][tc + b] = v;
+      }
+    }
+  if (!diag_next) return;
+  __syncthreads();
+  if (tid < 64) {
+    const int nb2 = min(CB, n - r0);
+    // factor_tile reads the lower triangle only
+    factor_tile<TT>(Li, nb2, A, n, r0, Dinv + (size_t)ti * CB * CB, status);
+  }
 }
 
-// forward (L y = b) and backward (L^T x = y) substitution, one workgroup,
-// 64-row blocks: wave 0 solves the diagonal block from LDS (lane r holds
-// unknown r, the solved value is broadcast lane to lane), then all threads
-// update the rest of the right-hand side.
+// forward (L y = b) then backward (L^T x = y) substitution with the stored
+// block inverses, one workgroup of 1024 threads; 16 threads cooperate on a
+// row so that every load of L is coalesced.
 template <typename TT>
-__global__ __launch_bounds__(1024) void k_trsv(const TT* A, int n, const double* b, double* x) {
+__global__ __launch_bounds__(1024) void k_trsv(const TT* A, int n, const TT* Dinv, const double* b,
+                                               double* x) {
   extern __shared__ unsigned char smem_raw[];
   TT* y = reinterpret_cast<TT*>(smem_raw);
-  __shared__ TT D[CB][CB + 1];
+  __shared__ TT rbuf[CB];
+  __shared__ TT part[16][CB + 1];
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += 1024) y[i] = (TT)b[i];
+  __syncthreads();
   const int nblk = (n + CB - 1) / CB;
-  // forward
+  const int row = tid / 16, sub = tid % 16;     // 64 rows x 16 threads
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * CB, nb = min(CB, n - k0);
-    for (int e = tid; e < CB * CB; e += 1024) {
-      const int r = e / CB, c = e % CB;
-      D[r][c] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * n + k0 + c] : (TT)0;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      TT v = tid < nb ? y[k0 + tid] : (TT)0;
-      for (int c = 0; c < nb; ++c) {
-        if (tid == c) v = v / D[c][c];
-        const TT yc = __shfl(v, c, 64);
-        if (tid > c && tid < nb) v -= D[tid][c] * yc;
+    // r = b_k - L_k,<k y_<k
+    TT acc = (TT)0;
+    if (row < nb) {
+      const TT* Lr = A + (size_t)(k0 + row) * n;
+      // k0 is a multiple of 64: each thread takes 4 columns of every 64
+      for (int q0 = 0; q0 < k0; q0 += 64) {
+        TT l[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) l[u] = Lr[q0 + sub + 16 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = fma(l[u], y[q0 + sub + 16 * u], acc);
       }
-      if (tid < nb) y[k0 + tid] = v;
     }
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 16);
+    if (sub == 0 && row < nb) rbuf[row] = y[k0 + row] - acc;
     __syncthreads();
-    for (int i = k0 + nb + tid; i < n; i += 1024) {
-      TT v = y[i];
-      const TT* row = A + (size_t)i * n + k0;
-      for (int m = 0; m < nb; ++m) v -= row[m] * y[k0 + m];
-      y[i] = v;
-    }
+    // y_k = inv(L_kk) r
+    const TT* Di = Dinv + (size_t)kb * CB * CB;
+    TT v = (TT)0;
+    if (row < nb)
+      for (int q = sub; q <= row; q += 16) v = fma(Di[row * CB + q], rbuf[q], v);
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 16);
+    if (sub == 0 && row < nb) y[k0 + row] = v;
     __syncthreads();
   }
-  // backward with L^T
+  // backward: x_k = inv(L_kk)^T (y_k - sum_{j>k} L_jk^T x_j)
+  const int c = tid % CB, g = tid / CB;         // 64 columns x 16 row groups
   for (int kb = nblk - 1; kb >= 0; --kb) {
     const int k0 = kb * CB, nb = min(CB, n - k0);
-    for (int e = tid; e < CB * CB; e += 1024) {
-      const int r = e / CB, c = e % CB;
-      D[r][c] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * n + k0 + c] : (TT)0;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      TT v = tid < nb ? y[k0 + tid] : (TT)0;
-      for (int c = nb - 1; c >= 0; --c) {
-        if (tid == c) v = v / D[c][c];
-        const TT yc = __shfl(v, c, 64);
-        if (tid < c) v -= D[c][tid] * yc;
+    TT acc = (TT)0;
+    if (c < nb) {
+      int r = k0 + nb + g;
+      for (; r + 48 < n; r += 64) {
+        TT l[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) l[u] = A[(size_t)(r + 16 * u) * n + k0 + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = fma(l[u], y[r + 16 * u], acc);
       }
-      if (tid < nb) y[k0 + tid] = v;
+      for (; r < n; r += 16) acc = fma(A[(size_t)r * n + k0 + c], y[r], acc);
+    }
+    part[g][c] = acc;
+    __syncthreads();
+    if (tid < CB) {
+      TT s = (TT)0;
+      for (int q = 0; q < 16; ++q) s += part[q][tid];
+      rbuf[tid] = tid < nb ? y[k0 + tid] - s : (TT)0;
     }
     __syncthreads();
-    for (int i = tid; i < k0; i += 1024) {
-      TT v = y[i];
-      for (int m = 0; m < nb; ++m) v -= A[(size_t)(k0 + m) * n + i] * y[k0 + m];
-      y[i] = v;
-    }
+    const TT* Di = Dinv + (size_t)kb * CB * CB;
+    // x_k[c'] = sum_{r >= c'} inv(L)[r][c'] rbuf[r]; 16 threads per c'
+    const int cc = tid / 16, sb = tid % 16;
+    TT v = (TT)0;
+    if (cc < nb)
+      for (int r = cc + sb; r < nb; r += 16) v = fma(Di[r * CB + cc], rbuf[r], v);
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 16);
+    __syncthreads();
+    if (sb == 0 && cc < nb) y[k0 + cc] = v;
     __syncthreads();
   }
   for (int i = tid; i < n; i += 1024) x[i] = (double)y[i];
@@ -514,61 +672,62 @@ __global__ void k_copy_add_diag(const TT* T, TT* A, size_t nn, int n, double lam
   A[e] = v;
 }
 
+size_t chol_dinv_elems(int n) { return (size_t)((n + CB - 1) / CB) * CB * CB; }
+
 template <typename TT>
-static int chol_t(int n, const TT* T, TT* A, double lambda, const double* b, double* x,
+static int chol_t(int n, const TT* T, TT* A, TT* Dinv, double lambda, const double* b, double* x,
                   uint32_t* status, hipStream_t s) {
   const size_t nn = (size_t)n * n;
   k_copy_add_diag<TT><<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(T, A, nn, n, lambda);
   MINSR_CHECK_LAUNCH();
   const int nblk = (n + CB - 1) / CB;
-  for (int kb = 0; kb < nblk; ++kb) {
-    k_potrf_diag<TT><<<1, 256, 0, s>>>(A, n, kb, status);
+  k_chol_diag<TT><<<1, 64, 0, s>>>(A, n, 0, Dinv, status);
+  MINSR_CHECK_LAUNCH();
+  for (int kb = 0; kb + 1 < nblk; ++kb) {
+    const int rows_below = n - (kb + 1) * CB;
+    k_chol_panel<TT><<<(rows_below + CB - 1) / CB, 256, 0, s>>>(A, n, kb, Dinv);
     MINSR_CHECK_LAUNCH();
-    const int rows_below = n - (kb * CB + std::min(CB, n - kb * CB));
-    if (rows_below > 0) {
-      k_trsm_panel<TT><<<(rows_below + 63) / 64, 64, 0, s>>>(A, n, kb);
-      MINSR_CHECK_LAUNCH();
-      const int nt = nblk - kb - 1;
-      k_syrk_trail<TT><<<nt * (nt + 1) / 2, 256, 0, s>>>(A, n, kb);
-      MINSR_CHECK_LAUNCH();
-    }
+    const int nt = nblk - kb - 1;
+    k_syrk_trail<TT><<<nt * (nt + 1) / 2, 256, 0, s>>>(A, n, kb, Dinv, status);
+    MINSR_CHECK_LAUNCH();
   }
   const size_t shm = (size_t)n * sizeof(TT);
   if (shm > 96 * 1024) return fail(MINSR_E_SHAPE, "triangular solve: n too large");
-  k_trsv<TT><<<1, 1024, shm, s>>>(A, n, b, x);
+  k_trsv<TT><<<1, 1024, shm, s>>>(A, n, Dinv, b, x);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
 }
 
-int launch_cholesky_solve(int n, const double* T, double* Lf, int f32, double lambda,
-                          const double* b, double* x, uint32_t* status, hipStream_t s) {
+int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
+                          double lambda, const double* b, double* x, uint32_t* status,
+                          hipStream_t s) {
   if (n == 0) return MINSR_OK;
   if (f32)
     return chol_t<float>(n, reinterpret_cast<const float*>(T), reinterpret_cast<float*>(Lf),
-                         lambda, b, x, status, s);
-  return chol_t<double>(n, T, Lf, lambda, b, x, status, s);
+                         reinterpret_cast<float*>(Dinv), lambda, b, x, status, s);
+  return chol_t<double>(n, T, Lf, Dinv, lambda, b, x, status, s);
 }
 
 // ================================================================ update
 // dpart[chunk][k] = sum over the chunk's rows a of R[a][k] x[a]  (FP64)
 template <typename TR>
-__global__ void k_update_part(const TR* R, int n, size_t Np, int RC, const double* x,
+__global__ void k_update_part(const TR* R, int n, size_t Np, size_t ld, int RC, const double* x,
                               double* part) {
   size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= Np) return;
   const int r0 = blockIdx.y * RC, r1 = min(n, r0 + RC);
   double s = 0.0;
-  for (int r = r0; r < r1; ++r) s += (double)(float)R[(size_t)r * Np + col] * x[r];
+  for (int r = r0; r < r1; ++r) s += (double)(float)R[(size_t)r * ld + col] * x[r];
   part[(size_t)blockIdx.y * Np + col] = s;
 }
 template <>
-__global__ void k_update_part<double>(const double* R, int n, size_t Np, int RC, const double* x,
-                                      double* part) {
+__global__ void k_update_part<double>(const double* R, int n, size_t Np, size_t ld, int RC,
+                                      const double* x, double* part) {
   size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= Np) return;
   const int r0 = blockIdx.y * RC, r1 = min(n, r0 + RC);
   double s = 0.0;
-  for (int r = r0; r < r1; ++r) s += R[(size_t)r * Np + col] * x[r];
+  for (int r = r0; r < r1; ++r) s += R[(size_t)r * ld + col] * x[r];
   part[(size_t)blockIdx.y * Np + col] = s;
 }
 
@@ -599,12 +758,13 @@ int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, d
   const int RC = 64;
   const int nrc = (n + RC - 1) / RC;
   dim3 grid((unsigned)((Np + 255) / 256), (unsigned)nrc);
+  const size_t ld = (Np + 63) / 64 * 64;
   if (dtype == MINSR_BF16)
-    k_update_part<__hip_bfloat16><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, n, Np, RC, x, dpart);
+    k_update_part<__hip_bfloat16><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, n, Np, ld, RC, x, dpart);
   else if (dtype == MINSR_F32)
-    k_update_part<float><<<grid, 256, 0, s>>>((const float*)R, n, Np, RC, x, dpart);
+    k_update_part<float><<<grid, 256, 0, s>>>((const float*)R, n, Np, ld, RC, x, dpart);
   else
-    k_update_part<double><<<grid, 256, 0, s>>>((const double*)R, n, Np, RC, x, dpart);
+    k_update_part<double><<<grid, 256, 0, s>>>((const double*)R, n, Np, ld, RC, x, dpart);
   MINSR_CHECK_LAUNCH();
   const unsigned g1 = (unsigned)((Np + 255) / 256);
   k_update_final<<<g1, 256, 0, s>>>(dpart, nrc, Np, eta, dtheta, status);

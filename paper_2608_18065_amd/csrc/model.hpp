@@ -40,6 +40,7 @@ struct minsr_model {
   double* colmean = nullptr;// [2][Np]
   double* T = nullptr;      // [n][n] Gram (FP64, or FP32 in the plain form)
   double* Lf = nullptr;     // [n][n] Cholesky factor of T + lambda I
+  double* Dinv = nullptr;   // [n/64][64][64] inverses of its diagonal blocks
   float* gpart = nullptr;   // split-K Gram partials
   size_t gpart_elems = 0;
   double* epsp = nullptr;   // [n] eps'
@@ -52,6 +53,7 @@ struct minsr_model {
   size_t eig_elems = 0;
   int last_n = 0;
   int last_form = 0;
+  int force_vector = 0;     // testing: route FP32 local energies to the vector kernel
 
   // per-phase event timing of minsr_step (profiling only)
   std::vector<hipEvent_t> ev;   // [t_max][NPHASE + 1]
@@ -73,19 +75,30 @@ int launch_eloc(minsr_model* m, const minsr_hamiltonian* H, int Ns, const uint8_
                 hipStream_t s, int which = 3);
 int launch_stats(minsr_model* m, int Ns, const double* eloc, double* stats, double* epsp,
                  uint32_t* status, hipStream_t s);
+// gru_mfma.hip: local-energy recurrence of FP32 models on MFMA
+bool eloc_mfma_supported(minsr_model* m);
+int launch_eloc_mfma(minsr_model* m, const minsr_hamiltonian* H, int Ns, const uint8_t* sigma,
+                     const void* states, const double* site, int M, hipStream_t s);
 // jacobian.hip: raw rows (scaled by 1/sqrt(Ns)) into O (compute precision)
 int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* states,
                     int ckpt_every, void* O, const double* g, double* vjp_part,
                     hipStream_t s);
 // linalg.hip
+// centred (colmean != null) or plain copy of O into R with row stride ldo
+// (ldo >= Np; columns Np..ldo-1 are written as zeros)
 int launch_center(int rows_per_block, int nblocks, size_t Np, const void* O, int in_f64,
-                  void* R, int out_dtype, double* colpart, double* colmean, hipStream_t s);
+                  void* R, int out_dtype, double* colpart, double* colmean, size_t ldo,
+                  hipStream_t s);
+// the step keeps O' with rows padded to a multiple of 64 columns
+inline size_t padded_ld(size_t Np) { return (Np + 63) / 64 * 64; }
 // which: 1 = tile products, 2 = split-K reduction and mirror, 3 = both
 int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gpart,
                 size_t gpart_elems, hipStream_t s, int which = 3);
 // factors T + lambda I into Lf (T is left unchanged) and solves for x
-int launch_cholesky_solve(int n, const double* T, double* Lf, int f32, double lambda,
-                          const double* b, double* x, uint32_t* status, hipStream_t s);
+int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
+                          double lambda, const double* b, double* x, uint32_t* status,
+                          hipStream_t s);
+size_t chol_dinv_elems(int n);
 int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* x,
                       double* eig, size_t eig_elems, uint32_t* status, hipStream_t s);
 int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, double eta,

@@ -266,3 +266,68 @@ def test_step_low_precision_forms(form, tol):
     d = o["dtheta"].cpu().numpy()
     err = np.linalg.norm(d - ref["dtheta"]) / np.linalg.norm(ref["dtheta"])
     assert err < tol, err
+
+
+# ------------------------------------------------ FP32 models (MFMA paths)
+
+HAMS32 = [
+    (dict(Lx=12, H=32), oham.Ham("tfim", J=1.0, h=0.9, pbc=True)),
+    (dict(Lx=16, H=64), oham.Ham("tfim", J=1.0, h=1.0, pbc=True)),
+    (dict(Lx=9, H=128, cplx=True), oham.Ham("cluster")),
+    (dict(Lx=4, Ly=3, dim=2, H=32, marshall=True, zero_mag=True), oham.Ham("j1j2", J=1.0)),
+    (dict(Lx=3, Ly=4, dim=2, H=64, cplx=True, marshall=True), oham.Ham("j1j2", J=1.0, J2=0.5)),
+    (dict(Lx=4, Ly=4, dim=2, H=128, cplx=True, marshall=True, zero_mag=True),
+     oham.Ham("j1j2", J=1.0, J2=0.5)),
+]
+
+
+@pytest.mark.parametrize("arch,ham", HAMS32, ids=lambda x: _ids(x) if isinstance(x, dict) else x.kind)
+def test_local_energy_fp32_model(arch, ham):
+    # FP32 recurrence (MFMA local-energy kernel) against the FP64 oracle on
+    # the same configurations; tolerance from FP32 rounding over N sites
+    spec, m = make_pair(**arch, dtype="f32")
+    th = scaled_theta(spec, 15, 1.0)
+    m.set_params(to_dev(th))
+    Ns = 45
+    sig, lp = omodel.sample(spec, th, philox.uniforms(78, 2, Ns, spec.N))
+    ref = oham.local_energy(spec, th, ham, sig, lp)
+    lp32 = m.logpsi(to_dev(sig.astype(np.uint8)))
+    eloc, _ = m.local_energy(_gpu_ham(ham), to_dev(sig.astype(np.uint8)), lp32)
+    assert rel_err(eloc.cpu().numpy(), ref) < 2e-4
+
+
+@pytest.mark.parametrize("arch", [dict(Lx=14, H=64), dict(Lx=9, H=128, cplx=True),
+                                  dict(Lx=4, Ly=3, dim=2, H=64, marshall=True)], ids=_ids)
+def test_jacobian_fp32_model(arch):
+    spec, m = make_pair(**arch, dtype="f32")
+    th = scaled_theta(spec, 16, 1.0)
+    m.set_params(to_dev(th))
+    Ns = 6
+    sig, _ = omodel.sample(spec, th, philox.uniforms(6, 1, Ns, spec.N))
+    D = ojac.log_derivatives(spec, th, sig)
+    ref = (np.concatenate([D.real, D.imag], axis=0) if spec.complex_head else D) / np.sqrt(Ns)
+    O, _ = m.jacobian(to_dev(sig.astype(np.uint8)))
+    assert rel_err(O.cpu().numpy(), ref) < 1e-4
+
+
+@pytest.mark.parametrize("form", [1, 2], ids=["bf16_mfma", "fp32"])
+def test_gram_matches_its_operand(form):
+    # T of the low-precision forms equals O' O'^T of the O' the kernel
+    # consumed, evaluated in FP64 (accumulation error only); several
+    # 128-tiles with a ragged edge (n = 300) and split-K over Np = 13312
+    import paper_2608_18065_amd as pm
+    spec, m = make_pair(Lx=16, H=64, cplx=True, dtype="f32", max_Ns=150)
+    th = scaled_theta(spec, 17, 1.0)
+    m.set_params(to_dev(th))
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    m.step(_gpu_ham(oham.Ham("cluster")), 150, 0.01, 1e-3, 0.0, mom, 3, 3, form=form)
+    torch.cuda.synchronize()
+    it = m.intermediates(form)
+    R = it["Oprime"].double().cpu().numpy()
+    assert R.shape == (300, m.Np)
+    T = it["T"].double().cpu().numpy()
+    assert np.array_equal(T, T.T)
+    ref = R @ R.T
+    assert np.max(np.abs(T - ref)) < 1e-5 * np.max(np.abs(ref))
+    # centred blocks: every column of each block of O' sums to ~0
+    assert np.max(np.abs(R[:150].sum(axis=0))) < 1e-2 * np.max(np.abs(R))
