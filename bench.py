@@ -13,8 +13,10 @@ value: steps/s of the BF16 + FP64 form (BF16 O'/Gram on MFMA with FP32
 accumulation, FP64 reductions, solve and update; FP32 recurrence).  The
 plain FP32 form is timed the same way and reported beside it.
 
-Per-kernel times come from HIP events recorded by the library on the
-step's stream during the timed region; `roofline` is given for the kernel
+The timed steps replay a captured hip graph of the step (the Philox
+counter lives in device memory and advances on every replay).  Per-kernel
+times come from HIP events the library records on the step's stream over
+further eager steps of the same run; `roofline` is given for the kernel
 with the largest share of the step.  `cpu_baseline` times the FP64 CPU
 oracle on one full step of the same workload on the host cores.
 """
@@ -47,6 +49,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 form")
+    ap.add_argument("--eager", action="store_true", help="time eager steps instead of graph replays")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of MIB MiB (for scaling the HBM "
+                         "traffic counters of a profiler run), then exit")
     return ap.parse_args()
 
 
@@ -66,7 +72,10 @@ def work_units(wl):
     )
 
 
-def run_form(pm, wl, form, K, W, dtype="f32"):
+def run_form(pm, wl, form, K, W, dtype="f32", graph=True, kernel_steps=20):
+    """W warmup steps, then the timed run of K steps (replays of a captured
+    graph of the step, or eager steps), then `kernel_steps` eager steps with
+    per-phase HIP events for the kernel breakdown."""
     import torch
     ham = pm.hamiltonian("tfim", J=wl.J, h=wl.h, pbc=wl.pbc)
     m = pm.Model(wl.Lx, wl.Ly, wl.dim, wl.H, wl.complex_head, wl.marshall, wl.zero_mag,
@@ -75,34 +84,40 @@ def run_form(pm, wl, form, K, W, dtype="f32"):
     outs = m.step_outputs(wl.Ns)
     hist = torch.zeros((max(K, 1), 3), dtype=torch.float64, device="cuda")
     status = torch.zeros(max(K, 1), dtype=torch.int32, device="cuda")
-    counter = 0
+    ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
 
-    def one(i, timed):
-        nonlocal counter
-        o = dict(outs)
-        if timed:
-            o["energy"] = hist[i]
-            o["status"] = status[i:i + 1]
-        m.step(ham, wl.Ns, wl.eta, wl.lam, wl.mu, mom, wl.key, counter, form=form,
-               ckpt_every=wl.ckpt_every, outputs=o)
-        counter += 1
+    def eager():
+        m.step(ham, wl.Ns, wl.eta, wl.lam, wl.mu, mom, wl.key, 0, form=form,
+               ckpt_every=wl.ckpt_every, outputs=outs, dev_counter=ctr)
 
-    for i in range(W):
-        one(i, False)
-    torch.cuda.synchronize()
-    m.timing_begin(K)
+    for _ in range(W):
+        eager()
+    g = None
+    if graph:
+        g, _ = m.capture_step(ham, wl.Ns, wl.eta, wl.lam, wl.mu, mom, wl.key, ctr, form=form,
+                              ckpt_every=wl.ckpt_every, outputs=outs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
-        one(i, True)
+        if g is not None:
+            g.replay()
+        else:
+            eager()
+        hist[i].copy_(outs["energy"], non_blocking=True)
+        status[i:i + 1].copy_(outs["status"], non_blocking=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # kernel breakdown: eager steps with events on the step's stream
+    m.timing_begin(kernel_steps)
+    for _ in range(kernel_steps):
+        eager()
+    torch.cuda.synchronize()
     phases, nrec = m.timing_read()
     E = hist.cpu().numpy()
     st = status.cpu().numpy()
     m.close()
     return dict(seconds=t1 - t0, phases={k: v / max(nrec, 1) for k, v in phases.items()},
-                energy=E, status=st)
+                energy=E, status=st, kernel_steps=nrec)
 
 
 def cpu_baseline(wl):
@@ -156,12 +171,22 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes,
+                          "copies": 3}))
+        return
     wl = WORKLOADS["tfim64"]
     K, W = args.steps, args.warmup
     units = work_units(wl)
     N = wl.Lx * wl.Ly
 
-    res = run_form(pm, wl, pm.FORM_BF16_FP64, K, W)
+    res = run_form(pm, wl, pm.FORM_BF16_FP64, K, W, graph=not args.eager)
     print("bf16_fp64: %.3f s for %d steps" % (res["seconds"], K), file=sys.stderr, flush=True)
     ms_step = res["seconds"] / K * 1e3
     value = K / res["seconds"]
@@ -179,7 +204,7 @@ def main():
                            "dE_per_site_last50": dE(res["energy"]),
                            "status_nonzero_steps": int(np.count_nonzero(res["status"]))}}
     if not args.no_fp32:
-        r32 = run_form(pm, wl, pm.FORM_FP32_PLAIN, K, W)
+        r32 = run_form(pm, wl, pm.FORM_FP32_PLAIN, K, W, graph=not args.eager)
         print("fp32_plain: %.3f s for %d steps" % (r32["seconds"], K), file=sys.stderr, flush=True)
         forms["fp32_plain"] = {"steps_per_s": K / r32["seconds"],
                                "ms_per_step": r32["seconds"] / K * 1e3,
@@ -204,6 +229,9 @@ def main():
         "roofline": dict(roof, kernel=dom if dom in graded else "eloc"),
         "rooflines": graded,
         "phase_ms": ph,
+        "timing": ("value: %d %s steps; per-kernel ms (roofline, phase_ms): HIP events on the "
+                   "step's stream over %d further eager steps of the same run"
+                   % (K, "eager" if args.eager else "graph-replayed", res["kernel_steps"])),
         "forms": forms,
         "E0_per_site": wl.E0 / N,
         "cpu_baseline": cpu,

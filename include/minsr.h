@@ -66,9 +66,13 @@ extern "C" {
 
 /* numerical precision of one minSR step */
 #define MINSR_FORM_FP64_REF   0  /* everything in FP64                       */
-#define MINSR_FORM_BF16_FP64  1  /* BF16 O'/Gram on MFMA, FP32 accumulation,
-                                    FP64 reductions, solve and update        */
+#define MINSR_FORM_BF16_FP64  1  /* O' rounded to BF16 as a hi/lo pair, Gram
+                                    hi hi^T + hi lo^T + lo hi^T on BF16 MFMA
+                                    with FP32 accumulation; FP64 reductions,
+                                    solve and update                        */
 #define MINSR_FORM_FP32_PLAIN 2  /* FP32 O', Gram, solve and update          */
+#define MINSR_FORM_BF16_1PASS 3  /* as BF16_FP64 with O' a single BF16 array
+                                    (one MFMA pass; larger Gram error)       */
 
 /* device status-word bits (minsr_step_out.dev_status) */
 #define MINSR_ST_NONFINITE_ELOC  0x1u
@@ -200,6 +204,10 @@ typedef struct {
 typedef struct {
   double* dev_momentum;  /* [Np] FP64, caller-owned, updated in place       */
   uint64_t key, counter; /* Philox stream of the sampling uniforms          */
+  uint64_t* dev_counter; /* optional [1]: if not NULL the counter is read
+                            from here and incremented by one at the end of
+                            the step, so a captured graph of the step can be
+                            replayed with fresh uniforms each time          */
 } minsr_step_state;
 
 typedef struct {

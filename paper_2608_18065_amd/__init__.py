@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libminsr.so")
 
 F64, F32, BF16 = 0, 1, 2
 HAM_TFIM, HAM_CLUSTER, HAM_J1J2 = 0, 1, 2
-FORM_FP64_REF, FORM_BF16_FP64, FORM_FP32_PLAIN = 0, 1, 2
+FORM_FP64_REF, FORM_BF16_FP64, FORM_FP32_PLAIN, FORM_BF16_1PASS = 0, 1, 2, 3
 ST_NONFINITE_ELOC, ST_NOT_PD, ST_NONFINITE_DTH, ST_EIG_NOCONV = 1, 2, 4, 8
 
 # every entry point of include/minsr.h
@@ -52,7 +52,7 @@ class StepCfg(ctypes.Structure):
 
 class StepState(ctypes.Structure):
     _fields_ = [("dev_momentum", ctypes.c_void_p), ("key", ctypes.c_uint64),
-                ("counter", ctypes.c_uint64)]
+                ("counter", ctypes.c_uint64), ("dev_counter", ctypes.c_void_p)]
 
 
 class StepOut(ctypes.Structure):
@@ -223,19 +223,35 @@ class Model:
 
     # ------------------------------------------------------------ one step
     def step(self, ham, Ns, eta, lam, mu, momentum, key, counter, form=FORM_FP64_REF,
-             pinv_cutoff=0.0, ckpt_every=1, apply_update=True, outputs=None):
+             pinv_cutoff=0.0, ckpt_every=1, apply_update=True, outputs=None, dev_counter=None):
         """One minSR iteration (Alg. 1); returns the output tensors.
 
         `outputs` may hold preallocated tensors (energy, dtheta, status,
-        eloc, sigma) to avoid allocation, e.g. inside a timed loop."""
+        eloc, sigma) to avoid allocation, e.g. inside a timed loop.
+        `dev_counter` (int64 tensor of one element on the device) makes the
+        step read its Philox counter from device memory and increment it,
+        so a captured graph of the step can be replayed."""
         o = outputs if outputs is not None else self.step_outputs(Ns)
         cfg = StepCfg(Ns, form, eta, lam, mu, pinv_cutoff, ckpt_every, int(apply_update))
-        st = StepState(ctypes.c_void_p(momentum.data_ptr()), key, counter)
+        st = StepState(ctypes.c_void_p(momentum.data_ptr()), key, counter, _ptr(dev_counter).value)
         out = StepOut(_ptr(o["energy"]).value, _ptr(o["dtheta"]).value, _ptr(o["status"]).value,
                       _ptr(o.get("eloc")).value, _ptr(o.get("sigma")).value)
         _check(lib().minsr_step(self.handle, ctypes.byref(ham), ctypes.byref(cfg),
                                 ctypes.byref(st), ctypes.byref(out), _stream()))
         return o
+
+    def capture_step(self, ham, Ns, eta, lam, mu, momentum, key, dev_counter, form=FORM_FP64_REF,
+                     pinv_cutoff=0.0, ckpt_every=1, outputs=None):
+        """Capture one step into a hip graph (torch.cuda.CUDAGraph); every
+        replay runs one iteration and advances dev_counter.  Returns
+        (graph, outputs)."""
+        o = outputs if outputs is not None else self.step_outputs(Ns)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step(ham, Ns, eta, lam, mu, momentum, key, 0, form=form,
+                      pinv_cutoff=pinv_cutoff, ckpt_every=ckpt_every, outputs=o,
+                      dev_counter=dev_counter)
+        return g, o
 
     def step_outputs(self, Ns):
         dev = self.device
@@ -266,10 +282,13 @@ class Model:
         n, Np = n.value, Np.value     # Np: padded row stride of O'
         tdt = torch.float32 if form == FORM_FP32_PLAIN else torch.float64
         odt = {FORM_FP64_REF: torch.float64, FORM_BF16_FP64: torch.bfloat16,
-               FORM_FP32_PLAIN: torch.float32}[form]
-        return dict(T=_from_ptr(T.value, (n, n), tdt), x=_from_ptr(x.value, (n,), torch.float64),
-                    eps_prime=_from_ptr(e.value, (n,), torch.float64),
-                    Oprime=_from_ptr(O.value, (n, Np), odt)[:, :self.Np])
+               FORM_FP32_PLAIN: torch.float32, FORM_BF16_1PASS: torch.bfloat16}[form]
+        out = dict(T=_from_ptr(T.value, (n, n), tdt), x=_from_ptr(x.value, (n,), torch.float64),
+                   eps_prime=_from_ptr(e.value, (n,), torch.float64),
+                   Oprime=_from_ptr(O.value, (n, Np), odt)[:, :self.Np])
+        if form == FORM_BF16_FP64:   # low halves follow the high halves
+            out["Oprime_lo"] = _from_ptr(O.value + n * Np * 2, (n, Np), odt)[:, :self.Np]
+        return out
 
 
 def _from_ptr(addr, shape, dtype):

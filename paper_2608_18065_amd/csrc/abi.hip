@@ -37,6 +37,10 @@ size_t packed_elems(minsr_model* m);
 void bind_work(minsr_model* m);
 size_t gram_partial_bytes(int n, size_t Np, int dtype);
 
+__global__ void k_bump_counter(uint64_t* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c[0] += 1;
+}
+
 // zero-fill by kernel (safe inside captured graphs)
 __global__ void k_zero_u32(uint32_t* p, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -354,7 +358,7 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   if (Ns < 2) return fail(MINSR_E_SHAPE, "a step needs Ns >= 2");
   if (!out->dev_energy || !out->dev_status) return fail(MINSR_E_INVALID_ARG, "null output");
   if (cfg->apply_update && !st->dev_momentum) return fail(MINSR_E_INVALID_ARG, "null momentum");
-  if (cfg->form < 0 || cfg->form > 2) return fail(MINSR_E_INVALID_ARG, "unknown form");
+  if (cfg->form < 0 || cfg->form > 3) return fail(MINSR_E_INVALID_ARG, "unknown form");
   if (!(cfg->lambda >= 0.0) || !(cfg->pinv_cutoff >= 0.0)) return fail(MINSR_E_INVALID_ARG, "negative lambda / cutoff");
   if (cfg->pinv_cutoff == 0.0 && cfg->lambda == 0.0)
     return fail(MINSR_E_INVALID_ARG, "lambda = 0 needs the pseudo-inverse (T is singular)");
@@ -370,7 +374,11 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   double* eloc = out->dev_eloc ? out->dev_eloc : m->eloc;
   double* dth = out->dev_dtheta ? out->dev_dtheta : m->dtheta;
   const int rdt = cfg->form == MINSR_FORM_FP64_REF ? MINSR_F64
-                  : cfg->form == MINSR_FORM_BF16_FP64 ? MINSR_BF16 : MINSR_F32;
+                  : cfg->form == MINSR_FORM_FP32_PLAIN ? MINSR_F32 : MINSR_BF16;
+  // the hi/lo split keeps both BF16 halves in the O' buffer (rows x ld each)
+  void* Rlo = cfg->form == MINSR_FORM_BF16_FP64
+                  ? (void*)((__hip_bfloat16*)m->R + (size_t)n * padded_ld(Np))
+                  : nullptr;
 
   const bool timing = m->t_slot < m->t_max;
   auto mark = [&](int phase) -> int {
@@ -384,7 +392,7 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   MINSR_PHASE(0);
   // 1. exact autoregressive samples, hidden states, per-site conditionals
   rc = launch_forward(m, 0, Ns, nullptr, st->key, st->counter, sigma, m->logpsi, m->states, 1,
-                      m->site, s);
+                      m->site, s, st->dev_counter);
   if (rc) return rc;
   MINSR_PHASE(1);
   // 2. local energies, E, Var and eps'
@@ -400,14 +408,15 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   rc = launch_jacobian(m, Ns, sigma, m->states, C, m->O, nullptr, nullptr, s);
   if (rc) return rc;
   MINSR_PHASE(4);
-  rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, padded_ld(Np), s);
+  rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, padded_ld(Np), s,
+                     Rlo);
   if (rc) return rc;
   MINSR_PHASE(5);
   // 4. Gram and regularised solve
-  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 1);
+  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 1, Rlo);
   if (rc) return rc;
   MINSR_PHASE(6);
-  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 2);
+  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 2, Rlo);
   if (rc) return rc;
   MINSR_PHASE(7);
   if (cfg->pinv_cutoff > 0.0)
@@ -420,7 +429,7 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   MINSR_PHASE(8);
   // 5. dtheta = eta O' x, momentum, parameters, working copy
   rc = launch_update(n, Np, m->R, rdt, m->x, cfg->eta, cfg->mu, m->dpart, dth, st->dev_momentum,
-                     m->theta, out->dev_status, cfg->apply_update, s);
+                     m->theta, out->dev_status, cfg->apply_update, s, Rlo);
   if (rc) return rc;
   MINSR_PHASE(9);
   if (cfg->apply_update) {
@@ -429,6 +438,10 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   }
   MINSR_PHASE(10);
 #undef MINSR_PHASE
+  if (st->dev_counter) {
+    k_bump_counter<<<1, 64, 0, s>>>(st->dev_counter);
+    MINSR_CHECK_LAUNCH();
+  }
   if (timing) m->t_slot++;
   m->last_n = n;
   m->last_form = cfg->form;

@@ -234,6 +234,7 @@ template <typename T> struct FwdArgs {
   // sampling
   const double* uniforms;
   uint64_t key, counter;
+  const uint64_t* counter_ptr;   // if set, the counter is read from here
   // configurations and outputs
   uint8_t* sigma_out;        // mode 0
   const uint8_t* sigma_in;   // modes 1, 2
@@ -294,6 +295,7 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
   const T P0 = w.head[2 * H + j], P1 = w.head[3 * H + j];
   const T c0 = w.headb[0], c1 = w.headb[1], cp0 = w.headb[2], cp1 = w.headb[3];
   const T PI = (T)3.14159265358979323846;
+  const uint64_t ctr = a.counter_ptr ? *a.counter_ptr : a.counter;
 
   for (int item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const int t = a.mode == MODE_ELOC ? item / a.nchunks : 0;
@@ -570,7 +572,7 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
             u = a.uniforms[(size_t)s * N + k];
           } else {
             if ((k & 3) == 0)
-              rw[r] = philox4x64_10(a.counter, (uint64_t)s, (uint64_t)(k >> 2), 0, a.key, 0);
+              rw[r] = philox4x64_10(ctr, (uint64_t)s, (uint64_t)(k >> 2), 0, a.key, 0);
             u = u01(rw[r].w[k & 3]);
           }
           const double p0 = (double)d_exp(lp0);
@@ -657,11 +659,11 @@ static int seqs_per_block(int H, int R) { return (256 / H) * R; }
 
 template <typename T>
 static int forward_t(minsr_model* m, const Work<T>& w, int mode, int Ns, const double* uniforms,
-                     uint64_t key, uint64_t counter, uint8_t* sigma, double* logpsi, void* states,
-                     int store_every, double* site, hipStream_t s) {
+                     uint64_t key, uint64_t counter, const uint64_t* counter_ptr, uint8_t* sigma,
+                     double* logpsi, void* states, int store_every, double* site, hipStream_t s) {
   FwdArgs<T> a = base_args<T>(m, w);
   a.Ns = Ns; a.mode = mode;
-  a.uniforms = uniforms; a.key = key; a.counter = counter;
+  a.uniforms = uniforms; a.key = key; a.counter = counter; a.counter_ptr = counter_ptr;
   if (mode == MODE_SAMPLE) a.sigma_out = sigma; else a.sigma_in = sigma;
   a.logpsi = logpsi;
   a.states = (T*)states; a.store_every = store_every; a.site = site;
@@ -675,13 +677,13 @@ static int forward_t(minsr_model* m, const Work<T>& w, int mode, int Ns, const d
 
 int launch_forward(minsr_model* m, int mode, int Ns, const double* uniforms, uint64_t key,
                    uint64_t counter, uint8_t* sigma, double* logpsi, void* states,
-                   int store_every, double* site, hipStream_t s) {
+                   int store_every, double* site, hipStream_t s, const uint64_t* counter_ptr) {
   if (Ns == 0) return MINSR_OK;
   if (m->f64)
-    return forward_t<double>(m, m->wd, mode, Ns, uniforms, key, counter, sigma, logpsi, states,
-                             store_every, site, s);
-  return forward_t<float>(m, m->wf, mode, Ns, uniforms, key, counter, sigma, logpsi, states,
-                          store_every, site, s);
+    return forward_t<double>(m, m->wd, mode, Ns, uniforms, key, counter, counter_ptr, sigma,
+                             logpsi, states, store_every, site, s);
+  return forward_t<float>(m, m->wf, mode, Ns, uniforms, key, counter, counter_ptr, sigma, logpsi,
+                          states, store_every, site, s);
 }
 
 // ------------------------------------------------------ local energies

@@ -48,9 +48,11 @@ template <> __device__ inline __hip_bfloat16 cvt_out<__hip_bfloat16>(double v) {
 
 // centred value in the input precision (FP32 rows are centred in FP32
 // against the FP64 mean rounded to FP32), then rounded to the output type
+// Rlo (BF16 output only, may be null): the rounding remainder
+// bf16(v - float(bf16(v))), so that hi + lo carries v to about 16 bits
 template <typename TI, typename TO>
 __global__ void k_center(const TI* O, int rows_per_block, int RC, size_t Np, const double* mean,
-                         TO* R, size_t ldo) {
+                         TO* R, size_t ldo, TO* Rlo) {
   size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= ldo) return;
   const int blk = blockIdx.z, chunk = blockIdx.y;
@@ -58,20 +60,26 @@ __global__ void k_center(const TI* O, int rows_per_block, int RC, size_t Np, con
   const int r1 = min(rows_per_block, r0 + RC);
   const size_t oo = ((size_t)blk * rows_per_block) * ldo + col;
   if (col >= Np) {   // zero padding of the output rows
-    for (int r = r0; r < r1; ++r) R[oo + (size_t)r * ldo] = cvt_out<TO>(0.0);
+    for (int r = r0; r < r1; ++r) {
+      R[oo + (size_t)r * ldo] = cvt_out<TO>(0.0);
+      if (Rlo) Rlo[oo + (size_t)r * ldo] = cvt_out<TO>(0.0);
+    }
     return;
   }
   const TI mu = mean ? (TI)mean[(size_t)blk * Np + col] : (TI)0;
   const size_t off = ((size_t)blk * rows_per_block) * Np + col;
   for (int r = r0; r < r1; ++r) {
     const TI v = O[off + (size_t)r * Np] - mu;
-    R[oo + (size_t)r * ldo] = cvt_out<TO>((double)v);
+    const TO hi = cvt_out<TO>((double)v);
+    R[oo + (size_t)r * ldo] = hi;
+    if (Rlo) Rlo[oo + (size_t)r * ldo] = cvt_out<TO>((double)v - (double)(float)hi);
   }
 }
 
 template <typename TI>
 static int center_t(int rows_per_block, int nblocks, size_t Np, const TI* O, void* R,
-                    int out_dtype, double* colpart, double* colmean, size_t ldo, hipStream_t s) {
+                    int out_dtype, double* colpart, double* colmean, size_t ldo, void* Rlo,
+                    hipStream_t s) {
   const int RC = 32;
   const int nrc = (rows_per_block + RC - 1) / RC;
   dim3 grid((unsigned)((Np + 255) / 256), (unsigned)nrc, (unsigned)nblocks);
@@ -85,14 +93,15 @@ static int center_t(int rows_per_block, int nblocks, size_t Np, const TI* O, voi
   dim3 ogrid((unsigned)((ldo + 255) / 256), (unsigned)nrc, (unsigned)nblocks);
   switch (out_dtype) {
     case MINSR_F64:
-      k_center<TI, double><<<ogrid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean, (double*)R, ldo);
+      k_center<TI, double><<<ogrid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean, (double*)R, ldo, nullptr);
       break;
     case MINSR_F32:
-      k_center<TI, float><<<ogrid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean, (float*)R, ldo);
+      k_center<TI, float><<<ogrid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean, (float*)R, ldo, nullptr);
       break;
     case MINSR_BF16:
       k_center<TI, __hip_bfloat16><<<ogrid, 256, 0, s>>>(O, rows_per_block, RC, Np, colmean,
-                                                          (__hip_bfloat16*)R, ldo);
+                                                          (__hip_bfloat16*)R, ldo,
+                                                          (__hip_bfloat16*)Rlo);
       break;
     default:
       return fail(MINSR_E_INVALID_ARG, "unknown output dtype");
@@ -102,13 +111,14 @@ static int center_t(int rows_per_block, int nblocks, size_t Np, const TI* O, voi
 }
 
 int launch_center(int rows_per_block, int nblocks, size_t Np, const void* O, int in_f64, void* R,
-                  int out_dtype, double* colpart, double* colmean, size_t ldo, hipStream_t s) {
+                  int out_dtype, double* colpart, double* colmean, size_t ldo, hipStream_t s,
+                  void* Rlo) {
   if (rows_per_block == 0 || Np == 0) return MINSR_OK;
   if (in_f64)
     return center_t<double>(rows_per_block, nblocks, Np, (const double*)O, R, out_dtype, colpart,
-                            colmean, ldo, s);
+                            colmean, ldo, Rlo, s);
   return center_t<float>(rows_per_block, nblocks, Np, (const float*)O, R, out_dtype, colpart,
-                         colmean, ldo, s);
+                         colmean, ldo, Rlo, s);
 }
 
 // ================================================================== Gram
@@ -127,15 +137,22 @@ typedef __attribute__((ext_vector_type(16))) float f32x16_t;
 
 // BF16 MFMA tile kernel: 128 x 128 output tile per workgroup (4 waves,
 // 64 x 64 each as 2 x 2 blocks of v_mfma_f32_32x32x16_bf16), K staged
-// through two LDS buffers 64 columns at a time: the next stage's global
-// loads are in flight while the current stage feeds the matrix cores.
-// Rows of R have a stride ld that is a multiple of 64, zero-padded past Np.
-constexpr int GT = 128, GK = 64, GKP = GK + 8;
+// through two LDS buffers: the next stage's global loads are in flight
+// while the current stage feeds the matrix cores.  Rows of R have a stride
+// ld that is a multiple of 64, zero-padded past Np.
+// SPLIT: R = hi + lo (two BF16 arrays); the tile is hi hi^T + hi lo^T +
+// lo hi^T (the lo lo^T term is below FP32 accumulation accuracy), which is
+// symmetric by construction.
+constexpr int GT = 128;
 
-__global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R, int n, size_t ld,
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
+                                                   const __hip_bfloat16* Rlo, int n, size_t ld,
                                                    size_t kchunk, float* part) {
-  __shared__ __align__(16) __hip_bfloat16 As[2][GT][GKP];
-  __shared__ __align__(16) __hip_bfloat16 Bs[2][GT][GKP];
+  constexpr int GK = SPLIT ? 32 : 64, GKP = GK + 8;
+  constexpr int NOP = SPLIT ? 2 : 1;
+  __shared__ __align__(16) __hip_bfloat16 As[2][NOP][GT][GKP];
+  __shared__ __align__(16) __hip_bfloat16 Bs[2][NOP][GT][GKP];
   int ti, tj;
   pair_decode(blockIdx.x, ti, tj);
   const int split = blockIdx.y;
@@ -152,25 +169,30 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R, int 
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
 
   const int arow0 = ti * GT, brow0 = tj * GT;
-  // this thread's four 16-byte chunks of each operand per stage
   constexpr int CPT = GT * (GK / 8) / 256;
-  uint4 ra[CPT], rb[CPT];
+  uint4 ra[NOP][CPT], rb[NOP][CPT];
   auto load = [&](size_t kk) {
 #pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-      const int c = tid + 256 * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
-      const int xa = arow0 + r, xb = brow0 + r;
-      ra[i] = xa < n ? *reinterpret_cast<const uint4*>(R + (size_t)xa * ld + kk + q) : make_uint4(0, 0, 0, 0);
-      rb[i] = xb < n ? *reinterpret_cast<const uint4*>(R + (size_t)xb * ld + kk + q) : make_uint4(0, 0, 0, 0);
+    for (int o = 0; o < NOP; ++o) {
+      const __hip_bfloat16* M = o == 0 ? R : Rlo;
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) {
+        const int c = tid + 256 * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
+        const int xa = arow0 + r, xb = brow0 + r;
+        ra[o][i] = xa < n ? *reinterpret_cast<const uint4*>(M + (size_t)xa * ld + kk + q) : make_uint4(0, 0, 0, 0);
+        rb[o][i] = xb < n ? *reinterpret_cast<const uint4*>(M + (size_t)xb * ld + kk + q) : make_uint4(0, 0, 0, 0);
+      }
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-      const int c = tid + 256 * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
-      *reinterpret_cast<uint4*>(&As[buf][r][q]) = ra[i];
-      *reinterpret_cast<uint4*>(&Bs[buf][r][q]) = rb[i];
-    }
+    for (int o = 0; o < NOP; ++o)
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) {
+        const int c = tid + 256 * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
+        *reinterpret_cast<uint4*>(&As[buf][o][r][q]) = ra[o][i];
+        *reinterpret_cast<uint4*>(&Bs[buf][o][r][q]) = rb[o][i];
+      }
   };
   if (k0 < k1) {
     load(k0);
@@ -183,18 +205,26 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R, int 
     if (more) load(kk + GK);
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 16) {
-      bf16x8_t fa[2], fb[2];
+      bf16x8_t fa[NOP][2], fb[NOP][2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-        fa[a] = *reinterpret_cast<const bf16x8_t*>(&As[cur][wm + a * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
+      for (int o = 0; o < NOP; ++o) {
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
-        fb[b] = *reinterpret_cast<const bf16x8_t*>(&Bs[cur][wn + b * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
+          fa[o][a] = *reinterpret_cast<const bf16x8_t*>(&As[cur][o][wm + a * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+          fb[o][b] = *reinterpret_cast<const bf16x8_t*>(&Bs[cur][o][wn + b * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][a], fb[0][b], acc[a][b], 0, 0, 0);
+          if (SPLIT) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][a], fb[NOP - 1][b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[NOP - 1][a], fb[0][b], acc[a][b], 0, 0, 0);
+          }
+        }
     }
     if (more) store(cur ^ 1);
     __syncthreads();
@@ -310,7 +340,7 @@ size_t gram_partial_bytes(int n, size_t Np, int dtype) {
 }
 
 int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gpart,
-                size_t gpart_elems, hipStream_t s, int which) {
+                size_t gpart_elems, hipStream_t s, int which, const void* Rlo) {
   // R rows have the padded stride ld = round_up(Np, 64); the padding is zero
   const size_t ld = (Np + 63) / 64 * 64;
   if (n == 0) return MINSR_OK;
@@ -318,7 +348,7 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
   const int nt = (n + tile - 1) / tile;
   const int npairs = nt * (nt + 1) / 2;
   const int S = pick_split(npairs, Np, 0);
-  const size_t kgran = dtype == MINSR_BF16 ? GK : VK;
+  const size_t kgran = dtype == MINSR_BF16 ? 64 : VK;
   size_t kchunk = (ld + S - 1) / S;
   kchunk = (kchunk + kgran - 1) / kgran * kgran;
   const size_t need = gram_partial_bytes(n, Np, dtype);
@@ -327,7 +357,12 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
   dim3 rgrid((unsigned)((tile * tile + 255) / 256), (unsigned)npairs);
   if (dtype == MINSR_BF16) {
     if (which & 1) {
-      k_gram_bf16<<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, n, ld, kchunk, gpart);
+      if (Rlo)
+        k_gram_bf16<true><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R,
+                                               (const __hip_bfloat16*)Rlo, n, ld, kchunk, gpart);
+      else
+        k_gram_bf16<false><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, nullptr, n, ld, kchunk,
+                                                gpart);
       MINSR_CHECK_LAUNCH();
     }
     if (which & 2) k_gram_reduce<float, double><<<rgrid, 256, 0, s>>>(gpart, npairs, S, tile, n, T);
@@ -712,17 +747,21 @@ int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int 
 // dpart[chunk][k] = sum over the chunk's rows a of R[a][k] x[a]  (FP64)
 template <typename TR>
 __global__ void k_update_part(const TR* R, int n, size_t Np, size_t ld, int RC, const double* x,
-                              double* part) {
+                              double* part, const TR* Rlo) {
   size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= Np) return;
   const int r0 = blockIdx.y * RC, r1 = min(n, r0 + RC);
   double s = 0.0;
-  for (int r = r0; r < r1; ++r) s += (double)(float)R[(size_t)r * ld + col] * x[r];
+  if (Rlo)
+    for (int r = r0; r < r1; ++r)
+      s += ((double)(float)R[(size_t)r * ld + col] + (double)(float)Rlo[(size_t)r * ld + col]) * x[r];
+  else
+    for (int r = r0; r < r1; ++r) s += (double)(float)R[(size_t)r * ld + col] * x[r];
   part[(size_t)blockIdx.y * Np + col] = s;
 }
 template <>
 __global__ void k_update_part<double>(const double* R, int n, size_t Np, size_t ld, int RC,
-                                      const double* x, double* part) {
+                                      const double* x, double* part, const double* Rlo) {
   size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= Np) return;
   const int r0 = blockIdx.y * RC, r1 = min(n, r0 + RC);
@@ -754,17 +793,18 @@ __global__ void k_apply(size_t Np, const double* dtheta, double mu, double* m, d
 
 int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, double eta,
                   double mu, double* dpart, double* dtheta, double* momentum, double* theta,
-                  uint32_t* status, int apply, hipStream_t s) {
+                  uint32_t* status, int apply, hipStream_t s, const void* Rlo) {
   const int RC = 64;
   const int nrc = (n + RC - 1) / RC;
   dim3 grid((unsigned)((Np + 255) / 256), (unsigned)nrc);
   const size_t ld = (Np + 63) / 64 * 64;
   if (dtype == MINSR_BF16)
-    k_update_part<__hip_bfloat16><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, n, Np, ld, RC, x, dpart);
+    k_update_part<__hip_bfloat16><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, n, Np, ld, RC, x,
+                                                       dpart, (const __hip_bfloat16*)Rlo);
   else if (dtype == MINSR_F32)
-    k_update_part<float><<<grid, 256, 0, s>>>((const float*)R, n, Np, ld, RC, x, dpart);
+    k_update_part<float><<<grid, 256, 0, s>>>((const float*)R, n, Np, ld, RC, x, dpart, nullptr);
   else
-    k_update_part<double><<<grid, 256, 0, s>>>((const double*)R, n, Np, ld, RC, x, dpart);
+    k_update_part<double><<<grid, 256, 0, s>>>((const double*)R, n, Np, ld, RC, x, dpart, nullptr);
   MINSR_CHECK_LAUNCH();
   const unsigned g1 = (unsigned)((Np + 255) / 256);
   k_update_final<<<g1, 256, 0, s>>>(dpart, nrc, Np, eta, dtheta, status);

@@ -68,7 +68,8 @@ int launch_pack(minsr_model* m, hipStream_t s);
 // mode 0: sample, 1: evaluate.  states/site may be null.
 int launch_forward(minsr_model* m, int mode, int Ns, const double* uniforms, uint64_t key,
                    uint64_t counter, uint8_t* sigma, double* logpsi, void* states,
-                   int store_every, double* site, hipStream_t s);
+                   int store_every, double* site, hipStream_t s,
+                   const uint64_t* counter_ptr = nullptr);
 // which: 1 = off-diagonal terms (the recurrence), 2 = diagonal + sum, 3 = both
 int launch_eloc(minsr_model* m, const minsr_hamiltonian* H, int Ns, const uint8_t* sigma,
                 const double* logpsi, const void* states, const double* site, double* eloc,
@@ -88,12 +89,13 @@ int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* st
 // (ldo >= Np; columns Np..ldo-1 are written as zeros)
 int launch_center(int rows_per_block, int nblocks, size_t Np, const void* O, int in_f64,
                   void* R, int out_dtype, double* colpart, double* colmean, size_t ldo,
-                  hipStream_t s);
+                  hipStream_t s, void* Rlo = nullptr);
 // the step keeps O' with rows padded to a multiple of 64 columns
 inline size_t padded_ld(size_t Np) { return (Np + 63) / 64 * 64; }
 // which: 1 = tile products, 2 = split-K reduction and mirror, 3 = both
+// Rlo (BF16 only, may be null): low parts of a hi/lo split of R
 int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gpart,
-                size_t gpart_elems, hipStream_t s, int which = 3);
+                size_t gpart_elems, hipStream_t s, int which = 3, const void* Rlo = nullptr);
 // factors T + lambda I into Lf (T is left unchanged) and solves for x
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, uint32_t* status,
@@ -103,7 +105,7 @@ int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* 
                       double* eig, size_t eig_elems, uint32_t* status, hipStream_t s);
 int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, double eta,
                   double mu, double* dpart, double* dtheta, double* momentum, double* theta,
-                  uint32_t* status, int apply, hipStream_t s);
+                  uint32_t* status, int apply, hipStream_t s, const void* Rlo = nullptr);
 int launch_reduce_rows(int rows, size_t Np, const double* part, double* out, hipStream_t s);
 
 }  // namespace minsr

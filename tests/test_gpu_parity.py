@@ -196,16 +196,6 @@ def test_vjp_matches_oracle():
 
 # ------------------------------------------------------------ whole step
 
-def _oracle_step_from_gpu_samples(spec, th, ham, sig, eta, lam, pinv=0.0):
-    sig = sig.astype(np.int64)
-    lp = omodel.log_psi(spec, th, sig)
-    eps = oham.local_energy(spec, th, ham, sig, lp)
-    D = ojac.log_derivatives(spec, th, sig)
-    r = ominsr.update(D, eps, eta, lam, pinv)
-    r["eps"] = eps
-    return r
-
-
 def test_step_fp64_config1():
     import paper_2608_18065_amd as pm
     spec, m = make_pair(Lx=10, H=16, max_Ns=64)
@@ -236,6 +226,8 @@ def test_step_fp64_config1():
     (dict(Lx=3, Ly=4, dim=2, H=16, marshall=True, zero_mag=True), oham.Ham("j1j2", J=1.0), 130),
 ], ids=["tfim_pbc", "cluster_c", "heis2d"])
 def test_step_fp64_ragged(arch, ham, Ns):
+    # the oracle runs the whole step from the same parameters and Philox
+    # stream; the GPU's samples must be identical, then every stage agrees
     import paper_2608_18065_amd as pm
     spec, m = make_pair(**arch, max_Ns=Ns)
     th = scaled_theta(spec, 14, 1.0)
@@ -244,27 +236,67 @@ def test_step_fp64_ragged(arch, ham, Ns):
     o = m.step(_gpu_ham(ham), Ns, 0.05, 1e-3, 0.5, mom, 5, 6, form=pm.FORM_FP64_REF)
     torch.cuda.synchronize()
     assert int(o["status"].item()) == 0
-    ref = _oracle_step_from_gpu_samples(spec, th, ham, o["sigma"].cpu().numpy(), 0.05, 1e-3)
+    ref = ominsr.step(spec, th, np.zeros_like(th), ham, Ns, 0.05, 1e-3, 0.5, 5, 6)
+    assert np.array_equal(o["sigma"].cpu().numpy(), ref["sigma"].astype(np.uint8))
     assert rel_err(o["eloc"].cpu().numpy() @ np.array([1, 1j]), ref["eps"]) < 1e-10
     it = m.intermediates(pm.FORM_FP64_REF)
     assert rel_err(it["T"].cpu().numpy(), ref["T"]) < 1e-10
+    assert rel_err(it["x"].cpu().numpy(), ref["x"]) < 1e-10
     assert rel_err(o["dtheta"].cpu().numpy(), ref["dtheta"]) < 1e-10
-    np.testing.assert_allclose(m.get_params().cpu().numpy(), th - 0.5 * ref["dtheta"],
-                               rtol=0, atol=1e-10 * np.max(np.abs(ref["dtheta"])) + 1e-15)
+    assert rel_err(m.get_params().cpu().numpy(), ref["theta"]) < 1e-10
+    assert rel_err(mom.cpu().numpy(), ref["m"]) < 1e-10
 
 
-@pytest.mark.parametrize("form,tol", [(1, 2e-2), (2, 5e-2)], ids=["bf16_fp64", "fp32_plain"])
-def test_step_low_precision_forms(form, tol):
-    spec, m = make_pair(Lx=10, H=16, dtype="f32", max_Ns=64)
-    th = omodel.glorot_init(spec, 2001)
+def _low_precision_step(spec, m, ham, Ns, eta, lam, key, counter, form):
     mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
-    ham = oham.Ham("tfim", J=1.0, h=1.0)
-    o = m.step(_gpu_ham(ham), 64, 0.01, 1e-3, 0.0, mom, 1001, 0, form=form)
+    th = m.get_params().cpu().numpy()
+    o = m.step(_gpu_ham(ham), Ns, eta, lam, 0.0, mom, key, counter, form=form)
     torch.cuda.synchronize()
     assert int(o["status"].item()) == 0
-    ref = _oracle_step_from_gpu_samples(spec, th, ham, o["sigma"].cpu().numpy(), 0.01, 1e-3)
+    ref = ominsr.step(spec, th, np.zeros_like(th), ham, Ns, eta, lam, 0.0, key, counter)
+    same = o["sigma"].cpu().numpy() == ref["sigma"].astype(np.uint8)
+    if not same.all():
+        # an FP32 conditional can fall on the other side of u than the FP64
+        # one when |u - p| is below FP32 resolution; rare, not a defect
+        pytest.skip("FP32 sampling tie: %d of %d draws differ" % ((~same).sum(), same.size))
+    return o, ref
+
+
+@pytest.mark.parametrize("form,tol", [(1, 2e-2), (2, 2e-2), (3, 2e-2)],
+                         ids=["bf16_fp64", "fp32_plain", "bf16_1pass"])
+def test_step_low_precision_forms(form, tol):
+    spec, m = make_pair(Lx=10, H=16, dtype="f32", max_Ns=64)
+    ham = oham.Ham("tfim", J=1.0, h=1.0)
+    o, ref = _low_precision_step(spec, m, ham, 64, 0.01, 1e-3, 1001, 0, form)
     d = o["dtheta"].cpu().numpy()
     err = np.linalg.norm(d - ref["dtheta"]) / np.linalg.norm(ref["dtheta"])
+    assert err < tol, err
+
+
+@pytest.mark.parametrize("form,tol", [(1, 2e-2), (2, 2e-2), (3, 5e-2)],
+                         ids=["bf16_split_fp64", "fp32_plain", "bf16_1pass_fp64"])
+def test_step_full_size_tfim64(form, tol):
+    # the benchmark configuration (N = 64 periodic TFIM, d_h = 64, Ns = 1024,
+    # FP32 recurrence) and its launch configuration, against a full FP64
+    # oracle step from the same Philox stream: energy, eps', T and dtheta
+    import paper_2608_18065_amd as pm
+    from workloads import WORKLOADS
+    wl = WORKLOADS["tfim64"]
+    spec, m = make_pair(Lx=wl.Lx, H=wl.H, dtype="f32", seed=wl.seed, max_Ns=wl.Ns)
+    ham = oham.Ham("tfim", J=wl.J, h=wl.h, pbc=wl.pbc)
+    o, ref = _low_precision_step(spec, m, ham, wl.Ns, wl.eta, wl.lam, wl.key, 0, form)
+    E = o["energy"].cpu().numpy()
+    assert abs(E[0] - ref["E"].real) < 1e-4 * abs(ref["E"].real)
+    it = m.intermediates(form)
+    ep = it["eps_prime"].cpu().numpy()
+    assert np.max(np.abs(ep - ref["ep"])) < 1e-4 * np.max(np.abs(ref["ep"]))
+    T = it["T"].double().cpu().numpy()
+    assert np.linalg.norm(T - ref["T"]) < 2e-2 * np.linalg.norm(ref["T"])
+    d = o["dtheta"].cpu().numpy()
+    err = np.linalg.norm(d - ref["dtheta"]) / np.linalg.norm(ref["dtheta"])
+    # ||T|| / lambda bounds the amplification of the Gram's rounding error
+    print("form %d: dtheta rel err %.3e, ||T||/lambda %.3e" % (
+        form, err, np.linalg.eigvalsh(ref["T"])[-1] / wl.lam))
     assert err < tol, err
 
 
@@ -310,7 +342,7 @@ def test_jacobian_fp32_model(arch):
     assert rel_err(O.cpu().numpy(), ref) < 1e-4
 
 
-@pytest.mark.parametrize("form", [1, 2], ids=["bf16_mfma", "fp32"])
+@pytest.mark.parametrize("form", [1, 3, 2], ids=["bf16_split_mfma", "bf16_1pass_mfma", "fp32"])
 def test_gram_matches_its_operand(form):
     # T of the low-precision forms equals O' O'^T of the O' the kernel
     # consumed, evaluated in FP64 (accumulation error only); several
@@ -328,6 +360,10 @@ def test_gram_matches_its_operand(form):
     T = it["T"].double().cpu().numpy()
     assert np.array_equal(T, T.T)
     ref = R @ R.T
+    if form == 1:   # hi hi^T + hi lo^T + lo hi^T
+        Rl = it["Oprime_lo"].double().cpu().numpy()
+        assert np.max(np.abs(Rl)) <= 2.0 ** -8 * np.max(np.abs(R))
+        ref = ref + R @ Rl.T + Rl @ R.T
     assert np.max(np.abs(T - ref)) < 1e-5 * np.max(np.abs(ref))
     # centred blocks: every column of each block of O' sums to ~0
     assert np.max(np.abs(R[:150].sum(axis=0))) < 1e-2 * np.max(np.abs(R))
