@@ -222,6 +222,51 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H,
                const minsr_step_cfg* cfg, const minsr_step_state* st,
                const minsr_step_out* out, hipStream_t s);
 
+/* ---- the regularised solve alone (Eq. minsrR; App. F) --------------------
+ * Solves with the symmetric positive semi-definite FP64 matrix dev_T
+ * (n x n, row-major, caller-owned, left unchanged):
+ *   pinv_cutoff == 0: (T + lambda I) x = b by tiled Cholesky (lambda >= 0;
+ *     only the lower triangle of T is read);
+ *   pinv_cutoff > 0: x = T^+ b, the pseudo-inverse that keeps the
+ *     eigenvalues > pinv_cutoff * lambda_max(T) (lambda must be 0; the full
+ *     matrix is read and assumed symmetric).
+ * This is the solve minsr_step runs, exposed for direct use and tests; it
+ * uses the model's workspace, so n <= max_Ns (2 max_Ns for a cRNN) and the
+ * call must not overlap a minsr_step on the same handle.  A pivot <= 0
+ * sets MINSR_ST_NOT_PD in *dev_status (OR-ed in; the caller clears it), and
+ * x is then not meaningful.                                                */
+int minsr_solve(minsr_model* m, int n, const double* dev_T, double lambda,
+                double pinv_cutoff, const double* dev_b, double* dev_x,
+                uint32_t* dev_status, hipStream_t s);
+
+/* ---- many independent instances in one graph ------------------------------
+ * A batch steps `count` independent minSR instances (each its own model,
+ * Hamiltonian, step configuration, state and outputs; models may differ in
+ * lattice, N_s and architecture).  The first minsr_batch_step captures one
+ * step of every instance into a single hip graph, each instance on its own
+ * stream forked from and joined back into a library-owned origin stream, so
+ * the instances' kernels run concurrently; that call and every later one
+ * launch the graph on `s` (which may be the null stream).  Every state must
+ * carry a dev_counter (the Philox counter advances on the device at each
+ * replay); all pointers in the descriptors must stay valid for the batch's
+ * life.  The graph bakes in the launch parameters each model holds (see
+ * minsr_set_tunable) at the first minsr_batch_step; later changes to them
+ * do not affect the batch.  minsr_batch_step enqueues on `s` only.         */
+int minsr_batch_create(minsr_model* const* models, const minsr_hamiltonian* hams,
+                       const minsr_step_cfg* cfgs, const minsr_step_state* states,
+                       const minsr_step_out* outs, int count, minsr_batch** out);
+int minsr_batch_step(minsr_batch* b, hipStream_t s);
+int minsr_batch_destroy(minsr_batch* b);
+
+/* ---- launch parameters chosen by the autotuner ---------------------------
+ * key "gram_split": split-K factor of the Gram (0 = built-in heuristic);
+ * key "eloc_grid": workgroups of the persistent local-energy launch
+ * (0 = one per work item up to the window limit);
+ * key "sample_r": sequences per thread of the sampling recurrence (1 or 4).
+ * Values are validated; MINSR_E_INVALID_ARG for an unknown key.           */
+int minsr_set_tunable(minsr_model* m, const char* key, int value);
+int minsr_get_tunable(const minsr_model* m, const char* key, int* value);
+
 /* Device pointers to the step's intermediates after the last minsr_step
  * on this handle (valid until the next call on it): T (n x n FP64, or
  * FP32 in the FP32_PLAIN form), x (n), eps' (n), with n = Ns (pRNN) or

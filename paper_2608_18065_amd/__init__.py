@@ -25,6 +25,8 @@ SYMBOLS = (
     "minsr_num_sites", "minsr_get_params", "minsr_set_params", "minsr_sample", "minsr_logpsi",
     "minsr_local_energy", "minsr_jacobian", "minsr_logpsi_vjp", "minsr_step",
     "minsr_step_intermediates", "minsr_timing_begin", "minsr_timing_read",
+    "minsr_batch_create", "minsr_batch_step", "minsr_batch_destroy", "minsr_set_tunable",
+    "minsr_get_tunable", "minsr_solve",
 )
 PHASES = ("sample", "eloc", "eloc_sum_stats", "jacobian", "center", "gram", "gram_reduce",
           "solve", "update", "repack")
@@ -86,7 +88,15 @@ def load_library(path=LIB_PATH):
                                      ctypes.POINTER(vp), ctypes.POINTER(vp),
                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
         "minsr_timing_begin": [vp, i32],
+        "minsr_batch_create": [ctypes.POINTER(vp), ctypes.POINTER(Hamiltonian),
+                               ctypes.POINTER(StepCfg), ctypes.POINTER(StepState),
+                               ctypes.POINTER(StepOut), i32, ctypes.POINTER(vp)],
+        "minsr_batch_step": [vp, vp],
+        "minsr_batch_destroy": [vp],
+        "minsr_set_tunable": [vp, ctypes.c_char_p, i32],
+        "minsr_get_tunable": [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)],
         "minsr_timing_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)],
+        "minsr_solve": [vp, i32, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -221,6 +231,19 @@ class Model:
         _check(lib().minsr_logpsi_vjp(self.handle, Ns, _ptr(sigma), _ptr(g), _ptr(out), _stream()))
         return out
 
+    def solve(self, T, b, lam=0.0, pinv_cutoff=0.0):
+        """x for (T + lam I) x = b (Cholesky) or x = T^+ b with a relative
+        eigenvalue cutoff (lam = 0); returns (x, status word tensor)."""
+        T = T.to(device=self.device, dtype=torch.float64).contiguous()
+        b = b.to(device=self.device, dtype=torch.float64).contiguous()
+        n = b.shape[0]
+        assert T.shape == (n, n)
+        x = torch.empty(n, dtype=torch.float64, device=self.device)
+        status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _check(lib().minsr_solve(self.handle, n, _ptr(T), float(lam), float(pinv_cutoff), _ptr(b),
+                                 _ptr(x), _ptr(status), _stream()))
+        return x, status
+
     # ------------------------------------------------------------ one step
     def step(self, ham, Ns, eta, lam, mu, momentum, key, counter, form=FORM_FP64_REF,
              pinv_cutoff=0.0, ckpt_every=1, apply_update=True, outputs=None, dev_counter=None):
@@ -261,6 +284,14 @@ class Model:
                     eloc=torch.empty((Ns, 2), dtype=torch.float64, device=dev),
                     sigma=torch.empty((Ns, self.N), dtype=torch.uint8, device=dev))
 
+    def set_tunable(self, key, value):
+        _check(lib().minsr_set_tunable(self.handle, key.encode(), int(value)))
+
+    def get_tunable(self, key):
+        v = ctypes.c_int()
+        _check(lib().minsr_get_tunable(self.handle, key.encode(), ctypes.byref(v)))
+        return v.value
+
     def timing_begin(self, max_steps):
         _check(lib().minsr_timing_begin(self.handle, max_steps))
 
@@ -289,6 +320,59 @@ class Model:
         if form == FORM_BF16_FP64:   # low halves follow the high halves
             out["Oprime_lo"] = _from_ptr(O.value + n * Np * 2, (n, Np), odt)[:, :self.Np]
         return out
+
+
+class Batch:
+    """Independent minSR instances stepped together by one hip graph.
+
+    `instances` is a list of dicts with keys model, ham, Ns, eta, lam, mu,
+    key and optionally form, pinv_cutoff, ckpt_every.  The batch owns each
+    instance's momentum, device Philox counter and output tensors
+    (`self.outputs[i]`, `self.momentum[i]`, `self.counters[i]`)."""
+
+    def __init__(self, instances):
+        n = len(instances)
+        self.instances = instances
+        self.momentum, self.counters, self.outputs = [], [], []
+        models = (ctypes.c_void_p * n)()
+        hams = (Hamiltonian * n)()
+        cfgs = (StepCfg * n)()
+        states = (StepState * n)()
+        outs = (StepOut * n)()
+        for i, inst in enumerate(instances):
+            m = inst["model"]
+            mom = torch.zeros(m.Np, dtype=torch.float64, device=m.device)
+            ctr = torch.zeros(1, dtype=torch.int64, device=m.device)
+            o = m.step_outputs(inst["Ns"])
+            self.momentum.append(mom)
+            self.counters.append(ctr)
+            self.outputs.append(o)
+            models[i] = m.handle.value
+            hams[i] = inst["ham"]
+            cfgs[i] = StepCfg(inst["Ns"], inst.get("form", FORM_FP64_REF), inst["eta"],
+                              inst["lam"], inst["mu"], inst.get("pinv_cutoff", 0.0),
+                              inst.get("ckpt_every", 1), 1)
+            states[i] = StepState(mom.data_ptr(), inst["key"], 0, ctr.data_ptr())
+            outs[i] = StepOut(o["energy"].data_ptr(), o["dtheta"].data_ptr(),
+                              o["status"].data_ptr(), o["eloc"].data_ptr(), o["sigma"].data_ptr())
+        h = ctypes.c_void_p()
+        _check(lib().minsr_batch_create(models, hams, cfgs, states, outs, n, ctypes.byref(h)))
+        self.handle = h
+        self._keep = (models, hams, cfgs, states, outs)
+
+    def step(self):
+        _check(lib().minsr_batch_step(self.handle, _stream()))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().minsr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _from_ptr(addr, shape, dtype):

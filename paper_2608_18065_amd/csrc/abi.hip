@@ -74,7 +74,7 @@ static void release(minsr_model* m) {
   void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->site, m->contrib,
                   m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
                   m->colpart, m->colmean, m->T, m->Lf, m->Dinv, m->gpart, m->epsp, m->x, m->vwork,
-                  m->dpart, m->dtheta, m->status, m->eig};
+                  m->dpart, m->dtheta, m->status, m->eig, m->csync};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : m->ev) (void)hipEventDestroy(e);
@@ -192,6 +192,7 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   rc = rc ? rc : alloc((void**)&m->epsp, rows * 8);
   rc = rc ? rc : alloc((void**)&m->x, rows * 8);
   rc = rc ? rc : alloc((void**)&m->vwork, rows * 8);
+  rc = rc ? rc : alloc((void**)&m->csync, chol_sync_words((int)rows) * 4);
   rc = rc ? rc : alloc((void**)&m->dpart, ((rows + 63) / 64) * Np * 8);
   rc = rc ? rc : alloc((void**)&m->dtheta, Np * 8);
   rc = rc ? rc : alloc((void**)&m->status, 16);
@@ -362,6 +363,10 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   if (!(cfg->lambda >= 0.0) || !(cfg->pinv_cutoff >= 0.0)) return fail(MINSR_E_INVALID_ARG, "negative lambda / cutoff");
   if (cfg->pinv_cutoff == 0.0 && cfg->lambda == 0.0)
     return fail(MINSR_E_INVALID_ARG, "lambda = 0 needs the pseudo-inverse (T is singular)");
+  if (cfg->pinv_cutoff > 0.0 && cfg->lambda != 0.0)
+    return fail(MINSR_E_INVALID_ARG, "the pseudo-inverse solve takes lambda = 0");
+  if (cfg->pinv_cutoff > 0.0 && cfg->form == MINSR_FORM_FP32_PLAIN)
+    return fail(MINSR_E_UNSUPPORTED, "the pseudo-inverse solve runs in FP64 only");
   if (cfg->form == MINSR_FORM_FP64_REF && !m->f64)
     return fail(MINSR_E_INVALID_ARG, "the FP64 reference form needs an FP64 model");
   const int C = m->dim == 1 ? cfg->ckpt_every : 1;
@@ -413,10 +418,12 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   if (rc) return rc;
   MINSR_PHASE(5);
   // 4. Gram and regularised solve
-  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 1, Rlo);
+  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 1, Rlo,
+                   m->tune_gram_split);
   if (rc) return rc;
   MINSR_PHASE(6);
-  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 2, Rlo);
+  rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 2, Rlo,
+                   m->tune_gram_split);
   if (rc) return rc;
   MINSR_PHASE(7);
   if (cfg->pinv_cutoff > 0.0)
@@ -424,7 +431,7 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
                            out->dev_status, s);
   else
     rc = launch_cholesky_solve(n, m->T, m->Lf, m->Dinv, rdt == MINSR_F32, cfg->lambda, m->epsp,
-                               m->x, out->dev_status, s);
+                               m->x, m->vwork, m->csync, out->dev_status, s);
   if (rc) return rc;
   MINSR_PHASE(8);
   // 5. dtheta = eta O' x, momentum, parameters, working copy
@@ -479,6 +486,34 @@ int minsr_timing_read(minsr_model* m, double* ms, int* nsteps) {
   return MINSR_OK;
 }
 
+int minsr_set_tunable(minsr_model* m, const char* key, int value) {
+  if (!m || !key) return fail(MINSR_E_INVALID_ARG, "null argument");
+  const std::string k(key);
+  if (k == "gram_split") {
+    if (value < 0 || value > 64) return fail(MINSR_E_INVALID_ARG, "gram_split in [0, 64]");
+    m->tune_gram_split = value;
+  } else if (k == "eloc_grid") {
+    if (value < 0 || value > (1 << 20)) return fail(MINSR_E_INVALID_ARG, "eloc_grid out of range");
+    m->tune_eloc_grid = value;
+  } else if (k == "sample_r") {
+    if (value != 0 && value != 1 && value != 4) return fail(MINSR_E_INVALID_ARG, "sample_r in {0, 1, 4}");
+    m->tune_sample_r = value;
+  } else {
+    return fail(MINSR_E_INVALID_ARG, "unknown tunable " + k);
+  }
+  return MINSR_OK;
+}
+
+int minsr_get_tunable(const minsr_model* m, const char* key, int* value) {
+  if (!m || !key || !value) return fail(MINSR_E_INVALID_ARG, "null argument");
+  const std::string k(key);
+  if (k == "gram_split") *value = m->tune_gram_split;
+  else if (k == "eloc_grid") *value = m->tune_eloc_grid;
+  else if (k == "sample_r") *value = m->tune_sample_r;
+  else return fail(MINSR_E_INVALID_ARG, "unknown tunable " + k);
+  return MINSR_OK;
+}
+
 int minsr_step_intermediates(minsr_model* m, const void** T, const double** x,
                              const double** eps_prime, const void** Oprime, int* n, int* Np) {
   if (!m) return fail(MINSR_E_INVALID_ARG, "null model");
@@ -491,4 +526,139 @@ int minsr_step_intermediates(minsr_model* m, const void** T, const double** x,
   return MINSR_OK;
 }
 
+int minsr_solve(minsr_model* m, int n, const double* dev_T, double lambda, double pinv_cutoff,
+                const double* dev_b, double* dev_x, uint32_t* dev_status, hipStream_t s) {
+  if (!m || !dev_T || !dev_b || !dev_x || !dev_status)
+    return fail(MINSR_E_INVALID_ARG, "null argument");
+  const int rows_max = (m->cplx ? 2 : 1) * m->d.max_Ns;
+  if (n < 0 || n > rows_max)
+    return fail(MINSR_E_SHAPE, "n = " + std::to_string(n) + " outside [0, " +
+                                   std::to_string(rows_max) + "]");
+  if (!(lambda >= 0.0) || !(pinv_cutoff >= 0.0))
+    return fail(MINSR_E_INVALID_ARG, "negative lambda / cutoff");
+  if (pinv_cutoff > 0.0) {
+    if (lambda != 0.0) return fail(MINSR_E_INVALID_ARG, "the pseudo-inverse solve takes lambda = 0");
+    return launch_pinv_solve(n, const_cast<double*>(dev_T), pinv_cutoff, dev_b, dev_x, m->eig,
+                             m->eig_elems, dev_status, s);
+  }
+  return launch_cholesky_solve(n, dev_T, m->Lf, m->Dinv, 0, lambda, dev_b, dev_x, m->vwork,
+                               m->csync, dev_status, s);
+}
+
+// ------------------------------------------------------------------ batch
+}  // extern "C"
+
+struct minsr_batch {
+  std::vector<minsr_model*> models;
+  std::vector<minsr_hamiltonian> hams;
+  std::vector<minsr_step_cfg> cfgs;
+  std::vector<minsr_step_state> states;
+  std::vector<minsr_step_out> outs;
+  std::vector<hipStream_t> streams;  // [i] instance i, [count] capture origin
+  std::vector<hipEvent_t> events;   // [0] fork, [1 + i] join of instance i
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void batch_release(minsr_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+  b->exec = nullptr; b->graph = nullptr;
+  b->events.clear(); b->streams.clear();
+}
+
+extern "C" {
+
+int minsr_batch_create(minsr_model* const* models, const minsr_hamiltonian* hams,
+                       const minsr_step_cfg* cfgs, const minsr_step_state* states,
+                       const minsr_step_out* outs, int count, minsr_batch** out) {
+  if (!models || !hams || !cfgs || !states || !outs || !out || count < 1)
+    return fail(MINSR_E_INVALID_ARG, "null argument or empty batch");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    if (!models[i]) return fail(MINSR_E_INVALID_ARG, "null model in batch");
+    if (!states[i].dev_counter)
+      return fail(MINSR_E_INVALID_ARG, "batch instances need a device-side Philox counter");
+    for (int j = 0; j < i; ++j)
+      if (models[j] == models[i]) return fail(MINSR_E_INVALID_ARG, "a model appears twice in a batch");
+  }
+  minsr_batch* b = new (std::nothrow) minsr_batch();
+  if (!b) return fail(MINSR_E_NOMEM, "host allocation failed");
+  b->models.assign(models, models + count);
+  b->hams.assign(hams, hams + count);
+  b->cfgs.assign(cfgs, cfgs + count);
+  b->states.assign(states, states + count);
+  b->outs.assign(outs, outs + count);
+  // one stream per instance plus a library-owned origin stream for the
+  // capture (the caller's stream may be the legacy null stream, which
+  // cannot be captured; the instantiated graph is launched on it instead)
+  for (int i = 0; i <= count; ++i) {
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      batch_release(b); delete b;
+      return fail(MINSR_E_DEVICE, "stream creation failed");
+    }
+    b->streams.push_back(st);
+  }
+  for (int i = 0; i <= count; ++i) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      batch_release(b); delete b;
+      return fail(MINSR_E_DEVICE, "event creation failed");
+    }
+    b->events.push_back(e);
+  }
+  *out = b;
+  return MINSR_OK;
+}
+
+static int batch_capture(minsr_batch* b) {
+  hipStream_t s = b->streams.back();
+  MINSR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = MINSR_OK;
+  if (hipEventRecord(b->events[0], s) != hipSuccess) rc = fail(MINSR_E_DEVICE, "fork record failed");
+  for (size_t i = 0; i < b->models.size() && !rc; ++i) {
+    minsr_model* m = b->models[i];
+    const int t_max = m->t_max;
+    m->t_max = 0;   // no event timing inside the graph
+    if (hipStreamWaitEvent(b->streams[i], b->events[0], 0) != hipSuccess)
+      rc = fail(MINSR_E_DEVICE, "fork wait failed");
+    if (!rc) rc = minsr_step(m, &b->hams[i], &b->cfgs[i], &b->states[i], &b->outs[i], b->streams[i]);
+    m->t_max = t_max;
+    if (!rc && hipEventRecord(b->events[1 + i], b->streams[i]) != hipSuccess)
+      rc = fail(MINSR_E_DEVICE, "join record failed");
+    if (!rc && hipStreamWaitEvent(s, b->events[1 + i], 0) != hipSuccess)
+      rc = fail(MINSR_E_DEVICE, "join wait failed");
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess || !g) return fail(MINSR_E_DEVICE, "graph capture failed");
+  b->graph = g;
+  MINSR_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return MINSR_OK;
+}
+
+int minsr_batch_step(minsr_batch* b, hipStream_t s) {
+  if (!b) return fail(MINSR_E_INVALID_ARG, "null batch");
+  if (!b->exec) {
+    int rc = batch_capture(b);
+    if (rc) return rc;
+  }
+  MINSR_HIP(hipGraphLaunch(b->exec, s));
+  return MINSR_OK;
+}
+
+int minsr_batch_destroy(minsr_batch* b) {
+  if (!b) return fail(MINSR_E_INVALID_ARG, "null batch");
+  (void)hipDeviceSynchronize();
+  batch_release(b);
+  delete b;
+  return MINSR_OK;
+}
 }  // extern "C"

@@ -667,11 +667,12 @@ static int forward_t(minsr_model* m, const Work<T>& w, int mode, int Ns, const d
   if (mode == MODE_SAMPLE) a.sigma_out = sigma; else a.sigma_in = sigma;
   a.logpsi = logpsi;
   a.states = (T*)states; a.store_every = store_every; a.site = site;
-  // few sequences per block: the site loop is latency-bound
-  const int R = 1;
+  // few sequences per block by default: the site loop is latency-bound
+  const int R = m->tune_sample_r == 4 ? 4 : 1;
   const int B = seqs_per_block(m->H, R);
   a.nchunks = (Ns + B - 1) / B;
   a.n_items = a.nchunks;
+  if (R == 4) return dispatch_dim<T, 4>(m, a, (unsigned)a.n_items, s);
   return dispatch_dim<T, 1>(m, a, (unsigned)a.n_items, s);
 }
 
@@ -745,6 +746,7 @@ static int eloc_t(minsr_model* m, const Work<T>& w, const minsr_hamiltonian* H, 
   a.nchunks = (Ns + B - 1) / B;
   a.n_items = a.nchunks * M;
   unsigned grid = (unsigned)a.n_items;
+  if (m->tune_eloc_grid > 0) grid = std::min<unsigned>(grid, (unsigned)m->tune_eloc_grid);
   if (m->dim == 2) {
     // the recompute windows are indexed by block: a persistent grid
     int cap = m->ring_blocks / B;

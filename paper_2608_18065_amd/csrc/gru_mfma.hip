@@ -284,6 +284,7 @@ int launch_eloc_mfma(minsr_model* m, const minsr_hamiltonian* H, int Ns, const u
   a.hx = H->h; a.J1 = H->J; a.J2 = H->J2; a.contrib = m->contrib; a.ring = (float*)m->ring;
   if (a.n_items == 0) return MINSR_OK;
   unsigned grid = (unsigned)a.n_items;
+  if (m->tune_eloc_grid > 0) grid = std::min<unsigned>(grid, (unsigned)m->tune_eloc_grid);
   if (m->dim == 2) {
     const int cap = m->ring_blocks / 32;
     if (cap < 1) return fail(MINSR_E_SHAPE, "recompute window too small");

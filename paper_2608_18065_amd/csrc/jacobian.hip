@@ -81,6 +81,9 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
   __shared__ T pbuf[SG][P][2][H];                      // partial sums of reverse products
   __shared__ T dacc[DIM == 2 ? SG : 1][WMAX][H];       // 2D adjoint window
   __shared__ T red[NT / 64][4];
+  constexpr int RCH = H < 16 ? H : 16;                  // rows per output chunk
+  constexpr int TPS = H * P;                            // threads per sample
+  __shared__ T stg[SG][RCH][H + 4];                     // output staging
 
   const int tid = threadIdx.x;
   const int sg = tid / (H * P);
@@ -149,6 +152,7 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
             ar += w.xc[(1 * ds + sprev) * H + j];
             ai += w.xc[(2 * ds + sprev) * H + j];
           }
+#pragma unroll 2
           for (int k4 = 0; k4 < H / V; ++k4) {
             const VT wu = fw[(k4 * H + j) * 3 + 0];
             const VT wr = fw[(k4 * H + j) * 3 + 1];
@@ -229,6 +233,7 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
           }
           __syncthreads();
           T hin = (T)0;
+#pragma unroll 2
           for (int k4 = 0; k4 < H / V; ++k4) {
             const VT w1 = f2[(k4 * H + j) * 2 + 0];
             const VT w2 = f2[(k4 * H + j) * 2 + 1];
@@ -256,6 +261,7 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
             ar += w.xc[(1 * ds + 2 + sv) * H + j];
             ai += w.xc[(2 * ds + 2 + sv) * H + j];
           }
+#pragma unroll 2
           for (int k4 = 0; k4 < H / V; ++k4) {
             const VT wu = fw[(k4 * H + j) * 3 + 0];
             const VT wr = fw[(k4 * H + j) * 3 + 1];
@@ -365,7 +371,7 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
         __syncthreads();
         // reverse product into the cell input: rows i of part p
         T part = (T)0;
-#pragma unroll 4
+#pragma unroll 1
         for (int i4 = p * CP / V; i4 < (p + 1) * CP / V; ++i4) {
           const VT wu = bw[(i4 * H + j) * 3 + 0];
           const VT wr = bw[(i4 * H + j) * 3 + 1];
@@ -419,7 +425,7 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
           }
           __syncthreads();
           T ph = (T)0, pv = (T)0;
-#pragma unroll 4
+#pragma unroll 1
           for (int i4 = p * CP / V; i4 < (p + 1) * CP / V; ++i4) {
             const VT w1 = b2[(i4 * H + j) * 2 + 0];
             const VT w2 = b2[(i4 * H + j) * 2 + 1];
@@ -452,31 +458,41 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
       }
     }
 
-    // ---- write this thread's share of the row
-    if (act) {
+    // ---- write the row: each gradient matrix goes through LDS in chunks of
+    // RCH rows so that the workgroup's stores cover contiguous memory
+    {
       const Layout& L = a.L;
       const size_t row = (size_t)seed * a.Ns + s;
       T* o = a.O + row * Np;
       const T sc = a.scale;
-      const int ldu = H + ds;
-#pragma unroll
-      for (int c = 0; c < CP; ++c) {
-        const int col = p * CP + c;
-        o[L.Wu + (size_t)j * ldu + col] = gWu[c] * sc;
-        o[L.Wr + (size_t)j * ldu + col] = gWr[c] * sc;
-        o[L.Wh + (size_t)j * H + col] = gWh[c] * sc;
-        if (DIM == 2) {
-          o[L.U1 + (size_t)j * H + col] = gU1[c] * sc;
-          o[L.U2 + (size_t)j * H + col] = gU2[c] * sc;
-        }
+      const int tps_id = p * H + j;
+#define MINSR_JAC_STAGE(ARR, XS, NX, OFF, LD)                                              \
+      for (int j0 = 0; j0 < H; j0 += RCH) {                                                \
+        if (j >= j0 && j < j0 + RCH) {                                                     \
+          _Pragma("unroll") for (int c = 0; c < CP; ++c) stg[sg][j - j0][p * CP + c] = ARR[c]; \
+          if ((NX) > 0 && p == 0) {                                                        \
+            _Pragma("unroll") for (int c = 0; c < (NX); ++c) stg[sg][j - j0][H + c] = XS[c]; \
+          }                                                                                \
+        }                                                                                  \
+        __syncthreads();                                                                   \
+        if (act) {                                                                         \
+          const int tot = RCH * (LD);                                                      \
+          for (int e = tps_id; e < tot; e += TPS)                                          \
+            o[(OFF) + (size_t)j0 * (LD) + e] = stg[sg][e / (LD)][e % (LD)] * sc;          \
+        }                                                                                  \
+        __syncthreads();                                                                   \
       }
-      if (p == 0) {
+      MINSR_JAC_STAGE(gWu, gxu, ds, L.Wu, H + ds)
+      MINSR_JAC_STAGE(gWr, gxr, ds, L.Wr, H + ds)
+      MINSR_JAC_STAGE(gWh, gxu, 0, L.Wh, H)
+      if constexpr (DIM == 2) {
+        MINSR_JAC_STAGE(gU1, gxu, 0, L.U1, H)
+        MINSR_JAC_STAGE(gU2, gxu, 0, L.U2, H)
+      }
+#undef MINSR_JAC_STAGE
+      if (act && p == 0) {
 #pragma unroll
-        for (int c = 0; c < ds; ++c) {
-          o[L.Wu + (size_t)j * ldu + H + c] = gxu[c] * sc;
-          o[L.Wr + (size_t)j * ldu + H + c] = gxr[c] * sc;
-          o[L.Win + (size_t)j * ds + c] = gxi[c] * sc;
-        }
+        for (int c = 0; c < ds; ++c) o[L.Win + (size_t)j * ds + c] = gxi[c] * sc;
         o[L.bu + j] = gbu * sc; o[L.br + j] = gbr * sc;
         o[L.bh + j] = gbh * sc; o[L.bin + j] = gbi * sc;
         const size_t hU = seed == 0 ? L.U : L.Uphi;
@@ -510,7 +526,7 @@ static int jac_dispatch(int H, const JacArgs<T>& a, hipStream_t s) {
     case 8: return launch_jac_t<T, 8, DIM, 1>(a, s);
     case 16: return launch_jac_t<T, 16, DIM, 1>(a, s);
     case 32: return launch_jac_t<T, 32, DIM, 1>(a, s);
-    case 64: return launch_jac_t<T, 64, DIM, DIM == 1 ? 1 : 2>(a, s);
+    case 64: return launch_jac_t<T, 64, DIM, DIM == 1 ? 1 : 4>(a, s);
     case 128: return launch_jac_t<T, 128, DIM, DIM == 1 ? 2 : 4>(a, s);
   }
   return fail(MINSR_E_UNSUPPORTED, "hidden width must be 8, 16, 32, 64 or 128");

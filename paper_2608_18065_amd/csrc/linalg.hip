@@ -322,36 +322,41 @@ __global__ void k_gram_reduce(const TA* part, int npairs, int nsplit, int tile, 
   T[(size_t)c * n + r] = (TT)s;
 }
 
-static int pick_split(int npairs, size_t Np, int kgran) {
-  int S = (1024 + npairs - 1) / npairs;
-  int maxS = (int)std::max<size_t>(1, Np / 512);
-  S = std::max(1, std::min(S, maxS));
-  (void)kgran;
-  return S;
+constexpr int MAX_SPLIT = 64;
+
+// split-K factor: requested, else enough for ~1024 workgroups; at most
+// MAX_SPLIT, 4096 workgroups in total, and chunks of >= 256 columns
+static int pick_split(int npairs, size_t Np, int want) {
+  int S = want > 0 ? want : (1024 + npairs - 1) / npairs;
+  const int by_grid = std::max(1, (4096 + npairs - 1) / npairs);
+  int maxS = (int)std::max<size_t>(1, std::min<size_t>(MAX_SPLIT, Np / 256));
+  maxS = std::min(maxS, by_grid);
+  return std::max(1, std::min(S, maxS));
 }
 
+// workspace for the largest split any setting may request
 size_t gram_partial_bytes(int n, size_t Np, int dtype) {
   const int tile = dtype == MINSR_BF16 ? GT : VT_;
   const int nt = (n + tile - 1) / tile;
   const int npairs = nt * (nt + 1) / 2;
-  const int S = pick_split(npairs, Np, 0);
+  const int S = std::max(pick_split(npairs, Np, 0), pick_split(npairs, Np, MAX_SPLIT));
   const size_t el = dtype == MINSR_F64 ? 8 : 4;
   return (size_t)S * npairs * tile * tile * el;
 }
 
 int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gpart,
-                size_t gpart_elems, hipStream_t s, int which, const void* Rlo) {
+                size_t gpart_elems, hipStream_t s, int which, const void* Rlo, int want_split) {
   // R rows have the padded stride ld = round_up(Np, 64); the padding is zero
   const size_t ld = (Np + 63) / 64 * 64;
   if (n == 0) return MINSR_OK;
   const int tile = dtype == MINSR_BF16 ? GT : VT_;
   const int nt = (n + tile - 1) / tile;
   const int npairs = nt * (nt + 1) / 2;
-  const int S = pick_split(npairs, Np, 0);
+  const int S = pick_split(npairs, Np, want_split);
   const size_t kgran = dtype == MINSR_BF16 ? 64 : VK;
   size_t kchunk = (ld + S - 1) / S;
   kchunk = (kchunk + kgran - 1) / kgran * kgran;
-  const size_t need = gram_partial_bytes(n, Np, dtype);
+  const size_t need = (size_t)S * npairs * tile * tile * (dtype == MINSR_F64 ? 8 : 4);
   if (need > gpart_elems * sizeof(float)) return fail(MINSR_E_SHAPE, "Gram workspace too small");
   dim3 grid((unsigned)npairs, (unsigned)S);
   dim3 rgrid((unsigned)((tile * tile + 255) / 256), (unsigned)npairs);
@@ -385,281 +390,332 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
 }
 
 // ============================================================= Cholesky
-// Right-looking blocked Cholesky of A = T + lambda I (lower, row-major,
-// block 64) into a separate buffer, so T survives.  Each diagonal block is
-// factored by one wavefront (lane r holds row r), which also forms the
-// block's inverse; panels below are multiplied by that inverse (a small
-// GEMM instead of a sequential substitution); the trailing update of the
-// lower tiles also factors the next diagonal block.  The triangular solves
-// reuse the stored block inverses.
+// Right-looking tiled Cholesky of A = T + lambda I (lower, row-major, tiles
+// of 64) into a separate buffer, so T survives, with the forward
+// substitution L y = b folded in.  One launch per block column k:
+//   every workgroup updates one trailing tile A_ij -= L_ik L_jk^T (i >= j > k);
+//   the workgroup of the next diagonal tile then factors it, forms the
+//   inverse of its factor and the block y_{k+1} = inv(L) b_{k+1}, and
+//   publishes them through a flag;
+//   the workgroups of the tiles below it wait for the flag, finish their
+//   panel tile L_i,k+1 = A_i,k+1 inv(L_k+1,k+1)^T and subtract
+//   L_i,k+1 y_k+1 from their block of b.
+// Roles come from a ticket taken when a workgroup starts, so the ticket-0
+// workgroup (the factoring one) is resident before anyone waits on it.
+// The backward substitution L^T x = y runs last, with the stored inverses.
 constexpr int CB = 64;
 
-// factor the 64 x 64 tile held in LDS (rows < nb valid; the lower triangle
-// is read), write L to A and inv(L) to Dinv.  Executed by the first
-// wavefront of a workgroup only: lane r keeps row r in registers; at column
-// c the pivot column is published through LDS, read back by every lane in
-// one batch of 16-byte loads, and applied as a rank-1 update to its row.
-template <typename TT>
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+// 1/sqrt(d) from the hardware estimate and Newton steps
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-(d * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float d) {
+  float y = __builtin_amdgcn_rsqf(d);
+  const float e = fmaf(-(d * y), y, 1.0f);
+  return fmaf(0.5f * y, e, y);
 }
 
+// Factor the tile in Ls (rows < nb valid, lower triangle read) with the
+// first two wavefronts of the workgroup; every thread of the workgroup must
+// call it.  Wave 0 keeps row `lane` of the tile in registers and performs
+// the column sweep; wave 1 keeps column `lane` of inv(L) and eliminates with
+// each finished column one barrier later.  Writes L to A and inv(L)
+// (row-major, zero above the diagonal) to Di and to the shared tile Is.
 template <typename TT>
-__device__ __forceinline__ void factor_tile(TT (*Ls)[CB + 1], int nb, TT* A, int n, int k0,
-                                            TT* Dinv, uint32_t* status) {
-  const int r = threadIdx.x;   // 0..63
-  __shared__ __align__(16) TT colc[CB];
-  __shared__ __align__(16) TT Lrow[CB][CB];
-  TT a[CB];
+__device__ void factor_block(const TT (*Ls)[CB + 1], TT (*Lc)[CB], TT* rd, TT (*Is)[CB + 1],
+                             int nb, TT* A, int n, int k0, TT* Di, uint32_t* status) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  TT v[CB];
+  if (wave == 0) {
 #pragma unroll
-  for (int q = 0; q < CB; ++q) a[q] = (q <= r && r < nb) ? Ls[r][q] : (r == q ? (TT)1 : (TT)0);
+    for (int q = 0; q < CB; ++q)
+      v[q] = (q <= lane && lane < nb) ? Ls[lane][q] : (lane == q ? (TT)1 : (TT)0);
+  } else {
+#pragma unroll
+    for (int q = 0; q < CB; ++q) v[q] = (q == lane) ? (TT)1 : (TT)0;
+  }
   bool bad = false;
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
-    if (c < nb) {
-      TT d = __shfl(a[c], c, 64);
+    TT lc = (TT)0;
+    if (wave == 0) {
+      TT d = lane_bcast(v[c], c);
       if (!(d > (TT)0)) { bad = true; d = (TT)1; }
-      const TT piv = sqrt(d);
-      const TT rp = (TT)1 / piv;
-      if (r == c) a[c] = piv;
-      else if (r > c) a[c] = a[c] * rp;
-      colc[r] = a[c];
-      wave_sync_lds<TT>();
-      const int Q0 = ((c + 1) / 2) * 2;   // even start: 16-byte aligned reads
+      const TT rp = rsqrt_nr(d);
+      lc = (lane == c) ? d * rp : v[c] * rp;
+      Lc[c][lane] = lc;
+      if (lane == 0) rd[c] = rp;
+    }
+    __syncthreads();
+    if (wave < 2) {
+      // the finished column, read in one batch of 16-byte loads
       TT cv[CB];
+      constexpr int VW = 16 / sizeof(TT);
+      using vec_t = typename std::conditional<sizeof(TT) == 8, double2, float4>::type;
+      const int Q0 = ((c + 1) / VW) * VW;
 #pragma unroll
-      for (int q = Q0; q < CB; q += 2) {
-        const auto v2 = *reinterpret_cast<const typename std::conditional<sizeof(TT) == 8, double2, float2>::type*>(&colc[q]);
-        cv[q] = v2.x; cv[q + 1] = v2.y;
+      for (int q = Q0; q < CB; q += VW) {
+        const vec_t t = *reinterpret_cast<const vec_t*>(&Lc[c][q]);
+        const TT* tp = reinterpret_cast<const TT*>(&t);
+#pragma unroll
+        for (int u = 0; u < VW; ++u) cv[q + u] = tp[u];
       }
-      if (r > c) {
-        const TT nl = -a[c];
+      if (wave == 0) {
+        v[c] = lc;
+        const TT nl = lane > c ? -lc : (TT)0;
 #pragma unroll
-        for (int q = c + 1; q < CB; ++q) a[q] = fma(nl, cv[q], a[q]);
+        for (int q = c + 1; q < CB; ++q) v[q] = fma(nl, cv[q], v[q]);
+      } else {
+        const TT z = v[c] * rd[c];
+        v[c] = z;
+#pragma unroll
+        for (int q = c + 1; q < CB; ++q) v[q] = fma(-cv[q], z, v[q]);
       }
-      wave_sync_lds<TT>();
     }
   }
-  if (bad && r == 0 && status) atomicOr(status, MINSR_ST_NOT_PD);
-  // write L and publish its rows for the inverse
+  if (wave == 0) {
+    if (bad && lane == 0 && status) atomicOr(status, MINSR_ST_NOT_PD);
+    if (lane < nb) {
 #pragma unroll
-  for (int q = 0; q < CB; ++q) {
-    const TT v = (q <= r && r < nb) ? a[q] : (r == q ? (TT)1 : (TT)0);
-    Lrow[r][q] = v;
-    if (q <= r && r < nb) A[(size_t)(k0 + r) * n + k0 + q] = v;
-  }
-  wave_sync_lds<TT>();
-  // inv(L): lane c solves L z = e_c (z_i = 0 for i < c); row i of L is
-  // read in one batch, the dot product uses four partial sums
-  const int c = r;
-  TT z[CB];
-#pragma unroll
-  for (int i = 0; i < CB; ++i) {
-    TT li[CB];
-#pragma unroll
-    for (int q = 0; q < i + 1; q += 2) {
-      const auto v2 = *reinterpret_cast<const typename std::conditional<sizeof(TT) == 8, double2, float2>::type*>(&Lrow[i][q]);
-      li[q] = v2.x; li[q + 1] = v2.y;
+      for (int q = 0; q < CB; ++q)
+        if (q <= lane) A[(size_t)(k0 + lane) * n + k0 + q] = v[q];
     }
-    TT p0 = (i == c) ? (TT)1 : (TT)0, p1 = 0, p2 = 0, p3 = 0;
+  } else if (wave == 1) {
+    // lane c holds column c of inv(L): rows i < c are zero
 #pragma unroll
-    for (int q = 0; q < i; ++q) {
-      const TT t = -li[q] * z[q];
-      if ((q & 3) == 0) p0 += t; else if ((q & 3) == 1) p1 += t;
-      else if ((q & 3) == 2) p2 += t; else p3 += t;
+    for (int i = 0; i < CB; ++i) {
+      const TT w = (i < nb && lane < nb) ? v[i] : (TT)0;
+      Di[(size_t)i * CB + lane] = w;
+      Is[i][lane] = w;
     }
-    z[i] = ((p0 + p1) + (p2 + p3)) / li[i];
   }
-#pragma unroll
-  for (int i = 0; i < CB; ++i) Dinv[(size_t)i * CB + c] = (i < nb && c < nb) ? z[i] : (TT)0;
 }
 
-template <typename TT>
-__global__ __launch_bounds__(64) void k_chol_diag(TT* A, int n, int kb, TT* Dinv, uint32_t* status) {
-  __shared__ TT Ls[CB][CB + 1];
-  const int k0 = kb * CB, nb = min(CB, n - k0);
-  {
-    // lane q reads column q of every row: 64 independent coalesced loads
-    const int q = threadIdx.x;
-    TT v[CB];
-#pragma unroll
-    for (int r = 0; r < CB; ++r) v[r] = (r < nb && q < nb) ? A[(size_t)(k0 + r) * n + k0 + q] : (TT)0;
-#pragma unroll
-    for (int r = 0; r < CB; ++r) Ls[r][q] = v[r];
-  }
-  __syncthreads();
-  factor_tile<TT>(Ls, nb, A, n, k0, Dinv + (size_t)kb * CB * CB, status);
-}
+struct CholArgs {
+  const void* T;        // source matrix (read while a tile is first touched)
+  void* A;              // factor
+  void* Dinv;           // [nblk][64][64]
+  void* y;              // [n] right-hand side, overwritten by L^-1 b block by block
+  uint32_t* sync;       // [2][nblk + 1]: tickets, then flags
+  uint32_t* status;
+  double lambda;
+  int n, nblk;
+};
 
-// panel rows below the diagonal block: A_ik <- A_ik inv(L_kk)^T
+// Block column k of the factorisation (k = -1: the first block column,
+// read straight from T).
 template <typename TT>
-__global__ __launch_bounds__(256) void k_chol_panel(TT* A, int n, int kb, const TT* Dinv) {
-  __shared__ TT As[CB][CB + 1];
-  __shared__ TT Is[CB][CB + 1];
-  const int k0 = kb * CB, nb = min(CB, n - k0);
-  const int r0 = k0 + nb + blockIdx.x * CB;
-  const TT* Di = Dinv + (size_t)kb * CB * CB;
-  const int tid = threadIdx.x;
-  {
-    TT va[CB * CB / 256], vi[CB * CB / 256];
-#pragma unroll
-    for (int i = 0; i < CB * CB / 256; ++i) {
-      const int e = tid + 256 * i, r = e / CB, q = e % CB;
-      va[i] = (r0 + r < n && q < nb) ? A[(size_t)(r0 + r) * n + k0 + q] : (TT)0;
-      vi[i] = Di[e];
-    }
-#pragma unroll
-    for (int i = 0; i < CB * CB / 256; ++i) {
-      const int e = tid + 256 * i, r = e / CB, q = e % CB;
-      As[r][q] = va[i];
-      Is[r][q] = vi[i];
-    }
-  }
-  __syncthreads();
-  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
-  TT acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (TT)0;
-#pragma unroll 4
-  for (int q = 0; q < CB; ++q) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = fma(As[tr + a][q], Is[tc + b][q], acc[a][b]);
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int r = r0 + tr + a, c = tc + b;
-      if (r < n && c < nb) A[(size_t)r * n + k0 + c] = acc[a][b];
-    }
-}
-
-// trailing update A_ij -= L_ik L_jk^T for the lower tiles i >= j > k; the
-// workgroup of the first diagonal tile then factors it
-template <typename TT>
-__global__ __launch_bounds__(256) void k_syrk_trail(TT* A, int n, int kb, TT* Dinv,
-                                                    uint32_t* status) {
+__global__ __launch_bounds__(256) void k_chol_step(CholArgs a, int k) {
   __shared__ TT Li[CB][CB + 1];
   __shared__ TT Lj[CB][CB + 1];
-  const int k0 = kb * CB;
-  const int nb = min(CB, n - k0);
-  const int base = kb + 1;
+  __shared__ __align__(16) TT Lc[CB][CB];
+  __shared__ TT rd[CB];
+  __shared__ TT yb[CB];
+  __shared__ int tk;
+  const int n = a.n, tid = threadIdx.x;
+  TT* A = reinterpret_cast<TT*>(a.A);
+  const TT* Tm = reinterpret_cast<const TT*>(a.T);
+  TT* y = reinterpret_cast<TT*>(a.y);
+  uint32_t* tickets = a.sync;
+  uint32_t* flags = a.sync + (a.nblk + 1);
+  const int kk = k + 1;                  // block column being finished
+  if (tid == 0)
+    tk = (int)__hip_atomic_fetch_add(&tickets[kk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int ticket = tk;
   int ti, tj;
-  pair_decode(blockIdx.x, ti, tj);
-  ti += base; tj += base;
+  if (k < 0) { ti = ticket; tj = 0; }
+  else { pair_decode(ticket, ti, tj); ti += kk; tj += kk; }
   const int r0 = ti * CB, c0 = tj * CB;
-  const int tid = threadIdx.x;
-  {
-    TT vi[CB * CB / 256], vj[CB * CB / 256];
+  const bool fresh = k <= 0;             // tile not written before: read T + lambda I
+  const TT* src = fresh ? Tm : A;
+  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+
+  // current tile values (lower part of diagonal tiles only)
+  TT t[4][4];
 #pragma unroll
-    for (int i = 0; i < CB * CB / 256; ++i) {
-      const int e = tid + 256 * i, r = e / CB, q = e % CB;
-      vi[i] = (r0 + r < n && q < nb) ? A[(size_t)(r0 + r) * n + k0 + q] : (TT)0;
-      vj[i] = (c0 + r < n && q < nb) ? A[(size_t)(c0 + r) * n + k0 + q] : (TT)0;
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      const int r = r0 + tr + x, c = c0 + tc + z;
+      TT val = (TT)0;
+      if (r < n && c < n && (ti != tj || c <= r)) {
+        val = src[(size_t)r * n + c];
+        if (fresh && r == c) val += (TT)a.lambda;
+      }
+      t[x][z] = val;
+    }
+  if (k >= 0) {
+    // A_ij -= L_ik L_jk^T
+    const int k0 = k * CB;
+    {
+      TT vi[CB * CB / 256], vj[CB * CB / 256];
+#pragma unroll
+      for (int i = 0; i < CB * CB / 256; ++i) {
+        const int e = tid + 256 * i, r = e / CB, q = e % CB;
+        vi[i] = (r0 + r < n) ? A[(size_t)(r0 + r) * n + k0 + q] : (TT)0;
+        vj[i] = (c0 + r < n) ? A[(size_t)(c0 + r) * n + k0 + q] : (TT)0;
+      }
+#pragma unroll
+      for (int i = 0; i < CB * CB / 256; ++i) {
+        const int e = tid + 256 * i, r = e / CB, q = e % CB;
+        Li[r][q] = vi[i];
+        Lj[r][q] = vj[i];
+      }
+    }
+    __syncthreads();
+    TT acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int z = 0; z < 4; ++z) acc[x][z] = (TT)0;
+#pragma unroll 4
+    for (int q = 0; q < CB; ++q) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int z = 0; z < 4; ++z) acc[x][z] = fma(Li[tr + x][q], Lj[tc + z][q], acc[x][z]);
     }
 #pragma unroll
-    for (int i = 0; i < CB * CB / 256; ++i) {
-      const int e = tid + 256 * i, r = e / CB, q = e % CB;
-      Li[r][q] = vi[i];
-      Lj[r][q] = vj[i];
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int z = 0; z < 4; ++z) t[x][z] -= acc[x][z];
+    __syncthreads();   // Li, Lj are reused below
+  }
+
+  if (tj != kk) {
+    // plain trailing tile
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int z = 0; z < 4; ++z) {
+        const int r = r0 + tr + x, c = c0 + tc + z;
+        if (r < n && c < n && (ti != tj || c <= r)) A[(size_t)r * n + c] = t[x][z];
+      }
+    return;
+  }
+
+  const int kb0 = kk * CB, nb = min(CB, n - kb0);
+  TT* Di = reinterpret_cast<TT*>(a.Dinv) + (size_t)kk * CB * CB;
+  if (ti == kk) {
+    // diagonal tile: factor, invert, y_kk = inv(L) b_kk, publish
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int z = 0; z < 4; ++z) Li[tr + x][tc + z] = t[x][z];
+    if (tid < CB) yb[tid] = tid < nb ? y[kb0 + tid] : (TT)0;
+    __syncthreads();
+    factor_block<TT>(Li, Lc, rd, Lj, nb, A, n, kb0, Di, a.status);
+    __syncthreads();
+    // y_kk = inv(L) b_kk with the inverse from shared memory, 4 threads a row
+    {
+      const int row = tid / 4, part = tid % 4;
+      TT s = (TT)0;
+      if (row < nb)
+        for (int q = part; q <= row; q += 4) s = fma(Lj[row][q], yb[q], s);
+      s += __shfl_xor(s, 1, 4);
+      s += __shfl_xor(s, 2, 4);
+      if (part == 0 && row < nb) y[kb0 + row] = s;
     }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&flags[kk], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+
+  // panel tile below the diagonal: wait for the factor of block kk
+  if (tid == 0) {
+    while (__hip_atomic_load(&flags[kk], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+      __builtin_amdgcn_s_sleep(2);
   }
   __syncthreads();
-  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
-  TT acc[4][4];
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (TT)0;
+    for (int z = 0; z < 4; ++z) Li[tr + x][tc + z] = t[x][z];
+#pragma unroll
+  for (int i = 0; i < CB * CB / 256; ++i) {
+    const int e = tid + 256 * i, r = e / CB, q = e % CB;
+    Lj[r][q] = Di[e];
+  }
+  if (tid < CB) yb[tid] = y[kb0 + tid < n ? kb0 + tid : 0];
+  __syncthreads();
+  TT l[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int z = 0; z < 4; ++z) l[x][z] = (TT)0;
 #pragma unroll 4
   for (int q = 0; q < CB; ++q) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = fma(Li[tr + a][q], Lj[tc + b][q], acc[a][b]);
+      for (int z = 0; z < 4; ++z) l[x][z] = fma(Li[tr + x][q], Lj[tc + z][q], l[x][z]);
   }
-  // the current values of this block's tile, read before the barrier
-  TT cur[4][4];
+  TT s[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int x = 0; x < 4; ++x) {
+    s[x] = (TT)0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int r = r0 + tr + a, c = c0 + tc + b;
-      cur[a][b] = (r < n && c < n && (ti != tj || c <= r)) ? A[(size_t)r * n + c] : (TT)0;
+    for (int z = 0; z < 4; ++z) {
+      const int r = r0 + tr + x, c = tc + z;
+      const bool ok = r < n && c < nb;
+      if (ok) A[(size_t)r * n + kb0 + c] = l[x][z];
+      s[x] = fma(ok ? l[x][z] : (TT)0, yb[c], s[x]);
     }
-  const bool diag_next = blockIdx.x == 0;   // tile (kb+1, kb+1)
-  __syncthreads();
+  }
+  // the 16 threads of a row group hold the 64 columns of rows tr..tr+3
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int x = 0; x < 4; ++x) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int r = r0 + tr + a, c = c0 + tc + b;
-      if (r < n && c < n && (ti != tj || c <= r)) {
-        const TT v = cur[a][b] - acc[a][b];
-        A[(size_t)r * n + c] = v;
-        if (diag_next) Li[tr + a][tc + b] = v;
-      }
+    for (int m = 1; m < 16; m <<= 1) s[x] += __shfl_xor(s[x], m, 16);
+  }
+  if (tid % 16 == 0) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int r = r0 + tr + x;
+      if (r < n) y[r] -= s[x];
     }
-  if (!diag_next) return;
-  __syncthreads();
-  if (tid < 64) {
-    const int nb2 = min(CB, n - r0);
-    // factor_tile reads the lower triangle only
-    factor_tile<TT>(Li, nb2, A, n, r0, Dinv + (size_t)ti * CB * CB, status);
   }
 }
 
-// forward (L y = b) then backward (L^T x = y) substitution with the stored
-// block inverses, one workgroup of 1024 threads; 16 threads cooperate on a
-// row so that every load of L is coalesced.
+// sync words and b -> y (one kernel, safe inside captured graphs)
 template <typename TT>
-__global__ __launch_bounds__(1024) void k_trsv(const TT* A, int n, const TT* Dinv, const double* b,
-                                               double* x) {
+__global__ void k_chol_prep(uint32_t* sync, int nsync, const double* b, TT* y, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsync) sync[i] = 0u;
+  if (i < n) y[i] = (TT)b[i];
+}
+
+// backward substitution x_k = inv(L_kk)^T (y_k - sum_{j>k} L_jk^T x_j), one
+// workgroup of 1024 threads (64 columns x 16 row groups, coalesced rows).
+template <typename TT>
+__global__ __launch_bounds__(1024) void k_trsv_back(const TT* A, int n, const TT* Dinv,
+                                                    const TT* yin, double* x) {
   extern __shared__ unsigned char smem_raw[];
   TT* y = reinterpret_cast<TT*>(smem_raw);
   __shared__ TT rbuf[CB];
   __shared__ TT part[16][CB + 1];
   const int tid = threadIdx.x;
-  for (int i = tid; i < n; i += 1024) y[i] = (TT)b[i];
+  for (int i = tid; i < n; i += 1024) y[i] = yin[i];
   __syncthreads();
   const int nblk = (n + CB - 1) / CB;
-  const int row = tid / 16, sub = tid % 16;     // 64 rows x 16 threads
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int k0 = kb * CB, nb = min(CB, n - k0);
-    // r = b_k - L_k,<k y_<k
-    TT acc = (TT)0;
-    if (row < nb) {
-      const TT* Lr = A + (size_t)(k0 + row) * n;
-      // k0 is a multiple of 64: each thread takes 4 columns of every 64
-      for (int q0 = 0; q0 < k0; q0 += 64) {
-        TT l[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) l[u] = Lr[q0 + sub + 16 * u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc = fma(l[u], y[q0 + sub + 16 * u], acc);
-      }
-    }
-#pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 16);
-    if (sub == 0 && row < nb) rbuf[row] = y[k0 + row] - acc;
-    __syncthreads();
-    // y_k = inv(L_kk) r
-    const TT* Di = Dinv + (size_t)kb * CB * CB;
-    TT v = (TT)0;
-    if (row < nb)
-      for (int q = sub; q <= row; q += 16) v = fma(Di[row * CB + q], rbuf[q], v);
-#pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 16);
-    if (sub == 0 && row < nb) y[k0 + row] = v;
-    __syncthreads();
-  }
-  // backward: x_k = inv(L_kk)^T (y_k - sum_{j>k} L_jk^T x_j)
   const int c = tid % CB, g = tid / CB;         // 64 columns x 16 row groups
   for (int kb = nblk - 1; kb >= 0; --kb) {
     const int k0 = kb * CB, nb = min(CB, n - k0);
@@ -698,49 +754,41 @@ __global__ __launch_bounds__(1024) void k_trsv(const TT* A, int n, const TT* Din
   for (int i = tid; i < n; i += 1024) x[i] = (double)y[i];
 }
 
-template <typename TT>
-__global__ void k_copy_add_diag(const TT* T, TT* A, size_t nn, int n, double lambda) {
-  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nn) return;
-  TT v = T[e];
-  if (e / n == e % n) v += (TT)lambda;
-  A[e] = v;
-}
-
 size_t chol_dinv_elems(int n) { return (size_t)((n + CB - 1) / CB) * CB * CB; }
+size_t chol_sync_words(int n) { return 2 * (size_t)((n + CB - 1) / CB + 1); }
 
 template <typename TT>
-static int chol_t(int n, const TT* T, TT* A, TT* Dinv, double lambda, const double* b, double* x,
-                  uint32_t* status, hipStream_t s) {
-  const size_t nn = (size_t)n * n;
-  k_copy_add_diag<TT><<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(T, A, nn, n, lambda);
-  MINSR_CHECK_LAUNCH();
+static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, double lambda,
+                  const double* b, double* x, uint32_t* status, hipStream_t s) {
   const int nblk = (n + CB - 1) / CB;
-  k_chol_diag<TT><<<1, 64, 0, s>>>(A, n, 0, Dinv, status);
-  MINSR_CHECK_LAUNCH();
-  for (int kb = 0; kb + 1 < nblk; ++kb) {
-    const int rows_below = n - (kb + 1) * CB;
-    k_chol_panel<TT><<<(rows_below + CB - 1) / CB, 256, 0, s>>>(A, n, kb, Dinv);
-    MINSR_CHECK_LAUNCH();
-    const int nt = nblk - kb - 1;
-    k_syrk_trail<TT><<<nt * (nt + 1) / 2, 256, 0, s>>>(A, n, kb, Dinv, status);
-    MINSR_CHECK_LAUNCH();
-  }
   const size_t shm = (size_t)n * sizeof(TT);
   if (shm > 96 * 1024) return fail(MINSR_E_SHAPE, "triangular solve: n too large");
-  k_trsv<TT><<<1, 1024, shm, s>>>(A, n, Dinv, b, x);
+  const int nsync = (int)chol_sync_words(n);
+  const int m = std::max(nsync, n);
+  k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n);
+  MINSR_CHECK_LAUNCH();
+  CholArgs a{T, A, Dinv, yv, sync, status, lambda, n, nblk};
+  k_chol_step<TT><<<nblk, 256, 0, s>>>(a, -1);
+  MINSR_CHECK_LAUNCH();
+  for (int k = 0; k + 1 < nblk; ++k) {
+    const int nt = nblk - k - 1;
+    k_chol_step<TT><<<nt * (nt + 1) / 2, 256, 0, s>>>(a, k);
+    MINSR_CHECK_LAUNCH();
+  }
+  k_trsv_back<TT><<<1, 1024, shm, s>>>(A, n, Dinv, yv, x);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
 }
 
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
-                          double lambda, const double* b, double* x, uint32_t* status,
-                          hipStream_t s) {
+                          double lambda, const double* b, double* x, double* yv, uint32_t* sync,
+                          uint32_t* status, hipStream_t s) {
   if (n == 0) return MINSR_OK;
   if (f32)
     return chol_t<float>(n, reinterpret_cast<const float*>(T), reinterpret_cast<float*>(Lf),
-                         reinterpret_cast<float*>(Dinv), lambda, b, x, status, s);
-  return chol_t<double>(n, T, Lf, Dinv, lambda, b, x, status, s);
+                         reinterpret_cast<float*>(Dinv), reinterpret_cast<float*>(yv), sync,
+                         lambda, b, x, status, s);
+  return chol_t<double>(n, T, Lf, Dinv, yv, sync, lambda, b, x, status, s);
 }
 
 // ================================================================ update

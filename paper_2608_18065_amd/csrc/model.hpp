@@ -45,7 +45,8 @@ struct minsr_model {
   size_t gpart_elems = 0;
   double* epsp = nullptr;   // [n] eps'
   double* x = nullptr;      // [n] solution
-  double* vwork = nullptr;  // [n] solver scratch
+  double* vwork = nullptr;  // [n] solver scratch (forward-substitution vector)
+  uint32_t* csync = nullptr;// Cholesky tickets and flags
   double* dpart = nullptr;  // update partials
   double* dtheta = nullptr; // [Np]
   uint32_t* status = nullptr;
@@ -54,6 +55,10 @@ struct minsr_model {
   int last_n = 0;
   int last_form = 0;
   int force_vector = 0;     // testing: route FP32 local energies to the vector kernel
+  // launch parameters (0 = built-in choice), set by the autotuner
+  int tune_gram_split = 0;
+  int tune_eloc_grid = 0;
+  int tune_sample_r = 0;
 
   // per-phase event timing of minsr_step (profiling only)
   std::vector<hipEvent_t> ev;   // [t_max][NPHASE + 1]
@@ -94,13 +99,17 @@ int launch_center(int rows_per_block, int nblocks, size_t Np, const void* O, int
 inline size_t padded_ld(size_t Np) { return (Np + 63) / 64 * 64; }
 // which: 1 = tile products, 2 = split-K reduction and mirror, 3 = both
 // Rlo (BF16 only, may be null): low parts of a hi/lo split of R
+// split: split-K factor (0 = heuristic)
 int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gpart,
-                size_t gpart_elems, hipStream_t s, int which = 3, const void* Rlo = nullptr);
+                size_t gpart_elems, hipStream_t s, int which = 3, const void* Rlo = nullptr,
+                int split = 0);
 // factors T + lambda I into Lf (T is left unchanged) and solves for x
+// (yv: n elements of scratch; sync: chol_sync_words(n) words)
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
-                          double lambda, const double* b, double* x, uint32_t* status,
-                          hipStream_t s);
+                          double lambda, const double* b, double* x, double* yv, uint32_t* sync,
+                          uint32_t* status, hipStream_t s);
 size_t chol_dinv_elems(int n);
+size_t chol_sync_words(int n);
 int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* x,
                       double* eig, size_t eig_elems, uint32_t* status, hipStream_t s);
 int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, double eta,

@@ -1,0 +1,35 @@
+"""Seeded synthetic matrices for the solve tests.
+
+Symmetric positive semi-definite matrices with a prescribed spectrum,
+T = Q diag(w) Q^T with Q the orthogonal factor of a Gaussian matrix, and
+right-hand sides.  This module only draws inputs; it computes nothing of
+the minSR method."""
+import numpy as np
+
+
+def orthogonal(n, rng):
+    q, r = np.linalg.qr(rng.standard_normal((n, n)))
+    return q * np.sign(np.diag(r))
+
+
+def spectrum_loguniform(n, cond, rng, zeros=0):
+    """n eigenvalues log-uniform in [1/cond, 1] (the largest exactly 1), the
+    last `zeros` of them exactly 0."""
+    w = np.exp(rng.uniform(np.log(1.0 / cond), 0.0, n))
+    w[0] = 1.0
+    if zeros:
+        w[n - zeros:] = 0.0
+    return w
+
+
+def psd_matrix(w, seed):
+    """Q diag(w) Q^T for a seeded orthogonal Q, symmetrised exactly."""
+    rng = np.random.default_rng(seed)
+    n = len(w)
+    Q = orthogonal(n, rng)
+    T = (Q * w) @ Q.T
+    return 0.5 * (T + T.T), Q
+
+
+def rhs(n, seed):
+    return np.random.default_rng(seed + 7919).standard_normal(n)
