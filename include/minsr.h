@@ -78,7 +78,8 @@ extern "C" {
 #define MINSR_ST_NONFINITE_ELOC  0x1u
 #define MINSR_ST_NOT_PD          0x2u   /* Cholesky met a pivot <= 0 / NaN */
 #define MINSR_ST_NONFINITE_DTH   0x4u
-#define MINSR_ST_EIG_NOCONV      0x8u
+#define MINSR_ST_EIG_NOCONV      0x8u   /* pseudo-inverse met a non-finite
+                                           tridiagonal entry                 */
 
 /* Architecture of one wave function (Sec. 2, Sec. 2.1 and App. A).
  *   Lx, Ly        lattice extent; a chain has Ly = 1 and dim = 1
@@ -89,15 +90,21 @@ extern "C" {
  *   zero_mag      restrict the autoregressive conditionals to S^z = 0
  *   compute_dtype MINSR_F64 or MINSR_F32: precision of every GRU evaluation
  *   init_seed     Philox key of the Glorot-uniform initialisation
- *   max_Ns        largest N_s any call on this handle will use           */
+ *   max_Ns        largest N_s any call on this handle will use
+ *   options       bit MINSR_OPT_PINV reserves the pseudo-inverse workspace
+ *                 at creation (about 2.2 n^2 doubles for n = max_Ns, or
+ *                 2 max_Ns for a cRNN; n <= 4096); without it the workspace
+ *                 is allocated by the first pseudo-inverse call, which
+ *                 therefore must not be captured into a graph             */
 typedef struct {
   int32_t Lx, Ly, dim, hidden;
   int32_t complex_head, marshall, zero_mag;
   int32_t compute_dtype;
   uint64_t init_seed;
   int32_t max_Ns;
-  int32_t reserved;
+  int32_t options;
 } minsr_model_desc;
+#define MINSR_OPT_PINV  0x1
 
 typedef struct {
   int32_t kind;      /* MINSR_HAM_*                                      */

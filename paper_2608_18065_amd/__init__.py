@@ -28,6 +28,7 @@ SYMBOLS = (
     "minsr_batch_create", "minsr_batch_step", "minsr_batch_destroy", "minsr_set_tunable",
     "minsr_get_tunable", "minsr_solve",
 )
+OPT_PINV = 0x1
 PHASES = ("sample", "eloc", "eloc_sum_stats", "jacobian", "center", "gram", "gram_reduce",
           "solve", "update", "repack")
 
@@ -37,7 +38,7 @@ class ModelDesc(ctypes.Structure):
                 ("hidden", ctypes.c_int32), ("complex_head", ctypes.c_int32),
                 ("marshall", ctypes.c_int32), ("zero_mag", ctypes.c_int32),
                 ("compute_dtype", ctypes.c_int32), ("init_seed", ctypes.c_uint64),
-                ("max_Ns", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_Ns", ctypes.c_int32), ("options", ctypes.c_int32)]
 
 
 class Hamiltonian(ctypes.Structure):
@@ -142,9 +143,10 @@ class Model:
     """One GRU wave function on the current HIP device (Sec. 2, App. A)."""
 
     def __init__(self, Lx, Ly=1, dim=1, hidden=16, complex_head=False, marshall=False,
-                 zero_mag=False, dtype="f64", seed=0, max_Ns=1024):
+                 zero_mag=False, dtype="f64", seed=0, max_Ns=1024, pinv=False):
         self.desc = ModelDesc(Lx, Ly, dim, hidden, int(complex_head), int(marshall),
-                              int(zero_mag), F64 if dtype == "f64" else F32, seed, max_Ns, 0)
+                              int(zero_mag), F64 if dtype == "f64" else F32, seed, max_Ns,
+                              OPT_PINV if pinv else 0)
         h = ctypes.c_void_p()
         _check(lib().minsr_create_model(ctypes.byref(self.desc), ctypes.byref(h)))
         self.handle = h

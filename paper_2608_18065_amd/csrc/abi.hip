@@ -70,6 +70,27 @@ static int alloc(void** p, size_t bytes) {
   return MINSR_OK;
 }
 
+// the pseudo-inverse workspace, allocated once per handle (not inside a
+// stream capture)
+static int ensure_pinv_ws(minsr_model* m, hipStream_t s) {
+  if (m->eig) return MINSR_OK;
+  const int rows = (m->cplx ? 2 : 1) * m->d.max_Ns;
+  const int nmax = std::min(rows, 4096);
+  if (s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return fail(MINSR_E_UNSUPPORTED,
+                  "pseudo-inverse workspace not reserved: create the model with MINSR_OPT_PINV "
+                  "or run one uncaptured pseudo-inverse call first");
+  }
+  const size_t e = pinv_workspace_doubles(nmax);
+  int rc = alloc((void**)&m->eig, e * 8);
+  if (rc) return rc;
+  m->eig_elems = e;
+  m->eig_nmax = nmax;
+  return MINSR_OK;
+}
+
 static void release(minsr_model* m) {
   void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->site, m->contrib,
                   m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
@@ -106,6 +127,7 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   if (d->compute_dtype != MINSR_F64 && d->compute_dtype != MINSR_F32)
     return fail(MINSR_E_INVALID_ARG, "compute_dtype must be MINSR_F64 or MINSR_F32");
   if (d->max_Ns < 1 || d->max_Ns > (1 << 16)) return fail(MINSR_E_INVALID_ARG, "max_Ns out of range");
+  if (d->options & ~MINSR_OPT_PINV) return fail(MINSR_E_INVALID_ARG, "unknown option bits");
 
   minsr_model* m = new (std::nothrow) minsr_model();
   if (!m) return fail(MINSR_E_NOMEM, "host allocation failed");
@@ -196,6 +218,7 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   rc = rc ? rc : alloc((void**)&m->dpart, ((rows + 63) / 64) * Np * 8);
   rc = rc ? rc : alloc((void**)&m->dtheta, Np * 8);
   rc = rc ? rc : alloc((void**)&m->status, 16);
+  if (!rc && (d->options & MINSR_OPT_PINV)) rc = ensure_pinv_ws(m, nullptr);
   if (rc) { release(m); delete m; return rc; }
 
   hipError_t e = hipMemcpy(m->nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -426,12 +449,15 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
                    m->tune_gram_split);
   if (rc) return rc;
   MINSR_PHASE(7);
-  if (cfg->pinv_cutoff > 0.0)
-    rc = launch_pinv_solve(n, m->T, cfg->pinv_cutoff, m->epsp, m->x, m->eig, m->eig_elems,
-                           out->dev_status, s);
-  else
+  if (cfg->pinv_cutoff > 0.0) {
+    rc = ensure_pinv_ws(m, s);
+    if (!rc)
+      rc = launch_pinv_solve(n, m->T, cfg->pinv_cutoff, m->epsp, m->x, m->eig, m->eig_elems,
+                             m->eig_nmax, out->dev_status, s);
+  } else {
     rc = launch_cholesky_solve(n, m->T, m->Lf, m->Dinv, rdt == MINSR_F32, cfg->lambda, m->epsp,
                                m->x, m->vwork, m->csync, out->dev_status, s);
+  }
   if (rc) return rc;
   MINSR_PHASE(8);
   // 5. dtheta = eta O' x, momentum, parameters, working copy
@@ -538,8 +564,10 @@ int minsr_solve(minsr_model* m, int n, const double* dev_T, double lambda, doubl
     return fail(MINSR_E_INVALID_ARG, "negative lambda / cutoff");
   if (pinv_cutoff > 0.0) {
     if (lambda != 0.0) return fail(MINSR_E_INVALID_ARG, "the pseudo-inverse solve takes lambda = 0");
+    const int rc = ensure_pinv_ws(m, s);
+    if (rc) return rc;
     return launch_pinv_solve(n, const_cast<double*>(dev_T), pinv_cutoff, dev_b, dev_x, m->eig,
-                             m->eig_elems, dev_status, s);
+                             m->eig_elems, m->eig_nmax, dev_status, s);
   }
   return launch_cholesky_solve(n, dev_T, m->Lf, m->Dinv, 0, lambda, dev_b, dev_x, m->vwork,
                                m->csync, dev_status, s);

@@ -879,11 +879,5 @@ int launch_reduce_rows(int rows, size_t Np, const double* part, double* out, hip
   return MINSR_OK;
 }
 
-int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* x, double* eig,
-                      size_t eig_elems, uint32_t* status, hipStream_t s) {
-  (void)n; (void)T; (void)cutoff; (void)b; (void)x; (void)eig; (void)eig_elems; (void)status;
-  (void)s;
-  return fail(MINSR_E_UNSUPPORTED, "pseudo-inverse solve not built yet");
-}
 
 }  // namespace minsr

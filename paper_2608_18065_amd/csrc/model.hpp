@@ -52,6 +52,7 @@ struct minsr_model {
   uint32_t* status = nullptr;
   double* eig = nullptr;    // eigen solver workspace
   size_t eig_elems = 0;
+  int eig_nmax = 0;         // largest n the eigen workspace serves
   int last_n = 0;
   int last_form = 0;
   int force_vector = 0;     // testing: route FP32 local energies to the vector kernel
@@ -110,8 +111,11 @@ int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int 
                           uint32_t* status, hipStream_t s);
 size_t chol_dinv_elems(int n);
 size_t chol_sync_words(int n);
+// x = T^+ b with eigenvalues <= cutoff * lambda_max dropped (n <= 4096);
+// eig: pinv_workspace_doubles(nmax) doubles, nmax >= n
 int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* x,
-                      double* eig, size_t eig_elems, uint32_t* status, hipStream_t s);
+                      double* eig, size_t eig_elems, int nmax, uint32_t* status, hipStream_t s);
+size_t pinv_workspace_doubles(int nmax);
 int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, double eta,
                   double mu, double* dpart, double* dtheta, double* momentum, double* theta,
                   uint32_t* status, int apply, hipStream_t s, const void* Rlo = nullptr);

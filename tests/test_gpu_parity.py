@@ -247,6 +247,37 @@ def test_step_fp64_ragged(arch, ham, Ns):
     assert rel_err(mom.cpu().numpy(), ref["m"]) < 1e-10
 
 
+def test_step_fp64_pinv_heisenberg2d():
+    # Alg. 1 with lambda = 0 and the pseudo-inverse cutoff of App. F on a
+    # small square-lattice Heisenberg model (Marshall sign, S^z = 0 mask)
+    import paper_2608_18065_amd as pm
+    Ns, cutoff = 120, 1e-8
+    spec, m = make_pair(Lx=4, Ly=4, dim=2, H=16, marshall=True, zero_mag=True, max_Ns=Ns)
+    th = scaled_theta(spec, 31, 1.0)
+    m.set_params(to_dev(th))
+    ham = oham.Ham("j1j2", J=1.0)
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    o = m.step(_gpu_ham(ham), Ns, 0.05, 0.0, 0.0, mom, 8, 3, form=pm.FORM_FP64_REF,
+               pinv_cutoff=cutoff)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == 0
+    ref = ominsr.step(spec, th, np.zeros_like(th), ham, Ns, 0.05, 0.0, 0.0, 8, 3,
+                      pinv_cutoff=cutoff)
+    assert np.array_equal(o["sigma"].cpu().numpy(), ref["sigma"].astype(np.uint8))
+    w = np.linalg.eigvalsh(ref["T"])
+    thr = cutoff * w.max()
+    assert np.all(np.abs(w - thr) > 1e-6 * thr), "ambiguous cutoff for this seed"
+    kept = w[w > thr]
+    # backward-stable eigensolvers on both sides: n u cond(kept spectrum)
+    tol = max(1e-10, 4.0 * Ns * np.finfo(float).eps * w.max() / kept.min())
+    it = m.intermediates(pm.FORM_FP64_REF)
+    assert rel_err(it["T"].cpu().numpy(), ref["T"]) < 1e-10
+    x = it["x"].cpu().numpy()
+    assert np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"]) < tol
+    d = o["dtheta"].cpu().numpy()
+    assert np.linalg.norm(d - ref["dtheta"]) / np.linalg.norm(ref["dtheta"]) < tol
+
+
 def _low_precision_step(spec, m, ham, Ns, eta, lam, key, counter, form):
     mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
     th = m.get_params().cpu().numpy()

@@ -77,3 +77,104 @@ def test_solve_rejects_bad_arguments(model):
     big = torch.eye(MAX_N + 1, dtype=torch.float64, device="cuda")
     with pytest.raises(pm.MinsrError):
         model.solve(big, torch.ones(MAX_N + 1, dtype=torch.float64, device="cuda"), lam=1.0)
+
+
+# ------------------------------------------------------------ pseudo-inverse
+U64 = np.finfo(float).eps
+
+
+def _pinv_tol(w, cutoff):
+    """Forward error bound of a backward-stable eigensolver applied to the
+    pseudo-inverse: ~ n u lambda_max / lambda_min(kept) (both sides), with a
+    floor at the FP64 bar."""
+    kept = w[w > cutoff * w.max()]
+    return max(1e-10, 4.0 * len(w) * U64 * w.max() / kept.min())
+
+
+def _check_gap(w, cutoff, rel=1e-6):
+    # no eigenvalue so close to the threshold that rounding could flip its
+    # keep/drop decision
+    thr = cutoff * w.max()
+    assert np.all(np.abs(w - thr) > rel * thr), "ambiguous cutoff in the test input"
+
+
+@pytest.fixture(scope="module")
+def pmodel():
+    need_gpu()
+    import paper_2608_18065_amd as pm
+    return pm.Model(16, hidden=16, dtype="f64", seed=1, max_Ns=MAX_N, pinv=True)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 65, 130, 333, 1000])
+def test_pinv_matches_oracle(pmodel, n):
+    rng = np.random.default_rng(1000 + n)
+    w = inputs.spectrum_loguniform(n, 1e6, rng, zeros=n // 5)
+    T, _ = inputs.psd_matrix(w, seed=200 + n)
+    b = inputs.rhs(n, seed=n)
+    cutoff = 1e-8
+    wo = np.linalg.eigvalsh(T)
+    _check_gap(wo, cutoff)
+    x, st = pmodel.solve(to_dev(T), to_dev(b), lam=0.0, pinv_cutoff=cutoff)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    ref = ominsr.solve(T, b, 0.0, cutoff)
+    assert _rel(x.cpu().numpy(), ref) < _pinv_tol(wo, cutoff)
+
+
+@pytest.mark.parametrize("n", [40, 257])
+def test_pinv_repeated_eigenvalues(pmodel, n):
+    # heavily repeated spectrum (deflation by rotations) with an exact null space
+    rng = np.random.default_rng(n)
+    w = np.round(rng.uniform(0.0, 3.0, n)) * 0.5
+    T, _ = inputs.psd_matrix(w, seed=300 + n)
+    b = inputs.rhs(n, seed=5)
+    x, st = pmodel.solve(to_dev(T), to_dev(b), lam=0.0, pinv_cutoff=1e-8)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    ref = ominsr.solve(T, b, 0.0, 1e-8)
+    assert _rel(x.cpu().numpy(), ref) < 1e-10
+
+
+def test_pinv_drops_below_cutoff(pmodel):
+    # half the spectrum far below the cutoff: x is the solution restricted to
+    # the kept eigenvectors, orthogonal to the dropped ones
+    n = 300
+    rng = np.random.default_rng(11)
+    w = np.exp(rng.uniform(np.log(1e-4), 0.0, n))
+    w[::2] = 1e-12 * rng.uniform(0.5, 1.0, n)[::2]
+    w[1] = 1.0
+    T, Q = inputs.psd_matrix(w, seed=12)
+    b = inputs.rhs(n, seed=13)
+    x, st = pmodel.solve(to_dev(T), to_dev(b), lam=0.0, pinv_cutoff=1e-8)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    keep = w > 1e-8 * w.max()
+    expect = Q[:, keep] @ ((Q[:, keep].T @ b) / w[keep])
+    assert _rel(xh, expect) < 1e-9
+    assert np.linalg.norm(Q[:, ~keep].T @ xh) < 1e-9 * np.linalg.norm(xh)
+
+
+def test_pinv_centred_gram_is_orthogonal_to_ones(pmodel):
+    # a centred Gram has T 1 = 0; the pseudo-inverse solution is orthogonal to 1
+    n, Np = 200, 500
+    rng = np.random.default_rng(21)
+    O = rng.standard_normal((n, Np))
+    O -= O.mean(axis=0, keepdims=True)
+    T = O @ O.T
+    T = 0.5 * (T + T.T)
+    b = rng.standard_normal(n)
+    x, st = pmodel.solve(to_dev(T), to_dev(b), lam=0.0, pinv_cutoff=1e-8)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    assert abs(xh.sum()) < 1e-10 * np.sqrt(n) * np.linalg.norm(xh)
+    ref = ominsr.solve(T, b, 0.0, 1e-8)
+    assert _rel(xh, ref) < _pinv_tol(np.linalg.eigvalsh(T), 1e-8)
+
+
+def test_pinv_zero_matrix(pmodel):
+    n = 70
+    T = np.zeros((n, n))
+    x, st = pmodel.solve(to_dev(T), to_dev(np.ones(n)), lam=0.0, pinv_cutoff=1e-8)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert float(x.abs().max()) == 0.0
