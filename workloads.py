@@ -6,7 +6,9 @@ Each configuration restates one benchmark system of the project:
   tfim10     1D transverse-field Ising, open chain N=10, J=h=1; 1D pRNN
              d_h=16; N_s=64; one step, lambda=1e-3, eta=0.01, mu=0
   tfim64     1D TFIM periodic N=64, J=h=1; 1D pRNN d_h=64 (13058 params);
-             N_s=1024, N+1 connected configurations per sample
+             N_s=1024, N+1 connected configurations per sample; eta=0.05,
+             lambda=1e-3, mu=0.7 (the N=200 step size 0.5 drives this
+             smaller chain into the ferromagnetic product state)
   cluster100 periodic cluster chain -sum Z X Z, N=100; 1D cRNN d_h=128
              (50948 params); N_s=2048; checkpoints every 10 sites
   heis10x10  open 10x10 Heisenberg; 2D pRNN d_h=128 with Marshall sign and
@@ -50,7 +52,7 @@ WORKLOADS = {
     "tfim10": Workload("tfim10", 10, 1, 1, 16, False, False, False, "tfim", 1.0, 1.0, 0.0, False,
                        64, 0.01, 1e-3, 0.0, 0.0, 1, 1001, 2001, -12.381489999654756),
     "tfim64": Workload("tfim64", 64, 1, 1, 64, False, False, False, "tfim", 1.0, 1.0, 0.0, True,
-                       1024, 0.5, 1e-3, 0.7, 0.0, 1, 1002, 2002, -81.49551266892574),
+                       1024, 0.05, 1e-3, 0.7, 0.0, 1, 1002, 2002, -81.49551266892574),
     "cluster100": Workload("cluster100", 100, 1, 1, 128, True, False, False, "cluster", 1.0, 0.0, 0.0, True,
                            2048, 5e-3, 1e-3, 0.1, 0.0, 10, 1003, 2003, -100.0),
     "heis10x10": Workload("heis10x10", 10, 10, 2, 128, False, True, True, "j1j2", 1.0, 0.0, 0.0, False,
