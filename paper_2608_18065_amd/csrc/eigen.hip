@@ -28,7 +28,7 @@ constexpr int PINV_MAX_N = 4096;
 // ------------------------------------------------------------ workspace
 struct PinvWs {
   // tridiagonalisation
-  double *A, *V, *W, *tau, *d, *e, *bq, *g, *s12, *scal;
+  double *A, *V, *W, *tau, *d, *e, *bq, *g, *s12, *scal, *pc, *pd;
   // divide and conquer, per depth parity (ping-pong)
   double *ev[2], *fr[2], *lr[2], *cv[2], *tv[2];
   // per-merge scratch, indexed by position in [0, n)
@@ -56,7 +56,7 @@ size_t pinv_workspace_doubles(int nmax) {
   const int D = depth_of(nmax) + 1;
   size_t u = 0;
   for (int l = 0; l < D; ++l) u += u_level_elems(nmax, l);
-  size_t dbl = n * n + 2 * TNB * n + 5 * n + 2 * TNB + 8   // tridiagonalisation
+  size_t dbl = n * n + 2 * TNB * n + 7 * n + 2 * TNB + 8   // tridiagonalisation
              + 10 * n                                      // ping-pong arrays
              + 11 * n                                      // merge scratch (uk has 3 n)
              + 2 * D * n                                   // rotation coefficients
@@ -74,7 +74,7 @@ static PinvWs carve(double* base, int n, int nmax) {
   w.A = take(N * N);
   w.V = take(TNB * N); w.W = take(TNB * N);
   w.tau = take(N); w.d = take(N); w.e = take(N); w.bq = take(N); w.g = take(N);
-  w.s12 = take(2 * TNB); w.scal = take(8);
+  w.s12 = take(2 * TNB); w.scal = take(8); w.pc = take(N); w.pd = take(N);
   for (int i = 0; i < 2; ++i) { w.ev[i] = take(N); w.fr[i] = take(N); w.lr[i] = take(N);
                                 w.cv[i] = take(N); w.tv[i] = take(N); }
   w.es = take(N); w.dl = take(N); w.wv = take(N); w.dlo = take(N); w.taus = take(N);
@@ -138,81 +138,56 @@ __device__ __host__ inline void node_of(int n, int lev, int slot, int& lo, int& 
 
 // ================================================== tridiagonalisation
 struct TriArgs {
-  double *A, *V, *W, *tau, *d, *e, *bq, *g, *s12;
+  double *A, *V, *W, *tau, *d, *e, *bq, *g, *s12, *pc, *pd;
   int n;
 };
 
 constexpr int TBS = 1024;
 constexpr int TPT = PINV_MAX_N / TBS;      // rows per thread in single-workgroup kernels
 
-// w_{jp} = tau (g - V s1 - W s2), then w += alpha v with alpha = -tau/2 w.v,
-// over rows i > jp; written to W[pp].  Rows owned: i = jp + 1 + tid + TBS u.
-__device__ void tri_finalize(const TriArgs& a, int jp, int pp, double* wreg, double* red) {
-  const int n = a.n, tid = threadIdx.x;
-  const double t = a.tau[jp];
-  const double* s1 = a.s12;
-  const double* s2 = a.s12 + TNB;
-  const double* vcol = a.V + (size_t)pp * n;
-  double part = 0.0;
-#pragma unroll
-  for (int u = 0; u < TPT; ++u) {
-    const int i = jp + 1 + tid + TBS * u;
-    double w = 0.0;
-    if (i < n) {
-      double r = a.g[i];
-      for (int q = 0; q < pp; ++q)
-        r -= a.V[(size_t)q * n + i] * s1[q] + a.W[(size_t)q * n + i] * s2[q];
-      w = t * r;
-      part += w * vcol[i];
-    }
-    wreg[u] = w;
-  }
-  const double alpha = -0.5 * t * block_sum(part, red);
-#pragma unroll
-  for (int u = 0; u < TPT; ++u) {
-    const int i = jp + 1 + tid + TBS * u;
-    if (i < n) {
-      wreg[u] += alpha * vcol[i];
-      a.W[(size_t)pp * n + i] = wreg[u];
-    }
-  }
-}
-
-// column j (position p in its panel): finalise the previous column's w,
-// update column j from the panel, form its reflector, apply it to b, and the
-// panel products s1 = W^T v, s2 = V^T v for the product with the trailing
-// matrix.
-__global__ __launch_bounds__(TBS) void k_tri_col(TriArgs a, int j, int p) {
+// Column j at position p of its panel, one workgroup.  With the product
+// g = (A - V W^T - W V^T) v_{j-1} and its partial dots g.v from the previous
+// column's multi-workgroup kernel, w_{j-1} = tau g + alpha v with
+// alpha = -tau^2/2 g.v is finalised elementwise; column j (whose panel terms
+// up to q = p - 2 the same kernel subtracted) receives the q = p - 1 term;
+// then the reflector, b <- H b, and s1 = W^T v, s2 = V^T v over q < p.
+__global__ __launch_bounds__(TBS) void k_tri_col(TriArgs a, int j, int p, int npd) {
   __shared__ double red[TBS / 64];
-  __shared__ double Vj[TNB], Wj[TNB];
   __shared__ double sh[4];
   __shared__ double part2[TBS / 64][2 * TNB];
   const int n = a.n, tid = threadIdx.x;
-  double wprev[TPT];
+  double col[TPT], wl[TPT], vl[TPT];
   if (p > 0) {
-    // rows i > j - 1 = rows i >= j; thread order matches the column below
-    tri_finalize(a, j - 1, p - 1, wprev, red);
-    if (tid == 0) Wj[p - 1] = wprev[0];   // row j is the first row owned
-  }
-  if (tid < p) {
-    Vj[tid] = a.V[(size_t)tid * n + j];
-    if (tid < p - 1) Wj[tid] = a.W[(size_t)tid * n + j];
-  }
-  __syncthreads();
-  // column j from row j of the panel-start matrix (symmetric), rows i >= j
-  double col[TPT];
+    const double tp = a.tau[j - 1];
+    double sp = 0.0;
+    for (int k = tid; k < npd; k += TBS) sp += a.pd[k];
+    const double alpha = -0.5 * tp * tp * block_sum(sp, red);
+    const double* vprev = a.V + (size_t)(p - 1) * n;
 #pragma unroll
-  for (int u = 0; u < TPT; ++u) {
-    const int i = j + tid + TBS * u;
-    double c = 0.0;
-    if (i < n) {
-      c = a.A[(size_t)j * n + i];
-      for (int q = 0; q < p; ++q) {
-        const double wq = (q == p - 1) ? wprev[u] : a.W[(size_t)q * n + i];
-        c -= a.V[(size_t)q * n + i] * Wj[q] + wq * Vj[q];
+    for (int u = 0; u < TPT; ++u) {
+      const int i = j + tid + TBS * u;
+      vl[u] = 0.0; wl[u] = 0.0;
+      if (i < n) {
+        vl[u] = vprev[i];
+        wl[u] = tp * a.g[i] + alpha * vl[u];
+        a.W[(size_t)(p - 1) * n + i] = wl[u];
       }
     }
-    col[u] = c;
+    if (tid == 0) { sh[1] = wl[0]; sh[2] = vl[0]; }      // row j
+    __syncthreads();
+    const double Wj = sh[1], Vj = sh[2];
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const int i = j + tid + TBS * u;
+      col[u] = i < n ? a.pc[i] - (vl[u] * Wj + wl[u] * Vj) : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const int i = j + tid + TBS * u;
+      col[u] = i < n ? a.A[(size_t)j * n + i] : 0.0;
+      wl[u] = 0.0; vl[u] = 0.0;
+    }
   }
   if (tid == 0) a.d[j] = col[0];
   if (j == n - 1) return;
@@ -224,7 +199,7 @@ __global__ __launch_bounds__(TBS) void k_tri_col(TriArgs a, int j, int p) {
     const int i = j + tid + TBS * u;
     if (i >= j + 2 && i < n) ps += col[u] * col[u];
   }
-  const double sig2 = block_sum(ps, red);   // includes a barrier after sh[0]
+  const double sig2 = block_sum(ps, red);   // its barriers publish sh[0]
   const double alpha = sh[0];
   double t, beta, sc;
   if (sig2 == 0.0) { t = 0.0; beta = alpha; sc = 0.0; }
@@ -266,10 +241,12 @@ __global__ __launch_bounds__(TBS) void k_tri_col(TriArgs a, int j, int p) {
       if (i > j && i < n) {
 #pragma unroll
         for (int q = 0; q < TNB; ++q) {
-          if (q < p) {
-            const double wq = (q == p - 1) ? wprev[u] : a.W[(size_t)q * n + i];
-            s[q] += wq * v[u];
+          if (q < p - 1) {
+            s[q] += a.W[(size_t)q * n + i] * v[u];
             s[TNB + q] += a.V[(size_t)q * n + i] * v[u];
+          } else if (q == p - 1) {
+            s[q] += wl[u] * v[u];
+            s[TNB + q] += vl[u] * v[u];
           }
         }
       }
@@ -289,23 +266,56 @@ __global__ __launch_bounds__(TBS) void k_tri_col(TriArgs a, int j, int p) {
   }
 }
 
-// g[i] = sum_{c > j} A[i][c] v[c], rows i > j: one wavefront per row
-__global__ __launch_bounds__(256) void k_tri_gemv(const double* A, const double* v, double* g,
-                                                  int n, int j) {
-  const int lane = threadIdx.x & 63;
-  const int i = j + 1 + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const double* row = A + (size_t)i * n;
-  double s = 0.0;
-  for (int c = j + 1 + lane; c < n; c += 64) s = fma(row[c], v[c], s);
-  s = wave_sum(s);
-  if (lane == 0) g[i] = s;
+// Rows i > j, one wavefront per row: g[i] = (A v)[i] - sum_{q<p} V_q[i] s1[q]
+// + W_q[i] s2[q]; per-workgroup partial dots g.v; and, when the next column
+// is in the same panel, its entries pc[i] = A[i][j+1] - sum_{q<p} (V_q[i]
+// W_q[j+1] + W_q[i] V_q[j+1]).
+__global__ __launch_bounds__(256) void k_tri_gemv(TriArgs a, int j, int p, int want_pc) {
+  __shared__ double pdw[4];
+  const int n = a.n, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = j + 1 + blockIdx.x * 4 + wv;
+  const double* v = a.V + (size_t)p * n;
+  double dot = 0.0;
+  if (i < n) {
+    const double* row = a.A + (size_t)i * n;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int c = j + 1 + lane;
+    for (; c + 192 < n; c += 256) {
+      const double r0 = row[c], r1 = row[c + 64], r2 = row[c + 128], r3 = row[c + 192];
+      const double v0 = v[c], v1 = v[c + 64], v2 = v[c + 128], v3 = v[c + 192];
+      s0 = fma(r0, v0, s0); s1 = fma(r1, v1, s1); s2 = fma(r2, v2, s2); s3 = fma(r3, v3, s3);
+    }
+    for (; c < n; c += 64) s0 = fma(row[c], v[c], s0);
+    double corr = 0.0, pcc = 0.0;
+    if (lane < p) {
+      const double vq = a.V[(size_t)lane * n + i], wq = a.W[(size_t)lane * n + i];
+      corr = vq * a.s12[lane] + wq * a.s12[TNB + lane];
+      if (want_pc)
+        pcc = vq * a.W[(size_t)lane * n + j + 1] + wq * a.V[(size_t)lane * n + j + 1];
+    }
+    const double gi = wave_sum(((s0 + s1) + (s2 + s3)) - corr);
+    if (want_pc) {
+      const double pcs = wave_sum(pcc);
+      if (lane == 0) a.pc[i] = row[j + 1] - pcs;
+    }
+    if (lane == 0) a.g[i] = gi;
+    dot = gi * v[i];
+  }
+  if (lane == 0) pdw[wv] = dot;
+  __syncthreads();
+  if (threadIdx.x == 0) a.pd[blockIdx.x] = (pdw[0] + pdw[1]) + (pdw[2] + pdw[3]);
 }
 
-__global__ __launch_bounds__(TBS) void k_tri_fin(TriArgs a, int jp, int pp) {
+// last column of a panel: w = tau g + alpha v over rows i > jp
+__global__ __launch_bounds__(TBS) void k_tri_fin(TriArgs a, int jp, int pp, int npd) {
   __shared__ double red[TBS / 64];
-  double w[TPT];
-  tri_finalize(a, jp, pp, w, red);
+  const int n = a.n, tid = threadIdx.x;
+  const double tp = a.tau[jp];
+  double sp = 0.0;
+  for (int k = tid; k < npd; k += TBS) sp += a.pd[k];
+  const double alpha = -0.5 * tp * tp * block_sum(sp, red);
+  const double* v = a.V + (size_t)pp * n;
+  for (int i = jp + 1 + tid; i < n; i += TBS) a.W[(size_t)pp * n + i] = tp * a.g[i] + alpha * v[i];
 }
 
 // A[i][c] -= sum_q V[q][i] W[q][c] + W[q][i] V[q][c], i, c >= j1: 64 x 64 tiles
@@ -753,26 +763,27 @@ int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* 
   if (!eig || eig_elems < pinv_workspace_doubles(nmax) || n > nmax)
     return fail(MINSR_E_INVALID_ARG, "pseudo-inverse workspace missing or too small");
   PinvWs w = carve(eig, n, nmax);
-  TriArgs ta{w.A, w.V, w.W, w.tau, w.d, w.e, w.bq, w.g, w.s12, n};
+  TriArgs ta{w.A, w.V, w.W, w.tau, w.d, w.e, w.bq, w.g, w.s12, w.pc, w.pd, n};
   const size_t nn = (size_t)n * n;
   k_pinv_copy<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(T, w.A, nn, b, w.bq, n);
   MINSR_CHECK_LAUNCH();
   // 1. tridiagonalisation
+  int npd = 0;
   for (int j0 = 0; j0 < n; j0 += TNB) {
     const int nb = std::min(TNB, n - j0);
     for (int p = 0; p < nb; ++p) {
       const int j = j0 + p;
-      k_tri_col<<<1, TBS, 0, s>>>(ta, j, p);
+      k_tri_col<<<1, TBS, 0, s>>>(ta, j, p, npd);
       MINSR_CHECK_LAUNCH();
       if (j < n - 1) {
-        k_tri_gemv<<<(unsigned)((n - j - 1 + 3) / 4), 256, 0, s>>>(w.A, w.V + (size_t)p * n, w.g,
-                                                                   n, j);
+        npd = (n - j - 1 + 3) / 4;
+        k_tri_gemv<<<(unsigned)npd, 256, 0, s>>>(ta, j, p, p + 1 < nb ? 1 : 0);
         MINSR_CHECK_LAUNCH();
       }
     }
     const int j1 = j0 + nb;
     if (j1 < n) {
-      k_tri_fin<<<1, TBS, 0, s>>>(ta, j1 - 1, nb - 1);
+      k_tri_fin<<<1, TBS, 0, s>>>(ta, j1 - 1, nb - 1, npd);
       MINSR_CHECK_LAUNCH();
       const unsigned tiles = (unsigned)((n - j1 + 63) / 64);
       k_tri_syr2k<<<dim3(tiles, tiles), 256, 0, s>>>(w.A, w.V, w.W, n, j1, nb);
