@@ -36,12 +36,16 @@ if ROOT not in sys.path:
 METRIC = ("minSR steps/sec at fixed ΔE/N; Jacobian GB/s & Gram MFMA util vs peak")
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
-PEAK_FP32_VEC_TFLOPS = 157.3
+PEAK_FP32_MFMA_TFLOPS = 157.3    # dense FP32 matrix cores (equal to the FP32 vector peak)
 
 # traffic measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE) per launch,
 # scaled by the counter's reading on a plain copy of known size; None until
 # taken for the current kernel version
-TRAFFIC_BYTES = {"eloc": None, "jacobian": None, "gram": None}
+TRAFFIC_BYTES = {"eloc": None,
+                 # k_jacobian: 8649.7 KiB fetched x 2.000 + 52376.3 KiB written x 1.000
+                 "jacobian": 8649.7 * 1024 * 2.0 + 52376.3 * 1024,
+                 # k_gram_bf16 (split form): 212999.8 KiB x 2.000 + 66816.0 KiB x 1.000
+                 "gram": 212999.8 * 1024 * 2.0 + 66816.0 * 1024}
 
 
 def parse():
@@ -52,6 +56,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 form")
     ap.add_argument("--eager", action="store_true", help="time eager steps instead of graph replays")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the short timings of the cluster100, heis10x10 and J1-J2 batch "
+                         "systems")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (for scaling the HBM "
                          "traffic counters of a profiler run), then exit")
@@ -122,6 +129,68 @@ def run_form(pm, wl, form, K, W, dtype="f32", graph=True, kernel_steps=20):
                 energy=E, status=st, kernel_steps=nrec)
 
 
+def time_workload(pm, wl, steps=3):
+    """One eager warmup step, then `steps` eager steps of one system in the
+    BF16 + FP64 form with per-phase events; ms per step and phases."""
+    import torch
+    ham = pm.hamiltonian(wl.ham, J=wl.J, h=wl.h, J2=wl.J2, pbc=wl.pbc)
+    m = pm.Model(wl.Lx, wl.Ly, wl.dim, wl.H, wl.complex_head, wl.marshall, wl.zero_mag,
+                 dtype="f32", seed=wl.seed, max_Ns=wl.Ns, pinv=wl.pinv_cutoff > 0)
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    outs = m.step_outputs(wl.Ns)
+    bad = 0
+
+    def st(i):
+        m.step(ham, wl.Ns, wl.eta, wl.lam, wl.mu, mom, wl.key, i, form=pm.FORM_BF16_FP64,
+               pinv_cutoff=wl.pinv_cutoff, ckpt_every=wl.ckpt_every, outputs=outs)
+
+    st(0)
+    torch.cuda.synchronize()
+    m.timing_begin(steps)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        st(1 + i)
+        bad += int(outs["status"].item() != 0)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ph, n = m.timing_read()
+    res = {"ms_per_step": dt * 1e3, "steps": steps, "Np": m.Np, "Ns": wl.Ns,
+           "N": wl.Lx * wl.Ly, "d_h": wl.H, "status_nonzero_steps": bad,
+           "phase_ms": {k: v / max(n, 1) for k, v in ph.items()}}
+    m.close()
+    return res
+
+
+def time_batch(pm, steps=2):
+    """The sixteen J1-J2 instances stepped by one captured graph (each
+    instance on its own stream): one warmup replay, then `steps` replays."""
+    import torch
+    from workloads import j1j2_batch
+    insts, models = [], []
+    for wl in j1j2_batch():
+        m = pm.Model(wl.Lx, wl.Ly, wl.dim, wl.H, wl.complex_head, wl.marshall, wl.zero_mag,
+                     dtype="f32", seed=wl.seed, max_Ns=wl.Ns)
+        models.append(m)
+        insts.append(dict(model=m, ham=pm.hamiltonian(wl.ham, J=wl.J, h=wl.h, J2=wl.J2,
+                                                       pbc=wl.pbc),
+                          Ns=wl.Ns, eta=wl.eta, lam=wl.lam, mu=wl.mu, key=wl.key,
+                          form=pm.FORM_BF16_FP64))
+    b = pm.Batch(insts)
+    b.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    bad = sum(int(o["status"].item() != 0) for o in b.outputs)
+    b.close()
+    for m in models:
+        m.close()
+    return {"ms_per_batch_step": dt * 1e3, "instance_steps_per_s": len(insts) / dt,
+            "instances": len(insts), "replays": steps, "status_nonzero_instances": bad}
+
+
 def cpu_baseline(wl):
     """One full FP64 oracle step of the workload on the host cores."""
     import numpy as np
@@ -154,9 +223,10 @@ def roofline_entry(name, ms, units):
         ach = units["jacobian_bytes"] / (ms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": TRAFFIC_BYTES["jacobian"], "ms": ms}
+    # FP32 models evaluate the recurrence on v_mfma_f32_32x32x2_f32
     ach = units["eloc_flop"] / (ms * 1e-3) / 1e12
-    return {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VEC_TFLOPS, "unit": "TFLOP/s",
-            "frac": ach / PEAK_FP32_VEC_TFLOPS, "traffic": TRAFFIC_BYTES["eloc"], "ms": ms}
+    return {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": TRAFFIC_BYTES["eloc"], "ms": ms}
 
 
 def main():
@@ -222,6 +292,17 @@ def main():
         (a, sa), (b, sb) = tail_mean(res["energy"]), tail_mean(r32["energy"])
         forms["dE_per_site_bf16_minus_fp32"] = [a - b, math.hypot(sa, sb)]
 
+    others = None
+    if not args.no_workloads:
+        others = {}
+        for name in ("cluster100", "heis10x10"):
+            others[name] = time_workload(pm, WORKLOADS[name])
+            print("%s: %.1f ms/step" % (name, others[name]["ms_per_step"]), file=sys.stderr,
+                  flush=True)
+        others["j1j2batch"] = time_batch(pm)
+        print("j1j2batch: %.1f ms per batch step" % others["j1j2batch"]["ms_per_batch_step"],
+              file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl)
@@ -244,6 +325,7 @@ def main():
                    % (K, "eager" if args.eager else "graph-replayed", res["kernel_steps"])),
         "forms": forms,
         "E0_per_site": wl.E0 / N,
+        "other_workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

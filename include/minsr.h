@@ -269,7 +269,9 @@ int minsr_batch_destroy(minsr_batch* b);
  * key "gram_split": split-K factor of the Gram (0 = built-in heuristic);
  * key "eloc_grid": workgroups of the persistent local-energy launch
  * (0 = one per work item up to the window limit);
- * key "sample_r": sequences per thread of the sampling recurrence (1 or 4).
+ * key "sample_r": sequences per thread of the sampling recurrence (1 or 4);
+ * key "jac_parts": threads per hidden unit of the Jacobian's reverse pass
+ * (1, 2 or 4; d_h = 64 and 128 only; 0 = built-in choice).
  * Values are validated; MINSR_E_INVALID_ARG for an unknown key.           */
 int minsr_set_tunable(minsr_model* m, const char* key, int value);
 int minsr_get_tunable(const minsr_model* m, const char* key, int* value);

@@ -12,6 +12,7 @@ this way.
     gram_split   Gram tiles + reduction       0 (heuristic), 1, 2, 4, 8, 16, 32
     eloc_grid    local-energy recurrence      0 (one per item), 256, 512, 1024, 2048
     sample_r     sampling recurrence          1, 4
+    jac_parts    Jacobian reverse pass        0 (built-in), 1, 2, 4
 """
 import json
 import os
@@ -24,11 +25,13 @@ CANDIDATES = {
     "gram_split": (0, 1, 2, 4, 8, 16, 32),
     "eloc_grid": (0, 256, 512, 1024, 2048),
     "sample_r": (1, 4),
+    "jac_parts": (0, 1, 2, 4),
 }
 PHASES = {
     "gram_split": ("gram", "gram_reduce"),
     "eloc_grid": ("eloc",),
     "sample_r": ("sample",),
+    "jac_parts": ("jacobian",),
 }
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 

@@ -93,6 +93,7 @@ static int ensure_pinv_ws(minsr_model* m, hipStream_t s) {
 
 static void release(minsr_model* m) {
   void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->site, m->contrib,
+                  m->elist, m->ecount, m->eitems,
                   m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
                   m->colpart, m->colmean, m->T, m->Lf, m->Dinv, m->gpart, m->epsp, m->x, m->vwork,
                   m->dpart, m->dtheta, m->status, m->eig, m->csync};
@@ -193,6 +194,9 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   rc = rc ? rc : alloc(&m->states, S * Nz * Hz * sz);
   rc = rc ? rc : alloc((void**)&m->site, S * Nz * 4 * 8);
   rc = rc ? rc : alloc((void**)&m->contrib, (size_t)m->max_terms * S * 2 * 8);
+  rc = rc ? rc : alloc((void**)&m->elist, (size_t)m->max_terms * S * 4);
+  rc = rc ? rc : alloc((void**)&m->ecount, ((size_t)m->max_terms + 1) * 4);
+  rc = rc ? rc : alloc((void**)&m->eitems, (size_t)m->max_terms * ((S + 31) / 32) * 2 * 4);
   if (m->dim == 2) {
     // recompute windows: one per sample (sampling) or per in-flight
     // local-energy sequence (persistent grid of up to 512 x 32 sequences)
@@ -524,6 +528,10 @@ int minsr_set_tunable(minsr_model* m, const char* key, int value) {
   } else if (k == "sample_r") {
     if (value != 0 && value != 1 && value != 4) return fail(MINSR_E_INVALID_ARG, "sample_r in {0, 1, 4}");
     m->tune_sample_r = value;
+  } else if (k == "jac_parts") {
+    if (value != 0 && value != 1 && value != 2 && value != 4)
+      return fail(MINSR_E_INVALID_ARG, "jac_parts in {0, 1, 2, 4}");
+    m->tune_jac_parts = value;
   } else {
     return fail(MINSR_E_INVALID_ARG, "unknown tunable " + k);
   }
@@ -536,6 +544,7 @@ int minsr_get_tunable(const minsr_model* m, const char* key, int* value) {
   if (k == "gram_split") *value = m->tune_gram_split;
   else if (k == "eloc_grid") *value = m->tune_eloc_grid;
   else if (k == "sample_r") *value = m->tune_sample_r;
+  else if (k == "jac_parts") *value = m->tune_jac_parts;
   else return fail(MINSR_E_INVALID_ARG, "unknown tunable " + k);
   return MINSR_OK;
 }

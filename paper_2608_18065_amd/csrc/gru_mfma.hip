@@ -28,7 +28,7 @@ struct ElocMArgs {
   const float* bias;
   const float* head;
   const float* headb;
-  int N, Ns, zero_mag, cplx, marshall, nchunks, n_items, W;
+  int N, Ns, zero_mag, cplx, marshall, nchunks, n_items, W, M;
   const int* nbr;
   const uint8_t* subA;
   const uint8_t* sigma;
@@ -39,6 +39,11 @@ struct ElocMArgs {
   double hx, J1, J2;
   double* contrib;
   float* ring;
+  // J1-J2: only samples whose pair is antiparallel are re-evaluated; items
+  // are (term, chunk of the compacted list)
+  const int* list;      // [M][Ns]
+  const int* count;     // [M], then the item count at [M]
+  const int* items;     // [items][2]
 };
 
 // hardware exp2 and reciprocal (about 1 ulp each): the GRU nonlinearities
@@ -95,8 +100,19 @@ __global__ __launch_bounds__(64 * (H / 32)) void k_eloc_mfma(ElocMArgs a) {
   __syncthreads();
   const float PI = 3.14159265358979323846f;
 
-  for (int item = blockIdx.x; item < a.n_items; item += gridDim.x) {
-    const int t = item / a.nchunks, chunk = item % a.nchunks;
+  const int n_items = a.list ? a.count[a.M] : a.n_items;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    int t, chunk;
+    if (a.list) { t = a.items[2 * item]; chunk = a.items[2 * item + 1]; }
+    else { t = item / a.nchunks; chunk = item % a.nchunks; }
+    const int navail = a.list ? a.count[t] : a.Ns;
+    const int* lst = a.list ? a.list + (size_t)t * a.Ns : nullptr;
+    // sample of row q of this item (row 0's sample for padding rows)
+    auto row_sample = [&](int q) {
+      int i = chunk * S + q;
+      if (i >= navail) i = 0;
+      return lst ? lst[i] : i;
+    };
     int f1, f2p = -1;
     double Jt = 0.0;
     if (a.ham_kind == MINSR_HAM_J1J2) {
@@ -106,9 +122,9 @@ __global__ __launch_bounds__(64 * (H / 32)) void k_eloc_mfma(ElocMArgs a) {
       f1 = t;
     }
     const int k0 = f1;
-    const int s = chunk * S + col;      // this lane's sequence (both halves)
-    const bool act = s < a.Ns;
-    const int sid = act ? s : 0;
+    const bool act = chunk * S + col < navail;   // this lane's sequence (both halves)
+    const int s = row_sample(col);
+    const int sid = s;
     const uint8_t* sg = a.sigma + (size_t)sid * N;
     const double* st = a.site + (size_t)sid * N * 4;
     int nup = 0, ndn = 0, dA = 0;
@@ -144,8 +160,7 @@ __global__ __launch_bounds__(64 * (H / 32)) void k_eloc_mfma(ElocMArgs a) {
     if (DIM == 1 && k0 + 1 < N) {
       for (int i = tid; i < S * H; i += NT) {
         const int q = i / H, u = i % H;
-        int sq = chunk * S + q;
-        sq = sq < a.Ns ? sq : 0;
+        const int sq = row_sample(q);
         hA[(k0 + 1) & 1][q][u] = a.states[((size_t)sq * N + k0) * H + u];
       }
     }
@@ -165,8 +180,7 @@ __global__ __launch_bounds__(64 * (H / 32)) void k_eloc_mfma(ElocMArgs a) {
           const int u = r < H ? r : r - H;
           float v = 0.f;
           if (pos >= 0) {
-            int sq = chunk * S + q;
-            sq = sq < a.Ns ? sq : 0;
+            const int sq = row_sample(q);
             if (pos <= k0) v = a.states[((size_t)sq * N + pos) * H + u];
             else v = a.ring[(((size_t)blockIdx.x * S + q) * a.W + pos % a.W) * H + u];
           }
@@ -278,6 +292,72 @@ __global__ __launch_bounds__(64 * (H / 32)) void k_eloc_mfma(ElocMArgs a) {
   }
 }
 
+// J1-J2 exchange terms vanish unless the pair is antiparallel: per term,
+// the samples with sigma_a != sigma_b in ascending order (one workgroup per
+// term, block-wide scan); the other samples' contributions are zeroed here.
+__global__ __launch_bounds__(1024) void k_eloc_compact(const uint8_t* sigma, const int* bonds,
+                                                       int N, int Ns, int* list, int* count,
+                                                       double* contrib) {
+  __shared__ int wsum[16];
+  __shared__ int base;
+  const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int fa = bonds[2 * t], fb = bonds[2 * t + 1];
+  if (tid == 0) base = 0;
+  __syncthreads();
+  for (int s0 = 0; s0 < Ns; s0 += 1024) {
+    const int s = s0 + tid;
+    int flag = 0;
+    if (s < Ns) {
+      const uint8_t* sg = sigma + (size_t)s * N;
+      flag = sg[fa] != sg[fb];
+      if (!flag) {
+        contrib[((size_t)t * Ns + s) * 2] = 0.0;
+        contrib[((size_t)t * Ns + s) * 2 + 1] = 0.0;
+      }
+    }
+    // inclusive scan within the wave, then across waves
+    int x = flag;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int off = base;
+    for (int i = 0; i < wv; ++i) off += wsum[i];
+    if (flag) list[(size_t)t * Ns + off + x - 1] = s;
+    __syncthreads();
+    if (tid == 0) {
+      int tot = 0;
+      for (int i = 0; i < 16; ++i) tot += wsum[i];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) count[t] = base;
+}
+
+// item table (term, chunk) over the compacted lists; the total goes to count[M]
+__global__ __launch_bounds__(1024) void k_eloc_items(int* count, int M, int* items) {
+  __shared__ int start[1025];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    int acc = 0;
+    for (int t = 0; t < M; ++t) { start[t] = acc; acc += (count[t] + 31) / 32; }
+    start[M] = acc;
+  }
+  __syncthreads();
+  for (int t = tid; t < M; t += 1024) {
+    const int nc = start[t + 1] - start[t];
+    for (int c = 0; c < nc; ++c) {
+      items[2 * (start[t] + c)] = t;
+      items[2 * (start[t] + c) + 1] = c;
+    }
+  }
+  if (tid == 0) count[M] = start[M];
+}
+
 bool eloc_mfma_supported(minsr_model* m) {
   return !m->f64 && (m->H == 32 || m->H == 64 || m->H == 128);
 }
@@ -295,7 +375,16 @@ int launch_eloc_mfma(minsr_model* m, const minsr_hamiltonian* H, int Ns, const u
   a.nbr = m->nbr; a.subA = m->subA; a.sigma = sigma; a.states = (const float*)states;
   a.site = site; a.bonds = m->bonds; a.n_nn = m->n_nn; a.ham_kind = H->kind;
   a.hx = H->h; a.J1 = H->J; a.J2 = H->J2; a.contrib = m->contrib; a.ring = (float*)m->ring;
+  a.M = M;
   if (a.n_items == 0) return MINSR_OK;
+  if (H->kind == MINSR_HAM_J1J2) {
+    if (M > 1024) return fail(MINSR_E_UNSUPPORTED, "more than 1024 exchange terms");
+    k_eloc_compact<<<M, 1024, 0, s>>>(sigma, m->bonds, m->N, Ns, m->elist, m->ecount, m->contrib);
+    MINSR_CHECK_LAUNCH();
+    k_eloc_items<<<1, 1024, 0, s>>>(m->ecount, M, m->eitems);
+    MINSR_CHECK_LAUNCH();
+    a.list = m->elist; a.count = m->ecount; a.items = m->eitems;
+  }
   unsigned grid = (unsigned)a.n_items;
   if (m->tune_eloc_grid > 0) grid = std::min<unsigned>(grid, (unsigned)m->tune_eloc_grid);
   if (m->dim == 2) {

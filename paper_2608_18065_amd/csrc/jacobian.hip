@@ -520,14 +520,23 @@ static int launch_jac_t(const JacArgs<T>& a, hipStream_t s) {
   return MINSR_OK;
 }
 
+// parts: threads per hidden unit (0 = built-in choice)
 template <typename T, int DIM>
-static int jac_dispatch(int H, const JacArgs<T>& a, hipStream_t s) {
+static int jac_dispatch(int H, int parts, const JacArgs<T>& a, hipStream_t s) {
   switch (H) {
     case 8: return launch_jac_t<T, 8, DIM, 1>(a, s);
     case 16: return launch_jac_t<T, 16, DIM, 1>(a, s);
     case 32: return launch_jac_t<T, 32, DIM, 1>(a, s);
-    case 64: return launch_jac_t<T, 64, DIM, DIM == 1 ? 1 : 4>(a, s);
-    case 128: return launch_jac_t<T, 128, DIM, DIM == 1 ? 2 : 4>(a, s);
+    case 64:
+      if (parts == 0) parts = DIM == 1 ? 1 : 4;
+      if (parts == 1) return launch_jac_t<T, 64, DIM, 1>(a, s);
+      if (parts == 2) return launch_jac_t<T, 64, DIM, 2>(a, s);
+      return launch_jac_t<T, 64, DIM, 4>(a, s);
+    case 128:
+      if (parts == 0) parts = 2;
+      if (parts == 1) return launch_jac_t<T, 128, DIM, 1>(a, s);
+      if (parts == 2) return launch_jac_t<T, 128, DIM, 2>(a, s);
+      return launch_jac_t<T, 128, DIM, 4>(a, s);
   }
   return fail(MINSR_E_UNSUPPORTED, "hidden width must be 8, 16, 32, 64 or 128");
 }
@@ -541,8 +550,8 @@ static int jac_t(minsr_model* m, const Work<T>& w, int Ns, const uint8_t* sigma,
   a.sigma = sigma; a.states = (const T*)states; a.O = (T*)O;
   a.scale = (T)(1.0 / std::sqrt((double)Ns));
   a.W2 = 2 * m->d.Lx;
-  if (m->dim == 1) return jac_dispatch<T, 1>(m->H, a, s);
-  return jac_dispatch<T, 2>(m->H, a, s);
+  if (m->dim == 1) return jac_dispatch<T, 1>(m->H, m->tune_jac_parts, a, s);
+  return jac_dispatch<T, 2>(m->H, m->tune_jac_parts, a, s);
 }
 
 int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* states,

@@ -327,7 +327,8 @@ constexpr int MAX_SPLIT = 64;
 // split-K factor: requested, else enough for ~1024 workgroups; at most
 // MAX_SPLIT, 4096 workgroups in total, and chunks of >= 256 columns
 static int pick_split(int npairs, size_t Np, int want) {
-  int S = want > 0 ? want : (1024 + npairs - 1) / npairs;
+  // default: about 4096 workgroups, at most 16 partial tiles per pair
+  int S = want > 0 ? want : std::min(16, (4096 + npairs - 1) / npairs);
   const int by_grid = std::max(1, (4096 + npairs - 1) / npairs);
   int maxS = (int)std::max<size_t>(1, std::min<size_t>(MAX_SPLIT, Np / 256));
   maxS = std::min(maxS, by_grid);
@@ -430,79 +431,119 @@ __device__ __forceinline__ float rsqrt_nr(float d) {
   return fmaf(0.5f * y, e, y);
 }
 
-// Factor the tile in Ls (rows < nb valid, lower triangle read) with the
-// first two wavefronts of the workgroup; every thread of the workgroup must
-// call it.  Wave 0 keeps row `lane` of the tile in registers and performs
-// the column sweep; wave 1 keeps column `lane` of inv(L) and eliminates with
-// each finished column one barrier later.  Writes L to A and inv(L)
-// (row-major, zero above the diagonal) to Di and to the shared tile Is.
+// Factor the 64 x 64 tile Lt (rows < nb valid, lower triangle read) with a
+// workgroup of four wavefronts; every thread must call it.  Wave w keeps, for
+// row `lane`, the sixteen columns [16w, 16w + 16) in registers.  Panel P
+// (the columns of wave P) is factored by wave P alone, the pivot column
+// reaching the other lanes through readlane; the later waves then subtract
+// the rank-16 product of the panel, read from shared memory.  The inverse
+// follows blockwise: each wave inverts its 16 x 16 diagonal block with the
+// same register broadcasts, the blocks below by Z_QP = -Z_QQ sum_R L_QR Z_RP.
+// Writes L to A and to Lt (zero above the diagonal), inv(L) to Di and Is.
 template <typename TT>
-__device__ void factor_block(const TT (*Ls)[CB + 1], TT (*Lc)[CB], TT* rd, TT (*Is)[CB + 1],
-                             int nb, TT* A, int n, int k0, TT* Di, uint32_t* status) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  TT v[CB];
-  if (wave == 0) {
+__device__ void factor_block(TT (*Lt)[CB + 1], TT (*Pn)[CB], TT (*Is)[CB + 1], int nb, TT* A,
+                             int n, int k0, TT* Di, uint32_t* status) {
+  constexpr int PB = 16;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  TT f[PB];
 #pragma unroll
-    for (int q = 0; q < CB; ++q)
-      v[q] = (q <= lane && lane < nb) ? Ls[lane][q] : (lane == q ? (TT)1 : (TT)0);
-  } else {
-#pragma unroll
-    for (int q = 0; q < CB; ++q) v[q] = (q == lane) ? (TT)1 : (TT)0;
+  for (int k = 0; k < PB; ++k) {
+    const int q = PB * w + k;
+    f[k] = lane < nb ? (q <= lane ? Lt[lane][q] : (TT)0) : (lane == q ? (TT)1 : (TT)0);
   }
   bool bad = false;
+  __syncthreads();
+  for (int P = 0; P < CB / PB; ++P) {
+    if (w == P) {
 #pragma unroll
-  for (int c = 0; c < CB; ++c) {
-    TT lc = (TT)0;
-    if (wave == 0) {
-      TT d = lane_bcast(v[c], c);
-      if (!(d > (TT)0)) { bad = true; d = (TT)1; }
-      const TT rp = rsqrt_nr(d);
-      lc = (lane == c) ? d * rp : v[c] * rp;
-      Lc[c][lane] = lc;
-      if (lane == 0) rd[c] = rp;
-    }
-    __syncthreads();
-    if (wave < 2) {
-      // the finished column, read in one batch of 16-byte loads
-      TT cv[CB];
-      constexpr int VW = 16 / sizeof(TT);
-      using vec_t = typename std::conditional<sizeof(TT) == 8, double2, float4>::type;
-      const int Q0 = ((c + 1) / VW) * VW;
-#pragma unroll
-      for (int q = Q0; q < CB; q += VW) {
-        const vec_t t = *reinterpret_cast<const vec_t*>(&Lc[c][q]);
-        const TT* tp = reinterpret_cast<const TT*>(&t);
-#pragma unroll
-        for (int u = 0; u < VW; ++u) cv[q + u] = tp[u];
-      }
-      if (wave == 0) {
-        v[c] = lc;
+      for (int cc = 0; cc < PB; ++cc) {
+        const int c = PB * P + cc;
+        TT d = lane_bcast(f[cc], c);
+        if (!(d > (TT)0)) { bad = true; d = (TT)1; }
+        const TT rp = rsqrt_nr(d);
+        const TT lc = (lane == c) ? d * rp : f[cc] * rp;
+        f[cc] = lc;
         const TT nl = lane > c ? -lc : (TT)0;
 #pragma unroll
-        for (int q = c + 1; q < CB; ++q) v[q] = fma(nl, cv[q], v[q]);
-      } else {
-        const TT z = v[c] * rd[c];
-        v[c] = z;
+        for (int kk = cc + 1; kk < PB; ++kk) f[kk] = fma(nl, lane_bcast(lc, PB * P + kk), f[kk]);
+      }
 #pragma unroll
-        for (int q = c + 1; q < CB; ++q) v[q] = fma(-cv[q], z, v[q]);
+      for (int cc = 0; cc < PB; ++cc) Pn[lane][cc] = f[cc];
+    }
+    __syncthreads();
+    if (w > P) {
+      TT own[PB];
+#pragma unroll
+      for (int cc = 0; cc < PB; ++cc) own[cc] = Pn[lane][cc];
+#pragma unroll
+      for (int k = 0; k < PB; ++k) {
+        const int q = PB * w + k;
+        TT s = (TT)0;
+#pragma unroll
+        for (int cc = 0; cc < PB; ++cc) s = fma(own[cc], Pn[q][cc], s);
+        f[k] -= s;
       }
     }
+    __syncthreads();
   }
-  if (wave == 0) {
-    if (bad && lane == 0 && status) atomicOr(status, MINSR_ST_NOT_PD);
-    if (lane < nb) {
+  if (bad && lane == 0 && status) atomicOr(status, MINSR_ST_NOT_PD);
+  // L to shared memory and A
 #pragma unroll
-      for (int q = 0; q < CB; ++q)
-        if (q <= lane) A[(size_t)(k0 + lane) * n + k0 + q] = v[q];
-    }
-  } else if (wave == 1) {
-    // lane c holds column c of inv(L): rows i < c are zero
+  for (int k = 0; k < PB; ++k) {
+    const int q = PB * w + k;
+    const TT v = q <= lane ? f[k] : (TT)0;
+    Lt[lane][q] = v;
+    if (q <= lane && lane < nb) A[(size_t)(k0 + lane) * n + k0 + q] = v;
+  }
+  // inverse of this wave's diagonal block: lane 16w + j keeps column j
+  {
+    TT z[PB];
 #pragma unroll
-    for (int i = 0; i < CB; ++i) {
-      const TT w = (i < nb && lane < nb) ? v[i] : (TT)0;
-      Di[(size_t)i * CB + lane] = w;
-      Is[i][lane] = w;
+    for (int i = 0; i < PB; ++i) z[i] = (PB * w + i == lane) ? (TT)1 : (TT)0;
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      const TT lii = lane_bcast(f[i], PB * w + i);
+      const TT zi = z[i] / lii;
+      z[i] = zi;
+#pragma unroll
+      for (int q = i + 1; q < PB; ++q) z[q] = fma(-lane_bcast(f[i], PB * w + q), zi, z[q]);
     }
+    if (lane >= PB * w && lane < PB * (w + 1)) {
+#pragma unroll
+      for (int i = 0; i < PB; ++i) Is[PB * w + i][lane] = z[i];
+    }
+  }
+  // the other blocks start at zero (the ones below are filled next)
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e / CB, j = e % CB;
+    if (i / PB != j / PB) Is[i][j] = (TT)0;
+  }
+  __syncthreads();
+  // blocks below the diagonal, one level of Q - P at a time
+  TT* tmp = &Pn[0][0];   // [3][16][16]
+  for (int lv = 1; lv < CB / PB; ++lv) {
+    const int nblk = CB / PB - lv;
+    for (int e = tid; e < nblk * PB * PB; e += 256) {
+      const int b = e / (PB * PB), i = (e / PB) % PB, j = e % PB;
+      const int P = b, Q = b + lv;
+      TT s = (TT)0;
+      for (int R = P; R < Q; ++R)
+        for (int k = 0; k < PB; ++k) s = fma(Lt[PB * Q + i][PB * R + k], Is[PB * R + k][PB * P + j], s);
+      tmp[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < nblk * PB * PB; e += 256) {
+      const int b = e / (PB * PB), i = (e / PB) % PB, j = e % PB;
+      const int P = b, Q = b + lv;
+      TT s = (TT)0;
+      for (int k = 0; k < PB; ++k) s = fma(Is[PB * Q + i][PB * Q + k], tmp[b * PB * PB + k * PB + j], s);
+      Is[PB * Q + i][PB * P + j] = -s;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e / CB, j = e % CB;
+    Di[e] = (i < nb && j < nb) ? Is[i][j] : (TT)0;
   }
 }
 
@@ -524,7 +565,6 @@ __global__ __launch_bounds__(256) void k_chol_step(CholArgs a, int k) {
   __shared__ TT Li[CB][CB + 1];
   __shared__ TT Lj[CB][CB + 1];
   __shared__ __align__(16) TT Lc[CB][CB];
-  __shared__ TT rd[CB];
   __shared__ TT yb[CB];
   __shared__ int tk;
   const int n = a.n, tid = threadIdx.x;
@@ -620,7 +660,7 @@ __global__ __launch_bounds__(256) void k_chol_step(CholArgs a, int k) {
       for (int z = 0; z < 4; ++z) Li[tr + x][tc + z] = t[x][z];
     if (tid < CB) yb[tid] = tid < nb ? y[kb0 + tid] : (TT)0;
     __syncthreads();
-    factor_block<TT>(Li, Lc, rd, Lj, nb, A, n, kb0, Di, a.status);
+    factor_block<TT>(Li, Lc, Lj, nb, A, n, kb0, Di, a.status);
     __syncthreads();
     // y_kk = inv(L) b_kk with the inverse from shared memory, 4 threads a row
     {
@@ -632,9 +672,14 @@ __global__ __launch_bounds__(256) void k_chol_step(CholArgs a, int k) {
       s += __shfl_xor(s, 2, 4);
       if (part == 0 && row < nb) y[kb0 + row] = s;
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&flags[kk], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (kk + 1 < a.nblk) {
+      // every wave's stores complete (a workgroup barrier alone does not wait
+      // for global stores), then one agent-scope release: a single L2
+      // write-back instead of one per wave
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+      __syncthreads();
+      if (tid == 0) __hip_atomic_store(&flags[kk], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
     return;
   }
 
@@ -643,8 +688,8 @@ __global__ __launch_bounds__(256) void k_chol_step(CholArgs a, int k) {
     while (__hip_atomic_load(&flags[kk], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
       __builtin_amdgcn_s_sleep(2);
   }
+  // the acquiring load invalidated this CU's L1 and its L2 for every wave
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll

@@ -27,6 +27,9 @@ struct minsr_model {
   void* states = nullptr;   // [max_Ns][N][H] hidden states
   double* site = nullptr;   // [max_Ns][N][4]: log p(0), log p(1), phi(0), phi(1)
   double* contrib = nullptr;// [max_terms][max_Ns][2]
+  int* elist = nullptr;     // [max_terms][max_Ns] samples with a nonzero matrix element
+  int* ecount = nullptr;    // [max_terms + 1] their counts, then the item count
+  int* eitems = nullptr;    // [max_terms * ceil(max_Ns / 32)][2] (term, chunk)
   double* diag = nullptr;   // [max_Ns]
   void* ring = nullptr;     // 2D local-energy recompute windows
   int ring_blocks = 0;
@@ -60,6 +63,7 @@ struct minsr_model {
   int tune_gram_split = 0;
   int tune_eloc_grid = 0;
   int tune_sample_r = 0;
+  int tune_jac_parts = 0;
 
   // per-phase event timing of minsr_step (profiling only)
   std::vector<hipEvent_t> ev;   // [t_max][NPHASE + 1]

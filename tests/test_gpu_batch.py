@@ -60,6 +60,7 @@ def test_tunables_roundtrip_and_effect_free():
     m2.set_tunable("gram_split", 3)
     m2.set_tunable("eloc_grid", 7)
     m2.set_tunable("sample_r", 4)
+    m2.set_tunable("jac_parts", 4)
     assert m2.get_tunable("gram_split") == 3
     with pytest.raises(pm.MinsrError):
         m2.set_tunable("nonsense", 1)
@@ -82,3 +83,24 @@ def test_tunables_roundtrip_and_effect_free():
     # low-precision forms against the FP64 reference
     d0, d1 = outs[0]["dtheta"], outs[1]["dtheta"]
     assert float((d0 - d1).norm() / d0.norm()) < 2e-2
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    need_gpu()
+    import paper_2608_18065_amd as pm
+    from paper_2608_18065_amd import autotune
+    m = pm.Model(16, hidden=64, dtype="f32", seed=4, max_Ns=256)
+    ham = pm.hamiltonian("tfim", pbc=True)
+    cache = str(tmp_path / "tune.json")
+    res = autotune.tune(m, ham, 256, reps=2, cache=cache)
+    assert set(res) == set(autotune.CANDIDATES)
+    for key, (best, times) in res.items():
+        assert best in autotune.CANDIDATES[key]
+        assert times[best] == min(times.values())
+        assert m.get_tunable(key) == best
+    # a fresh model of the same shape picks the cached values up
+    m2 = pm.Model(16, hidden=64, dtype="f32", seed=5, max_Ns=256)
+    applied = autotune.apply(m2, 256, cache=cache)
+    assert applied == {k: v[0] for k, v in res.items()}
+    for k, v in applied.items():
+        assert m2.get_tunable(k) == v

@@ -373,6 +373,25 @@ def test_jacobian_fp32_model(arch):
     assert rel_err(O.cpu().numpy(), ref) < 1e-4
 
 
+@pytest.mark.parametrize("arch,parts", [(dict(Lx=14, H=64), 2), (dict(Lx=14, H=64), 4),
+                                         (dict(Lx=9, H=128, cplx=True), 1),
+                                         (dict(Lx=9, H=128, cplx=True), 4),
+                                         (dict(Lx=4, Ly=3, dim=2, H=64, marshall=True), 1)],
+                         ids=["h64p2", "h64p4", "h128c_p1", "h128c_p4", "2d_p1"])
+def test_jacobian_thread_parts(arch, parts):
+    # every split of the reverse products over threads gives the oracle's rows
+    spec, m = make_pair(**arch, dtype="f32")
+    th = scaled_theta(spec, 17, 1.0)
+    m.set_params(to_dev(th))
+    m.set_tunable("jac_parts", parts)
+    Ns = 5
+    sig, _ = omodel.sample(spec, th, philox.uniforms(9, 1, Ns, spec.N))
+    D = ojac.log_derivatives(spec, th, sig)
+    ref = (np.concatenate([D.real, D.imag], axis=0) if spec.complex_head else D) / np.sqrt(Ns)
+    O, _ = m.jacobian(to_dev(sig.astype(np.uint8)))
+    assert rel_err(O.cpu().numpy(), ref) < 1e-4
+
+
 @pytest.mark.parametrize("form", [1, 3, 2], ids=["bf16_split_mfma", "bf16_1pass_mfma", "fp32"])
 def test_gram_matches_its_operand(form):
     # T of the low-precision forms equals O' O'^T of the O' the kernel
