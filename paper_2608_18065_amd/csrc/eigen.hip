@@ -154,22 +154,34 @@ constexpr int TPT = PINV_MAX_N / TBS;      // rows per thread in single-workgrou
 __global__ __launch_bounds__(TBS) void k_tri_col(TriArgs a, int j, int p, int npd) {
   __shared__ double red[TBS / 64];
   __shared__ double sh[4];
-  __shared__ double part2[TBS / 64][2 * TNB];
+  __shared__ double vsh[PINV_MAX_N], wsh[PINV_MAX_N], vlsh[PINV_MAX_N];
+  __shared__ double gpart[32];
   const int n = a.n, tid = threadIdx.x;
   double col[TPT], wl[TPT], vl[TPT];
+  // every global operand of this thread's rows is requested up front, so
+  // the kernel waits for memory once rather than once per phase
+  double gl_[TPT], pc_[TPT], bq_[TPT];
+  const double* vprev = a.V + (size_t)(p > 0 ? p - 1 : 0) * n;
+#pragma unroll
+  for (int u = 0; u < TPT; ++u) {
+    const int i = j + tid + TBS * u;
+    const bool ok = i < n;
+    vl[u] = (ok && p > 0) ? vprev[i] : 0.0;
+    gl_[u] = (ok && p > 0) ? a.g[i] : 0.0;
+    pc_[u] = ok ? (p > 0 ? a.pc[i] : a.A[(size_t)j * n + i]) : 0.0;
+    bq_[u] = ok ? a.bq[i] : 0.0;
+  }
   if (p > 0) {
     const double tp = a.tau[j - 1];
     double sp = 0.0;
     for (int k = tid; k < npd; k += TBS) sp += a.pd[k];
     const double alpha = -0.5 * tp * tp * block_sum(sp, red);
-    const double* vprev = a.V + (size_t)(p - 1) * n;
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
       const int i = j + tid + TBS * u;
-      vl[u] = 0.0; wl[u] = 0.0;
+      wl[u] = 0.0;
       if (i < n) {
-        vl[u] = vprev[i];
-        wl[u] = tp * a.g[i] + alpha * vl[u];
+        wl[u] = tp * gl_[u] + alpha * vl[u];
         a.W[(size_t)(p - 1) * n + i] = wl[u];
       }
     }
@@ -179,15 +191,11 @@ __global__ __launch_bounds__(TBS) void k_tri_col(TriArgs a, int j, int p, int np
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
       const int i = j + tid + TBS * u;
-      col[u] = i < n ? a.pc[i] - (vl[u] * Wj + wl[u] * Vj) : 0.0;
+      col[u] = i < n ? pc_[u] - (vl[u] * Wj + wl[u] * Vj) : 0.0;
     }
   } else {
 #pragma unroll
-    for (int u = 0; u < TPT; ++u) {
-      const int i = j + tid + TBS * u;
-      col[u] = i < n ? a.A[(size_t)j * n + i] : 0.0;
-      wl[u] = 0.0; vl[u] = 0.0;
-    }
+    for (int u = 0; u < TPT; ++u) { col[u] = pc_[u]; wl[u] = 0.0; }
   }
   if (tid == 0) a.d[j] = col[0];
   if (j == n - 1) return;
@@ -221,47 +229,61 @@ __global__ __launch_bounds__(TBS) void k_tri_col(TriArgs a, int j, int p, int np
     if (i > j && i < n) {
       a.V[(size_t)p * n + i] = vi;
       a.A[(size_t)j * n + i] = vi;
-      pb += vi * a.bq[i];
+      pb += vi * bq_[u];
     }
   }
   const double vb = t * block_sum(pb, red);
 #pragma unroll
   for (int u = 0; u < TPT; ++u) {
     const int i = j + tid + TBS * u;
-    if (i > j && i < n) a.bq[i] -= vb * v[u];
+    if (i > j && i < n) a.bq[i] = bq_[u] - vb * v[u];
   }
-  // s1[q] = W[q] . v, s2[q] = V[q] . v over rows > j, q < p
+  // s1[q] = W[q] . v, s2[q] = V[q] . v over rows > j, q < p: thread group
+  // g (32 threads) owns one of the 2p values and strides over the rows, so
+  // every load is coalesced within the group and each value needs a single
+  // 32-lane reduction; v and the finalised column p - 1 come from LDS
   if (p > 0) {
-    double s[2 * TNB];
-#pragma unroll
-    for (int q = 0; q < 2 * TNB; ++q) s[q] = 0.0;
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
       const int i = j + tid + TBS * u;
-      if (i > j && i < n) {
-#pragma unroll
-        for (int q = 0; q < TNB; ++q) {
-          if (q < p - 1) {
-            s[q] += a.W[(size_t)q * n + i] * v[u];
-            s[TNB + q] += a.V[(size_t)q * n + i] * v[u];
-          } else if (q == p - 1) {
-            s[q] += wl[u] * v[u];
-            s[TNB + q] += vl[u] * v[u];
-          }
-        }
-      }
-    }
-    const int lane = tid & 63, wv = tid >> 6;
-#pragma unroll
-    for (int q = 0; q < 2 * TNB; ++q) {
-      const double r = wave_sum(s[q]);
-      if (lane == 0) part2[wv][q] = r;
+      if (i < n) { vsh[i - j] = v[u]; wsh[i - j] = wl[u]; vlsh[i - j] = vl[u]; }
     }
     __syncthreads();
-    if (tid < 2 * TNB) {
+    // 32 groups of 32 threads; each of the 2p values gets gpv groups that
+    // split its rows; four independent accumulators keep loads in flight
+    const int grp = tid >> 5, gl = tid & 31;
+    const int nval = 2 * p, gpv = nval >= 32 ? 1 : 32 / nval;
+    const int val = grp / gpv, sub = grp % gpv;
+    double acc = 0.0;
+    if (val < nval) {
+      const bool isw = val < p;
+      const int q = isw ? val : val - p;
+      const double* colp = (isw ? a.W : a.V) + (size_t)q * n;
+      const double* xs = (q == p - 1) ? (isw ? wsh : vlsh) : nullptr;
+      const int stride = 32 * gpv;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int i = j + 1 + sub * 32 + gl;
+      for (; i + 3 * stride < n; i += 4 * stride) {
+        const double x0 = xs ? xs[i - j] : colp[i];
+        const double x1 = xs ? xs[i + stride - j] : colp[i + stride];
+        const double x2 = xs ? xs[i + 2 * stride - j] : colp[i + 2 * stride];
+        const double x3 = xs ? xs[i + 3 * stride - j] : colp[i + 3 * stride];
+        a0 = fma(x0, vsh[i - j], a0);
+        a1 = fma(x1, vsh[i + stride - j], a1);
+        a2 = fma(x2, vsh[i + 2 * stride - j], a2);
+        a3 = fma(x3, vsh[i + 3 * stride - j], a3);
+      }
+      for (; i < n; i += stride) a0 = fma(xs ? xs[i - j] : colp[i], vsh[i - j], a0);
+      acc = (a0 + a1) + (a2 + a3);
+#pragma unroll
+      for (int m = 16; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 32);
+    }
+    if (gl == 0) gpart[grp] = acc;
+    __syncthreads();
+    if (tid < nval) {
       double r = 0.0;
-      for (int w = 0; w < TBS / 64; ++w) r += part2[w][tid];
-      a.s12[tid] = r;
+      for (int k = 0; k < gpv; ++k) r += gpart[tid * gpv + k];
+      a.s12[tid < p ? tid : TNB + (tid - p)] = r;
     }
   }
 }
@@ -280,6 +302,13 @@ __global__ __launch_bounds__(256) void k_tri_gemv(TriArgs a, int j, int p, int w
     const double* row = a.A + (size_t)i * n;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int c = j + 1 + lane;
+    for (; c + 448 < n; c += 512) {
+      double r[8], x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) { r[q] = row[c + 64 * q]; x[q] = v[c + 64 * q]; }
+      s0 = fma(r[0], x[0], s0); s1 = fma(r[1], x[1], s1); s2 = fma(r[2], x[2], s2); s3 = fma(r[3], x[3], s3);
+      s0 = fma(r[4], x[4], s0); s1 = fma(r[5], x[5], s1); s2 = fma(r[6], x[6], s2); s3 = fma(r[7], x[7], s3);
+    }
     for (; c + 192 < n; c += 256) {
       const double r0 = row[c], r1 = row[c + 64], r2 = row[c + 128], r3 = row[c + 192];
       const double v0 = v[c], v1 = v[c + 64], v2 = v[c + 128], v3 = v[c + 192];
