@@ -152,7 +152,7 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
             ar += w.xc[(1 * ds + sprev) * H + j];
             ai += w.xc[(2 * ds + sprev) * H + j];
           }
-#pragma unroll 2
+#pragma unroll 4
           for (int k4 = 0; k4 < H / V; ++k4) {
             const VT wu = fw[(k4 * H + j) * 3 + 0];
             const VT wr = fw[(k4 * H + j) * 3 + 1];
@@ -369,9 +369,10 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
           }
         }
         __syncthreads();
-        // reverse product into the cell input: rows i of part p
-        T part = (T)0;
-#pragma unroll 1
+        // reverse product into the cell input: rows i of part p; four
+        // partial sums so that several weight loads are in flight
+        T partv[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll 4
         for (int i4 = p * CP / V; i4 < (p + 1) * CP / V; ++i4) {
           const VT wu = bw[(i4 * H + j) * 3 + 0];
           const VT wr = bw[(i4 * H + j) * 3 + 1];
@@ -385,6 +386,7 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
           const T* d0s = reinterpret_cast<const T*>(&d0);
           const T* d1s = reinterpret_cast<const T*>(&d1);
           const T* d2s = reinterpret_cast<const T*>(&d2);
+          T& part = partv[i4 & 3];
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             part = fma(wus[v], d0s[v], part);
@@ -392,6 +394,7 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
             part = fma(wgs[v], d2s[v], part);
           }
         }
+        const T part = (partv[0] + partv[1]) + (partv[2] + partv[3]);
         T dhin;
         if (P > 1) {
           pbuf[sg][p][0][j] = part;

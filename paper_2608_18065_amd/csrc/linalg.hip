@@ -327,8 +327,8 @@ constexpr int MAX_SPLIT = 64;
 // split-K factor: requested, else enough for ~1024 workgroups; at most
 // MAX_SPLIT, 4096 workgroups in total, and chunks of >= 256 columns
 static int pick_split(int npairs, size_t Np, int want) {
-  // default: about 4096 workgroups, at most 16 partial tiles per pair
-  int S = want > 0 ? want : std::min(16, (4096 + npairs - 1) / npairs);
+  // default: about 4096 workgroups, at most 8 partial tiles per pair
+  int S = want > 0 ? want : std::min(8, (4096 + npairs - 1) / npairs);
   const int by_grid = std::max(1, (4096 + npairs - 1) / npairs);
   int maxS = (int)std::max<size_t>(1, std::min<size_t>(MAX_SPLIT, Np / 256));
   maxS = std::min(maxS, by_grid);
