@@ -41,11 +41,13 @@ PEAK_FP32_MFMA_TFLOPS = 157.3    # dense FP32 matrix cores (equal to the FP32 ve
 # traffic measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE) per launch,
 # scaled by the counter's reading on a plain copy of known size; None until
 # taken for the current kernel version
-TRAFFIC_BYTES = {"eloc": None,
-                 # k_jacobian: 8649.7 KiB fetched x 2.000 + 52376.3 KiB written x 1.000
-                 "jacobian": 8649.7 * 1024 * 2.0 + 52376.3 * 1024,
-                 # k_gram_bf16 (split form): 212999.8 KiB x 2.000 + 66816.0 KiB x 1.000
-                 "gram": 212999.8 * 1024 * 2.0 + 66816.0 * 1024}
+TRAFFIC_BYTES = {
+    # k_eloc_mfma: 9423.0 KiB fetched x 2.000 + 1024.0 KiB written x 1.000
+    "eloc": 9423.0 * 1024 * 2.0 + 1024.0 * 1024,
+    # k_jacobian: 8661.7 KiB fetched x 2.000 + 52380.7 KiB written x 1.000
+    "jacobian": 8661.7 * 1024 * 2.0 + 52380.7 * 1024,
+    # k_gram_bf16 (split form, 8-way split-K): 187973.1 KiB x 2.000 + 18432.0 KiB x 1.000
+    "gram": 187973.1 * 1024 * 2.0 + 18432.0 * 1024}
 
 
 def parse():
