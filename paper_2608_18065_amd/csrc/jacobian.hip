@@ -16,6 +16,7 @@
 // and the state one row up).
 #include "model.hpp"
 #include <cmath>
+#include <type_traits>
 
 namespace minsr {
 
@@ -45,12 +46,17 @@ template <typename T> struct JacArgs {
 
 constexpr int SEGMAX = 16;
 
-template <int H, int P> struct JShape {
+// WL: the gate weights (forward and transposed packings) are staged in LDS
+// once per workgroup and shared by its samples, instead of being streamed
+// from L2 at every site (FP32, 1D, d_h <= 64, checkpoint stride <= 4).
+template <int H, int P, bool WL = false> struct JShape {
   static constexpr int TPS = H * P;                        // threads per sample
-  static constexpr int NT = TPS < 64 ? 64 : TPS;
+  static constexpr int NT0 = TPS < 64 ? 64 : TPS;
+  static constexpr int NT = WL ? (NT0 * 4 > 256 ? NT0 : NT0 * 4) : NT0;
   static constexpr int SG = NT / TPS;                      // samples per block
   static constexpr int NW = H > 64 ? H / 64 : 1;           // waves per p-subgroup
 };
+constexpr int SEGMAX_WL = 4;
 
 template <int H> struct JReduce {
   template <typename T> __device__ static T run(T v) {
@@ -61,14 +67,17 @@ template <int H> struct JReduce {
   }
 };
 
-template <typename T, int H, int DIM, int P>
-__global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
+template <typename T, int H, int DIM, int P, bool WL = false>
+__global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> a) {
   using VT = typename VecJ<T>::type;
   constexpr int V = VecJ<T>::V;
-  constexpr int NT = JShape<H, P>::NT, SG = JShape<H, P>::SG, NW = JShape<H, P>::NW;
+  constexpr int NT = JShape<H, P, WL>::NT, SG = JShape<H, P, WL>::SG;
+  constexpr int NW = JShape<H, P, WL>::NW;
   constexpr int HP = H + V;
   constexpr int CP = H / P;           // gradient columns per part
-  constexpr int SEGN = DIM == 1 ? SEGMAX : 1;
+  constexpr int SEGN = DIM == 1 ? (WL ? SEGMAX_WL : SEGMAX) : 1;
+  constexpr int NWV = WL ? (H / V) * H * 3 : 1;        // staged weight vectors per packing
+  __shared__ VT wlf[NWV], wlb[NWV];
   constexpr int WMAX = DIM == 2 ? 32 : 1;
   constexpr int ds = DIM == 1 ? 2 : 4;
 
@@ -97,6 +106,16 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
   const Work<T> w = a.w;
   const VT* fw = reinterpret_cast<const VT*>(w.fw);
   const VT* bw = reinterpret_cast<const VT*>(w.bw);
+  if constexpr (WL) {
+    for (int e = threadIdx.x; e < NWV; e += NT) { wlf[e] = fw[e]; wlb[e] = bw[e]; }
+    __syncthreads();
+  }
+  auto FW = [&](int idx) -> VT {
+    if constexpr (WL) return wlf[idx]; else return fw[idx];
+  };
+  auto BW = [&](int idx) -> VT {
+    if constexpr (WL) return wlb[idx]; else return bw[idx];
+  };
   const VT* f2 = reinterpret_cast<const VT*>(w.f2);
   const VT* b2 = reinterpret_cast<const VT*>(w.b2);
   const uint8_t* sig = a.sigma + (size_t)sid * N;
@@ -130,9 +149,18 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
 
     const int C = DIM == 1 ? a.C : 1;
     const int nseg = (N + C - 1) / C;
+    // 1D: the checkpoint a segment starts from is requested one segment
+    // ahead, so its load overlaps the previous segment's work
+    auto ckpt = [&](int sgi) -> T {
+      const int kss = sgi * C;
+      return (sgi < 0 || kss == 0) ? (T)0 : st[(size_t)(kss - 1) * H + j];
+    };
+    T hnext = (DIM == 1 && p == 0) ? ckpt(nseg - 1) : (T)0;
     for (int segi = nseg - 1; segi >= 0; --segi) {
       const int ks = segi * C;
       const int len = (ks + C <= N) ? C : N - ks;
+      const T hck = hnext;
+      if (DIM == 1 && p == 0) hnext = ckpt(segi - 1);
 
       // zero-magnetisation counts of sigma_{<ks}
       int nup = 0, ndn = 0;
@@ -141,7 +169,7 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
 
       if (DIM == 1) {
         // ---- forward recompute of the segment from its checkpoint
-        if (p == 0) tx[sg][0][j] = ks == 0 ? (T)0 : st[(size_t)(ks - 1) * H + j];
+        if (p == 0) tx[sg][0][j] = hck;
         __syncthreads();
         for (int kk = 0; kk < len; ++kk) {
           const int k = ks + kk;
@@ -154,9 +182,9 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
           }
 #pragma unroll 4
           for (int k4 = 0; k4 < H / V; ++k4) {
-            const VT wu = fw[(k4 * H + j) * 3 + 0];
-            const VT wr = fw[(k4 * H + j) * 3 + 1];
-            const VT wg = fw[(k4 * H + j) * 3 + 2];
+            const VT wu = FW((k4 * H + j) * 3 + 0);
+            const VT wr = FW((k4 * H + j) * 3 + 1);
+            const VT wg = FW((k4 * H + j) * 3 + 2);
             const T* wus = reinterpret_cast<const T*>(&wu);
             const T* wrs = reinterpret_cast<const T*>(&wr);
             const T* wgs = reinterpret_cast<const T*>(&wg);
@@ -263,9 +291,9 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
           }
 #pragma unroll 2
           for (int k4 = 0; k4 < H / V; ++k4) {
-            const VT wu = fw[(k4 * H + j) * 3 + 0];
-            const VT wr = fw[(k4 * H + j) * 3 + 1];
-            const VT wg = fw[(k4 * H + j) * 3 + 2];
+            const VT wu = FW((k4 * H + j) * 3 + 0);
+            const VT wr = FW((k4 * H + j) * 3 + 1);
+            const VT wg = FW((k4 * H + j) * 3 + 2);
             const T* wus = reinterpret_cast<const T*>(&wu);
             const T* wrs = reinterpret_cast<const T*>(&wr);
             const T* wgs = reinterpret_cast<const T*>(&wg);
@@ -374,9 +402,9 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
         T partv[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll 4
         for (int i4 = p * CP / V; i4 < (p + 1) * CP / V; ++i4) {
-          const VT wu = bw[(i4 * H + j) * 3 + 0];
-          const VT wr = bw[(i4 * H + j) * 3 + 1];
-          const VT wg = bw[(i4 * H + j) * 3 + 2];
+          const VT wu = BW((i4 * H + j) * 3 + 0);
+          const VT wr = BW((i4 * H + j) * 3 + 1);
+          const VT wg = BW((i4 * H + j) * 3 + 2);
           const T* wus = reinterpret_cast<const T*>(&wu);
           const T* wrs = reinterpret_cast<const T*>(&wr);
           const T* wgs = reinterpret_cast<const T*>(&wg);
@@ -514,11 +542,11 @@ __global__ __launch_bounds__((JShape<H, P>::NT)) void k_jacobian(JacArgs<T> a) {
   }
 }
 
-template <typename T, int H, int DIM, int P>
+template <typename T, int H, int DIM, int P, bool WL = false>
 static int launch_jac_t(const JacArgs<T>& a, hipStream_t s) {
-  constexpr int NT = JShape<H, P>::NT, SG = JShape<H, P>::SG;
+  constexpr int NT = JShape<H, P, WL>::NT, SG = JShape<H, P, WL>::SG;
   unsigned grid = (unsigned)((a.Ns + SG - 1) / SG);
-  k_jacobian<T, H, DIM, P><<<grid, NT, 0, s>>>(a);
+  k_jacobian<T, H, DIM, P, WL><<<grid, NT, 0, s>>>(a);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
 }
@@ -529,9 +557,14 @@ static int jac_dispatch(int H, int parts, const JacArgs<T>& a, hipStream_t s) {
   switch (H) {
     case 8: return launch_jac_t<T, 8, DIM, 1>(a, s);
     case 16: return launch_jac_t<T, 16, DIM, 1>(a, s);
-    case 32: return launch_jac_t<T, 32, DIM, 1>(a, s);
+    case 32:
+      if constexpr (DIM == 1 && std::is_same<T, float>::value)
+        if (a.C <= SEGMAX_WL) return launch_jac_t<T, 32, DIM, 1, true>(a, s);
+      return launch_jac_t<T, 32, DIM, 1>(a, s);
     case 64:
       if (parts == 0) parts = DIM == 1 ? 1 : 4;
+      if constexpr (DIM == 1 && std::is_same<T, float>::value)
+        if (parts == 1 && a.C <= SEGMAX_WL) return launch_jac_t<T, 64, DIM, 1, true>(a, s);
       if (parts == 1) return launch_jac_t<T, 64, DIM, 1>(a, s);
       if (parts == 2) return launch_jac_t<T, 64, DIM, 2>(a, s);
       return launch_jac_t<T, 64, DIM, 4>(a, s);
