@@ -740,6 +740,291 @@ __global__ __launch_bounds__(256) void k_chol_step(CholArgs a, int k) {
   }
 }
 
+// ------------------------------------------- FP64 path on the matrix cores
+// The same algorithm for FP64 with every tile product (trailing updates,
+// panel products, the blocked inverse) on the 16 x 16 x 4 FP64 MFMA.  Lane l
+// of a wavefront supplies A[l % 16][l / 16] and B[l / 16][l % 16] of the
+// product and receives D[l / 16 + 4 v][l % 16] in element v.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+constexpr int LDT = CB + 1;   // row stride of the shared tiles (odd: rows fall in distinct banks)
+
+__device__ __forceinline__ int mrow(int lane, int v) { return (lane >> 4) + 4 * v; }
+
+// acc (+/-)= X[xr + i][k0 + k] Y[yr + j][k0 + k] summed over k < K, for the
+// 16 x 16 block (i, j)
+template <int K, bool NEG>
+__device__ __forceinline__ f64x4_t mm_nt(f64x4_t acc, const double (*X)[LDT], int xr,
+                                         const double (*Y)[LDT], int yr, int k0, int lane) {
+#pragma unroll
+  for (int s = 0; s < K; s += 4) {
+    const double xa = X[xr + (lane & 15)][k0 + s + (lane >> 4)];
+    const double yb = Y[yr + (lane & 15)][k0 + s + (lane >> 4)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(NEG ? -xa : xa, yb, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Factor the 64 x 64 tile S (lower triangle; rows >= nb are made identity
+// rows) in place and write inv(L) into Z, with four wavefronts.  Panels of
+// 16 columns are factored by wave 0 alone (row `lane` in registers, pivot
+// column entries by readlane); after each panel the four waves subtract its
+// rank-16 product from the 16 x 16 blocks of the trailing lower triangle on
+// the MFMA.  The inverse is blockwise: wave w inverts diagonal block w by
+// forward substitution (lane j: column j), then level by level
+// Z_QP = -Z_QQ sum_{P <= R < Q} L_QR Z_RP, one block per wave.  Writes L to
+// A (rows < nb), inv(L) to Di (zero outside the leading nb x nb block).
+__device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm)[16][17],
+                                 double* rinv, int nb, double* A, int n, int k0, double* Di,
+                                 uint32_t* status) {
+  constexpr int PB = 16, NB = CB / 16;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    if (r >= nb && c <= r) S[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int P = 0; P < CB / PB; ++P) {
+    const int p0 = PB * P, p1 = p0 + PB;
+    if (w == 0) {
+      double f[PB];
+#pragma unroll
+      for (int cc = 0; cc < PB; ++cc) f[cc] = S[lane][p0 + cc];
+#pragma unroll
+      for (int cc = 0; cc < PB; ++cc) {
+        const int c = p0 + cc;
+        double d = lane_bcast(f[cc], c);
+        if (!(d > 0.0)) { bad = true; d = 1.0; }
+        const double rp = rsqrt_nr(d);
+        const double lc = (lane == c) ? d * rp : f[cc] * rp;
+        f[cc] = lc;
+        if (lane == c) rinv[c] = rp;
+        const double nl = lane > c ? -lc : 0.0;
+#pragma unroll
+        for (int kk = cc + 1; kk < PB; ++kk) f[kk] = fma(nl, lane_bcast(lc, p0 + kk), f[kk]);
+      }
+#pragma unroll
+      for (int cc = 0; cc < PB; ++cc) S[lane][p0 + cc] = lane >= p0 + cc ? f[cc] : 0.0;
+    }
+    __syncthreads();
+    if (p1 < CB) {
+      // blocks (Q, R), Q >= R >= p1 / 16 of the trailing lower triangle
+      const int R0 = p1 / 16, nr = NB - R0;
+      for (int pi = w; pi < nr * (nr + 1) / 2; pi += 4) {
+        int q = 0, rem = pi;
+        while (rem > q) { rem -= q + 1; ++q; }
+        const int Q = R0 + q, R = R0 + rem;
+        f64x4_t t;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) t[v] = S[16 * Q + mrow(lane, v)][16 * R + (lane & 15)];
+        t = mm_nt<PB, true>(t, S, 16 * Q, S, 16 * R, p0, lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[16 * Q + mrow(lane, v)][16 * R + (lane & 15)] = t[v];
+      }
+    }
+    __syncthreads();
+  }
+  if (bad && lane == 0 && status) atomicOr(status, MINSR_ST_NOT_PD);
+  // diagonal blocks of the inverse
+  if (lane < 16) {
+    const int b0 = 16 * w, j = lane;
+    double z[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < i; ++m) s = fma(-S[b0 + i][b0 + m], z[m], s);
+      z[i] = s * rinv[b0 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Z[b0 + i][b0 + j] = z[i];
+  }
+  __syncthreads();
+  // blocks below the diagonal, level lv = Q - P, block P on wave P
+  for (int lv = 1; lv < NB; ++lv) {
+    const int P = w, Q = w + lv;
+    if (Q < NB) {
+      f64x4_t t = {0.0, 0.0, 0.0, 0.0};
+      for (int R = P; R < Q; ++R) {
+#pragma unroll
+        for (int s = 0; s < 16; s += 4) {
+          const double la = S[16 * Q + (lane & 15)][16 * R + s + (lane >> 4)];
+          const double zb = Z[16 * R + s + (lane >> 4)][16 * P + (lane & 15)];
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(la, zb, t, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tm[w][mrow(lane, v)][lane & 15] = t[v];
+    }
+    __syncthreads();
+    if (Q < NB) {
+      f64x4_t u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 16; s += 4) {
+        const double za = Z[16 * Q + (lane & 15)][16 * Q + s + (lane >> 4)];
+        const double tb = Tm[w][s + (lane >> 4)][lane & 15];
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64(-za, tb, u, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Z[16 * Q + mrow(lane, v)][16 * P + (lane & 15)] = u[v];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e / CB, j = e % CB;
+    if (j <= i && i < nb) A[(size_t)(k0 + i) * n + k0 + j] = S[i][j];
+    Di[e] = (i < nb && j < nb && i / 16 >= j / 16) ? Z[i][j] : 0.0;
+  }
+}
+
+// Block column k of the FP64 factorisation (k = -1: the first block column).
+// Roles and synchronisation as in k_chol_step; wave w holds rows
+// [16w, 16w + 16) of its tile as four 16 x 16 MFMA result blocks.
+__global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
+  __shared__ double X[CB][LDT];
+  __shared__ double Y[CB][LDT];
+  __shared__ double Tm[4][16][17];
+  __shared__ double rinv[CB];
+  __shared__ double yb[CB];
+  __shared__ int tk;
+  const int n = a.n, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  double* A = reinterpret_cast<double*>(a.A);
+  const double* Tm0 = reinterpret_cast<const double*>(a.T);
+  double* y = reinterpret_cast<double*>(a.y);
+  uint32_t* tickets = a.sync;
+  uint32_t* flags = a.sync + (a.nblk + 1);
+  const int kk = k + 1;
+  if (tid == 0)
+    tk = (int)__hip_atomic_fetch_add(&tickets[kk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int ticket = tk;
+  int ti, tj;
+  if (k < 0) { ti = ticket; tj = 0; }
+  else { pair_decode(ticket, ti, tj); ti += kk; tj += kk; }
+  const int r0 = ti * CB, c0 = tj * CB;
+  const bool fresh = k <= 0;
+  const double* src = fresh ? Tm0 : A;
+
+  // current tile values in the MFMA result layout
+  f64x4_t t[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 16 * w + mrow(lane, v), col = c0 + 16 * c + (lane & 15);
+      double val = 0.0;
+      if (r < n && col < n && (ti != tj || col <= r)) {
+        val = src[(size_t)r * n + col];
+        if (fresh && r == col) val += a.lambda;
+      }
+      t[c][v] = val;
+    }
+  if (k >= 0) {
+    // A_ij -= L_ik L_jk^T
+    const int k0 = k * CB;
+    {
+      double vi[CB * CB / 256], vj[CB * CB / 256];
+#pragma unroll
+      for (int i = 0; i < CB * CB / 256; ++i) {
+        const int e = tid + 256 * i, r = e / CB, q = e % CB;
+        vi[i] = (r0 + r < n) ? A[(size_t)(r0 + r) * n + k0 + q] : 0.0;
+        vj[i] = (c0 + r < n) ? A[(size_t)(c0 + r) * n + k0 + q] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < CB * CB / 256; ++i) {
+        const int e = tid + 256 * i, r = e / CB, q = e % CB;
+        X[r][q] = vi[i];
+        Y[r][q] = vj[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) t[c] = mm_nt<CB, true>(t[c], X, 16 * w, Y, 16 * c, 0, lane);
+    __syncthreads();   // X, Y are reused below
+  }
+
+  if (tj != kk) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * w + mrow(lane, v), col = c0 + 16 * c + (lane & 15);
+        if (r < n && col < n && (ti != tj || col <= r)) A[(size_t)r * n + col] = t[c][v];
+      }
+    return;
+  }
+
+  const int kb0 = kk * CB, nb = min(CB, n - kb0);
+  double* Di = reinterpret_cast<double*>(a.Dinv) + (size_t)kk * CB * CB;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[16 * w + mrow(lane, v)][16 * c + (lane & 15)] = t[c][v];
+  if (ti == kk) {
+    // diagonal tile: factor, invert, y_kk = inv(L) b_kk, publish
+    if (tid < CB) yb[tid] = tid < nb ? y[kb0 + tid] : 0.0;
+    __syncthreads();
+    factor_block_f64(X, Y, Tm, rinv, nb, A, n, kb0, Di, a.status);
+    __syncthreads();
+    {
+      const int row = tid / 4, part = tid % 4;
+      double s = 0.0;
+      if (row < nb)
+        for (int q = part; q <= row; q += 4) s = fma(Y[row][q], yb[q], s);
+      s += __shfl_xor(s, 1, 4);
+      s += __shfl_xor(s, 2, 4);
+      if (part == 0 && row < nb) y[kb0 + row] = s;
+    }
+    if (kk + 1 < a.nblk) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
+      __syncthreads();
+      if (tid == 0) __hip_atomic_store(&flags[kk], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+
+  // panel tile: wait for the factor of block kk, then L_ik = A_ik inv(L_kk)^T
+  if (tid == 0) {
+    while (__hip_atomic_load(&flags[kk], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+      __builtin_amdgcn_s_sleep(2);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < CB * CB / 256; ++i) {
+    const int e = tid + 256 * i;
+    Y[e / CB][e % CB] = Di[e];
+  }
+  if (tid < CB) yb[tid] = y[kb0 + tid < n ? kb0 + tid : 0];
+  __syncthreads();
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    f64x4_t l = {0.0, 0.0, 0.0, 0.0};
+    l = mm_nt<CB, false>(l, X, 16 * w, Y, 16 * c, 0, lane);
+    const int col = 16 * c + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 16 * w + mrow(lane, v);
+      const bool ok = r < n && col < nb;
+      if (ok) A[(size_t)r * n + kb0 + col] = l[v];
+      s[v] = fma(ok ? l[v] : 0.0, yb[col], s[v]);
+    }
+  }
+  // the 16 lanes of a row hold its 64 columns, four per lane
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) s[v] += __shfl_xor(s[v], m, 16);
+  }
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 16 * w + mrow(lane, v);
+      if (r < n) y[r] -= s[v];
+    }
+  }
+}
+
 // sync words and b -> y (one kernel, safe inside captured graphs)
 template <typename TT>
 __global__ void k_chol_prep(uint32_t* sync, int nsync, const double* b, TT* y, int n) {
@@ -813,11 +1098,13 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
   k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n);
   MINSR_CHECK_LAUNCH();
   CholArgs a{T, A, Dinv, yv, sync, status, lambda, n, nblk};
-  k_chol_step<TT><<<nblk, 256, 0, s>>>(a, -1);
-  MINSR_CHECK_LAUNCH();
-  for (int k = 0; k + 1 < nblk; ++k) {
+  for (int k = -1; k + 1 < nblk; ++k) {
     const int nt = nblk - k - 1;
-    k_chol_step<TT><<<nt * (nt + 1) / 2, 256, 0, s>>>(a, k);
+    const int grid = k < 0 ? nblk : nt * (nt + 1) / 2;
+    if constexpr (std::is_same<TT, double>::value)
+      k_chol_step_f64<<<grid, 256, 0, s>>>(a, k);
+    else
+      k_chol_step<TT><<<grid, 256, 0, s>>>(a, k);
     MINSR_CHECK_LAUNCH();
   }
   k_trsv_back<TT><<<1, 1024, shm, s>>>(A, n, Dinv, yv, x);
