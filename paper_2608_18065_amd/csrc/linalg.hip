@@ -1033,66 +1033,87 @@ __global__ void k_chol_prep(uint32_t* sync, int nsync, const double* b, TT* y, i
   if (i < n) y[i] = (TT)b[i];
 }
 
-// backward substitution x_k = inv(L_kk)^T (y_k - sum_{j>k} L_jk^T x_j), one
-// workgroup of 1024 threads (64 columns x 16 row groups, coalesced rows).
+// Backward substitution L^T x = y by one workgroup per block of 64:
+//   x_k = inv(L_kk)^T (y_k - sum_{j>k} L_jk^T x_j).
+// The workgroup with ticket t takes block k = nblk - 1 - t, so it only waits
+// for blocks whose workgroups started before it.  It keeps inv(L_kk) in
+// shared memory, adds the products L_jk^T x_j for j = nblk-1 down to k+1 in
+// that fixed order as the x_j are published (the tile of the next j is
+// requested before waiting), then publishes x_k through its flag.
 template <typename TT>
-__global__ __launch_bounds__(1024) void k_trsv_back(const TT* A, int n, const TT* Dinv,
-                                                    const TT* yin, double* x) {
-  extern __shared__ unsigned char smem_raw[];
-  TT* y = reinterpret_cast<TT*>(smem_raw);
-  __shared__ TT rbuf[CB];
-  __shared__ TT part[16][CB + 1];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < n; i += 1024) y[i] = yin[i];
+__global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const TT* Dinv,
+                                                      const TT* y, double* x, uint32_t* sync,
+                                                      int nblk) {
+  __shared__ TT Dk[CB][CB + 1];
+  __shared__ TT xj[CB];
+  __shared__ TT part[4][CB];
+  __shared__ TT rb[CB];
+  __shared__ int tk;
+  uint32_t* ticket_ctr = sync + nblk;                // the unused last ticket word
+  uint32_t* bflags = sync + 2 * (nblk + 1);
+  const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
+  if (tid == 0)
+    tk = (int)__hip_atomic_fetch_add(ticket_ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  const int nblk = (n + CB - 1) / CB;
-  const int c = tid % CB, g = tid / CB;         // 64 columns x 16 row groups
-  for (int kb = nblk - 1; kb >= 0; --kb) {
-    const int k0 = kb * CB, nb = min(CB, n - k0);
-    TT acc = (TT)0;
-    if (c < nb) {
-      int r = k0 + nb + g;
-      for (; r + 48 < n; r += 64) {
-        TT l[4];
+  const int kb = nblk - 1 - tk;
+  const int k0 = kb * CB, nb = min(CB, n - k0);
+  const TT* Di = Dinv + (size_t)kb * CB * CB;
+  for (int e = tid; e < CB * CB; e += 256) Dk[e / CB][e % CB] = Di[e];
+  TT acc = (TT)0;
+  TT l[16];
+  auto fetch = [&](int j) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) l[u] = A[(size_t)(r + 16 * u) * n + k0 + c];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc = fma(l[u], y[r + 16 * u], acc);
-      }
-      for (; r < n; r += 16) acc = fma(A[(size_t)r * n + k0 + c], y[r], acc);
+    for (int u = 0; u < 16; ++u) {
+      const int r = j * CB + 16 * g + u;
+      l[u] = (r < n && c < nb) ? A[(size_t)r * n + k0 + c] : (TT)0;
     }
-    part[g][c] = acc;
-    __syncthreads();
-    if (tid < CB) {
-      TT s = (TT)0;
-      for (int q = 0; q < 16; ++q) s += part[q][tid];
-      rbuf[tid] = tid < nb ? y[k0 + tid] - s : (TT)0;
+  };
+  if (kb + 1 < nblk) fetch(nblk - 1);
+  for (int j = nblk - 1; j > kb; --j) {
+    if (tid == 0) {
+      while (__hip_atomic_load(&bflags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        __builtin_amdgcn_s_sleep(1);
     }
     __syncthreads();
-    const TT* Di = Dinv + (size_t)kb * CB * CB;
-    // x_k[c'] = sum_{r >= c'} inv(L)[r][c'] rbuf[r]; 16 threads per c'
-    const int cc = tid / 16, sb = tid % 16;
+    if (tid < CB) xj[tid] = (TT)x[min(j * CB + tid, n - 1)];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc = fma(l[u], xj[16 * g + u], acc);
+    if (j - 1 > kb) fetch(j - 1);
+    __syncthreads();   // xj is rewritten next iteration
+  }
+  part[g][c] = acc;
+  __syncthreads();
+  if (tid < CB) {
+    const TT s = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+    rb[tid] = tid < nb ? y[k0 + tid] - s : (TT)0;
+  }
+  __syncthreads();
+  // x_k[cc] = sum_{r >= cc} inv(L_kk)[r][cc] rb[r], four threads per cc
+  {
+    const int cc = tid >> 2, sb = tid & 3;
     TT v = (TT)0;
     if (cc < nb)
-      for (int r = cc + sb; r < nb; r += 16) v = fma(Di[r * CB + cc], rbuf[r], v);
-#pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 16);
-    __syncthreads();
-    if (sb == 0 && cc < nb) y[k0 + cc] = v;
-    __syncthreads();
+      for (int r = cc + sb; r < nb; r += 4) v = fma(Dk[r][cc], rb[r], v);
+    v += __shfl_xor(v, 1, 4);
+    v += __shfl_xor(v, 2, 4);
+    if (sb == 0 && cc < nb) x[k0 + cc] = (double)v;
   }
-  for (int i = tid; i < n; i += 1024) x[i] = (double)y[i];
+  if (kb > 0) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&bflags[kb], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 size_t chol_dinv_elems(int n) { return (size_t)((n + CB - 1) / CB) * CB * CB; }
-size_t chol_sync_words(int n) { return 2 * (size_t)((n + CB - 1) / CB + 1); }
+// tickets and flags of the factorisation, then the flags of the backward pass
+size_t chol_sync_words(int n) { return 3 * (size_t)((n + CB - 1) / CB + 1); }
 
 template <typename TT>
 static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, double lambda,
                   const double* b, double* x, uint32_t* status, hipStream_t s) {
   const int nblk = (n + CB - 1) / CB;
-  const size_t shm = (size_t)n * sizeof(TT);
-  if (shm > 96 * 1024) return fail(MINSR_E_SHAPE, "triangular solve: n too large");
   const int nsync = (int)chol_sync_words(n);
   const int m = std::max(nsync, n);
   k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n);
@@ -1107,7 +1128,7 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
       k_chol_step<TT><<<grid, 256, 0, s>>>(a, k);
     MINSR_CHECK_LAUNCH();
   }
-  k_trsv_back<TT><<<1, 1024, shm, s>>>(A, n, Dinv, yv, x);
+  k_trsv_back_mt<TT><<<nblk, 256, 0, s>>>(A, n, Dinv, yv, x, sync, nblk);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
 }
