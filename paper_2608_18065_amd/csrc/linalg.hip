@@ -766,16 +766,17 @@ __device__ __forceinline__ f64x4_t mm_nt(f64x4_t acc, const double (*X)[LDT], in
 
 // Factor the 64 x 64 tile S (lower triangle; rows >= nb are made identity
 // rows) in place and write inv(L) into Z, with four wavefronts.  Panels of
-// 16 columns are factored by wave 0 alone (row `lane` in registers, pivot
-// column entries by readlane); after each panel the four waves subtract its
+// 16 columns are factored by wave 0 alone (row `lane` in registers, the
+// pivot column reaching the other lanes through readlane and the scratch
+// column lb); after each panel the four waves subtract its
 // rank-16 product from the 16 x 16 blocks of the trailing lower triangle on
 // the MFMA.  The inverse is blockwise: wave w inverts diagonal block w by
 // forward substitution (lane j: column j), then level by level
 // Z_QP = -Z_QQ sum_{P <= R < Q} L_QR Z_RP, one block per wave.  Writes L to
 // A (rows < nb), inv(L) to Di (zero outside the leading nb x nb block).
 __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm)[16][17],
-                                 double* rinv, int nb, double* A, int n, int k0, double* Di,
-                                 uint32_t* status) {
+                                 double* rinv, double* lb, int nb, double* A, int n, int k0,
+                                 double* Di, uint32_t* status) {
   constexpr int PB = 16, NB = CB / 16;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   for (int e = tid; e < CB * CB; e += 256) {
@@ -799,9 +800,15 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
         const double lc = (lane == c) ? d * rp : f[cc] * rp;
         f[cc] = lc;
         if (lane == c) rinv[c] = rp;
-        const double nl = lane > c ? -lc : 0.0;
+        // the next pivot column by readlane (short dependency chain), the
+        // others with the column broadcast through shared memory
+        if (cc + 1 < PB) {
+          const double nl = lane > c ? -lc : 0.0;
+          lb[lane] = lc;
+          f[cc + 1] = fma(nl, lane_bcast(lc, c + 1), f[cc + 1]);
 #pragma unroll
-        for (int kk = cc + 1; kk < PB; ++kk) f[kk] = fma(nl, lane_bcast(lc, p0 + kk), f[kk]);
+          for (int kk = cc + 2; kk < PB; ++kk) f[kk] = fma(nl, lb[p0 + kk], f[kk]);
+        }
       }
 #pragma unroll
       for (int cc = 0; cc < PB; ++cc) S[lane][p0 + cc] = lane >= p0 + cc ? f[cc] : 0.0;
@@ -885,6 +892,7 @@ __global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
   __shared__ double Y[CB][LDT];
   __shared__ double Tm[4][16][17];
   __shared__ double rinv[CB];
+  __shared__ double lb[CB];
   __shared__ double yb[CB];
   __shared__ int tk;
   const int n = a.n, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -920,26 +928,28 @@ __global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
       t[c][v] = val;
     }
   if (k >= 0) {
-    // A_ij -= L_ik L_jk^T
+    // A_ij -= L_ik L_jk^T (one operand tile for diagonal tiles)
     const int k0 = k * CB;
+    const bool diag = ti == tj;
     {
       double vi[CB * CB / 256], vj[CB * CB / 256];
 #pragma unroll
       for (int i = 0; i < CB * CB / 256; ++i) {
         const int e = tid + 256 * i, r = e / CB, q = e % CB;
         vi[i] = (r0 + r < n) ? A[(size_t)(r0 + r) * n + k0 + q] : 0.0;
-        vj[i] = (c0 + r < n) ? A[(size_t)(c0 + r) * n + k0 + q] : 0.0;
+        if (!diag) vj[i] = (c0 + r < n) ? A[(size_t)(c0 + r) * n + k0 + q] : 0.0;
       }
 #pragma unroll
       for (int i = 0; i < CB * CB / 256; ++i) {
         const int e = tid + 256 * i, r = e / CB, q = e % CB;
         X[r][q] = vi[i];
-        Y[r][q] = vj[i];
+        if (!diag) Y[r][q] = vj[i];
       }
     }
     __syncthreads();
+    const double (*Yo)[LDT] = diag ? X : Y;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) t[c] = mm_nt<CB, true>(t[c], X, 16 * w, Y, 16 * c, 0, lane);
+    for (int c = 0; c < 4; ++c) t[c] = mm_nt<CB, true>(t[c], X, 16 * w, Yo, 16 * c, 0, lane);
     __syncthreads();   // X, Y are reused below
   }
 
@@ -964,7 +974,7 @@ __global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
     // diagonal tile: factor, invert, y_kk = inv(L) b_kk, publish
     if (tid < CB) yb[tid] = tid < nb ? y[kb0 + tid] : 0.0;
     __syncthreads();
-    factor_block_f64(X, Y, Tm, rinv, nb, A, n, kb0, Di, a.status);
+    factor_block_f64(X, Y, Tm, rinv, lb, nb, A, n, kb0, Di, a.status);
     __syncthreads();
     {
       const int row = tid / 4, part = tid % 4;
