@@ -919,13 +919,12 @@ __global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
   for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
+      // every load is issued (clamped address), the mask applies to the value:
+      // a guarded load would be waited for before the next one is issued
       const int r = r0 + 16 * w + mrow(lane, v), col = c0 + 16 * c + (lane & 15);
-      double val = 0.0;
-      if (r < n && col < n && (ti != tj || col <= r)) {
-        val = src[(size_t)r * n + col];
-        if (fresh && r == col) val += a.lambda;
-      }
-      t[c][v] = val;
+      double val = src[(size_t)min(r, n - 1) * n + min(col, n - 1)];
+      if (fresh && r == col) val += a.lambda;
+      t[c][v] = (r < n && col < n && (ti != tj || col <= r)) ? val : 0.0;
     }
   if (k >= 0) {
     // A_ij -= L_ik L_jk^T (one operand tile for diagonal tiles)
@@ -936,8 +935,12 @@ __global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
 #pragma unroll
       for (int i = 0; i < CB * CB / 256; ++i) {
         const int e = tid + 256 * i, r = e / CB, q = e % CB;
-        vi[i] = (r0 + r < n) ? A[(size_t)(r0 + r) * n + k0 + q] : 0.0;
-        if (!diag) vj[i] = (c0 + r < n) ? A[(size_t)(c0 + r) * n + k0 + q] : 0.0;
+        const double xi = A[(size_t)min(r0 + r, n - 1) * n + k0 + q];
+        vi[i] = (r0 + r < n) ? xi : 0.0;
+        if (!diag) {
+          const double xj = A[(size_t)min(c0 + r, n - 1) * n + k0 + q];
+          vj[i] = (c0 + r < n) ? xj : 0.0;
+        }
       }
 #pragma unroll
       for (int i = 0; i < CB * CB / 256; ++i) {
@@ -1068,14 +1071,22 @@ __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const 
   const int kb = nblk - 1 - tk;
   const int k0 = kb * CB, nb = min(CB, n - k0);
   const TT* Di = Dinv + (size_t)kb * CB * CB;
-  for (int e = tid; e < CB * CB; e += 256) Dk[e / CB][e % CB] = Di[e];
+  {
+    TT dv[CB * CB / 256];   // all loads in flight before the first store
+#pragma unroll
+    for (int i = 0; i < CB * CB / 256; ++i) dv[i] = Di[tid + 256 * i];
+#pragma unroll
+    for (int i = 0; i < CB * CB / 256; ++i) Dk[(tid + 256 * i) / CB][(tid + 256 * i) % CB] = dv[i];
+  }
   TT acc = (TT)0;
   TT l[16];
   auto fetch = [&](int j) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
+      // clamped and unguarded, so that all sixteen loads are in flight: rows
+      // beyond n meet zeros in xj, columns beyond nb are never used
       const int r = j * CB + 16 * g + u;
-      l[u] = (r < n && c < nb) ? A[(size_t)r * n + k0 + c] : (TT)0;
+      l[u] = A[(size_t)min(r, n - 1) * n + k0 + min(c, nb - 1)];
     }
   };
   if (kb + 1 < nblk) fetch(nblk - 1);
@@ -1085,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const 
         __builtin_amdgcn_s_sleep(1);
     }
     __syncthreads();
-    if (tid < CB) xj[tid] = (TT)x[min(j * CB + tid, n - 1)];
+    if (tid < CB) xj[tid] = j * CB + tid < n ? (TT)x[j * CB + tid] : (TT)0;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc = fma(l[u], xj[16 * g + u], acc);
