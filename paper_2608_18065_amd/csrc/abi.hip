@@ -92,7 +92,8 @@ static int ensure_pinv_ws(minsr_model* m, hipStream_t s) {
 }
 
 static void release(minsr_model* m) {
-  void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->site, m->contrib,
+  void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->gates, m->site,
+                  m->contrib,
                   m->elist, m->ecount, m->eitems,
                   m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
                   m->colpart, m->colmean, m->T, m->Lf, m->Dinv, m->gpart, m->epsp, m->x, m->vwork,
@@ -192,6 +193,10 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   rc = rc ? rc : alloc((void**)&m->subA, subA.size());
   rc = rc ? rc : alloc((void**)&m->bonds, std::max<size_t>(bonds.size(), 2) * sizeof(int));
   rc = rc ? rc : alloc(&m->states, S * Nz * Hz * sz);
+  // the Jacobian of these models reads the sampler's gate values instead of
+  // recomputing them (checkpoint stride 1)
+  if (m->dim == 1 && !m->f64 && m->H <= 64)
+    rc = rc ? rc : alloc(&m->gates, S * Nz * 4 * Hz * sz);
   rc = rc ? rc : alloc((void**)&m->site, S * Nz * 4 * 8);
   rc = rc ? rc : alloc((void**)&m->contrib, (size_t)m->max_terms * S * 2 * 8);
   rc = rc ? rc : alloc((void**)&m->elist, (size_t)m->max_terms * S * 4);
@@ -340,14 +345,15 @@ int minsr_jacobian(minsr_model* m, int Ns, const uint8_t* dev_sigma, int out_dty
   if (ckpt_every < 1 || ckpt_every > 16) return fail(MINSR_E_INVALID_ARG, "ckpt_every in [1, 16]");
   if (centered && !dev_colmean) return fail(MINSR_E_INVALID_ARG, "centred output needs dev_colmean");
   const int C = m->dim == 1 ? ckpt_every : 1;
+  void* tape = C == 1 ? m->gates : nullptr;
   rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
-                      m->states, C, nullptr, s);
+                      m->states, C, nullptr, s, nullptr, tape);
   if (rc) return rc;
   const int native = m->f64 ? MINSR_F64 : MINSR_F32;
   const int nb = m->cplx ? 2 : 1;
   if (!centered && out_dtype == native)
-    return launch_jacobian(m, Ns, dev_sigma, m->states, C, dev_O, nullptr, nullptr, s);
-  rc = launch_jacobian(m, Ns, dev_sigma, m->states, C, m->O, nullptr, nullptr, s);
+    return launch_jacobian(m, Ns, dev_sigma, m->states, C, dev_O, nullptr, nullptr, s, tape);
+  rc = launch_jacobian(m, Ns, dev_sigma, m->states, C, m->O, nullptr, nullptr, s, tape);
   if (rc) return rc;
   return launch_center(Ns, nb, m->L.Np, m->O, m->f64, dev_O, out_dtype, m->colpart,
                        centered ? dev_colmean : nullptr, m->L.Np, s);
@@ -363,9 +369,9 @@ int minsr_logpsi_vjp(minsr_model* m, int Ns, const uint8_t* dev_sigma, const dou
     return MINSR_OK;
   }
   rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
-                      m->states, 1, nullptr, s);
+                      m->states, 1, nullptr, s, nullptr, m->gates);
   if (rc) return rc;
-  rc = launch_jacobian(m, Ns, dev_sigma, m->states, 1, m->O, nullptr, nullptr, s);
+  rc = launch_jacobian(m, Ns, dev_sigma, m->states, 1, m->O, nullptr, nullptr, s, m->gates);
   if (rc) return rc;
   const size_t Np = m->L.Np;
   const double scale = std::sqrt((double)Ns);
@@ -424,7 +430,7 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   MINSR_PHASE(0);
   // 1. exact autoregressive samples, hidden states, per-site conditionals
   rc = launch_forward(m, 0, Ns, nullptr, st->key, st->counter, sigma, m->logpsi, m->states, 1,
-                      m->site, s, st->dev_counter);
+                      m->site, s, st->dev_counter, C == 1 ? m->gates : nullptr);
   if (rc) return rc;
   MINSR_PHASE(1);
   // 2. local energies, E, Var and eps'
@@ -437,7 +443,8 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   if (rc) return rc;
   MINSR_PHASE(3);
   // 3. log-derivatives, centring and real form
-  rc = launch_jacobian(m, Ns, sigma, m->states, C, m->O, nullptr, nullptr, s);
+  rc = launch_jacobian(m, Ns, sigma, m->states, C, m->O, nullptr, nullptr, s,
+                       C == 1 ? m->gates : nullptr);
   if (rc) return rc;
   MINSR_PHASE(4);
   rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, padded_ld(Np), s,

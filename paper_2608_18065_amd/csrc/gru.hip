@@ -240,6 +240,7 @@ template <typename T> struct FwdArgs {
   const uint8_t* sigma_in;   // modes 1, 2
   double* logpsi;            // modes 0, 1: [Ns][2]
   T* states;                 // modes 0, 1: optional [Ns][N][H]
+  T* gates;                  // modes 0, 1 (1D): optional [Ns][N][4][H] u, r, g, ht
   int store_every;
   double* site;              // modes 0, 1: optional [Ns][N][4]
   // local energies (mode 2)
@@ -485,13 +486,13 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
           }
         }
       }
-      T hn[R];
+      T hn[R], gu[R], gr[R], gt[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const T u = d_sigmoid(au[r]);
-        const T rr = d_sigmoid(ar[r]);
-        const T ht = d_tanh(rr * ag[r] + ai[r]);
-        hn[r] = ((T)1 - u) * hin_own[r] + u * ht;
+        gu[r] = d_sigmoid(au[r]);
+        gr[r] = d_sigmoid(ar[r]);
+        gt[r] = d_tanh(gr[r] * ag[r] + ai[r]);
+        hn[r] = ((T)1 - gu[r]) * hin_own[r] + gu[r] * gt[r];
       }
       // publish the new state
 #pragma unroll
@@ -508,6 +509,10 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
         if (a.mode != MODE_ELOC && a.states && act[r] &&
             ((k + 1) % a.store_every == 0 || DIM == 2))
           a.states[((size_t)s * N + k) * H + j] = hn[r];
+        if (DIM == 1 && a.mode != MODE_ELOC && a.gates && act[r]) {
+          T* gk = a.gates + ((size_t)s * N + k) * 4 * H;
+          gk[j] = gu[r]; gk[H + j] = gr[r]; gk[2 * H + j] = ag[r]; gk[3 * H + j] = gt[r];
+        }
       }
       // output head: logits (and phase pre-activations) of every sequence
       T z0[R], z1[R], q0[R], q1[R];
@@ -660,13 +665,15 @@ static int seqs_per_block(int H, int R) { return (256 / H) * R; }
 template <typename T>
 static int forward_t(minsr_model* m, const Work<T>& w, int mode, int Ns, const double* uniforms,
                      uint64_t key, uint64_t counter, const uint64_t* counter_ptr, uint8_t* sigma,
-                     double* logpsi, void* states, int store_every, double* site, hipStream_t s) {
+                     double* logpsi, void* states, int store_every, double* site, void* gates,
+                     hipStream_t s) {
   FwdArgs<T> a = base_args<T>(m, w);
   a.Ns = Ns; a.mode = mode;
   a.uniforms = uniforms; a.key = key; a.counter = counter; a.counter_ptr = counter_ptr;
   if (mode == MODE_SAMPLE) a.sigma_out = sigma; else a.sigma_in = sigma;
   a.logpsi = logpsi;
   a.states = (T*)states; a.store_every = store_every; a.site = site;
+  a.gates = (m->dim == 1 && store_every == 1 && mode != MODE_ELOC) ? (T*)gates : nullptr;
   // few sequences per block by default: the site loop is latency-bound
   const int R = m->tune_sample_r == 4 ? 4 : 1;
   const int B = seqs_per_block(m->H, R);
@@ -678,13 +685,14 @@ static int forward_t(minsr_model* m, const Work<T>& w, int mode, int Ns, const d
 
 int launch_forward(minsr_model* m, int mode, int Ns, const double* uniforms, uint64_t key,
                    uint64_t counter, uint8_t* sigma, double* logpsi, void* states,
-                   int store_every, double* site, hipStream_t s, const uint64_t* counter_ptr) {
+                   int store_every, double* site, hipStream_t s, const uint64_t* counter_ptr,
+                   void* gates) {
   if (Ns == 0) return MINSR_OK;
   if (m->f64)
     return forward_t<double>(m, m->wd, mode, Ns, uniforms, key, counter, counter_ptr, sigma,
-                             logpsi, states, store_every, site, s);
+                             logpsi, states, store_every, site, gates, s);
   return forward_t<float>(m, m->wf, mode, Ns, uniforms, key, counter, counter_ptr, sigma, logpsi,
-                          states, store_every, site, s);
+                          states, store_every, site, gates, s);
 }
 
 // ------------------------------------------------------ local energies

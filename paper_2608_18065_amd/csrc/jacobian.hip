@@ -10,6 +10,8 @@
 // 1D: hidden states are checkpointed every C sites; each segment is
 // recomputed forward (with the same arithmetic as the sampling kernel, so
 // any C gives bitwise identical rows) into an LDS tape and then reversed.
+// With C = 1 and the sampler's gate tape the forward products are skipped:
+// the gate values are read back instead of recomputed (same values).
 // 2D: every hidden state is stored; the reverse pass recomputes one site
 // at a time from its two predecessors and keeps the adjoints of the last
 // 2 Lx states in an LDS window (a state feeds its right/left neighbour
@@ -39,6 +41,7 @@ template <typename T> struct JacArgs {
   const int* nbr;
   const uint8_t* sigma;
   const T* states;       // [Ns][N][H]; 1D: rows k with (k+1) % C == 0 are read
+  const T* gates;        // 1D, C == 1, optional: [Ns][N][4][H] u, r, g, ht of the sampler
   T* O;                  // [rows][Np]
   T scale;               // 1 / sqrt(Ns)
   int W2;                // 2D adjoint window
@@ -156,11 +159,25 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
       return (sgi < 0 || kss == 0) ? (T)0 : st[(size_t)(kss - 1) * H + j];
     };
     T hnext = (DIM == 1 && p == 0) ? ckpt(nseg - 1) : (T)0;
+    // with the sampler's gate tape (C == 1) the segment of one site needs no
+    // gate products: its gates and state are requested one site ahead
+    const bool tape = DIM == 1 && a.gates != nullptr;
+    const T* gt = tape ? a.gates + (size_t)sid * N * 4 * H : nullptr;
+    T gnx[4] = {(T)0, (T)0, (T)0, (T)0}, hnx = (T)0;
+    auto tape_fetch = [&](int k) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) gnx[q] = gt[((size_t)k * 4 + q) * H + j];
+      hnx = st[(size_t)k * H + j];
+    };
+    if (tape) tape_fetch(N - 1);
     for (int segi = nseg - 1; segi >= 0; --segi) {
       const int ks = segi * C;
       const int len = (ks + C <= N) ? C : N - ks;
       const T hck = hnext;
       if (DIM == 1 && p == 0) hnext = ckpt(segi - 1);
+      T gcur[4] = {gnx[0], gnx[1], gnx[2], gnx[3]};
+      const T hcur = hnx;
+      if (tape && segi > 0) tape_fetch(segi - 1);
 
       // zero-magnetisation counts of sigma_{<ks}
       int nup = 0, ndn = 0;
@@ -173,35 +190,42 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
         __syncthreads();
         for (int kk = 0; kk < len; ++kk) {
           const int k = ks + kk;
-          const int sprev = k > 0 ? sig[k - 1] : -1;
-          T au = bu, ar = br, ag = bh, ai = bi;
-          if (sprev >= 0) {
-            au += w.xc[(0 * ds + sprev) * H + j];
-            ar += w.xc[(1 * ds + sprev) * H + j];
-            ai += w.xc[(2 * ds + sprev) * H + j];
-          }
-#pragma unroll 4
-          for (int k4 = 0; k4 < H / V; ++k4) {
-            const VT wu = FW((k4 * H + j) * 3 + 0);
-            const VT wr = FW((k4 * H + j) * 3 + 1);
-            const VT wg = FW((k4 * H + j) * 3 + 2);
-            const T* wus = reinterpret_cast<const T*>(&wu);
-            const T* wrs = reinterpret_cast<const T*>(&wr);
-            const T* wgs = reinterpret_cast<const T*>(&wg);
-            const VT xv = *reinterpret_cast<const VT*>(&tx[sg][kk][k4 * V]);
-            const T* xs = reinterpret_cast<const T*>(&xv);
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-              au = fma(wus[v], xs[v], au);
-              ar = fma(wrs[v], xs[v], ar);
-              ag = fma(wgs[v], xs[v], ag);
+          T u, rr, ag, ht, hn;
+          if (tape) {
+            u = gcur[0]; rr = gcur[1]; ag = gcur[2]; ht = gcur[3];
+            hn = hcur;
+          } else {
+            const int sprev = k > 0 ? sig[k - 1] : -1;
+            T au = bu, ar = br, agg = bh, ai = bi;
+            if (sprev >= 0) {
+              au += w.xc[(0 * ds + sprev) * H + j];
+              ar += w.xc[(1 * ds + sprev) * H + j];
+              ai += w.xc[(2 * ds + sprev) * H + j];
             }
+#pragma unroll 4
+            for (int k4 = 0; k4 < H / V; ++k4) {
+              const VT wu = FW((k4 * H + j) * 3 + 0);
+              const VT wr = FW((k4 * H + j) * 3 + 1);
+              const VT wg = FW((k4 * H + j) * 3 + 2);
+              const T* wus = reinterpret_cast<const T*>(&wu);
+              const T* wrs = reinterpret_cast<const T*>(&wr);
+              const T* wgs = reinterpret_cast<const T*>(&wg);
+              const VT xv = *reinterpret_cast<const VT*>(&tx[sg][kk][k4 * V]);
+              const T* xs = reinterpret_cast<const T*>(&xv);
+#pragma unroll
+              for (int v = 0; v < V; ++v) {
+                au = fma(wus[v], xs[v], au);
+                ar = fma(wrs[v], xs[v], ar);
+                agg = fma(wgs[v], xs[v], agg);
+              }
+            }
+            const T hprev = tx[sg][kk][j];
+            u = j_sigmoid(au);
+            rr = j_sigmoid(ar);
+            ag = agg;
+            ht = j_tanh(rr * ag + ai);
+            hn = ((T)1 - u) * hprev + u * ht;
           }
-          const T hprev = tx[sg][kk][j];
-          const T u = j_sigmoid(au);
-          const T rr = j_sigmoid(ar);
-          const T ht = j_tanh(rr * ag + ai);
-          const T hn = ((T)1 - u) * hprev + u * ht;
           T z0 = JReduce<H>::run(U0 * hn), z1 = JReduce<H>::run(U1v * hn);
           T q0 = (T)0, q1 = (T)0;
           if (a.cplx) { q0 = JReduce<H>::run(P0 * hn); q1 = JReduce<H>::run(P1 * hn); }
@@ -579,11 +603,12 @@ static int jac_dispatch(int H, int parts, const JacArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 static int jac_t(minsr_model* m, const Work<T>& w, int Ns, const uint8_t* sigma,
-                 const void* states, int C, void* O, hipStream_t s) {
+                 const void* states, int C, void* O, const void* gates, hipStream_t s) {
   JacArgs<T> a{};
   a.w = w; a.L = m->L; a.N = m->N; a.Ns = Ns; a.C = C;
   a.zero_mag = m->d.zero_mag; a.cplx = m->cplx; a.nbr = m->nbr;
   a.sigma = sigma; a.states = (const T*)states; a.O = (T*)O;
+  a.gates = (m->dim == 1 && C == 1) ? (const T*)gates : nullptr;
   a.scale = (T)(1.0 / std::sqrt((double)Ns));
   a.W2 = 2 * m->d.Lx;
   if (m->dim == 1) return jac_dispatch<T, 1>(m->H, m->tune_jac_parts, a, s);
@@ -591,14 +616,15 @@ static int jac_t(minsr_model* m, const Work<T>& w, int Ns, const uint8_t* sigma,
 }
 
 int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* states,
-                    int ckpt_every, void* O, const double* g, double* vjp_part, hipStream_t s) {
+                    int ckpt_every, void* O, const double* g, double* vjp_part, hipStream_t s,
+                    const void* gates) {
   (void)g; (void)vjp_part;
   if (Ns == 0) return MINSR_OK;
   if (m->dim == 2 && 2 * m->d.Lx > 32) return fail(MINSR_E_UNSUPPORTED, "2D lattices need Lx <= 16");
   if (ckpt_every < 1 || ckpt_every > SEGMAX)
     return fail(MINSR_E_INVALID_ARG, "ckpt_every must be in [1, 16]");
-  if (m->f64) return jac_t<double>(m, m->wd, Ns, sigma, states, ckpt_every, O, s);
-  return jac_t<float>(m, m->wf, Ns, sigma, states, ckpt_every, O, s);
+  if (m->f64) return jac_t<double>(m, m->wd, Ns, sigma, states, ckpt_every, O, gates, s);
+  return jac_t<float>(m, m->wf, Ns, sigma, states, ckpt_every, O, gates, s);
 }
 
 }  // namespace minsr

@@ -25,6 +25,7 @@ struct minsr_model {
   // ---- workspace sized for d.max_Ns
   int max_terms = 0;        // off-diagonal terms per sample (upper bound)
   void* states = nullptr;   // [max_Ns][N][H] hidden states
+  void* gates = nullptr;    // [max_Ns][N][4][H] gate tape (FP32 1D models, d_h <= 64)
   double* site = nullptr;   // [max_Ns][N][4]: log p(0), log p(1), phi(0), phi(1)
   double* contrib = nullptr;// [max_terms][max_Ns][2]
   int* elist = nullptr;     // [max_terms][max_Ns] samples with a nonzero matrix element
@@ -76,10 +77,12 @@ namespace minsr {
 int launch_init_theta(minsr_model* m, hipStream_t s);
 int launch_pack(minsr_model* m, hipStream_t s);
 // mode 0: sample, 1: evaluate.  states/site may be null.
+// gates (1D, store_every == 1, may be null): [Ns][N][4][H] gate values u, r,
+// candidate pre-activation and candidate of every site, for the Jacobian.
 int launch_forward(minsr_model* m, int mode, int Ns, const double* uniforms, uint64_t key,
                    uint64_t counter, uint8_t* sigma, double* logpsi, void* states,
                    int store_every, double* site, hipStream_t s,
-                   const uint64_t* counter_ptr = nullptr);
+                   const uint64_t* counter_ptr = nullptr, void* gates = nullptr);
 // which: 1 = off-diagonal terms (the recurrence), 2 = diagonal + sum, 3 = both
 int launch_eloc(minsr_model* m, const minsr_hamiltonian* H, int Ns, const uint8_t* sigma,
                 const double* logpsi, const void* states, const double* site, double* eloc,
@@ -91,9 +94,11 @@ bool eloc_mfma_supported(minsr_model* m);
 int launch_eloc_mfma(minsr_model* m, const minsr_hamiltonian* H, int Ns, const uint8_t* sigma,
                      const void* states, const double* site, int M, hipStream_t s);
 // jacobian.hip: raw rows (scaled by 1/sqrt(Ns)) into O (compute precision)
+// gates: the tape written by launch_forward for the same configurations
+// (used with ckpt_every == 1 only; may be null)
 int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* states,
                     int ckpt_every, void* O, const double* g, double* vjp_part,
-                    hipStream_t s);
+                    hipStream_t s, const void* gates = nullptr);
 // linalg.hip
 // centred (colmean != null) or plain copy of O into R with row stride ldo
 // (ldo >= Np; columns Np..ldo-1 are written as zeros)

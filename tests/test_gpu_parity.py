@@ -167,6 +167,22 @@ def test_checkpointed_jacobian_bitwise(arch, C):
     assert torch.equal(O1, Oc)
 
 
+@pytest.mark.parametrize("arch", [dict(Lx=20, H=64), dict(Lx=23, H=32, cplx=True),
+                                  dict(Lx=13, H=16)], ids=_ids)
+@pytest.mark.parametrize("C", [3, 10])
+def test_checkpointed_jacobian_bitwise_fp32(arch, C):
+    # FP32 1D: stride 1 reads the sampler's gate tape, stride 3 recomputes the
+    # segments with the weights staged in shared memory, stride 10 streams
+    # them from memory; every path gives the same rows bit for bit
+    spec, m = make_pair(**arch, dtype="f32")
+    th = scaled_theta(spec, 11, 1.5)
+    m.set_params(to_dev(th))
+    sig, _ = m.sample(19, key=3, counter=4)
+    O1, _ = m.jacobian(sig, ckpt_every=1)
+    Oc, _ = m.jacobian(sig, ckpt_every=C)
+    assert torch.equal(O1, Oc)
+
+
 def test_jacobian_centered_colmean():
     spec, m = make_pair(Lx=10, H=16, cplx=True)
     th = scaled_theta(spec, 12, 1.0)
