@@ -59,12 +59,20 @@ __device__ __forceinline__ float fast_tanh(float y) {
   return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + fast_exp(2.f * y));
 }
 
+// log(1 + e^d) for d <= 0 from the hardware exp2 and log2 (1 + e^d lies in
+// [1, 2], so the absolute error stays at FP32 rounding level)
+__device__ __forceinline__ float fast_log1p_exp(float d) {
+  return 0.6931471805599453f * __builtin_amdgcn_logf(1.f + fast_exp(d));
+}
+
 __device__ inline f32x16_m mfma_f32(float a, float b, f32x16_m c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
 template <int H, int DIM>
-__global__ __launch_bounds__(64 * (H / 32)) void k_eloc_mfma(ElocMArgs a) {
+// d_h <= 64: two waves per SIMD (at most 256 registers each), so one wave's
+// elementwise update overlaps the other's matrix products
+__global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(ElocMArgs a) {
   constexpr int S = 32;
   constexpr int HP = H + 4;
   constexpr int KS = H / 2;
@@ -264,7 +272,7 @@ __global__ __launch_bounds__(64 * (H / 32)) void k_eloc_mfma(ElocMArgs a) {
       const float zz0 = z0 + hb[0], zz1 = z1 + hb[1];
       const float mx = zz0 > zz1 ? zz0 : zz1;
       const float d = zz0 > zz1 ? zz1 - zz0 : zz0 - zz1;
-      const float lse = mx + log1pf(expf(d));
+      const float lse = mx + fast_log1p_exp(d);
       float lp0 = zz0 - lse, lp1 = zz1 - lse;
       if (a.zero_mag) {
         if (nup >= N / 2) { lp0 = -INFINITY; lp1 = 0.f; }
