@@ -289,6 +289,14 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
   const VT* fw = reinterpret_cast<const VT*>(w.fw);
   const VT* f2 = reinterpret_cast<const VT*>(w.f2);
   const int ds = DIM == 1 ? 2 : 4;
+  // FP32 1D, d_h <= 64: the thread's gate weights (3 H values of its unit)
+  // stay in registers for the whole kernel, so a site costs no weight loads
+  constexpr bool WR = sizeof(T) == 4 && DIM == 1 && H <= 64 && R == 1;
+  VT wreg[WR ? (H / V) * 3 : 1];
+  if constexpr (WR) {
+#pragma unroll
+    for (int i = 0; i < (H / V) * 3; ++i) wreg[i] = fw[((i / 3) * H + j) * 3 + i % 3];
+  }
 
   // per-unit constants
   const T bu = w.bias[j], br = w.bias[H + j], bh = w.bias[2 * H + j], bi = w.bias[3 * H + j];
@@ -466,11 +474,7 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
           }
         }
       }
-#pragma unroll 2
-      for (int k4 = 0; k4 < H / V; ++k4) {
-        const VT wu = fw[(k4 * H + j) * 3 + 0];
-        const VT wr = fw[(k4 * H + j) * 3 + 1];
-        const VT wg = fw[(k4 * H + j) * 3 + 2];
+      auto gate_step = [&](int k4, const VT& wu, const VT& wr, const VT& wg) {
         const T* wus = reinterpret_cast<const T*>(&wu);
         const T* wrs = reinterpret_cast<const T*>(&wr);
         const T* wgs = reinterpret_cast<const T*>(&wg);
@@ -485,6 +489,16 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
             ag[r] = fma(wgs[v], xs[v], ag[r]);
           }
         }
+      };
+      if constexpr (WR) {
+#pragma unroll
+        for (int k4 = 0; k4 < H / V; ++k4)
+          gate_step(k4, wreg[k4 * 3 + 0], wreg[k4 * 3 + 1], wreg[k4 * 3 + 2]);
+      } else {
+#pragma unroll 2
+        for (int k4 = 0; k4 < H / V; ++k4)
+          gate_step(k4, fw[(k4 * H + j) * 3 + 0], fw[(k4 * H + j) * 3 + 1],
+                    fw[(k4 * H + j) * 3 + 2]);
       }
       T hn[R], gu[R], gr[R], gt[R];
 #pragma unroll
