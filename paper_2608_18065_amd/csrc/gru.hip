@@ -159,7 +159,13 @@ __global__ void k_pack(T* out, PackArgs p) {
       if (q == 0) v = th[p.Wu + (long long)unit * (H + ds) + H + c];
       else if (q == 1) v = th[p.Wr + (long long)unit * (H + ds) + H + c];
       else v = th[p.Win + (long long)unit * ds + c];
+      // 1D: exactly one one-hot column is set at every re-evaluated site,
+      // so the biases of u, r and the input term ride on these columns
+      if (p.dim == 1) v += th[(q == 0 ? p.bu : q == 1 ? p.br : p.bin) + unit];
     }
+    // 1D: the local-energy kernel takes exp2 of the pre-activations, so
+    // u, r are scaled by -log2(e) and the candidate terms by 2 log2(e)
+    if (p.dim == 1) v *= q < 2 ? -1.4426950408889634 : 2.8853900817779268;
   } else {                                // m2 [wave][s][lane]: U1 (half 0), U2 (half 1)
     long long r = e - p.o_m2;
     const int lane = (int)(r % 64); r /= 64;

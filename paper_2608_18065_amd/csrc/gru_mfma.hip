@@ -13,9 +13,13 @@
 // paper's x = [h; sigma]; its one-hot columns enter as extra K-steps.  The
 // elementwise GRU update runs in the accumulator layout (lane l holds unit
 // l mod 32 of 16 sequences), the new state goes back to LDS, and each lane
-// then reduces the output head for its own sequence.  2D models form
-// h' = U1 h_horizontal + U2 h_vertical with one more MFMA product per site
-// (B fragments streamed from L2) before the cell.
+// then reduces the output head for its own sequence.  In 1D every
+// re-evaluated site has exactly one one-hot column set, so the packed
+// fragments carry the biases of u, r and the input term on those columns,
+// and they are pre-scaled (-log2 e for u, r; 2 log2 e for the candidate)
+// so that each nonlinearity is one hardware exp2 and one reciprocal.
+// 2D models form h' = U1 h_horizontal + U2 h_vertical with one more MFMA
+// product per site (B fragments streamed from L2) before the cell.
 #include "model.hpp"
 
 namespace minsr {
@@ -103,6 +107,7 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
   }
   const float bu = a.bias[unit], br = a.bias[H + unit], bh = a.bias[2 * H + unit];
   const float bi = a.bias[3 * H + unit];
+  const float bgs = (float)(2.8853900817779268 * (double)bh);   // 2 log2(e) b_h
   for (int i = tid; i < 4 * H; i += NT) hw[i / H][i % H] = a.head[i];
   if (tid < 4) hb[tid] = a.headb[tid];
   __syncthreads();
@@ -147,6 +152,9 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
       oldlp += st[4 * k + v];
       oldph += st[4 * k + 2 + v];
     }
+    uint64_t smask = 0;
+    if (N <= 64)
+      for (int k = k0 + 1; k < N; ++k) smask |= (uint64_t)(sg[k] & 1) << k;
     const int vflip = sg[k0] ^ 1;
     double lp = st[4 * k0 + vflip];
     double ph = st[4 * k0 + 2 + vflip];
@@ -212,10 +220,17 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
         for (int e = 0; e < 16; ++e) hA[cb][(e / 4) * 8 + half * 4 + (e % 4)][unit] = hin[e];
         __syncthreads();
       }
-      // gate pre-activations of the 32 sequences for this wave's units
+      // gate pre-activations of the 32 sequences for this wave's units (1D:
+      // scaled for exp2, biases of u, r and the input term in the one-hot
+      // fragments, so those accumulators start from zero)
       f32x16_m au, ar, ag, ai;
+      if (DIM == 1) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) { au[e] = bu; ar[e] = br; ag[e] = bh; ai[e] = bi; }
+        for (int e = 0; e < 16; ++e) { au[e] = 0.f; ar[e] = 0.f; ag[e] = bgs; ai[e] = 0.f; }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) { au[e] = bu; ar[e] = br; ag[e] = bh; ai[e] = bi; }
+      }
 #pragma unroll
       for (int s4 = 0; s4 < KS; s4 += 4) {
         const float4 av = *reinterpret_cast<const float4*>(&hA[cb][col][s4 + half * KS]);
@@ -240,10 +255,20 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
       for (int e = 0; e < 16; ++e) {
         const int row = (e / 4) * 8 + half * 4 + (e % 4);
         const float hp = DIM == 1 ? hA[cb][row][unit] : hin[e];
-        const float u = fast_sigmoid(au[e]);
-        const float rr = fast_sigmoid(ar[e]);
-        const float ht = fast_tanh(rr * ag[e] + ai[e]);
-        const float hn = (1.f - u) * hp + u * ht;
+        float hn;
+        if (DIM == 1) {
+          // pre-scaled: u = 1 / (1 + 2^au), tanh y = 1 - 2 / (1 + 2^y')
+          const float u = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(au[e]));
+          const float rr = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(ar[e]));
+          const float y = fmaf(rr, ag[e], ai[e]);
+          const float ht = fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(y)), 1.f);
+          hn = fmaf(u, ht - hp, hp);
+        } else {
+          const float u = fast_sigmoid(au[e]);
+          const float rr = fast_sigmoid(ar[e]);
+          const float ht = fast_tanh(rr * ag[e] + ai[e]);
+          hn = (1.f - u) * hp + u * ht;
+        }
         hA[nb][row][unit] = hn;
         if (DIM == 2) a.ring[(((size_t)blockIdx.x * S + row) * a.W + k % a.W) * H + unit] = hn;
       }
@@ -278,7 +303,7 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
         if (nup >= N / 2) { lp0 = -INFINITY; lp1 = 0.f; }
         else if (ndn >= N / 2) { lp0 = 0.f; lp1 = -INFINITY; }
       }
-      int v = sg[k];
+      int v = N <= 64 ? (int)((smask >> k) & 1u) : (int)sg[k];
       if (k == f2p) v ^= 1;
       lp += (double)(v == 0 ? lp0 : lp1);
       if (a.cplx) {
