@@ -779,11 +779,13 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
                                  double* Di, uint32_t* status) {
   constexpr int PB = 16, NB = CB / 16;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int r = e / CB, c = e % CB;
-    if (r >= nb && c <= r) S[r][c] = (r == c) ? 1.0 : 0.0;
+  if (nb < CB) {   // the last, partial block only
+    for (int e = tid; e < CB * CB; e += 256) {
+      const int r = e / CB, c = e % CB;
+      if (r >= nb && c <= r) S[r][c] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   bool bad = false;
   for (int P = 0; P < CB / PB; ++P) {
     const int p0 = PB * P, p1 = p0 + PB;
