@@ -726,31 +726,41 @@ struct DiagArgs {
   double J, J2;
 };
 
-__global__ void k_eloc_sum(DiagArgs a) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.Ns) return;
+// one wavefront per sample: lanes take bonds and terms in strides of 64,
+// then a fixed butterfly sums them
+__global__ __launch_bounds__(256) void k_eloc_sum(DiagArgs a) {
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (s >= a.Ns) return;   // uniform per wavefront
   const uint8_t* sg = a.sigma + (size_t)s * a.N;
   double d = 0.0;
   if (a.kind == MINSR_HAM_TFIM) {
-    for (int i = 0; i + 1 < a.N; ++i) d += (1.0 - 2.0 * sg[i]) * (1.0 - 2.0 * sg[i + 1]);
-    if (a.pbc && a.N > 2) d += (1.0 - 2.0 * sg[a.N - 1]) * (1.0 - 2.0 * sg[0]);
-    d = -a.J * d;
+    const int nbond = (a.pbc && a.N > 2) ? a.N : a.N - 1;
+    for (int i = lane; i < nbond; i += 64) {
+      const int j = i + 1 < a.N ? i + 1 : 0;
+      d += -a.J * ((1.0 - 2.0 * sg[i]) * (1.0 - 2.0 * sg[j]));
+    }
   } else if (a.kind == MINSR_HAM_J1J2) {
-    for (int b = 0; b < a.n_nn + a.n_nnn; ++b) {
-      double Jb = b < a.n_nn ? a.J : a.J2;
-      if (Jb == 0.0) continue;
-      int p = a.bonds[2 * b], q = a.bonds[2 * b + 1];
+    for (int b = lane; b < a.n_nn + a.n_nnn; b += 64) {
+      const double Jb = b < a.n_nn ? a.J : a.J2;
+      const int p = a.bonds[2 * b], q = a.bonds[2 * b + 1];
       d += 0.25 * Jb * (1.0 - 2.0 * sg[p]) * (1.0 - 2.0 * sg[q]);
     }
   }
   double re = d, im = 0.0;
-  for (int t = 0; t < a.M; ++t) {
+  for (int t = lane; t < a.M; t += 64) {
     const double* c = a.contrib + ((size_t)t * a.Ns + s) * 2;
     re += c[0];
     im += c[1];
   }
-  a.eloc[2 * s] = re;
-  a.eloc[2 * s + 1] = im;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    re += __shfl_xor(re, m, 64);
+    im += __shfl_xor(im, m, 64);
+  }
+  if (lane == 0) {
+    a.eloc[2 * s] = re;
+    a.eloc[2 * s + 1] = im;
+  }
 }
 
 template <typename T>
@@ -794,7 +804,7 @@ static int eloc_t(minsr_model* m, const Work<T>& w, const minsr_hamiltonian* H, 
   d.sigma = sigma; d.contrib = m->contrib; d.eloc = eloc; d.bonds = m->bonds;
   d.n_nn = m->n_nn; d.n_nnn = m->n_nnn; d.N = m->N; d.Ns = Ns; d.M = M; d.kind = H->kind;
   d.pbc = H->pbc; d.J = H->J; d.J2 = H->J2;
-  k_eloc_sum<<<(Ns + 255) / 256, 256, 0, s>>>(d);
+  k_eloc_sum<<<(Ns + 3) / 4, 256, 0, s>>>(d);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
 }
