@@ -222,7 +222,7 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   rc = rc ? rc : alloc((void**)&m->gpart, m->gpart_elems * sizeof(float));
   rc = rc ? rc : alloc((void**)&m->epsp, rows * 8);
   rc = rc ? rc : alloc((void**)&m->x, rows * 8);
-  rc = rc ? rc : alloc((void**)&m->vwork, rows * 8);
+  rc = rc ? rc : alloc((void**)&m->vwork, chol_vec_elems((int)rows) * 8);
   rc = rc ? rc : alloc((void**)&m->csync, chol_sync_words((int)rows) * 4);
   rc = rc ? rc : alloc((void**)&m->dpart, ((rows + 63) / 64) * Np * 8);
   rc = rc ? rc : alloc((void**)&m->dtheta, Np * 8);

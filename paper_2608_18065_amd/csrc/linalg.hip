@@ -393,7 +393,9 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
 // ============================================================= Cholesky
 // Right-looking tiled Cholesky of A = T + lambda I (lower, row-major, tiles
 // of 64) into a separate buffer, so T survives, with the forward
-// substitution L y = b folded in.  One launch per block column k:
+// substitution L y = b folded in.  FP64 runs the whole factorisation in one
+// launch (k_chol_persist_f64, below).  FP32 takes one launch per block
+// column k:
 //   every workgroup updates one trailing tile A_ij -= L_ik L_jk^T (i >= j > k);
 //   the workgroup of the next diagonal tile then factors it, forms the
 //   inverse of its factor and the block y_{k+1} = inv(L) b_{k+1}, and
@@ -886,10 +888,20 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
   }
 }
 
-// Block column k of the FP64 factorisation (k = -1: the first block column).
-// Roles and synchronisation as in k_chol_step; wave w holds rows
-// [16w, 16w + 16) of its tile as four 16 x 16 MFMA result blocks.
-__global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
+// FP64, the whole factorisation in one launch: one workgroup per lower tile
+// (i, j), keeping the tile in registers from its first read of T + lambda I
+// to its final value.  Roles come from a ticket in column-major order of the
+// tiles, (0,0), (1,0), ..., (1,1), (2,1), ..., so a workgroup only waits for
+// tiles of earlier columns or for the diagonal tile of its own column, all of
+// which took earlier tickets: every wait ends whether or not the whole grid
+// is resident.  A tile applies the updates of columns k < j as their panel
+// tiles are published (flag per tile); the diagonal tile then factors,
+// inverts and solves its block of L y = b from the contributions L_jk y_k
+// that the panel tiles left in per-tile slots (summed in the order of k);
+// a panel tile waits for its diagonal tile, forms L_ij = A_ij inv(L_jj)^T,
+// stores it with its contribution L_ij y_j, and publishes.
+__global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* ctl,
+                                                          double* cpart) {
   __shared__ double X[CB][LDT];
   __shared__ double Y[CB][LDT];
   __shared__ double Tm[4][16][17];
@@ -897,87 +909,92 @@ __global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
   __shared__ double lb[CB];
   __shared__ double yb[CB];
   __shared__ int tk;
-  const int n = a.n, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int n = a.n, nblk = a.nblk, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   double* A = reinterpret_cast<double*>(a.A);
-  const double* Tm0 = reinterpret_cast<const double*>(a.T);
+  const double* T0 = reinterpret_cast<const double*>(a.T);
   double* y = reinterpret_cast<double*>(a.y);
-  uint32_t* tickets = a.sync;
-  uint32_t* flags = a.sync + (a.nblk + 1);
-  const int kk = k + 1;
+  uint32_t* dflag = ctl + 1;              // [nblk]: diagonal tile j published
+  uint32_t* pflag = ctl + 1 + nblk;       // [nblk][nblk]: panel tile (i, j) published
   if (tid == 0)
-    tk = (int)__hip_atomic_fetch_add(&tickets[kk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tk = (int)__hip_atomic_fetch_add(&ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  const int ticket = tk;
-  int ti, tj;
-  if (k < 0) { ti = ticket; tj = 0; }
-  else { pair_decode(ticket, ti, tj); ti += kk; tj += kk; }
-  const int r0 = ti * CB, c0 = tj * CB;
-  const bool fresh = k <= 0;
-  const double* src = fresh ? Tm0 : A;
+  int j = 0, rem = tk;
+  while (rem >= nblk - j) { rem -= nblk - j; ++j; }
+  const int i = j + rem;
+  const int r0 = i * CB, c0 = j * CB;
+  const bool diag = i == j;
+  // relaxed polls (an acquiring load would invalidate this CU's caches at
+  // every poll, slowing the many waiting tiles' neighbours), one acquire
+  // fence once the flag is seen
+  auto wait_flag = [&](const uint32_t* f) {
+    if (tid == 0) {
+      while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+  };
+  auto publish = [&](uint32_t* f) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(f, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  };
 
-  // current tile values in the MFMA result layout
+  // T + lambda I in the MFMA result layout (wave w: rows 16w.., four blocks)
   f64x4_t t[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      // every load is issued (clamped address), the mask applies to the value:
-      // a guarded load would be waited for before the next one is issued
       const int r = r0 + 16 * w + mrow(lane, v), col = c0 + 16 * c + (lane & 15);
-      double val = src[(size_t)min(r, n - 1) * n + min(col, n - 1)];
-      if (fresh && r == col) val += a.lambda;
-      t[c][v] = (r < n && col < n && (ti != tj || col <= r)) ? val : 0.0;
+      double val = T0[(size_t)min(r, n - 1) * n + min(col, n - 1)];
+      if (r == col) val += a.lambda;
+      t[c][v] = (r < n && col < n && (!diag || col <= r)) ? val : 0.0;
     }
-  if (k >= 0) {
-    // A_ij -= L_ik L_jk^T (one operand tile for diagonal tiles)
+  // updates A_ij -= L_ik L_jk^T, k < j, in order of k
+  for (int k = 0; k < j; ++k) {
+    wait_flag(&pflag[i * nblk + k]);
+    if (!diag) wait_flag(&pflag[j * nblk + k]);
     const int k0 = k * CB;
-    const bool diag = ti == tj;
     {
       double vi[CB * CB / 256], vj[CB * CB / 256];
 #pragma unroll
-      for (int i = 0; i < CB * CB / 256; ++i) {
-        const int e = tid + 256 * i, r = e / CB, q = e % CB;
-        const double xi = A[(size_t)min(r0 + r, n - 1) * n + k0 + q];
-        vi[i] = (r0 + r < n) ? xi : 0.0;
+      for (int q = 0; q < CB * CB / 256; ++q) {
+        const int e = tid + 256 * q, r = e / CB, cc = e % CB;
+        const double xi = A[(size_t)min(r0 + r, n - 1) * n + k0 + cc];
+        vi[q] = (r0 + r < n) ? xi : 0.0;
         if (!diag) {
-          const double xj = A[(size_t)min(c0 + r, n - 1) * n + k0 + q];
-          vj[i] = (c0 + r < n) ? xj : 0.0;
+          const double xj = A[(size_t)min(c0 + r, n - 1) * n + k0 + cc];
+          vj[q] = (c0 + r < n) ? xj : 0.0;
         }
       }
 #pragma unroll
-      for (int i = 0; i < CB * CB / 256; ++i) {
-        const int e = tid + 256 * i, r = e / CB, q = e % CB;
-        X[r][q] = vi[i];
-        if (!diag) Y[r][q] = vj[i];
+      for (int q = 0; q < CB * CB / 256; ++q) {
+        const int e = tid + 256 * q, r = e / CB, cc = e % CB;
+        X[r][cc] = vi[q];
+        if (!diag) Y[r][cc] = vj[q];
       }
     }
     __syncthreads();
     const double (*Yo)[LDT] = diag ? X : Y;
 #pragma unroll
     for (int c = 0; c < 4; ++c) t[c] = mm_nt<CB, true>(t[c], X, 16 * w, Yo, 16 * c, 0, lane);
-    __syncthreads();   // X, Y are reused below
+    __syncthreads();   // X, Y are rewritten next
   }
 
-  if (tj != kk) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = r0 + 16 * w + mrow(lane, v), col = c0 + 16 * c + (lane & 15);
-        if (r < n && col < n && (ti != tj || col <= r)) A[(size_t)r * n + col] = t[c][v];
-      }
-    return;
-  }
-
-  const int kb0 = kk * CB, nb = min(CB, n - kb0);
-  double* Di = reinterpret_cast<double*>(a.Dinv) + (size_t)kk * CB * CB;
+  const int kb0 = j * CB, nb = min(CB, n - kb0);
+  double* Di = reinterpret_cast<double*>(a.Dinv) + (size_t)j * CB * CB;
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int v = 0; v < 4; ++v) X[16 * w + mrow(lane, v)][16 * c + (lane & 15)] = t[c][v];
-  if (ti == kk) {
-    // diagonal tile: factor, invert, y_kk = inv(L) b_kk, publish
-    if (tid < CB) yb[tid] = tid < nb ? y[kb0 + tid] : 0.0;
+  if (diag) {
+    // b_j - sum_k L_jk y_k (the contributions are published with their tiles)
+    if (tid < CB) {
+      double r = tid < nb ? y[kb0 + tid] : 0.0;
+      for (int k = 0; k < j; ++k) r -= cpart[((size_t)j * nblk + k) * CB + tid];
+      yb[tid] = tid < nb ? r : 0.0;
+    }
     __syncthreads();
     factor_block_f64(X, Y, Tm, rinv, lb, nb, A, n, kb0, Di, a.status);
     __syncthreads();
@@ -990,24 +1007,18 @@ __global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
       s += __shfl_xor(s, 2, 4);
       if (part == 0 && row < nb) y[kb0 + row] = s;
     }
-    if (kk + 1 < a.nblk) {
-      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
-      __syncthreads();
-      if (tid == 0) __hip_atomic_store(&flags[kk], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (j + 1 < nblk) publish(&dflag[j]);
     return;
   }
 
-  // panel tile: wait for the factor of block kk, then L_ik = A_ik inv(L_kk)^T
-  if (tid == 0) {
-    while (__hip_atomic_load(&flags[kk], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-      __builtin_amdgcn_s_sleep(2);
-  }
-  __syncthreads();
+  // panel tile: L_ij = A_ij inv(L_jj)^T and its contribution L_ij y_j
+  wait_flag(&dflag[j]);
+  {
+    double dv[CB * CB / 256];
 #pragma unroll
-  for (int i = 0; i < CB * CB / 256; ++i) {
-    const int e = tid + 256 * i;
-    Y[e / CB][e % CB] = Di[e];
+    for (int q = 0; q < CB * CB / 256; ++q) dv[q] = Di[tid + 256 * q];
+#pragma unroll
+    for (int q = 0; q < CB * CB / 256; ++q) Y[(tid + 256 * q) / CB][(tid + 256 * q) % CB] = dv[q];
   }
   if (tid < CB) yb[tid] = y[kb0 + tid < n ? kb0 + tid : 0];
   __syncthreads();
@@ -1025,7 +1036,6 @@ __global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
       s[v] = fma(ok ? l[v] : 0.0, yb[col], s[v]);
     }
   }
-  // the 16 lanes of a row hold its 64 columns, four per lane
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
 #pragma unroll
@@ -1033,11 +1043,10 @@ __global__ __launch_bounds__(256) void k_chol_step_f64(CholArgs a, int k) {
   }
   if ((lane & 15) == 0) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = r0 + 16 * w + mrow(lane, v);
-      if (r < n) y[r] -= s[v];
-    }
+    for (int v = 0; v < 4; ++v)
+      cpart[((size_t)i * nblk + j) * CB + 16 * w + mrow(lane, v)] = s[v];
   }
+  publish(&pflag[i * nblk + j]);
 }
 
 // sync words and b -> y (one kernel, safe inside captured graphs)
@@ -1057,15 +1066,15 @@ __global__ void k_chol_prep(uint32_t* sync, int nsync, const double* b, TT* y, i
 // requested before waiting), then publishes x_k through its flag.
 template <typename TT>
 __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const TT* Dinv,
-                                                      const TT* y, double* x, uint32_t* sync,
+                                                      const TT* y, double* x, uint32_t* bsync,
                                                       int nblk) {
   __shared__ TT Dk[CB][CB + 1];
   __shared__ TT xj[CB];
   __shared__ TT part[4][CB];
   __shared__ TT rb[CB];
   __shared__ int tk;
-  uint32_t* ticket_ctr = sync + nblk;                // the unused last ticket word
-  uint32_t* bflags = sync + 2 * (nblk + 1);
+  uint32_t* ticket_ctr = bsync;                      // then one flag per block
+  uint32_t* bflags = bsync + 1;
   const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
   if (tid == 0)
     tk = (int)__hip_atomic_fetch_add(ticket_ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1094,8 +1103,9 @@ __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const 
   if (kb + 1 < nblk) fetch(nblk - 1);
   for (int j = nblk - 1; j > kb; --j) {
     if (tid == 0) {
-      while (__hip_atomic_load(&bflags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+      while (__hip_atomic_load(&bflags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
         __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (tid < CB) xj[tid] = j * CB + tid < n ? (TT)x[j * CB + tid] : (TT)0;
@@ -1130,8 +1140,22 @@ __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const 
 }
 
 size_t chol_dinv_elems(int n) { return (size_t)((n + CB - 1) / CB) * CB * CB; }
-// tickets and flags of the factorisation, then the flags of the backward pass
-size_t chol_sync_words(int n) { return 3 * (size_t)((n + CB - 1) / CB + 1); }
+// sync words: [2 (nblk + 1)] tickets and flags of the launch-per-column
+// factorisation (FP32), [nblk + 1] ticket and flags of the backward pass,
+// [1 + nblk + nblk^2] ticket, diagonal and panel flags of the one-launch
+// factorisation (FP64)
+static size_t chol_sync_bwd(int nblk) { return 2 * (size_t)(nblk + 1); }
+static size_t chol_sync_one(int nblk) { return 3 * (size_t)(nblk + 1); }
+size_t chol_sync_words(int n) {
+  const size_t nblk = (size_t)((n + CB - 1) / CB);
+  return chol_sync_one((int)nblk) + 1 + nblk + nblk * nblk;
+}
+// solver vector: y (n, rounded up to whole blocks), then the per-tile
+// contributions L_ij y_j of the one-launch factorisation ([nblk][nblk][64])
+size_t chol_vec_elems(int n) {
+  const size_t nblk = (size_t)((n + CB - 1) / CB);
+  return nblk * CB + nblk * nblk * CB;
+}
 
 template <typename TT>
 static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, double lambda,
@@ -1142,16 +1166,19 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
   k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n);
   MINSR_CHECK_LAUNCH();
   CholArgs a{T, A, Dinv, yv, sync, status, lambda, n, nblk};
-  for (int k = -1; k + 1 < nblk; ++k) {
-    const int nt = nblk - k - 1;
-    const int grid = k < 0 ? nblk : nt * (nt + 1) / 2;
-    if constexpr (std::is_same<TT, double>::value)
-      k_chol_step_f64<<<grid, 256, 0, s>>>(a, k);
-    else
-      k_chol_step<TT><<<grid, 256, 0, s>>>(a, k);
+  if constexpr (std::is_same<TT, double>::value) {
+    k_chol_persist_f64<<<nblk * (nblk + 1) / 2, 256, 0, s>>>(a, sync + chol_sync_one(nblk),
+                                                             yv + (size_t)nblk * CB);
     MINSR_CHECK_LAUNCH();
+  } else {
+    for (int k = -1; k + 1 < nblk; ++k) {
+      const int nt = nblk - k - 1;
+      const int grid = k < 0 ? nblk : nt * (nt + 1) / 2;
+      k_chol_step<TT><<<grid, 256, 0, s>>>(a, k);
+      MINSR_CHECK_LAUNCH();
+    }
   }
-  k_trsv_back_mt<TT><<<nblk, 256, 0, s>>>(A, n, Dinv, yv, x, sync, nblk);
+  k_trsv_back_mt<TT><<<nblk, 256, 0, s>>>(A, n, Dinv, yv, x, sync + chol_sync_bwd(nblk), nblk);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
 }

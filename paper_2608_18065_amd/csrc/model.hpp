@@ -49,7 +49,7 @@ struct minsr_model {
   size_t gpart_elems = 0;
   double* epsp = nullptr;   // [n] eps'
   double* x = nullptr;      // [n] solution
-  double* vwork = nullptr;  // [n] solver scratch (forward-substitution vector)
+  double* vwork = nullptr;  // solver scratch: forward-substitution vector, tile contributions
   uint32_t* csync = nullptr;// Cholesky tickets and flags
   double* dpart = nullptr;  // update partials
   double* dtheta = nullptr; // [Np]
@@ -114,12 +114,13 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
                 size_t gpart_elems, hipStream_t s, int which = 3, const void* Rlo = nullptr,
                 int split = 0);
 // factors T + lambda I into Lf (T is left unchanged) and solves for x
-// (yv: n elements of scratch; sync: chol_sync_words(n) words)
+// (yv: chol_vec_elems(n) elements of scratch; sync: chol_sync_words(n) words)
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, double* yv, uint32_t* sync,
                           uint32_t* status, hipStream_t s);
 size_t chol_dinv_elems(int n);
 size_t chol_sync_words(int n);
+size_t chol_vec_elems(int n);
 // x = T^+ b with eigenvalues <= cutoff * lambda_max dropped (n <= 4096);
 // eig: pinv_workspace_doubles(nmax) doubles, nmax >= n
 int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* x,
