@@ -67,9 +67,9 @@ extern "C" {
 /* numerical precision of one minSR step */
 #define MINSR_FORM_FP64_REF   0  /* everything in FP64                       */
 #define MINSR_FORM_BF16_FP64  1  /* O' rounded to BF16 as a hi/lo pair, Gram
-                                    hi hi^T + hi lo^T + lo hi^T on BF16 MFMA
-                                    with FP32 accumulation; FP64 reductions,
-                                    solve and update                        */
+                                    (hi + lo)(hi + lo)^T on BF16 MFMA (four
+                                    products, FP32 accumulation flushed to
+                                    FP64); FP64 reductions, solve, update   */
 #define MINSR_FORM_FP32_PLAIN 2  /* FP32 O', Gram, solve and update          */
 #define MINSR_FORM_BF16_1PASS 3  /* as BF16_FP64 with O' a single BF16 array
                                     (one MFMA pass; larger Gram error)       */

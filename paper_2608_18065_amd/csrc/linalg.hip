@@ -141,9 +141,15 @@ typedef __attribute__((ext_vector_type(16))) float f32x16_t;
 // while the current stage feeds the matrix cores.  Rows of R have a stride
 // ld that is a multiple of 64, zero-padded past Np.
 // SPLIT: R = hi + lo (two BF16 arrays); the tile is hi hi^T + hi lo^T +
-// lo hi^T (the lo lo^T term is below FP32 accumulation accuracy), which is
-// symmetric by construction.
+// lo hi^T + lo lo^T, the exact Gram of hi + lo, so T stays positive
+// semidefinite up to accumulation error.  (lo is the BF16 residual of R,
+// about 2^-8 of it, so lo lo^T is about 2^-16 of T: leaving it out subtracts
+// a positive semidefinite matrix of that size, which made T + lambda I
+// indefinite for lambda = 1e-3 once |T| grew to a few hundred.)
+// The FP32 accumulators are added into FP64 ones every GFLUSH stages and
+// restarted, so no FP32 sum runs over more than 128 (split) or 256 inputs.
 constexpr int GT = 128;
+constexpr int GFLUSH = 4;
 
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
@@ -161,12 +167,21 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   f32x16_t acc[2][2];
+  double accd[2][2][16];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
+      for (int e = 0; e < 16; ++e) { acc[a][b][e] = 0.f; accd[a][b][e] = 0.0; }
+  auto flush = [&]() {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) { accd[a][b][e] += (double)acc[a][b][e]; acc[a][b][e] = 0.f; }
+  };
 
   const int arow0 = ti * GT, brow0 = tj * GT;
   constexpr int CPT = GT * (GK / 8) / 256;
@@ -199,7 +214,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
     store(0);
   }
   __syncthreads();
-  int cur = 0;
+  int cur = 0, stages = 0;
   for (size_t kk = k0; kk < k1; kk += GK) {
     const bool more = kk + GK < k1;
     if (more) load(kk + GK);
@@ -223,13 +238,16 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
           if (SPLIT) {
             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][a], fb[NOP - 1][b], acc[a][b], 0, 0, 0);
             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[NOP - 1][a], fb[0][b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[NOP - 1][a], fb[NOP - 1][b], acc[a][b], 0, 0, 0);
           }
         }
     }
+    if (++stages == GFLUSH) { flush(); stages = 0; }
     if (more) store(cur ^ 1);
     __syncthreads();
     cur ^= 1;
   }
+  flush();
   // write the partial tile: acc element e of lane l is row
   // (e / 4) * 8 + (l / 32) * 4 + e % 4, column l % 32 of its 32 x 32 block
   float* out = part + ((size_t)split * gridDim.x + blockIdx.x) * GT * GT;
@@ -241,7 +259,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
       for (int e = 0; e < 16; ++e) {
         const int r = wm + a * 32 + (e / 4) * 8 + (lane >> 5) * 4 + (e % 4);
         const int c = wn + b * 32 + (lane & 31);
-        out[r * GT + c] = acc[a][b][e];
+        out[r * GT + c] = (float)accd[a][b][e];
       }
 }
 
@@ -353,7 +371,11 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
   const int tile = dtype == MINSR_BF16 ? GT : VT_;
   const int nt = (n + tile - 1) / tile;
   const int npairs = nt * (nt + 1) / 2;
-  const int S = pick_split(npairs, Np, want_split);
+  // the MFMA tile kernel holds one workgroup per CU (FP64 accumulators):
+  // by default the split keeps the grid to one round of the 256 CUs
+  const int want = (dtype == MINSR_BF16 && want_split <= 0)
+                       ? std::max(1, std::min(8, 256 / npairs)) : want_split;
+  const int S = pick_split(npairs, Np, want);
   const size_t kgran = dtype == MINSR_BF16 ? 64 : VK;
   size_t kchunk = (ld + S - 1) / S;
   kchunk = (kchunk + kgran - 1) / kgran * kgran;

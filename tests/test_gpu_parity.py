@@ -425,11 +425,17 @@ def test_gram_matches_its_operand(form):
     assert R.shape == (300, m.Np)
     T = it["T"].double().cpu().numpy()
     assert np.array_equal(T, T.T)
-    ref = R @ R.T
-    if form == 1:   # hi hi^T + hi lo^T + lo hi^T
+    if form == 1:   # (hi + lo)(hi + lo)^T
         Rl = it["Oprime_lo"].double().cpu().numpy()
         assert np.max(np.abs(Rl)) <= 2.0 ** -8 * np.max(np.abs(R))
-        ref = ref + R @ Rl.T + Rl @ R.T
+        R = R + Rl
+    ref = R @ R.T
     assert np.max(np.abs(T - ref)) < 1e-5 * np.max(np.abs(ref))
+    # T is the Gram of its operand up to accumulation error, so positive
+    # semidefinite to that accuracy (the operand's centred blocks give it
+    # null directions, where a missing term would show as a negative pivot)
+    w, wr = np.linalg.eigvalsh(T), np.linalg.eigvalsh(ref)
+    print("min eig T %.3e  exact %.3e  max %.3e" % (w[0], wr[0], w[-1]))
+    assert w[0] > -1e-7 * w[-1]
     # centred blocks: every column of each block of O' sums to ~0
     assert np.max(np.abs(R[:150].sum(axis=0))) < 1e-2 * np.max(np.abs(R))
