@@ -42,12 +42,12 @@ PEAK_FP32_MFMA_TFLOPS = 157.3    # dense FP32 matrix cores (equal to the FP32 ve
 # scaled by the counter's reading on a plain copy of known size; None until
 # taken for the current kernel version
 TRAFFIC_BYTES = {
-    # k_eloc_mfma: 9423.0 KiB fetched x 2.000 + 1024.0 KiB written x 1.000
-    "eloc": 9423.0 * 1024 * 2.0 + 1024.0 * 1024,
-    # k_jacobian: 8661.7 KiB fetched x 2.000 + 52380.7 KiB written x 1.000
-    "jacobian": 8661.7 * 1024 * 2.0 + 52380.7 * 1024,
-    # k_gram_bf16 (split form, 8-way split-K): 187973.1 KiB x 2.000 + 18432.0 KiB x 1.000
-    "gram": 187973.1 * 1024 * 2.0 + 18432.0 * 1024}
+    # k_eloc_mfma: 9403.5 KiB fetched x 2.000 + 1024.0 KiB written x 1.000
+    "eloc": 9403.5 * 1024 * 2.0 + 1024.0 * 1024,
+    # k_jacobian (gate-tape path): 41522.7 KiB fetched x 2.000 + 52414.0 KiB written x 1.000
+    "jacobian": 41522.7 * 1024 * 2.0 + 52414.0 * 1024,
+    # k_gram_bf16 (split form, four products, 7-way split-K): 187087.0 KiB x 2.000 + 16128.0 KiB x 1.000
+    "gram": 187087.0 * 1024 * 2.0 + 16128.0 * 1024}
 
 
 def parse():
@@ -76,8 +76,9 @@ def work_units(wl):
         Np=Np,
         # GRU gate products (3 H x H) and the two logits per re-evaluated site
         eloc_flop=seq_sites * (6 * H * H + 4 * H),
-        # O written once in FP32 (Ns rows of Np)
-        jacobian_bytes=Ns * Np * 4,
+        # O written once in FP32 (Ns rows of Np); the sampler's gate tape
+        # (4 H per site) and hidden states (H per site) read once, FP32
+        jacobian_bytes=Ns * Np * 4 + Ns * N * 5 * H * 4,
         # useful flops of the symmetric Gram: n (n + 1) Np
         gram_flop=Ns * (Ns + 1) * Np,
     )

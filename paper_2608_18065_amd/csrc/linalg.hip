@@ -372,9 +372,25 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
   const int nt = (n + tile - 1) / tile;
   const int npairs = nt * (nt + 1) / 2;
   // the MFMA tile kernel holds one workgroup per CU (FP64 accumulators):
-  // by default the split keeps the grid to one round of the 256 CUs
-  const int want = (dtype == MINSR_BF16 && want_split <= 0)
-                       ? std::max(1, std::min(8, 256 / npairs)) : want_split;
+  // by default the split (1..8) minimises rounds of the grid over the CUs
+  // times the K range of one workgroup
+  int want = want_split;
+  if (dtype == MINSR_BF16 && want_split <= 0) {
+    static int ncu = 0;
+    if (ncu == 0) {
+      int dev = 0, v = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+        ncu = v;
+      else
+        ncu = 256;
+    }
+    double best = 1e300;
+    for (int S = 1; S <= 8; ++S) {
+      const double cost = (double)((npairs * S + ncu - 1) / ncu) / S;
+      if (cost < best * (1.0 - 1e-9)) { best = cost; want = S; }
+    }
+  }
   const int S = pick_split(npairs, Np, want);
   const size_t kgran = dtype == MINSR_BF16 ? 64 : VK;
   size_t kchunk = (ld + S - 1) / S;
