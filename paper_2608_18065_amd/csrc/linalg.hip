@@ -33,9 +33,15 @@ __global__ void k_colmean(const double* part, int nrc, int rows_per_block, int n
   size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= Np) return;
   for (int b = 0; b < nblocks; ++b) {
-    double s = 0.0;
-    for (int c = 0; c < nrc; ++c) s += part[((size_t)b * nrc + c) * Np + col];
-    mean[(size_t)b * Np + col] = s / rows_per_block;
+    // four partial sums so that several loads are in flight
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int c = 0;
+    for (; c + 4 <= nrc; c += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s4[u] += part[((size_t)b * nrc + c + u) * Np + col];
+    }
+    for (; c < nrc; ++c) s4[0] += part[((size_t)b * nrc + c) * Np + col];
+    mean[(size_t)b * Np + col] = ((s4[0] + s4[1]) + (s4[2] + s4[3])) / rows_per_block;
   }
 }
 
@@ -1248,6 +1254,44 @@ __global__ void k_update_part(const TR* R, int n, size_t Np, size_t ld, int RC, 
     for (int r = r0; r < r1; ++r) s += (double)(float)R[(size_t)r * ld + col] * x[r];
   part[(size_t)blockIdx.y * Np + col] = s;
 }
+
+// BF16 hi/lo: two adjacent columns per thread (4-byte loads), rows in steps
+// of four with their loads issued together; each column's sum runs over the
+// rows in order, as above
+__global__ void k_update_part_bf16x2(const __hip_bfloat16* R, const __hip_bfloat16* Rlo, int n,
+                                     size_t Np, size_t ld, int RC, const double* x, double* part) {
+  const size_t col = 2 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (col >= Np) return;
+  const int r0 = blockIdx.y * RC, r1 = min(n, r0 + RC);
+  double s0 = 0.0, s1 = 0.0;
+  auto term = [&](int r, double& a0, double& a1) {
+    // ld is a multiple of 64 and col even: the pair lies inside the padded row
+    const __hip_bfloat162 h = *reinterpret_cast<const __hip_bfloat162*>(R + (size_t)r * ld + col);
+    const __hip_bfloat162 l = *reinterpret_cast<const __hip_bfloat162*>(Rlo + (size_t)r * ld + col);
+    const double xr = x[r];
+    a0 += ((double)__bfloat162float(h.x) + (double)__bfloat162float(l.x)) * xr;
+    a1 += ((double)__bfloat162float(h.y) + (double)__bfloat162float(l.y)) * xr;
+  };
+  int r = r0;
+  for (; r + 4 <= r1; r += 4) {
+    __hip_bfloat162 h[4], l[4];
+    double xr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      h[u] = *reinterpret_cast<const __hip_bfloat162*>(R + (size_t)(r + u) * ld + col);
+      l[u] = *reinterpret_cast<const __hip_bfloat162*>(Rlo + (size_t)(r + u) * ld + col);
+      xr[u] = x[r + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s0 += ((double)__bfloat162float(h[u].x) + (double)__bfloat162float(l[u].x)) * xr[u];
+      s1 += ((double)__bfloat162float(h[u].y) + (double)__bfloat162float(l[u].y)) * xr[u];
+    }
+  }
+  for (; r < r1; ++r) term(r, s0, s1);
+  part[(size_t)blockIdx.y * Np + col] = s0;
+  if (col + 1 < Np) part[(size_t)blockIdx.y * Np + col + 1] = s1;
+}
 template <>
 __global__ void k_update_part<double>(const double* R, int n, size_t Np, size_t ld, int RC,
                                       const double* x, double* part, const double* Rlo) {
@@ -1288,8 +1332,12 @@ int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, d
   dim3 grid((unsigned)((Np + 255) / 256), (unsigned)nrc);
   const size_t ld = (Np + 63) / 64 * 64;
   if (dtype == MINSR_BF16)
-    k_update_part<__hip_bfloat16><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, n, Np, ld, RC, x,
-                                                       dpart, (const __hip_bfloat16*)Rlo);
+    if (Rlo)
+      k_update_part_bf16x2<<<dim3((unsigned)((Np + 511) / 512), (unsigned)nrc), 256, 0, s>>>(
+          (const __hip_bfloat16*)R, (const __hip_bfloat16*)Rlo, n, Np, ld, RC, x, dpart);
+    else
+      k_update_part<__hip_bfloat16><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, n, Np, ld, RC, x,
+                                                         dpart, nullptr);
   else if (dtype == MINSR_F32)
     k_update_part<float><<<grid, 256, 0, s>>>((const float*)R, n, Np, ld, RC, x, dpart, nullptr);
   else
