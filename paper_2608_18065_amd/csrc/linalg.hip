@@ -331,19 +331,33 @@ __global__ __launch_bounds__(256) void k_gram_vec(const TI* R, int n, size_t Np,
 
 // sum the split-K partials in split order; write T (lower and mirror)
 template <typename TA, typename TT>
-__global__ void k_gram_reduce(const TA* part, int npairs, int nsplit, int tile, int n, TT* T) {
-  const int pair = blockIdx.y;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= tile * tile) return;
+__global__ __launch_bounds__(256) void k_gram_reduce(const TA* part, int npairs, int nsplit,
+                                                     int tile, int n, TT* T) {
+  // one 32 x 32 sub-tile per workgroup: partials summed in split order, the
+  // tile written row-wise and its mirror through a shared-memory transpose,
+  // so both stores are coalesced rows
+  __shared__ TT sh[32][33];
+  const int pair = blockIdx.y, nsub = tile / 32;
+  const int sr = blockIdx.x / nsub, sc = blockIdx.x % nsub;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   int ti, tj;
   pair_decode(pair, ti, tj);
-  const int r = ti * tile + e / tile, c = tj * tile + e % tile;
-  if (r >= n || c >= n) return;
-  if (ti == tj && c > r) return;
-  TA s = (TA)0;
-  for (int k = 0; k < nsplit; ++k) s += part[((size_t)k * npairs + pair) * tile * tile + e];
-  T[(size_t)r * n + c] = (TT)s;
-  T[(size_t)c * n + r] = (TT)s;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int lr = sr * 32 + ty + 8 * q, lc = sc * 32 + tx;
+    const int r = ti * tile + lr, c = tj * tile + lc;
+    TA s = (TA)0;
+    for (int k = 0; k < nsplit; ++k) s += part[((size_t)k * npairs + pair) * tile * tile + lr * tile + lc];
+    sh[ty + 8 * q][tx] = (TT)s;
+    if (r < n && c < n && (ti != tj || c <= r)) T[(size_t)r * n + c] = (TT)s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int lr = sr * 32 + tx, lc = sc * 32 + ty + 8 * q;   // element (lr, lc) to T[c][r]
+    const int r = ti * tile + lr, c = tj * tile + lc;
+    if (r < n && c < n && (ti != tj || c <= r)) T[(size_t)c * n + r] = sh[tx][ty + 8 * q];
+  }
 }
 
 constexpr int MAX_SPLIT = 64;
@@ -404,7 +418,7 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
   const size_t need = (size_t)S * npairs * tile * tile * (dtype == MINSR_F64 ? 8 : 4);
   if (need > gpart_elems * sizeof(float)) return fail(MINSR_E_SHAPE, "Gram workspace too small");
   dim3 grid((unsigned)npairs, (unsigned)S);
-  dim3 rgrid((unsigned)((tile * tile + 255) / 256), (unsigned)npairs);
+  dim3 rgrid((unsigned)((tile / 32) * (tile / 32)), (unsigned)npairs);
   if (dtype == MINSR_BF16) {
     if (which & 1) {
       if (Rlo)
