@@ -92,7 +92,7 @@ static int ensure_pinv_ws(minsr_model* m, hipStream_t s) {
 }
 
 static void release(minsr_model* m) {
-  void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->gates, m->site,
+  void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->gates, m->jdp, m->site,
                   m->contrib,
                   m->elist, m->ecount, m->eitems,
                   m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
@@ -195,8 +195,10 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   rc = rc ? rc : alloc(&m->states, S * Nz * Hz * sz);
   // the Jacobian of these models reads the sampler's gate values instead of
   // recomputing them (checkpoint stride 1)
-  if (m->dim == 1 && !m->f64 && m->H <= 64)
+  if (m->dim == 1 && !m->f64 && m->H <= 64) {
     rc = rc ? rc : alloc(&m->gates, S * Nz * 4 * Hz * sz);
+    if (m->H >= 32) rc = rc ? rc : alloc(&m->jdp, (m->cplx ? 2 : 1) * S * Nz * 3 * Hz * sz);
+  }
   rc = rc ? rc : alloc((void**)&m->site, S * Nz * 4 * 8);
   rc = rc ? rc : alloc((void**)&m->contrib, (size_t)m->max_terms * S * 2 * 8);
   rc = rc ? rc : alloc((void**)&m->elist, (size_t)m->max_terms * S * 4);
@@ -466,8 +468,11 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
       rc = launch_pinv_solve(n, m->T, cfg->pinv_cutoff, m->epsp, m->x, m->eig, m->eig_elems,
                              m->eig_nmax, out->dev_status, s);
   } else {
+    // BF16 forms: T carries FP32 accumulation error of about 2^-22 of its
+    // largest diagonal entry, so the shift is kept at least 2^-21 of that
     rc = launch_cholesky_solve(n, m->T, m->Lf, m->Dinv, rdt == MINSR_F32, cfg->lambda, m->epsp,
-                               m->x, m->vwork, m->csync, out->dev_status, s);
+                               m->x, m->vwork, m->csync, out->dev_status, s,
+                               rdt == MINSR_BF16 ? 0x1p-21 : 0.0);
   }
   if (rc) return rc;
   MINSR_PHASE(8);

@@ -42,6 +42,7 @@ template <typename T> struct JacArgs {
   const uint8_t* sigma;
   const T* states;       // [Ns][N][H]; 1D: rows k with (k+1) % C == 0 are read
   const T* gates;        // 1D, C == 1, optional: [Ns][N][4][H] u, r, g, ht of the sampler
+  T* dp;                 // deferred gradients: [nseeds][Ns][N][3][H] gate adjoints
   T* O;                  // [rows][Np]
   T scale;               // 1 / sqrt(Ns)
   int W2;                // 2D adjoint window
@@ -70,7 +71,12 @@ template <int H> struct JReduce {
   }
 };
 
-template <typename T, int H, int DIM, int P, bool WL = false>
+// GD (deferred gradients; FP32 1D with the gate tape): the W_u, W_r, W_h
+// blocks of the row are not accumulated here; the reverse pass stores the
+// gate adjoints of every site and k_jac_wgrad forms those blocks as
+// products over the sites on the matrix cores.  The reverse weights of the
+// thread's unit then stay in registers.
+template <typename T, int H, int DIM, int P, bool WL = false, bool GD = false>
 __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> a) {
   using VT = typename VecJ<T>::type;
   constexpr int V = VecJ<T>::V;
@@ -119,6 +125,11 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
   auto BW = [&](int idx) -> VT {
     if constexpr (WL) return wlb[idx]; else return bw[idx];
   };
+  VT bwr[GD ? 3 * (H / V) : 1];
+  if constexpr (GD) {
+#pragma unroll
+    for (int i = 0; i < 3 * (H / V); ++i) bwr[i] = bw[((i / 3) * H + j) * 3 + i % 3];
+  }
   const VT* f2 = reinterpret_cast<const VT*>(w.f2);
   const VT* b2 = reinterpret_cast<const VT*>(w.b2);
   const uint8_t* sig = a.sigma + (size_t)sid * N;
@@ -134,11 +145,13 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
   const int nseeds = a.cplx ? 2 : 1;
   for (int seed = 0; seed < nseeds; ++seed) {
     // ---- accumulators (this thread's share of the sample's row)
-    T gWu[CP], gWr[CP], gWh[CP], gU1[DIM == 2 ? CP : 1], gU2[DIM == 2 ? CP : 1];
+    constexpr int CPG = GD ? 1 : CP;
+    T gWu[CPG], gWr[CPG], gWh[CPG], gU1[DIM == 2 ? CP : 1], gU2[DIM == 2 ? CP : 1];
 #pragma unroll
-    for (int c = 0; c < CP; ++c) {
-      gWu[c] = gWr[c] = gWh[c] = (T)0;
-      if (DIM == 2) { gU1[c] = gU2[c] = (T)0; }
+    for (int c = 0; c < CPG; ++c) gWu[c] = gWr[c] = gWh[c] = (T)0;
+    if constexpr (DIM == 2) {
+#pragma unroll
+      for (int c = 0; c < CP; ++c) gU1[c] = gU2[c] = (T)0;
     }
     T gxu[ds], gxr[ds], gxi[ds];
 #pragma unroll
@@ -395,6 +408,12 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
         const T dpu = du * u * ((T)1 - u);
         const T dpr = dr * rr * ((T)1 - rr);
         if (p == 0) { dbuf[sg][0][j] = dpu; dbuf[sg][1][j] = dpr; dbuf[sg][2][j] = dg; }
+        if constexpr (GD) {
+          if (act) {
+            T* d = a.dp + ((((size_t)seed * a.Ns + s) * N + k) * 3) * H;
+            d[j] = dpu; d[H + j] = dpr; d[2 * H + j] = dg;
+          }
+        }
         gbu += dpu; gbr += dpr; gbh += dg; gbi += da;
         if (DIM == 1) {
           if (k > 0) {
@@ -406,7 +425,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
           if (sv >= 0) { gxu[2 + sv] += dpu; gxr[2 + sv] += dpr; gxi[2 + sv] += da; }
         }
         // outer products with the cell input, columns of part p
-        {
+        if constexpr (!GD) {
           const T* xrow = DIM == 1 ? &tx[sg][kk][p * CP] : &tx[sg][0][p * CP];
 #pragma unroll
           for (int c4 = 0; c4 < CP / V; ++c4) {
@@ -424,11 +443,11 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
         // reverse product into the cell input: rows i of part p; four
         // partial sums so that several weight loads are in flight
         T partv[4] = {(T)0, (T)0, (T)0, (T)0};
-#pragma unroll 4
+#pragma unroll (GD ? H / V : 4)
         for (int i4 = p * CP / V; i4 < (p + 1) * CP / V; ++i4) {
-          const VT wu = BW((i4 * H + j) * 3 + 0);
-          const VT wr = BW((i4 * H + j) * 3 + 1);
-          const VT wg = BW((i4 * H + j) * 3 + 2);
+          const VT wu = GD ? bwr[(i4 * 3 + 0) % (GD ? 3 * (H / V) : 1)] : BW((i4 * H + j) * 3 + 0);
+          const VT wr = GD ? bwr[(i4 * 3 + 1) % (GD ? 3 * (H / V) : 1)] : BW((i4 * H + j) * 3 + 1);
+          const VT wg = GD ? bwr[(i4 * 3 + 2) % (GD ? 3 * (H / V) : 1)] : BW((i4 * H + j) * 3 + 2);
           const T* wus = reinterpret_cast<const T*>(&wu);
           const T* wrs = reinterpret_cast<const T*>(&wr);
           const T* wgs = reinterpret_cast<const T*>(&wg);
@@ -537,9 +556,19 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
         }                                                                                  \
         __syncthreads();                                                                   \
       }
-      MINSR_JAC_STAGE(gWu, gxu, ds, L.Wu, H + ds)
-      MINSR_JAC_STAGE(gWr, gxr, ds, L.Wr, H + ds)
-      MINSR_JAC_STAGE(gWh, gxu, 0, L.Wh, H)
+      if constexpr (!GD) {
+        MINSR_JAC_STAGE(gWu, gxu, ds, L.Wu, H + ds)
+        MINSR_JAC_STAGE(gWr, gxr, ds, L.Wr, H + ds)
+        MINSR_JAC_STAGE(gWh, gxu, 0, L.Wh, H)
+      } else if (act && p == 0) {
+        // the one-hot input columns of W_u, W_r (the H x H blocks come from
+        // k_jac_wgrad)
+#pragma unroll
+        for (int c = 0; c < ds; ++c) {
+          o[L.Wu + (size_t)j * (H + ds) + H + c] = gxu[c] * sc;
+          o[L.Wr + (size_t)j * (H + ds) + H + c] = gxr[c] * sc;
+        }
+      }
       if constexpr (DIM == 2) {
         MINSR_JAC_STAGE(gU1, gxu, 0, L.U1, H)
         MINSR_JAC_STAGE(gU2, gxu, 0, L.U2, H)
@@ -566,13 +595,52 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
   }
 }
 
-template <typename T, int H, int DIM, int P, bool WL = false>
+template <typename T, int H, int DIM, int P, bool WL = false, bool GD = false>
 static int launch_jac_t(const JacArgs<T>& a, hipStream_t s) {
   constexpr int NT = JShape<H, P, WL>::NT, SG = JShape<H, P, WL>::SG;
   unsigned grid = (unsigned)((a.Ns + SG - 1) / SG);
-  k_jacobian<T, H, DIM, P, WL><<<grid, NT, 0, s>>>(a);
+  k_jacobian<T, H, DIM, P, WL, GD><<<grid, NT, 0, s>>>(a);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
+}
+
+typedef __attribute__((ext_vector_type(16))) float f32x16_j;
+
+// W_u, W_r, W_h blocks of one row (deferred gradients): for gate q,
+// dW_q[j][c] = sum over sites k of dp_q[k][j] h_{k-1}[c] (h_{-1} = 0), a
+// [H x N] x [N x H] product on v_mfma_f32_32x32x2_f32 (lane l supplies
+// A[l % 32][l / 32] and B[l / 32][l % 32]; element e of lane l is row
+// 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32).  One workgroup per row,
+// each wave a share of the 3 (H / 32)^2 output blocks.
+template <int H>
+__global__ __launch_bounds__(256) void k_jac_wgrad(JacArgs<float> a) {
+  constexpr int NB = H / 32, NBLK = 3 * NB * NB, ds = 2;
+  const int row = blockIdx.x, s = row % a.Ns;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int N = a.N;
+  const float* dp = a.dp + (size_t)row * N * 3 * H;
+  const float* st = a.states + (size_t)s * N * H;
+  float* o = a.O + (size_t)row * a.L.Np;
+  const int kl = lane >> 5, cl = lane & 31;
+  for (int b = w; b < NBLK; b += 4) {
+    const int q = b / (NB * NB), jb = (b / NB) % NB, cb = b % NB;
+    f32x16_j acc;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+    for (int k2 = 0; k2 < N; k2 += 2) {
+      const int k = k2 + kl;
+      const float av = k < N ? dp[((size_t)k * 3 + q) * H + jb * 32 + cl] : 0.f;
+      const float bv = (k >= 1 && k < N) ? st[(size_t)(k - 1) * H + cb * 32 + cl] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+    const size_t off = q == 0 ? a.L.Wu : q == 1 ? a.L.Wr : a.L.Wh;
+    const int ldq = q < 2 ? H + ds : H;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int jr = jb * 32 + 8 * (e / 4) + 4 * kl + e % 4;
+      o[off + (size_t)jr * ldq + cb * 32 + cl] = acc[e] * a.scale;
+    }
+  }
 }
 
 // parts: threads per hidden unit (0 = built-in choice)
@@ -582,11 +650,28 @@ static int jac_dispatch(int H, int parts, const JacArgs<T>& a, hipStream_t s) {
     case 8: return launch_jac_t<T, 8, DIM, 1>(a, s);
     case 16: return launch_jac_t<T, 16, DIM, 1>(a, s);
     case 32:
-      if constexpr (DIM == 1 && std::is_same<T, float>::value)
+      if constexpr (DIM == 1 && std::is_same<T, float>::value) {
+        if (a.dp) {
+          const int rc = launch_jac_t<T, 32, DIM, 1, false, true>(a, s);
+          if (rc) return rc;
+          k_jac_wgrad<32><<<(unsigned)(a.Ns * (a.cplx ? 2 : 1)), 256, 0, s>>>(a);
+          MINSR_CHECK_LAUNCH();
+          return MINSR_OK;
+        }
         if (a.C <= SEGMAX_WL) return launch_jac_t<T, 32, DIM, 1, true>(a, s);
+      }
       return launch_jac_t<T, 32, DIM, 1>(a, s);
     case 64:
       if (parts == 0) parts = DIM == 1 ? 1 : 4;
+      if constexpr (DIM == 1 && std::is_same<T, float>::value) {
+        if (a.dp && parts == 1) {
+          const int rc = launch_jac_t<T, 64, DIM, 1, false, true>(a, s);
+          if (rc) return rc;
+          k_jac_wgrad<64><<<(unsigned)(a.Ns * (a.cplx ? 2 : 1)), 256, 0, s>>>(a);
+          MINSR_CHECK_LAUNCH();
+          return MINSR_OK;
+        }
+      }
       if constexpr (DIM == 1 && std::is_same<T, float>::value)
         if (parts == 1 && a.C <= SEGMAX_WL) return launch_jac_t<T, 64, DIM, 1, true>(a, s);
       if (parts == 1) return launch_jac_t<T, 64, DIM, 1>(a, s);
@@ -609,6 +694,8 @@ static int jac_t(minsr_model* m, const Work<T>& w, int Ns, const uint8_t* sigma,
   a.zero_mag = m->d.zero_mag; a.cplx = m->cplx; a.nbr = m->nbr;
   a.sigma = sigma; a.states = (const T*)states; a.O = (T*)O;
   a.gates = (m->dim == 1 && C == 1) ? (const T*)gates : nullptr;
+  // deferred weight gradients with the tape (FP32, 1D, d_h 32 or 64)
+  a.dp = (a.gates && m->jdp && (m->H == 32 || m->H == 64)) ? (T*)m->jdp : nullptr;
   a.scale = (T)(1.0 / std::sqrt((double)Ns));
   a.W2 = 2 * m->d.Lx;
   if (m->dim == 1) return jac_dispatch<T, 1>(m->H, m->tune_jac_parts, a, s);

@@ -615,6 +615,7 @@ struct CholArgs {
   uint32_t* sync;       // [2][nblk + 1]: tickets, then flags
   uint32_t* status;
   double lambda;
+  const double* lam_dev;  // if set, the shift actually used (FP64 one-launch kernel)
   int n, nblk;
 };
 
@@ -981,6 +982,7 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
   const int i = j + rem;
   const int r0 = i * CB, c0 = j * CB;
   const bool diag = i == j;
+  const double lam = a.lam_dev ? *a.lam_dev : a.lambda;
   // relaxed polls (an acquiring load would invalidate this CU's caches at
   // every poll, slowing the many waiting tiles' neighbours), one acquire
   // fence once the flag is seen
@@ -1006,7 +1008,7 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
     for (int v = 0; v < 4; ++v) {
       const int r = r0 + 16 * w + mrow(lane, v), col = c0 + 16 * c + (lane & 15);
       double val = T0[(size_t)min(r, n - 1) * n + min(col, n - 1)];
-      if (r == col) val += a.lambda;
+      if (r == col) val += lam;
       t[c][v] = (r < n && col < n && (!diag || col <= r)) ? val : 0.0;
     }
   // updates A_ij -= L_ik L_jk^T, k < j, in order of k
@@ -1212,19 +1214,42 @@ size_t chol_sync_words(int n) {
 // contributions L_ij y_j of the one-launch factorisation ([nblk][nblk][64])
 size_t chol_vec_elems(int n) {
   const size_t nblk = (size_t)((n + CB - 1) / CB);
-  return nblk * CB + nblk * nblk * CB;
+  return nblk * CB + nblk * nblk * CB + 1;   // + the shift actually used
+}
+
+// lambda_eff = max(lambda, rel * max_i T_ii): the shift never falls below the
+// accuracy to which a low-precision Gram is computed
+__global__ __launch_bounds__(256) void k_lambda_floor(const double* T, int n, double lambda,
+                                                      double rel, double* lam_out) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) mx = fmax(mx, T[(size_t)i * n + i]);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lam_out[0] = fmax(lambda, rel * red[0]);
 }
 
 template <typename TT>
 static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, double lambda,
-                  const double* b, double* x, uint32_t* status, hipStream_t s) {
+                  const double* b, double* x, uint32_t* status, hipStream_t s,
+                  double lam_floor_rel) {
   const int nblk = (n + CB - 1) / CB;
   const int nsync = (int)chol_sync_words(n);
   const int m = std::max(nsync, n);
   k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n);
   MINSR_CHECK_LAUNCH();
-  CholArgs a{T, A, Dinv, yv, sync, status, lambda, n, nblk};
+  CholArgs a{T, A, Dinv, yv, sync, status, lambda, nullptr, n, nblk};
   if constexpr (std::is_same<TT, double>::value) {
+    if (lam_floor_rel > 0.0) {
+      double* lam_slot = yv + chol_vec_elems(n) - 1;
+      k_lambda_floor<<<1, 256, 0, s>>>(T, n, lambda, lam_floor_rel, lam_slot);
+      MINSR_CHECK_LAUNCH();
+      a.lam_dev = lam_slot;
+    }
     k_chol_persist_f64<<<nblk * (nblk + 1) / 2, 256, 0, s>>>(a, sync + chol_sync_one(nblk),
                                                              yv + (size_t)nblk * CB);
     MINSR_CHECK_LAUNCH();
@@ -1243,13 +1268,13 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
 
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, double* yv, uint32_t* sync,
-                          uint32_t* status, hipStream_t s) {
+                          uint32_t* status, hipStream_t s, double lam_floor_rel) {
   if (n == 0) return MINSR_OK;
   if (f32)
     return chol_t<float>(n, reinterpret_cast<const float*>(T), reinterpret_cast<float*>(Lf),
                          reinterpret_cast<float*>(Dinv), reinterpret_cast<float*>(yv), sync,
-                         lambda, b, x, status, s);
-  return chol_t<double>(n, T, Lf, Dinv, yv, sync, lambda, b, x, status, s);
+                         lambda, b, x, status, s, 0.0);
+  return chol_t<double>(n, T, Lf, Dinv, yv, sync, lambda, b, x, status, s, lam_floor_rel);
 }
 
 // ================================================================ update

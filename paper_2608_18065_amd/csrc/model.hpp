@@ -26,6 +26,7 @@ struct minsr_model {
   int max_terms = 0;        // off-diagonal terms per sample (upper bound)
   void* states = nullptr;   // [max_Ns][N][H] hidden states
   void* gates = nullptr;    // [max_Ns][N][4][H] gate tape (FP32 1D models, d_h <= 64)
+  void* jdp = nullptr;      // [seeds][max_Ns][N][3][H] gate adjoints of the Jacobian (same models)
   double* site = nullptr;   // [max_Ns][N][4]: log p(0), log p(1), phi(0), phi(1)
   double* contrib = nullptr;// [max_terms][max_Ns][2]
   int* elist = nullptr;     // [max_terms][max_Ns] samples with a nonzero matrix element
@@ -115,9 +116,11 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
                 int split = 0);
 // factors T + lambda I into Lf (T is left unchanged) and solves for x
 // (yv: chol_vec_elems(n) elements of scratch; sync: chol_sync_words(n) words)
+// lam_floor_rel > 0 (FP64 solve of a low-precision Gram): the shift used is
+// max(lambda, lam_floor_rel * max_i T_ii)
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, double* yv, uint32_t* sync,
-                          uint32_t* status, hipStream_t s);
+                          uint32_t* status, hipStream_t s, double lam_floor_rel = 0.0);
 size_t chol_dinv_elems(int n);
 size_t chol_sync_words(int n);
 size_t chol_vec_elems(int n);

@@ -173,14 +173,21 @@ def test_checkpointed_jacobian_bitwise(arch, C):
 def test_checkpointed_jacobian_bitwise_fp32(arch, C):
     # FP32 1D: stride 1 reads the sampler's gate tape, stride 3 recomputes the
     # segments with the weights staged in shared memory, stride 10 streams
-    # them from memory; every path gives the same rows bit for bit
+    # them from memory.  The recurrences are bitwise the same on every path;
+    # for d_h 32 and 64 the stride-1 path forms the W_u, W_r, W_h blocks as
+    # products over the sites on the matrix cores (another summation order),
+    # so those rows agree to FP32 accumulation accuracy and all others
+    # bit for bit
     spec, m = make_pair(**arch, dtype="f32")
     th = scaled_theta(spec, 11, 1.5)
     m.set_params(to_dev(th))
     sig, _ = m.sample(19, key=3, counter=4)
     O1, _ = m.jacobian(sig, ckpt_every=1)
     Oc, _ = m.jacobian(sig, ckpt_every=C)
-    assert torch.equal(O1, Oc)
+    if arch["H"] in (32, 64):
+        assert rel_err(O1.cpu().numpy(), Oc.cpu().numpy()) < 1e-5
+    else:
+        assert torch.equal(O1, Oc)
 
 
 def test_jacobian_centered_colmean():
