@@ -71,11 +71,57 @@ template <int H> struct JReduce {
   }
 };
 
+typedef __attribute__((ext_vector_type(16))) float f32x16_j;
+
+// W_u, W_r, W_h blocks of one row (deferred gradients): for gate q,
+// dW_q[j][c] = sum over sites k of dp_q[k][j] h_{k-1}[c] (h_{-1} = 0), a
+// [H x N] x [N x H] product on v_mfma_f32_32x32x2_f32 (lane l supplies
+// A[l % 32][l / 32] and B[l / 32][l % 32]; element e of lane l is row
+// 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32).  Wave w of nw takes every
+// nw-th of the 3 (H / 32)^2 output blocks.
+template <int H>
+__device__ void wgrad_row(const JacArgs<float>& a, int row, int s, int lane, int w, int nw) {
+  constexpr int NB = H / 32, NBLK = 3 * NB * NB, ds = 2;
+  const int N = a.N;
+  const float* dp = a.dp + (size_t)row * N * 3 * H;
+  const float* st = a.states + (size_t)s * N * H;
+  float* o = a.O + (size_t)row * a.L.Np;
+  const int kl = lane >> 5, cl = lane & 31;
+  for (int b = w; b < NBLK; b += nw) {
+    const int q = b / (NB * NB), jb = (b / NB) % NB, cb = b % NB;
+    f32x16_j acc;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+    // sites in groups of 16: the group's operand loads (clamped addresses,
+    // masked values) are issued before its eight products
+    for (int k16 = 0; k16 < N; k16 += 16) {
+      float av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k16 + 2 * u + kl;
+        const float x = dp[((size_t)min(k, N - 1) * 3 + q) * H + jb * 32 + cl];
+        const float y = st[(size_t)max(min(k, N) - 1, 0) * H + cb * 32 + cl];
+        av[u] = k < N ? x : 0.f;
+        bv[u] = (k >= 1 && k < N) ? y : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+    }
+    const size_t off = q == 0 ? a.L.Wu : q == 1 ? a.L.Wr : a.L.Wh;
+    const int ldq = q < 2 ? H + ds : H;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int jr = jb * 32 + 8 * (e / 4) + 4 * kl + e % 4;
+      o[off + (size_t)jr * ldq + cb * 32 + cl] = acc[e] * a.scale;
+    }
+  }
+}
+
 // GD (deferred gradients; FP32 1D with the gate tape): the W_u, W_r, W_h
 // blocks of the row are not accumulated here; the reverse pass stores the
-// gate adjoints of every site and k_jac_wgrad forms those blocks as
-// products over the sites on the matrix cores.  The reverse weights of the
-// thread's unit then stay in registers.
+// gate adjoints of every site and k_jac_wgrad (wgrad_row) then forms those
+// blocks as products over the sites on the matrix cores.  The reverse
+// weights of the thread's unit stay in registers.
 template <typename T, int H, int DIM, int P, bool WL = false, bool GD = false>
 __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> a) {
   using VT = typename VecJ<T>::type;
@@ -561,8 +607,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
         MINSR_JAC_STAGE(gWr, gxr, ds, L.Wr, H + ds)
         MINSR_JAC_STAGE(gWh, gxu, 0, L.Wh, H)
       } else if (act && p == 0) {
-        // the one-hot input columns of W_u, W_r (the H x H blocks come from
-        // k_jac_wgrad)
+        // the one-hot input columns of W_u, W_r (the H x H blocks follow)
 #pragma unroll
         for (int c = 0; c < ds; ++c) {
           o[L.Wu + (size_t)j * (H + ds) + H + c] = gxu[c] * sc;
@@ -595,6 +640,23 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
   }
 }
 
+// the W_u, W_r, W_h blocks of every row after the reverse pass: one
+// workgroup of four waves per row, many rows in flight (their operand loads
+// are latency-bound, so the pass's own tail would serialise them)
+template <int H>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_jac_wgrad(JacArgs<float> a) {
+  wgrad_row<H>(a, blockIdx.x, blockIdx.x % a.Ns, threadIdx.x & 63, threadIdx.x >> 6, 4);
+}
+
+template <int H>
+static int launch_wgrad(const JacArgs<float>& a, hipStream_t s) {
+  const unsigned rows = (unsigned)(a.Ns * (a.cplx ? 2 : 1));
+  k_jac_wgrad<H><<<rows, 256, 0, s>>>(a);
+  MINSR_CHECK_LAUNCH();
+  return MINSR_OK;
+}
+
 template <typename T, int H, int DIM, int P, bool WL = false, bool GD = false>
 static int launch_jac_t(const JacArgs<T>& a, hipStream_t s) {
   constexpr int NT = JShape<H, P, WL>::NT, SG = JShape<H, P, WL>::SG;
@@ -602,45 +664,6 @@ static int launch_jac_t(const JacArgs<T>& a, hipStream_t s) {
   k_jacobian<T, H, DIM, P, WL, GD><<<grid, NT, 0, s>>>(a);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
-}
-
-typedef __attribute__((ext_vector_type(16))) float f32x16_j;
-
-// W_u, W_r, W_h blocks of one row (deferred gradients): for gate q,
-// dW_q[j][c] = sum over sites k of dp_q[k][j] h_{k-1}[c] (h_{-1} = 0), a
-// [H x N] x [N x H] product on v_mfma_f32_32x32x2_f32 (lane l supplies
-// A[l % 32][l / 32] and B[l / 32][l % 32]; element e of lane l is row
-// 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32).  One workgroup per row,
-// each wave a share of the 3 (H / 32)^2 output blocks.
-template <int H>
-__global__ __launch_bounds__(256) void k_jac_wgrad(JacArgs<float> a) {
-  constexpr int NB = H / 32, NBLK = 3 * NB * NB, ds = 2;
-  const int row = blockIdx.x, s = row % a.Ns;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int N = a.N;
-  const float* dp = a.dp + (size_t)row * N * 3 * H;
-  const float* st = a.states + (size_t)s * N * H;
-  float* o = a.O + (size_t)row * a.L.Np;
-  const int kl = lane >> 5, cl = lane & 31;
-  for (int b = w; b < NBLK; b += 4) {
-    const int q = b / (NB * NB), jb = (b / NB) % NB, cb = b % NB;
-    f32x16_j acc;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = 0.f;
-    for (int k2 = 0; k2 < N; k2 += 2) {
-      const int k = k2 + kl;
-      const float av = k < N ? dp[((size_t)k * 3 + q) * H + jb * 32 + cl] : 0.f;
-      const float bv = (k >= 1 && k < N) ? st[(size_t)(k - 1) * H + cb * 32 + cl] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-    }
-    const size_t off = q == 0 ? a.L.Wu : q == 1 ? a.L.Wr : a.L.Wh;
-    const int ldq = q < 2 ? H + ds : H;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int jr = jb * 32 + 8 * (e / 4) + 4 * kl + e % 4;
-      o[off + (size_t)jr * ldq + cb * 32 + cl] = acc[e] * a.scale;
-    }
-  }
 }
 
 // parts: threads per hidden unit (0 = built-in choice)
@@ -653,10 +676,7 @@ static int jac_dispatch(int H, int parts, const JacArgs<T>& a, hipStream_t s) {
       if constexpr (DIM == 1 && std::is_same<T, float>::value) {
         if (a.dp) {
           const int rc = launch_jac_t<T, 32, DIM, 1, false, true>(a, s);
-          if (rc) return rc;
-          k_jac_wgrad<32><<<(unsigned)(a.Ns * (a.cplx ? 2 : 1)), 256, 0, s>>>(a);
-          MINSR_CHECK_LAUNCH();
-          return MINSR_OK;
+          return rc ? rc : launch_wgrad<32>(a, s);
         }
         if (a.C <= SEGMAX_WL) return launch_jac_t<T, 32, DIM, 1, true>(a, s);
       }
@@ -666,10 +686,7 @@ static int jac_dispatch(int H, int parts, const JacArgs<T>& a, hipStream_t s) {
       if constexpr (DIM == 1 && std::is_same<T, float>::value) {
         if (a.dp && parts == 1) {
           const int rc = launch_jac_t<T, 64, DIM, 1, false, true>(a, s);
-          if (rc) return rc;
-          k_jac_wgrad<64><<<(unsigned)(a.Ns * (a.cplx ? 2 : 1)), 256, 0, s>>>(a);
-          MINSR_CHECK_LAUNCH();
-          return MINSR_OK;
+          return rc ? rc : launch_wgrad<64>(a, s);
         }
       }
       if constexpr (DIM == 1 && std::is_same<T, float>::value)
