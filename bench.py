@@ -44,10 +44,8 @@ PEAK_FP32_MFMA_TFLOPS = 157.3    # dense FP32 matrix cores (equal to the FP32 ve
 TRAFFIC_BYTES = {
     # k_eloc_mfma: 9403.5 KiB fetched x 2.000 + 1024.0 KiB written x 1.000
     "eloc": 9403.5 * 1024 * 2.0 + 1024.0 * 1024,
-    # k_jacobian (gate-tape path): 41522.7 KiB fetched x 2.000 + 52414.0 KiB written x 1.000
-    "jacobian": 41522.7 * 1024 * 2.0 + 52414.0 * 1024,
-    # k_gram_bf16 (split form, four products, 7-way split-K): 187087.0 KiB x 2.000 + 16128.0 KiB x 1.000
-    "gram": 187087.0 * 1024 * 2.0 + 16128.0 * 1024}
+    "jacobian": None,
+    "gram": None}
 
 
 def parse():

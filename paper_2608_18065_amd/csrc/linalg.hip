@@ -153,14 +153,16 @@ typedef __attribute__((ext_vector_type(16))) float f32x16_t;
 // a positive semidefinite matrix of that size, which made T + lambda I
 // indefinite for lambda = 1e-3 once |T| grew to a few hundred.)
 // The FP32 accumulators are added into FP64 ones every GFLUSH stages and
-// restarted, so no FP32 sum runs over more than 128 (split) or 256 inputs.
+// restarted, so no FP32 sum runs over more than 128 (split) or 256 inputs;
+// the partial tiles are written in FP64 (rounding them to FP32 put an error
+// of about 2^-24 |T| on every element, whose 2-norm reached 6e-7 |T|_max).
 constexpr int GT = 128;
 constexpr int GFLUSH = 4;
 
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
                                                    const __hip_bfloat16* Rlo, int n, size_t ld,
-                                                   size_t kchunk, float* part) {
+                                                   size_t kchunk, double* part) {
   constexpr int GK = SPLIT ? 32 : 64, GKP = GK + 8;
   constexpr int NOP = SPLIT ? 2 : 1;
   __shared__ __align__(16) __hip_bfloat16 As[2][NOP][GT][GKP];
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
   flush();
   // write the partial tile: acc element e of lane l is row
   // (e / 4) * 8 + (l / 32) * 4 + e % 4, column l % 32 of its 32 x 32 block
-  float* out = part + ((size_t)split * gridDim.x + blockIdx.x) * GT * GT;
+  double* out = part + ((size_t)split * gridDim.x + blockIdx.x) * GT * GT;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
       for (int e = 0; e < 16; ++e) {
         const int r = wm + a * 32 + (e / 4) * 8 + (lane >> 5) * 4 + (e % 4);
         const int c = wn + b * 32 + (lane & 31);
-        out[r * GT + c] = (float)accd[a][b][e];
+        out[r * GT + c] = accd[a][b][e];
       }
 }
 
@@ -379,7 +381,7 @@ size_t gram_partial_bytes(int n, size_t Np, int dtype) {
   const int nt = (n + tile - 1) / tile;
   const int npairs = nt * (nt + 1) / 2;
   const int S = std::max(pick_split(npairs, Np, 0), pick_split(npairs, Np, MAX_SPLIT));
-  const size_t el = dtype == MINSR_F64 ? 8 : 4;
+  const size_t el = dtype == MINSR_F32 ? 4 : 8;
   return (size_t)S * npairs * tile * tile * el;
 }
 
@@ -415,21 +417,22 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
   const size_t kgran = dtype == MINSR_BF16 ? 64 : VK;
   size_t kchunk = (ld + S - 1) / S;
   kchunk = (kchunk + kgran - 1) / kgran * kgran;
-  const size_t need = (size_t)S * npairs * tile * tile * (dtype == MINSR_F64 ? 8 : 4);
+  const size_t need = (size_t)S * npairs * tile * tile * (dtype == MINSR_F32 ? 4 : 8);
   if (need > gpart_elems * sizeof(float)) return fail(MINSR_E_SHAPE, "Gram workspace too small");
   dim3 grid((unsigned)npairs, (unsigned)S);
   dim3 rgrid((unsigned)((tile / 32) * (tile / 32)), (unsigned)npairs);
   if (dtype == MINSR_BF16) {
+    double* dp = reinterpret_cast<double*>(gpart);
     if (which & 1) {
       if (Rlo)
         k_gram_bf16<true><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R,
-                                               (const __hip_bfloat16*)Rlo, n, ld, kchunk, gpart);
+                                               (const __hip_bfloat16*)Rlo, n, ld, kchunk, dp);
       else
         k_gram_bf16<false><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, nullptr, n, ld, kchunk,
-                                                gpart);
+                                                dp);
       MINSR_CHECK_LAUNCH();
     }
-    if (which & 2) k_gram_reduce<float, double><<<rgrid, 256, 0, s>>>(gpart, npairs, S, tile, n, T);
+    if (which & 2) k_gram_reduce<double, double><<<rgrid, 256, 0, s>>>(dp, npairs, S, tile, n, T);
   } else if (dtype == MINSR_F32) {
     if (which & 1) {
       k_gram_vec<float, float><<<grid, 256, 0, s>>>((const float*)R, n, ld, kchunk, gpart);
@@ -827,9 +830,10 @@ __device__ __forceinline__ f64x4_t mm_nt(f64x4_t acc, const double (*X)[LDT], in
 
 // Factor the 64 x 64 tile S (lower triangle; rows >= nb are made identity
 // rows) in place and write inv(L) into Z, with four wavefronts.  Panels of
-// 16 columns are factored by wave 0 alone (row `lane` in registers, the
-// pivot column reaching the other lanes through readlane and the scratch
-// column lb); after each panel the four waves subtract its
+// 16 columns are factored by wave 0 alone, two columns at a time (row
+// `lane` in registers, the pair's columns reaching the other lanes through
+// readlane and the scratch columns lb[2][64]); after each panel the four
+// waves subtract its
 // rank-16 product from the 16 x 16 blocks of the trailing lower triangle on
 // the MFMA.  The inverse is blockwise: wave w inverts diagonal block w by
 // forward substitution (lane j: column j), then level by level
@@ -854,23 +858,41 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
       double f[PB];
 #pragma unroll
       for (int cc = 0; cc < PB; ++cc) f[cc] = S[lane][p0 + cc];
+      // columns in pairs: with d0 = A_cc, a10 = A_c+1,c, d1 = A_c+1,c+1 and
+      // det = d0 d1 - a10^2, 1/L_cc = rsqrt(d0) and 1/L_c+1,c+1 =
+      // sqrt(d0) rsqrt(det) come from two independent chains; rows above the
+      // pair are left as they are (upper triangle, cleared below)
 #pragma unroll
-      for (int cc = 0; cc < PB; ++cc) {
+      for (int cc = 0; cc < PB; cc += 2) {
         const int c = p0 + cc;
-        double d = lane_bcast(f[cc], c);
-        if (!(d > 0.0)) { bad = true; d = 1.0; }
-        const double rp = rsqrt_nr(d);
-        const double lc = (lane == c) ? d * rp : f[cc] * rp;
-        f[cc] = lc;
-        if (lane == c) rinv[c] = rp;
-        // the next pivot column by readlane (short dependency chain), the
-        // others with the column broadcast through shared memory
-        if (cc + 1 < PB) {
-          const double nl = lane > c ? -lc : 0.0;
-          lb[lane] = lc;
-          f[cc + 1] = fma(nl, lane_bcast(lc, c + 1), f[cc + 1]);
+        double d0 = lane_bcast(f[cc], c);
+        const double a10 = lane_bcast(f[cc], c + 1);
+        const double d1 = lane_bcast(f[cc + 1], c + 1);
+        double det = fma(-a10, a10, d0 * d1);
+        if (!(d0 > 0.0)) { bad = true; d0 = 1.0; det = 1.0; }
+        if (!(det > 0.0)) { bad = true; det = 1.0; }
+        const double inv0 = rsqrt_nr(d0);
+        const double invdet = rsqrt_nr(det);
+        const double inv1 = (d0 * inv0) * invdet;
+        const double l10 = a10 * inv0;
+        const double lc0 = f[cc] * inv0;                       // lane c: sqrt(d0)
+        const double lc1 = fma(-lc0, l10, f[cc + 1]) * inv1;   // lane c + 1: sqrt(det / d0)
+        f[cc] = lc0;
+        f[cc + 1] = lc1;
+        if (lane == c) rinv[c] = inv0;
+        if (lane == c + 1) rinv[c + 1] = inv1;
+        // rank-2 update: the next pair's columns by readlane (short chain),
+        // the others with the two columns broadcast through shared memory
+        if (cc + 2 < PB) {
+          lb[lane] = lc0;
+          lb[CB + lane] = lc1;
+          const double b0 = lane_bcast(lc0, c + 2), b1 = lane_bcast(lc1, c + 2);
+          const double e0 = lane_bcast(lc0, c + 3), e1 = lane_bcast(lc1, c + 3);
+          f[cc + 2] = fma(-lc1, b1, fma(-lc0, b0, f[cc + 2]));
+          f[cc + 3] = fma(-lc1, e1, fma(-lc0, e0, f[cc + 3]));
 #pragma unroll
-          for (int kk = cc + 2; kk < PB; ++kk) f[kk] = fma(nl, lb[p0 + kk], f[kk]);
+          for (int kk = cc + 4; kk < PB; ++kk)
+            f[kk] = fma(-lc1, lb[CB + p0 + kk], fma(-lc0, lb[p0 + kk], f[kk]));
         }
       }
 #pragma unroll
@@ -965,7 +987,7 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
   __shared__ double Y[CB][LDT];
   __shared__ double Tm[4][16][17];
   __shared__ double rinv[CB];
-  __shared__ double lb[CB];
+  __shared__ double lb[2 * CB];
   __shared__ double yb[CB];
   __shared__ int tk;
   const int n = a.n, nblk = a.nblk, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
