@@ -969,18 +969,22 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
   }
 }
 
-// FP64, the whole factorisation in one launch: one workgroup per lower tile
-// (i, j), keeping the tile in registers from its first read of T + lambda I
-// to its final value.  Roles come from a ticket in column-major order of the
-// tiles, (0,0), (1,0), ..., (1,1), (2,1), ..., so a workgroup only waits for
-// tiles of earlier columns or for the diagonal tile of its own column, all of
-// which took earlier tickets: every wait ends whether or not the whole grid
-// is resident.  A tile applies the updates of columns k < j as their panel
-// tiles are published (flag per tile); the diagonal tile then factors,
-// inverts and solves its block of L y = b from the contributions L_jk y_k
-// that the panel tiles left in per-tile slots (summed in the order of k);
-// a panel tile waits for its diagonal tile, forms L_ij = A_ij inv(L_jj)^T,
-// stores it with its contribution L_ij y_j, and publishes.
+// FP64, the whole factorisation in one launch, tiles held in registers from
+// their first read of T + lambda I to their final value.  Roles come from a
+// ticket: ticket 0 factors block 0; then, block column k by block column k,
+// one workgroup takes the pair of tiles (k+1, k) and (k+1, k+1), and one
+// workgroup each panel tile (i, k), i >= k + 2.  A workgroup only waits for
+// tiles of earlier columns or for the diagonal block of its own column, all
+// of which took earlier tickets, so every wait ends whether or not the whole
+// grid is resident.  Tiles apply the updates A -= L_ik L_jk^T of earlier
+// columns as their panel tiles are published (flag per tile); a panel tile
+// then waits for its diagonal block, forms L_ij = A_ij inv(L_jj)^T, stores
+// it with its contribution L_ij y_j to the forward substitution, and
+// publishes.  The pair workgroup of block j applies its own L_j,j-1 to the
+// diagonal tile from shared memory, so the step from one diagonal block to
+// the next crosses workgroups once; it then factors, inverts and solves its
+// block of L y = b from the contributions of the tiles of row j (summed in
+// the order of k) and publishes the block.
 __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* ctl,
                                                           double* cpart) {
   __shared__ double X[CB][LDT];
@@ -989,21 +993,29 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
   __shared__ double rinv[CB];
   __shared__ double lb[2 * CB];
   __shared__ double yb[CB];
+  __shared__ double cown[CB];
   __shared__ int tk;
   const int n = a.n, nblk = a.nblk, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   double* A = reinterpret_cast<double*>(a.A);
   const double* T0 = reinterpret_cast<const double*>(a.T);
   double* y = reinterpret_cast<double*>(a.y);
-  uint32_t* dflag = ctl + 1;              // [nblk]: diagonal tile j published
+  uint32_t* dflag = ctl + 1;              // [nblk]: diagonal block j published
   uint32_t* pflag = ctl + 1 + nblk;       // [nblk][nblk]: panel tile (i, j) published
   if (tid == 0)
     tk = (int)__hip_atomic_fetch_add(&ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  int j = 0, rem = tk;
-  while (rem >= nblk - j) { rem -= nblk - j; ++j; }
-  const int i = j + rem;
-  const int r0 = i * CB, c0 = j * CB;
-  const bool diag = i == j;
+  // the panel tile (pi, pj), if any, and the diagonal block jd, if any
+  bool has_panel = false, has_diag = true;
+  int pi = 0, pj = 0, jd = 0;
+  if (tk > 0) {
+    int k = 0, rem = tk - 1;
+    while (rem >= nblk - k - 1) { rem -= nblk - k - 1; ++k; }
+    has_panel = true;
+    pj = k;
+    pi = k + 1 + rem;
+    has_diag = rem == 0;
+    jd = k + 1;
+  }
   const double lam = a.lam_dev ? *a.lam_dev : a.lambda;
   // relaxed polls (an acquiring load would invalidate this CU's caches at
   // every poll, slowing the many waiting tiles' neighbours), one acquire
@@ -1021,114 +1033,144 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
     __syncthreads();
     if (tid == 0) __hip_atomic_store(f, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   };
+  // tile (r0, c0) of T + lambda I in the MFMA result layout (wave w: rows
+  // 16w.., four 16 x 16 blocks), the diagonal tile lower triangle only
+  auto load_tile = [&](f64x4_t (&t)[4], int r0, int c0, bool diag) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * w + mrow(lane, v), col = c0 + 16 * c + (lane & 15);
+        double val = T0[(size_t)min(r, n - 1) * n + min(col, n - 1)];
+        if (r == col) val += lam;
+        t[c][v] = (r < n && col < n && (!diag || col <= r)) ? val : 0.0;
+      }
+  };
+  auto tile_to_lds = [&](const f64x4_t (&t)[4], double (*M)[LDT]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) M[16 * w + mrow(lane, v)][16 * c + (lane & 15)] = t[c][v];
+  };
 
-  // T + lambda I in the MFMA result layout (wave w: rows 16w.., four blocks)
-  f64x4_t t[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = r0 + 16 * w + mrow(lane, v), col = c0 + 16 * c + (lane & 15);
-      double val = T0[(size_t)min(r, n - 1) * n + min(col, n - 1)];
-      if (r == col) val += lam;
-      t[c][v] = (r < n && col < n && (!diag || col <= r)) ? val : 0.0;
-    }
-  // updates A_ij -= L_ik L_jk^T, k < j, in order of k
-  for (int k = 0; k < j; ++k) {
-    wait_flag(&pflag[i * nblk + k]);
-    if (!diag) wait_flag(&pflag[j * nblk + k]);
-    const int k0 = k * CB;
+  f64x4_t tp[4], td[4];
+  if (has_panel) load_tile(tp, pi * CB, pj * CB, false);
+  if (has_diag) load_tile(td, jd * CB, jd * CB, true);
+  // updates of columns k < pj, in order of k; the pair workgroup's diagonal
+  // tile takes L_jd,k L_jd,k^T from the same rows
+  const int nk = has_panel ? pj : 0;
+  for (int k = 0; k < nk; ++k) {
+    wait_flag(&pflag[pi * nblk + k]);
+    wait_flag(&pflag[pj * nblk + k]);
+    const int k0 = k * CB, ri = pi * CB, rj = pj * CB;
     {
       double vi[CB * CB / 256], vj[CB * CB / 256];
 #pragma unroll
       for (int q = 0; q < CB * CB / 256; ++q) {
         const int e = tid + 256 * q, r = e / CB, cc = e % CB;
-        const double xi = A[(size_t)min(r0 + r, n - 1) * n + k0 + cc];
-        vi[q] = (r0 + r < n) ? xi : 0.0;
-        if (!diag) {
-          const double xj = A[(size_t)min(c0 + r, n - 1) * n + k0 + cc];
-          vj[q] = (c0 + r < n) ? xj : 0.0;
-        }
+        const double xi = A[(size_t)min(ri + r, n - 1) * n + k0 + cc];
+        vi[q] = (ri + r < n) ? xi : 0.0;
+        vj[q] = A[(size_t)(rj + r) * n + k0 + cc];   // pj < pi: a full block
       }
 #pragma unroll
       for (int q = 0; q < CB * CB / 256; ++q) {
         const int e = tid + 256 * q, r = e / CB, cc = e % CB;
         X[r][cc] = vi[q];
-        if (!diag) Y[r][cc] = vj[q];
+        Y[r][cc] = vj[q];
       }
     }
     __syncthreads();
-    const double (*Yo)[LDT] = diag ? X : Y;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) t[c] = mm_nt<CB, true>(t[c], X, 16 * w, Yo, 16 * c, 0, lane);
+    for (int c = 0; c < 4; ++c) tp[c] = mm_nt<CB, true>(tp[c], X, 16 * w, Y, 16 * c, 0, lane);
+    if (has_diag) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) td[c] = mm_nt<CB, true>(td[c], X, 16 * w, X, 16 * c, 0, lane);
+    }
     __syncthreads();   // X, Y are rewritten next
   }
 
-  const int kb0 = j * CB, nb = min(CB, n - kb0);
-  double* Di = reinterpret_cast<double*>(a.Dinv) + (size_t)j * CB * CB;
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) X[16 * w + mrow(lane, v)][16 * c + (lane & 15)] = t[c][v];
-  if (diag) {
-    // b_j - sum_k L_jk y_k (the contributions are published with their tiles)
-    if (tid < CB) {
-      double r = tid < nb ? y[kb0 + tid] : 0.0;
-      for (int k = 0; k < j; ++k) r -= cpart[((size_t)j * nblk + k) * CB + tid];
-      yb[tid] = tid < nb ? r : 0.0;
-    }
-    __syncthreads();
-    factor_block_f64(X, Y, Tm, rinv, lb, nb, A, n, kb0, Di, a.status);
-    __syncthreads();
+  if (has_panel) {
+    // L = A_pi,pj inv(L_pj,pj)^T and its contribution L y_pj
+    const int kb0 = pj * CB;   // pj < pi <= nblk - 1: a full block
+    wait_flag(&dflag[pj]);
+    tile_to_lds(tp, X);
     {
-      const int row = tid / 4, part = tid % 4;
-      double s = 0.0;
-      if (row < nb)
-        for (int q = part; q <= row; q += 4) s = fma(Y[row][q], yb[q], s);
-      s += __shfl_xor(s, 1, 4);
-      s += __shfl_xor(s, 2, 4);
-      if (part == 0 && row < nb) y[kb0 + row] = s;
+      const double* Di = reinterpret_cast<const double*>(a.Dinv) + (size_t)pj * CB * CB;
+      double dv[CB * CB / 256];
+#pragma unroll
+      for (int q = 0; q < CB * CB / 256; ++q) dv[q] = Di[tid + 256 * q];
+#pragma unroll
+      for (int q = 0; q < CB * CB / 256; ++q) Y[(tid + 256 * q) / CB][(tid + 256 * q) % CB] = dv[q];
     }
-    if (j + 1 < nblk) publish(&dflag[j]);
-    return;
-  }
-
-  // panel tile: L_ij = A_ij inv(L_jj)^T and its contribution L_ij y_j
-  wait_flag(&dflag[j]);
-  {
-    double dv[CB * CB / 256];
+    if (tid < CB) yb[tid] = y[kb0 + tid];
+    __syncthreads();
+    const int r0 = pi * CB;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    f64x4_t l[4];
 #pragma unroll
-    for (int q = 0; q < CB * CB / 256; ++q) dv[q] = Di[tid + 256 * q];
+    for (int c = 0; c < 4; ++c) {
+      l[c] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      l[c] = mm_nt<CB, false>(l[c], X, 16 * w, Y, 16 * c, 0, lane);
+      const int col = 16 * c + (lane & 15);
 #pragma unroll
-    for (int q = 0; q < CB * CB / 256; ++q) Y[(tid + 256 * q) / CB][(tid + 256 * q) % CB] = dv[q];
-  }
-  if (tid < CB) yb[tid] = y[kb0 + tid < n ? kb0 + tid : 0];
-  __syncthreads();
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    f64x4_t l = {0.0, 0.0, 0.0, 0.0};
-    l = mm_nt<CB, false>(l, X, 16 * w, Y, 16 * c, 0, lane);
-    const int col = 16 * c + (lane & 15);
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * w + mrow(lane, v);
+        if (r < n) A[(size_t)r * n + kb0 + col] = l[c][v];
+        s[v] = fma(r < n ? l[c][v] : 0.0, yb[col], s[v]);
+      }
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = r0 + 16 * w + mrow(lane, v);
-      const bool ok = r < n && col < nb;
-      if (ok) A[(size_t)r * n + kb0 + col] = l[v];
-      s[v] = fma(ok ? l[v] : 0.0, yb[col], s[v]);
+#pragma unroll
+      for (int m = 1; m < 16; m <<= 1) s[v] += __shfl_xor(s[v], m, 16);
     }
-  }
+    if (!has_diag) {
+      if ((lane & 15) == 0) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < 4; ++v)
+          cpart[((size_t)pi * nblk + pj) * CB + 16 * w + mrow(lane, v)] = s[v];
+      }
+      publish(&pflag[pi * nblk + pj]);
+      return;
+    }
+    // the pair workgroup: keep the contribution, subtract L L^T from the
+    // diagonal tile (rows beyond n of L are zero), then publish L
+    if ((lane & 15) == 0) {
 #pragma unroll
-    for (int m = 1; m < 16; m <<= 1) s[v] += __shfl_xor(s[v], m, 16);
-  }
-  if ((lane & 15) == 0) {
+      for (int v = 0; v < 4; ++v) cown[16 * w + mrow(lane, v)] = s[v];
+    }
+    __syncthreads();   // X, Y, yb are no longer read
+    tile_to_lds(l, X);
+    __syncthreads();
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      cpart[((size_t)i * nblk + j) * CB + 16 * w + mrow(lane, v)] = s[v];
+    for (int c = 0; c < 4; ++c) td[c] = mm_nt<CB, true>(td[c], X, 16 * w, X, 16 * c, 0, lane);
+    publish(&pflag[pi * nblk + pj]);
   }
-  publish(&pflag[i * nblk + j]);
+
+  // the diagonal block jd: factor, invert, and solve its block of L y = b
+  const int kb0 = jd * CB, nb = min(CB, n - kb0);
+  double* Di = reinterpret_cast<double*>(a.Dinv) + (size_t)jd * CB * CB;
+  __syncthreads();   // X is rewritten
+  tile_to_lds(td, X);
+  if (tid < CB) {
+    double r = tid < nb ? y[kb0 + tid] : 0.0;
+    for (int k = 0; k + 1 < jd; ++k) r -= cpart[((size_t)jd * nblk + k) * CB + tid];
+    if (jd > 0) r -= cown[tid];
+    yb[tid] = tid < nb ? r : 0.0;
+  }
+  __syncthreads();
+  factor_block_f64(X, Y, Tm, rinv, lb, nb, A, n, kb0, Di, a.status);
+  __syncthreads();
+  {
+    const int row = tid / 4, part = tid % 4;
+    double s = 0.0;
+    if (row < nb)
+      for (int q = part; q <= row; q += 4) s = fma(Y[row][q], yb[q], s);
+    s += __shfl_xor(s, 1, 4);
+    s += __shfl_xor(s, 2, 4);
+    if (part == 0 && row < nb) y[kb0 + row] = s;
+  }
+  if (jd + 1 < nblk) publish(&dflag[jd]);
 }
 
 // sync words and b -> y (one kernel, safe inside captured graphs)
@@ -1272,7 +1314,7 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
       MINSR_CHECK_LAUNCH();
       a.lam_dev = lam_slot;
     }
-    k_chol_persist_f64<<<nblk * (nblk + 1) / 2, 256, 0, s>>>(a, sync + chol_sync_one(nblk),
+    k_chol_persist_f64<<<1 + nblk * (nblk - 1) / 2, 256, 0, s>>>(a, sync + chol_sync_one(nblk),
                                                              yv + (size_t)nblk * CB);
     MINSR_CHECK_LAUNCH();
   } else {
