@@ -833,15 +833,15 @@ __device__ __forceinline__ f64x4_t mm_nt(f64x4_t acc, const double (*X)[LDT], in
 // 16 columns are factored by wave 0 alone, two columns at a time (row
 // `lane` in registers, the pair's columns reaching the other lanes through
 // readlane and the scratch columns lb[2][64]); after each panel the four
-// waves subtract its
-// rank-16 product from the 16 x 16 blocks of the trailing lower triangle on
-// the MFMA.  The inverse is blockwise: wave w inverts diagonal block w by
-// forward substitution (lane j: column j), then level by level
-// Z_QP = -Z_QQ sum_{P <= R < Q} L_QR Z_RP, one block per wave.  Writes L to
-// A (rows < nb), inv(L) to Di (zero outside the leading nb x nb block).
+// waves subtract its rank-16 product from the 16 x 16 blocks of the
+// trailing lower triangle on the MFMA.  The inverse is blockwise: wave w
+// inverts diagonal block w by forward substitution (lane j: column j), then
+// level by level Z_QP = -Z_QQ sum_{P <= R < Q} L_QR Z_RP, one block per
+// wave.  L stays in S (the caller stores it); inv(L) goes to Z and to Di
+// (zero outside the leading nb x nb block).
 __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm)[16][17],
-                                 double* rinv, double* lb, int nb, double* A, int n, int k0,
-                                 double* Di, uint32_t* status) {
+                                 double* rinv, double* lb, int nb, int k0, double* Di,
+                                 uint32_t* status) {
   constexpr int PB = 16, NB = CB / 16;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   if (nb < CB) {   // the last, partial block only
@@ -918,15 +918,18 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
   }
   if (bad && lane == 0 && status) atomicOr(status, MINSR_ST_NOT_PD);
   // diagonal blocks of the inverse
+  // (lane j: column j by forward substitution, the terms of each row taken
+  // in order of m, column by column so the dependent chain is one fma deep)
   if (lane < 16) {
     const int b0 = 16 * w, j = lane;
     double z[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      double s = (i == j) ? 1.0 : 0.0;
+    for (int i = 0; i < 16; ++i) z[i] = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-      for (int m = 0; m < i; ++m) s = fma(-S[b0 + i][b0 + m], z[m], s);
-      z[i] = s * rinv[b0 + i];
+    for (int m = 0; m < 16; ++m) {
+      z[m] *= rinv[b0 + m];
+#pragma unroll
+      for (int i = m + 1; i < 16; ++i) z[i] = fma(-S[b0 + i][b0 + m], z[m], z[i]);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) Z[b0 + i][b0 + j] = z[i];
@@ -962,10 +965,18 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
     }
     __syncthreads();
   }
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int i = e / CB, j = e % CB;
-    if (j <= i && i < nb) A[(size_t)(k0 + i) * n + k0 + j] = S[i][j];
-    Di[e] = (i < nb && j < nb && i / 16 >= j / 16) ? Z[i][j] : 0.0;
+  {
+    double zv[CB * CB / 256];
+#pragma unroll
+    for (int q = 0; q < CB * CB / 256; ++q) {
+      const int e = tid + 256 * q;
+      zv[q] = Z[e / CB][e % CB];
+    }
+#pragma unroll
+    for (int q = 0; q < CB * CB / 256; ++q) {
+      const int e = tid + 256 * q, i = e / CB, j = e % CB;
+      Di[e] = (i < nb && j < nb && i / 16 >= j / 16) ? zv[q] : 0.0;
+    }
   }
 }
 
@@ -1088,6 +1099,23 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
     }
     __syncthreads();   // X, Y are rewritten next
   }
+  // b_jd less the contributions L_jd,k y_k, k < jd - 1, of the panel tiles of
+  // row jd (published with their flags, seen above), summed in order of k
+  // while the diagonal block jd - 1 is still being factored
+  const int kbd = jd * CB, nb = min(CB, n - kbd);
+  double bpart = 0.0;
+  if (has_diag && tid < CB) {
+    bpart = tid < nb ? y[kbd + tid] : 0.0;
+    const int kmax = jd - 1;
+    for (int k0 = 0; k0 < kmax; k0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = cpart[((size_t)jd * nblk + min(k0 + u, kmax - 1)) * CB + tid];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) bpart -= k0 + u < kmax ? v[u] : 0.0;
+    }
+  }
 
   if (has_panel) {
     // L = A_pi,pj inv(L_pj,pj)^T and its contribution L y_pj
@@ -1106,11 +1134,17 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
     __syncthreads();
     const int r0 = pi * CB;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
+    // inv(L) is block lower triangular: column block c of L takes the first
+    // 16 (c + 1) columns of the tile
     f64x4_t l[4];
 #pragma unroll
+    for (int c = 0; c < 4; ++c) l[c] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    l[0] = mm_nt<16, false>(l[0], X, 16 * w, Y, 0, 0, lane);
+    l[1] = mm_nt<32, false>(l[1], X, 16 * w, Y, 16, 0, lane);
+    l[2] = mm_nt<48, false>(l[2], X, 16 * w, Y, 32, 0, lane);
+    l[3] = mm_nt<64, false>(l[3], X, 16 * w, Y, 48, 0, lane);
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
-      l[c] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-      l[c] = mm_nt<CB, false>(l[c], X, 16 * w, Y, 16 * c, 0, lane);
       const int col = 16 * c + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -1148,29 +1182,41 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
   }
 
   // the diagonal block jd: factor, invert, and solve its block of L y = b
-  const int kb0 = jd * CB, nb = min(CB, n - kb0);
+  const int kb0 = kbd;
   double* Di = reinterpret_cast<double*>(a.Dinv) + (size_t)jd * CB * CB;
   __syncthreads();   // X is rewritten
   tile_to_lds(td, X);
   if (tid < CB) {
-    double r = tid < nb ? y[kb0 + tid] : 0.0;
-    for (int k = 0; k + 1 < jd; ++k) r -= cpart[((size_t)jd * nblk + k) * CB + tid];
-    if (jd > 0) r -= cown[tid];
+    const double r = jd > 0 ? bpart - cown[tid] : bpart;
     yb[tid] = tid < nb ? r : 0.0;
   }
   __syncthreads();
-  factor_block_f64(X, Y, Tm, rinv, lb, nb, A, n, kb0, Di, a.status);
+  factor_block_f64(X, Y, Tm, rinv, lb, nb, kb0, Di, a.status);
   __syncthreads();
   {
+    // y_jd = inv(L) yb: four threads per row, terms q = part, part + 4, ...
+    // up to the diagonal (Y above the diagonal blocks is not cleared)
     const int row = tid / 4, part = tid % 4;
+    double zr[CB / 4], yq[CB / 4];
+#pragma unroll
+    for (int u = 0; u < CB / 4; ++u) {
+      zr[u] = Y[row][part + 4 * u];
+      yq[u] = yb[part + 4 * u];
+    }
     double s = 0.0;
-    if (row < nb)
-      for (int q = part; q <= row; q += 4) s = fma(Y[row][q], yb[q], s);
+#pragma unroll
+    for (int u = 0; u < CB / 4; ++u) s = fma(part + 4 * u <= row ? zr[u] : 0.0, yq[u], s);
     s += __shfl_xor(s, 1, 4);
     s += __shfl_xor(s, 2, 4);
     if (part == 0 && row < nb) y[kb0 + row] = s;
   }
   if (jd + 1 < nblk) publish(&dflag[jd]);
+  // the diagonal block of L, which no tile of this factorisation reads
+#pragma unroll
+  for (int q = 0; q < CB * CB / 256; ++q) {
+    const int e = tid + 256 * q, i = e / CB, j = e % CB;
+    if (j <= i && i < nb) A[(size_t)(kb0 + i) * n + kb0 + j] = X[i][j];
+  }
 }
 
 // sync words and b -> y (one kernel, safe inside captured graphs)
