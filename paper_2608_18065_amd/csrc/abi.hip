@@ -94,7 +94,7 @@ static int ensure_pinv_ws(minsr_model* m, hipStream_t s) {
 static void release(minsr_model* m) {
   void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->gates, m->jdp, m->site,
                   m->contrib,
-                  m->elist, m->ecount, m->eitems,
+                  m->elist, m->ecount, m->eitems, m->eloc_q,
                   m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
                   m->colpart, m->colmean, m->T, m->Lf, m->Dinv, m->gpart, m->epsp, m->x, m->vwork,
                   m->dpart, m->dtheta, m->status, m->eig, m->csync};
@@ -229,6 +229,7 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   rc = rc ? rc : alloc((void**)&m->dpart, ((rows + 63) / 64) * Np * 8);
   rc = rc ? rc : alloc((void**)&m->dtheta, Np * 8);
   rc = rc ? rc : alloc((void**)&m->status, 16);
+  rc = rc ? rc : alloc((void**)&m->eloc_q, 16);
   if (!rc && (d->options & MINSR_OPT_PINV)) rc = ensure_pinv_ws(m, nullptr);
   if (rc) { release(m); delete m; return rc; }
 
@@ -236,6 +237,7 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   if (e == hipSuccess) e = hipMemcpy(m->subA, subA.data(), subA.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !bonds.empty())
     e = hipMemcpy(m->bonds, bonds.data(), bonds.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->eloc_q, 0, 16);
   if (e != hipSuccess) { release(m); delete m; return fail(MINSR_E_DEVICE, hipGetErrorString(e)); }
   bind_work(m);
   rc = launch_init_theta(m, nullptr);

@@ -73,6 +73,143 @@ __device__ inline f32x16_m mfma_f32(float a, float b, f32x16_m c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// One connected configuration being re-evaluated: sample s with the flips of
+// Hamiltonian term t (sites f1 and, for an exchange, f2p > f1), restarted at
+// site k0 = f1 from the stored hidden state of the unflipped prefix.
+struct ElocSeq {
+  int t, chunk, navail, f1, f2p, k0, s, nup, ndn, dA, sprev;
+  bool act;
+  double oldlp, oldph, lp, ph, mel;
+  uint64_t smask;
+  const int* lst;
+  const uint8_t* sg;
+};
+
+// sample of row q of an item (row 0's sample for padding rows)
+__device__ inline int eloc_row_sample(const ElocMArgs& a, const ElocSeq& e, int q) {
+  int i = e.chunk * 32 + q;
+  if (i >= e.navail) i = 0;
+  return e.lst ? e.lst[i] : i;
+}
+
+// item -> (term, chunk of 32 samples), and row `col`'s sequence: its matrix
+// element, the old configuration's log-amplitude from k0 on, the spin
+// counts of the prefix (zero-magnetisation mask), and the log-amplitude of
+// the new configuration up to and including site k0
+__device__ inline ElocSeq eloc_begin(const ElocMArgs& a, int item, int col) {
+  ElocSeq e;
+  const int N = a.N;
+  if (a.list) { e.t = a.items[2 * item]; e.chunk = a.items[2 * item + 1]; }
+  else { e.t = item / a.nchunks; e.chunk = item % a.nchunks; }
+  e.navail = a.list ? a.count[e.t] : a.Ns;
+  e.lst = a.list ? a.list + (size_t)e.t * a.Ns : nullptr;
+  e.f2p = -1;
+  double Jt = 0.0;
+  if (a.ham_kind == MINSR_HAM_J1J2) {
+    e.f1 = a.bonds[2 * e.t]; e.f2p = a.bonds[2 * e.t + 1];
+    Jt = e.t < a.n_nn ? a.J1 : a.J2;
+  } else {
+    e.f1 = e.t;
+  }
+  e.k0 = e.f1;
+  e.act = e.chunk * 32 + col < e.navail;
+  e.s = eloc_row_sample(a, e, col);
+  e.sg = a.sigma + (size_t)e.s * N;
+  const uint8_t* sg = e.sg;
+  const double* st = a.site + (size_t)e.s * N * 4;
+  e.nup = 0; e.ndn = 0; e.dA = 0;
+  e.oldlp = 0.0; e.oldph = 0.0;
+  for (int k = 0; k <= e.k0; ++k) {
+    int v = sg[k];
+    if (k == e.f1) v ^= 1;
+    e.nup += v == 0; e.ndn += v == 1;
+  }
+  for (int k = e.k0; k < N; ++k) {
+    const int v = sg[k];
+    e.oldlp += st[4 * k + v];
+    e.oldph += st[4 * k + 2 + v];
+  }
+  e.smask = 0;
+  if (N <= 64)
+    for (int k = e.k0 + 1; k < N; ++k) e.smask |= (uint64_t)(sg[k] & 1) << k;
+  const int vflip = sg[e.k0] ^ 1;
+  e.lp = st[4 * e.k0 + vflip];
+  e.ph = st[4 * e.k0 + 2 + vflip];
+  e.sprev = vflip;
+  if (a.ham_kind == MINSR_HAM_TFIM) {
+    e.mel = -a.hx;
+  } else if (a.ham_kind == MINSR_HAM_CLUSTER) {
+    const double zl = 1.0 - 2.0 * sg[(e.f1 - 1 + N) % N];
+    const double zr = 1.0 - 2.0 * sg[(e.f1 + 1) % N];
+    e.mel = -zl * zr;
+  } else {
+    e.mel = sg[e.f1] != sg[e.f2p] ? 0.5 * Jt : 0.0;
+  }
+  if (a.marshall) {
+    if (a.subA[e.f1]) e.dA += 1 - 2 * sg[e.f1];
+    if (e.f2p >= 0 && a.subA[e.f2p]) e.dA += 1 - 2 * sg[e.f2p];
+  }
+  return e;
+}
+
+// output head at site k for this lane's sequence, from its new hidden state
+// hrow (units [half H/2, (half + 1) H/2) here, the other half from lane
+// l ^ 32), and the running log-amplitude of the new configuration
+template <int H>
+__device__ inline void eloc_site(const ElocMArgs& a, ElocSeq& e, const float* hrow,
+                                 const float (*hw)[H], const float* hb, int half, int k) {
+  const float PI = 3.14159265358979323846f;
+  const int N = a.N;
+  float z0 = 0.f, z1 = 0.f, q0 = 0.f, q1 = 0.f;
+#pragma unroll 4
+  for (int u4 = 0; u4 < H / 2; u4 += 4) {
+    const int u0 = half * (H / 2) + u4;
+    const float4 h4 = *reinterpret_cast<const float4*>(&hrow[u0]);
+    const float4 w0 = *reinterpret_cast<const float4*>(&hw[0][u0]);
+    const float4 w1 = *reinterpret_cast<const float4*>(&hw[1][u0]);
+    z0 = fmaf(w0.x, h4.x, z0); z0 = fmaf(w0.y, h4.y, z0); z0 = fmaf(w0.z, h4.z, z0); z0 = fmaf(w0.w, h4.w, z0);
+    z1 = fmaf(w1.x, h4.x, z1); z1 = fmaf(w1.y, h4.y, z1); z1 = fmaf(w1.z, h4.z, z1); z1 = fmaf(w1.w, h4.w, z1);
+    if (a.cplx) {
+      const float4 p0 = *reinterpret_cast<const float4*>(&hw[2][u0]);
+      const float4 p1 = *reinterpret_cast<const float4*>(&hw[3][u0]);
+      q0 = fmaf(p0.x, h4.x, q0); q0 = fmaf(p0.y, h4.y, q0); q0 = fmaf(p0.z, h4.z, q0); q0 = fmaf(p0.w, h4.w, q0);
+      q1 = fmaf(p1.x, h4.x, q1); q1 = fmaf(p1.y, h4.y, q1); q1 = fmaf(p1.z, h4.z, q1); q1 = fmaf(p1.w, h4.w, q1);
+    }
+  }
+  z0 += __shfl_xor(z0, 32, 64);
+  z1 += __shfl_xor(z1, 32, 64);
+  q0 += __shfl_xor(q0, 32, 64);
+  q1 += __shfl_xor(q1, 32, 64);
+  const float zz0 = z0 + hb[0], zz1 = z1 + hb[1];
+  const float mx = zz0 > zz1 ? zz0 : zz1;
+  const float d = zz0 > zz1 ? zz1 - zz0 : zz0 - zz1;
+  const float lse = mx + fast_log1p_exp(d);
+  float lp0 = zz0 - lse, lp1 = zz1 - lse;
+  if (a.zero_mag) {
+    if (e.nup >= N / 2) { lp0 = -INFINITY; lp1 = 0.f; }
+    else if (e.ndn >= N / 2) { lp0 = 0.f; lp1 = -INFINITY; }
+  }
+  int v = N <= 64 ? (int)((e.smask >> k) & 1u) : (int)e.sg[k];
+  if (k == e.f2p) v ^= 1;
+  e.lp += (double)(v == 0 ? lp0 : lp1);
+  if (a.cplx) {
+    const float aa = v == 0 ? q0 + hb[2] : q1 + hb[3];
+    e.ph += (double)(PI * aa / (1.f + fabsf(aa)));
+  }
+  e.nup += v == 0; e.ndn += v == 1;
+  e.sprev = v;
+}
+
+// the term's contribution to E_loc of the sample (one lane per sequence)
+__device__ inline void eloc_end(const ElocMArgs& a, const ElocSeq& e) {
+  const double dre = 0.5 * (e.lp - e.oldlp);
+  const double dim_ = (e.ph - e.oldph) + 3.14159265358979323846 * (double)e.dA;
+  const double x = e.mel == 0.0 ? 0.0 : exp(dre);
+  double* o = a.contrib + ((size_t)e.t * a.Ns + e.s) * 2;
+  o[0] = e.mel * x * cos(dim_);
+  o[1] = e.mel * x * sin(dim_);
+}
+
 template <int H, int DIM>
 // d_h <= 64: two waves per SIMD (at most 256 registers each), so one wave's
 // elementwise update overlaps the other's matrix products
@@ -111,72 +248,16 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
   for (int i = tid; i < 4 * H; i += NT) hw[i / H][i % H] = a.head[i];
   if (tid < 4) hb[tid] = a.headb[tid];
   __syncthreads();
-  const float PI = 3.14159265358979323846f;
 
   const int n_items = a.list ? a.count[a.M] : a.n_items;
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
-    int t, chunk;
-    if (a.list) { t = a.items[2 * item]; chunk = a.items[2 * item + 1]; }
-    else { t = item / a.nchunks; chunk = item % a.nchunks; }
-    const int navail = a.list ? a.count[t] : a.Ns;
-    const int* lst = a.list ? a.list + (size_t)t * a.Ns : nullptr;
-    // sample of row q of this item (row 0's sample for padding rows)
-    auto row_sample = [&](int q) {
-      int i = chunk * S + q;
-      if (i >= navail) i = 0;
-      return lst ? lst[i] : i;
-    };
-    int f1, f2p = -1;
-    double Jt = 0.0;
-    if (a.ham_kind == MINSR_HAM_J1J2) {
-      f1 = a.bonds[2 * t]; f2p = a.bonds[2 * t + 1];
-      Jt = t < a.n_nn ? a.J1 : a.J2;
-    } else {
-      f1 = t;
-    }
-    const int k0 = f1;
-    const bool act = chunk * S + col < navail;   // this lane's sequence (both halves)
-    const int s = row_sample(col);
-    const int sid = s;
-    const uint8_t* sg = a.sigma + (size_t)sid * N;
-    const double* st = a.site + (size_t)sid * N * 4;
-    int nup = 0, ndn = 0, dA = 0;
-    double oldlp = 0.0, oldph = 0.0;
-    for (int k = 0; k <= k0; ++k) {
-      int v = sg[k];
-      if (k == f1) v ^= 1;
-      nup += v == 0; ndn += v == 1;
-    }
-    for (int k = k0; k < N; ++k) {
-      const int v = sg[k];
-      oldlp += st[4 * k + v];
-      oldph += st[4 * k + 2 + v];
-    }
-    uint64_t smask = 0;
-    if (N <= 64)
-      for (int k = k0 + 1; k < N; ++k) smask |= (uint64_t)(sg[k] & 1) << k;
-    const int vflip = sg[k0] ^ 1;
-    double lp = st[4 * k0 + vflip];
-    double ph = st[4 * k0 + 2 + vflip];
-    int sprev = vflip;
-    double mel;
-    if (a.ham_kind == MINSR_HAM_TFIM) {
-      mel = -a.hx;
-    } else if (a.ham_kind == MINSR_HAM_CLUSTER) {
-      const double zl = 1.0 - 2.0 * sg[(f1 - 1 + N) % N];
-      const double zr = 1.0 - 2.0 * sg[(f1 + 1) % N];
-      mel = -zl * zr;
-    } else {
-      mel = sg[f1] != sg[f2p] ? 0.5 * Jt : 0.0;
-    }
-    if (a.marshall) {
-      if (a.subA[f1]) dA += 1 - 2 * sg[f1];
-      if (f2p >= 0 && a.subA[f2p]) dA += 1 - 2 * sg[f2p];
-    }
+    ElocSeq e = eloc_begin(a, item, col);
+    const int k0 = e.k0, f1 = e.f1, f2p = e.f2p;
+    const uint8_t* sg = e.sg;
     if (DIM == 1 && k0 + 1 < N) {
       for (int i = tid; i < S * H; i += NT) {
         const int q = i / H, u = i % H;
-        const int sq = row_sample(q);
+        const int sq = eloc_row_sample(a, e, q);
         hA[(k0 + 1) & 1][q][u] = a.states[((size_t)sq * N + k0) * H + u];
       }
     }
@@ -196,7 +277,7 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
           const int u = r < H ? r : r - H;
           float v = 0.f;
           if (pos >= 0) {
-            const int sq = row_sample(q);
+            const int sq = eloc_row_sample(a, e, q);
             if (pos <= k0) v = a.states[((size_t)sq * N + pos) * H + u];
             else v = a.ring[(((size_t)blockIdx.x * S + q) * a.W + pos % a.W) * H + u];
           }
@@ -205,7 +286,7 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
         __syncthreads();
         f32x16_m acc;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+        for (int q = 0; q < 16; ++q) acc[q] = 0.f;
         const float* m2 = a.m2 + (size_t)w * H * 64 + lane;
 #pragma unroll 4
         for (int s4 = 0; s4 < H; s4 += 4) {
@@ -217,7 +298,7 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
         }
         hin = acc;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) hA[cb][(e / 4) * 8 + half * 4 + (e % 4)][unit] = hin[e];
+        for (int q = 0; q < 16; ++q) hA[cb][(q / 4) * 8 + half * 4 + (q % 4)][unit] = hin[q];
         __syncthreads();
       }
       // gate pre-activations of the 32 sequences for this wave's units (1D:
@@ -226,10 +307,10 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
       f32x16_m au, ar, ag, ai;
       if (DIM == 1) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) { au[e] = 0.f; ar[e] = 0.f; ag[e] = bgs; ai[e] = 0.f; }
+        for (int q = 0; q < 16; ++q) { au[q] = 0.f; ar[q] = 0.f; ag[q] = bgs; ai[q] = 0.f; }
       } else {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) { au[e] = bu; ar[e] = br; ag[e] = bh; ai[e] = bi; }
+        for (int q = 0; q < 16; ++q) { au[q] = bu; ar[q] = br; ag[q] = bh; ai[q] = bi; }
       }
 #pragma unroll
       for (int s4 = 0; s4 < KS; s4 += 4) {
@@ -241,7 +322,7 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
       }
       // one-hot spin inputs: this lane supplies column c = 2x + half
       if (DIM == 1) {
-        const float o = sprev == half ? 1.f : 0.f;
+        const float o = e.sprev == half ? 1.f : 0.f;
         au = mfma_f32(o, Wu[KS], au); ar = mfma_f32(o, Wr[KS], ar); ai = mfma_f32(o, Wi[0], ai);
       } else {
         const float o0 = sh == half ? 1.f : 0.f;
@@ -249,79 +330,184 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
         au = mfma_f32(o0, Wu[KS], au); ar = mfma_f32(o0, Wr[KS], ar); ai = mfma_f32(o0, Wi[0], ai);
         au = mfma_f32(o1, Wu[KS + 1], au); ar = mfma_f32(o1, Wr[KS + 1], ar); ai = mfma_f32(o1, Wi[1], ai);
       }
-      // GRU update in the accumulator layout: element e is sequence
-      // (e / 4) * 8 + half * 4 + e % 4, unit `unit`
+      // GRU update in the accumulator layout: element q is sequence
+      // (q / 4) * 8 + half * 4 + q % 4, unit `unit`
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = (e / 4) * 8 + half * 4 + (e % 4);
-        const float hp = DIM == 1 ? hA[cb][row][unit] : hin[e];
+      for (int q = 0; q < 16; ++q) {
+        const int row = (q / 4) * 8 + half * 4 + (q % 4);
+        const float hp = DIM == 1 ? hA[cb][row][unit] : hin[q];
         float hn;
         if (DIM == 1) {
           // pre-scaled: u = 1 / (1 + 2^au), tanh y = 1 - 2 / (1 + 2^y')
-          const float u = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(au[e]));
-          const float rr = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(ar[e]));
-          const float y = fmaf(rr, ag[e], ai[e]);
+          const float u = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(au[q]));
+          const float rr = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(ar[q]));
+          const float y = fmaf(rr, ag[q], ai[q]);
           const float ht = fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(y)), 1.f);
           hn = fmaf(u, ht - hp, hp);
         } else {
-          const float u = fast_sigmoid(au[e]);
-          const float rr = fast_sigmoid(ar[e]);
-          const float ht = fast_tanh(rr * ag[e] + ai[e]);
+          const float u = fast_sigmoid(au[q]);
+          const float rr = fast_sigmoid(ar[q]);
+          const float ht = fast_tanh(rr * ag[q] + ai[q]);
           hn = (1.f - u) * hp + u * ht;
         }
         hA[nb][row][unit] = hn;
         if (DIM == 2) a.ring[(((size_t)blockIdx.x * S + row) * a.W + k % a.W) * H + unit] = hn;
       }
       __syncthreads();
-      // output head of this lane's sequence over units [half H/2, (half+1) H/2)
-      float z0 = 0.f, z1 = 0.f, q0 = 0.f, q1 = 0.f;
-#pragma unroll 4
-      for (int u4 = 0; u4 < H / 2; u4 += 4) {
-        const int u0 = half * (H / 2) + u4;
-        const float4 h4 = *reinterpret_cast<const float4*>(&hA[nb][col][u0]);
-        const float4 w0 = *reinterpret_cast<const float4*>(&hw[0][u0]);
-        const float4 w1 = *reinterpret_cast<const float4*>(&hw[1][u0]);
-        z0 = fmaf(w0.x, h4.x, z0); z0 = fmaf(w0.y, h4.y, z0); z0 = fmaf(w0.z, h4.z, z0); z0 = fmaf(w0.w, h4.w, z0);
-        z1 = fmaf(w1.x, h4.x, z1); z1 = fmaf(w1.y, h4.y, z1); z1 = fmaf(w1.z, h4.z, z1); z1 = fmaf(w1.w, h4.w, z1);
-        if (a.cplx) {
-          const float4 p0 = *reinterpret_cast<const float4*>(&hw[2][u0]);
-          const float4 p1 = *reinterpret_cast<const float4*>(&hw[3][u0]);
-          q0 = fmaf(p0.x, h4.x, q0); q0 = fmaf(p0.y, h4.y, q0); q0 = fmaf(p0.z, h4.z, q0); q0 = fmaf(p0.w, h4.w, q0);
-          q1 = fmaf(p1.x, h4.x, q1); q1 = fmaf(p1.y, h4.y, q1); q1 = fmaf(p1.z, h4.z, q1); q1 = fmaf(p1.w, h4.w, q1);
+      eloc_site<H>(a, e, &hA[nb][col][0], hw, hb, half, k);
+    }
+    if (w == 0 && half == 0 && e.act) eloc_end(a, e);
+    __syncthreads();
+  }
+}
+
+// 1D models, d_h <= 64: each wave re-evaluates its own item (32 connected
+// configurations that share their first flipped site) over all d_h units,
+// so a wave never waits for another between sites.  The workgroup's eight
+// waves share one copy of the B-operand fragments of W_u, W_r, W_h and of
+// the one-hot columns in shared memory (four K-steps per 16-byte read);
+// each wave keeps the 32 x d_h state of its sequences in its own buffer,
+// updated in place (a wave reads all of it into the matrix products before
+// it writes the new state).  Items are dealt by position p: even positions
+// take items from the front of the list (term t restarts at site t, so the
+// longest first), odd ones from the back, and the two waves that share a
+// SIMD take positions 2q and 2q + 1, so their lengths add up to about the
+// same everywhere.  Positions beyond the first round come from a counter;
+// the last wave to finish resets it for the next launch.
+constexpr int EW_WAVES = 8;
+// s_getreg operand for the SIMD id (bits 5:4 of HW_ID): any value yields a
+// permutation of the first-round positions, the id only balances them
+constexpr int HWREG_SIMD_ID = 4 | (4 << 6) | (1 << 11);
+
+template <int H>
+__global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, uint32_t* queue) {
+  constexpr int S = 32;
+  constexpr int HP = H + 4;
+  constexpr int KS = H / 2;
+  constexpr int NCB = H / 32;              // 32-unit column blocks
+  constexpr int NSTEP = 3 * KS + 3;
+  __shared__ __align__(16) float4 Bh[NCB][3][KS / 4][64];   // u, r, h: K-steps 4j..4j+3
+  __shared__ __align__(16) float Bx[NCB][3][64];            // one-hot step of u, r, input
+  __shared__ __align__(16) float hS[EW_WAVES][S][HP];
+  __shared__ __align__(16) float hw[4][H];
+  __shared__ float hb[4];
+  __shared__ float bgs_s[H];
+  __shared__ int simd_of[EW_WAVES];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (lane == 0) simd_of[w] = (int)(__builtin_amdgcn_s_getreg(HWREG_SIMD_ID) & 3);
+  const int half = lane >> 5, col = lane & 31;
+  const int N = a.N;
+  for (int i = tid; i < NCB * 3 * KS * 64; i += 64 * EW_WAVES) {
+    const int l = i % 64, st = (i / 64) % KS, g = (i / (64 * KS)) % 3, cb = i / (64 * KS * 3);
+    const float* base = a.mw + (size_t)cb * NSTEP * 64 + l;
+    const int off = g == 0 ? 0 : g == 1 ? KS + 1 : 2 * (KS + 1);
+    reinterpret_cast<float*>(&Bh[cb][g][st / 4][l])[st % 4] = base[(size_t)(off + st) * 64];
+  }
+  for (int i = tid; i < NCB * 3 * 64; i += 64 * EW_WAVES) {
+    const int l = i % 64, g = (i / 64) % 3, cb = i / (64 * 3);
+    const float* base = a.mw + (size_t)cb * NSTEP * 64 + l;
+    const int off = g == 0 ? KS : g == 1 ? 2 * KS + 1 : 3 * KS + 2;
+    Bx[cb][g][l] = base[(size_t)off * 64];
+  }
+  for (int i = tid; i < 4 * H; i += 64 * EW_WAVES) hw[i / H][i % H] = a.head[i];
+  for (int i = tid; i < H; i += 64 * EW_WAVES) bgs_s[i] = (float)(2.8853900817779268 * (double)a.bias[2 * H + i]);
+  if (tid < 4) hb[tid] = a.headb[tid];
+  __syncthreads();
+
+  float (*hA)[HP] = hS[w];
+  // the wave's own shared-memory writes visible to all its lanes
+  auto wave_sync = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  const int n_items = a.list ? a.count[a.M] : a.n_items;
+  // rank of this wave among the workgroup's, ordered by (SIMD, wave)
+  int rank = 0;
+  {
+    const int me = simd_of[w];
+#pragma unroll
+    for (int v = 0; v < EW_WAVES; ++v) rank += simd_of[v] < me || (simd_of[v] == me && v < w);
+  }
+  const int first_round = (int)gridDim.x * EW_WAVES;
+  for (int p = (int)blockIdx.x * EW_WAVES + rank; p < n_items;) {
+    const int item = (p & 1) ? n_items - 1 - (p >> 1) : (p >> 1);
+    ElocSeq e = eloc_begin(a, item, col);
+    const int k0 = e.k0;
+    if (k0 + 1 < N) {
+      for (int i = lane; i < S * H; i += 64) {
+        const int q = i / H, u = i % H;
+        const int sq = eloc_row_sample(a, e, q);
+        hA[q][u] = a.states[((size_t)sq * N + k0) * H + u];
+      }
+    }
+    wave_sync();
+    for (int k = k0 + 1; k < N; ++k) {
+      f32x16_m au[NCB], ar[NCB], ag[NCB], ai[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const float g0 = bgs_s[32 * cb + col];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) { au[cb][q] = 0.f; ar[cb][q] = 0.f; ag[cb][q] = g0; ai[cb][q] = 0.f; }
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < KS; s4 += 4) {
+        const float4 av = *reinterpret_cast<const float4*>(&hA[col][s4 + half * KS]);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const float4 bu = Bh[cb][0][s4 / 4][lane];
+          const float4 br = Bh[cb][1][s4 / 4][lane];
+          const float4 bg = Bh[cb][2][s4 / 4][lane];
+          au[cb] = mfma_f32(av.x, bu.x, au[cb]); ar[cb] = mfma_f32(av.x, br.x, ar[cb]); ag[cb] = mfma_f32(av.x, bg.x, ag[cb]);
+          au[cb] = mfma_f32(av.y, bu.y, au[cb]); ar[cb] = mfma_f32(av.y, br.y, ar[cb]); ag[cb] = mfma_f32(av.y, bg.y, ag[cb]);
+          au[cb] = mfma_f32(av.z, bu.z, au[cb]); ar[cb] = mfma_f32(av.z, br.z, ar[cb]); ag[cb] = mfma_f32(av.z, bg.z, ag[cb]);
+          au[cb] = mfma_f32(av.w, bu.w, au[cb]); ar[cb] = mfma_f32(av.w, br.w, ar[cb]); ag[cb] = mfma_f32(av.w, bg.w, ag[cb]);
         }
       }
-      z0 += __shfl_xor(z0, 32, 64);
-      z1 += __shfl_xor(z1, 32, 64);
-      q0 += __shfl_xor(q0, 32, 64);
-      q1 += __shfl_xor(q1, 32, 64);
-      const float zz0 = z0 + hb[0], zz1 = z1 + hb[1];
-      const float mx = zz0 > zz1 ? zz0 : zz1;
-      const float d = zz0 > zz1 ? zz1 - zz0 : zz0 - zz1;
-      const float lse = mx + fast_log1p_exp(d);
-      float lp0 = zz0 - lse, lp1 = zz1 - lse;
-      if (a.zero_mag) {
-        if (nup >= N / 2) { lp0 = -INFINITY; lp1 = 0.f; }
-        else if (ndn >= N / 2) { lp0 = 0.f; lp1 = -INFINITY; }
+      {
+        const float o = e.sprev == half ? 1.f : 0.f;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          au[cb] = mfma_f32(o, Bx[cb][0][lane], au[cb]);
+          ar[cb] = mfma_f32(o, Bx[cb][1][lane], ar[cb]);
+          ai[cb] = mfma_f32(o, Bx[cb][2][lane], ai[cb]);
+        }
       }
-      int v = N <= 64 ? (int)((smask >> k) & 1u) : (int)sg[k];
-      if (k == f2p) v ^= 1;
-      lp += (double)(v == 0 ? lp0 : lp1);
-      if (a.cplx) {
-        const float aa = v == 0 ? q0 + hb[2] : q1 + hb[3];
-        ph += (double)(PI * aa / (1.f + fabsf(aa)));
+      // GRU update in the accumulator layout, in place: element q of block cb
+      // is sequence (q / 4) * 8 + half * 4 + q % 4, unit 32 cb + col
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int unit = 32 * cb + col;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int row = (q / 4) * 8 + half * 4 + (q % 4);
+          const float hp = hA[row][unit];
+          const float u = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(au[cb][q]));
+          const float rr = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(ar[cb][q]));
+          const float y = fmaf(rr, ag[cb][q], ai[cb][q]);
+          const float ht = fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(y)), 1.f);
+          hA[row][unit] = fmaf(u, ht - hp, hp);
+        }
       }
-      nup += v == 0; ndn += v == 1;
-      sprev = v;
+      wave_sync();
+      eloc_site<H>(a, e, &hA[col][0], hw, hb, half, k);
+      wave_sync();   // the head's reads precede the next state's writes
     }
-    if (w == 0 && half == 0 && act) {
-      const double dre = 0.5 * (lp - oldlp);
-      const double dim_ = (ph - oldph) + 3.14159265358979323846 * (double)dA;
-      const double e = mel == 0.0 ? 0.0 : exp(dre);
-      double* o = a.contrib + ((size_t)t * a.Ns + s) * 2;
-      o[0] = mel * e * cos(dim_);
-      o[1] = mel * e * sin(dim_);
+    if (half == 0 && e.act) eloc_end(a, e);
+    int next = 0;
+    if (lane == 0) next = (int)atomicAdd(&queue[0], 1u);
+    p = first_round + __builtin_amdgcn_readfirstlane(next);
+  }
+  // the last wave out resets the counter for the next launch
+  if (lane == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t done = atomicAdd(&queue[1], 1u);
+    if (done + 1 == gridDim.x * EW_WAVES) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      atomicExch(&queue[0], 0u);
+      atomicExch(&queue[1], 0u);
     }
-    __syncthreads();
   }
 }
 
@@ -418,6 +604,25 @@ int launch_eloc_mfma(minsr_model* m, const minsr_hamiltonian* H, int Ns, const u
     MINSR_CHECK_LAUNCH();
     a.list = m->elist; a.count = m->ecount; a.items = m->eitems;
   }
+  if (m->dim == 1 && m->H <= 64) {
+    // one workgroup of eight independent waves per compute unit (the shared
+    // weights and eight state buffers fill most of its shared memory)
+    static int ncu = 0;
+    if (ncu == 0) {
+      int dev = 0, v = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+        ncu = v;
+      else
+        ncu = 256;
+    }
+    unsigned grid = std::min<unsigned>((unsigned)ncu, (unsigned)((a.n_items + EW_WAVES - 1) / EW_WAVES));
+    if (m->tune_eloc_grid > 0) grid = std::min<unsigned>(grid, (unsigned)m->tune_eloc_grid);
+    if (m->H == 32) k_eloc_mfma_w<32><<<grid, 64 * EW_WAVES, 0, s>>>(a, m->eloc_q);
+    else k_eloc_mfma_w<64><<<grid, 64 * EW_WAVES, 0, s>>>(a, m->eloc_q);
+    MINSR_CHECK_LAUNCH();
+    return MINSR_OK;
+  }
   unsigned grid = (unsigned)a.n_items;
   if (m->tune_eloc_grid > 0) grid = std::min<unsigned>(grid, (unsigned)m->tune_eloc_grid);
   if (m->dim == 2) {
@@ -428,9 +633,7 @@ int launch_eloc_mfma(minsr_model* m, const minsr_hamiltonian* H, int Ns, const u
   const unsigned nt = 64u * (unsigned)(m->H / 32);
 #define MINSR_ELOC_MFMA(HH, DD) k_eloc_mfma<HH, DD><<<grid, nt, 0, s>>>(a)
   if (m->dim == 1) {
-    if (m->H == 32) MINSR_ELOC_MFMA(32, 1);
-    else if (m->H == 64) MINSR_ELOC_MFMA(64, 1);
-    else MINSR_ELOC_MFMA(128, 1);
+    MINSR_ELOC_MFMA(128, 1);
   } else {
     if (m->H == 32) MINSR_ELOC_MFMA(32, 2);
     else if (m->H == 64) MINSR_ELOC_MFMA(64, 2);

@@ -32,6 +32,7 @@ struct minsr_model {
   int* elist = nullptr;     // [max_terms][max_Ns] samples with a nonzero matrix element
   int* ecount = nullptr;    // [max_terms + 1] their counts, then the item count
   int* eitems = nullptr;    // [max_terms * ceil(max_Ns / 32)][2] (term, chunk)
+  uint32_t* eloc_q = nullptr;  // local-energy work queue: next item, finished waves (zero between launches)
   double* diag = nullptr;   // [max_Ns]
   void* ring = nullptr;     // 2D local-energy recompute windows
   int ring_blocks = 0;
