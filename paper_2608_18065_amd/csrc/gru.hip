@@ -262,13 +262,44 @@ template <typename T> struct FwdArgs {
 
 enum { MODE_SAMPLE = 0, MODE_EVAL = 1, MODE_ELOC = 2 };
 
+// value of the lane picked by DPP control C (quad permutations, row mirrors)
+template <int C> __device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), C, 0xF, 0xF, false));
+}
+template <int C> __device__ inline double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), C, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), C, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int L> __device__ inline float lane_val(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
+}
+template <int L> __device__ inline double lane_val(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), L);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), L);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <int H> struct GroupReduce {
-  // butterfly over the min(H, 64) lanes of a group inside one wavefront;
-  // every lane ends with the same value
+  // sum over the min(H, 64) lanes of a group inside one wavefront, every
+  // lane ending with the total: inside rows of 16 lanes by DPP (neighbours,
+  // pairs of neighbours, then the mirrored halves and rows, whose lanes by
+  // then hold equal values), across rows from one lane of each; no step
+  // goes through the LDS crossbar
   template <typename T> __device__ static T run(T v) {
     constexpr int W = H < 64 ? H : 64;
-#pragma unroll
-    for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    v += dpp_mov<0xB1>(v);                      // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);                      // quad_perm [2, 3, 0, 1]
+    if constexpr (W > 4) v += dpp_mov<0x141>(v);   // row_half_mirror
+    if constexpr (W > 8) v += dpp_mov<0x140>(v);   // row_mirror
+    if constexpr (W == 32) {
+      const T lo = lane_val<0>(v) + lane_val<16>(v), hi = lane_val<32>(v) + lane_val<48>(v);
+      v = (threadIdx.x & 32) ? hi : lo;
+    } else if constexpr (W == 64) {
+      v = (lane_val<0>(v) + lane_val<16>(v)) + (lane_val<32>(v) + lane_val<48>(v));
+    }
     return v;
   }
 };
