@@ -337,6 +337,15 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
 
   // per-unit constants
   const T bu = w.bias[j], br = w.bias[H + j], bh = w.bias[2 * H + j], bi = w.bias[3 * H + j];
+  // 1D: the input columns of unit j for both spin values, so the spin just
+  // drawn selects a register instead of starting a load
+  T xc1[3][2];
+  if (DIM == 1) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) xc1[q][c] = w.xc[(q * 2 + c) * H + j];
+  }
   const T U0 = w.head[j], U1v = w.head[H + j];
   const T P0 = w.head[2 * H + j], P1 = w.head[3 * H + j];
   const T c0 = w.headb[0], c1 = w.headb[1], cp0 = w.headb[2], cp1 = w.headb[3];
@@ -494,9 +503,9 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
         au[r] = bu; ar[r] = br; ag[r] = bh; ai[r] = bi;
         if (DIM == 1) {
           if (sprev[r] >= 0) {
-            au[r] += w.xc[(0 * ds + sprev[r]) * H + j];
-            ar[r] += w.xc[(1 * ds + sprev[r]) * H + j];
-            ai[r] += w.xc[(2 * ds + sprev[r]) * H + j];
+            au[r] += sprev[r] ? xc1[0][1] : xc1[0][0];
+            ar[r] += sprev[r] ? xc1[1][1] : xc1[1][0];
+            ai[r] += sprev[r] ? xc1[2][1] : xc1[2][0];
           }
         } else {
           if (sh[r] >= 0) {
