@@ -384,6 +384,14 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
       nup[r] = 0; ndn[r] = 0; nA[r] = 0; sprev[r] = -1; dA[r] = 0;
       rw[r].w[0] = rw[r].w[1] = rw[r].w[2] = rw[r].w[3] = 0;
     }
+    // d_h >= 64, one sequence per group: lane c draws Philox block c of the
+    // sequence (sites 4c .. 4c + 3) before the site loop, and site k takes
+    // its word from lane k / 4, off the sequential path
+    constexpr bool PRE_OK = H >= 64 && R == 1;
+    const bool pre = PRE_OK && a.mode == MODE_SAMPLE && !a.uniforms && N <= 4 * 64;
+    U64x4 rpre;
+    rpre.w[0] = rpre.w[1] = rpre.w[2] = rpre.w[3] = 0;
+    if (pre) rpre = philox4x64_10(ctr, (uint64_t)sidx[0], (uint64_t)(tid & 63), 0, a.key, 0);
 
     if (a.mode == MODE_ELOC) {
       // prefix statistics of the flipped configuration and the old suffix
@@ -635,6 +643,12 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
           double u;
           if (a.uniforms) {
             u = a.uniforms[(size_t)s * N + k];
+          } else if (pre) {
+            const int q = k & 3;
+            const uint64_t wq = q == 0 ? rpre.w[0] : q == 1 ? rpre.w[1] : q == 2 ? rpre.w[2] : rpre.w[3];
+            const int lo = __builtin_amdgcn_readlane((int)(uint32_t)wq, k >> 2);
+            const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(wq >> 32), k >> 2);
+            u = u01(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
           } else {
             if ((k & 3) == 0)
               rw[r] = philox4x64_10(ctr, (uint64_t)s, (uint64_t)(k >> 2), 0, a.key, 0);
