@@ -839,12 +839,16 @@ __device__ __forceinline__ f64x4_t mm_nt(f64x4_t acc, const double (*X)[LDT], in
 // level by level Z_QP = -Z_QQ sum_{P <= R < Q} L_QR Z_RP, one block per
 // wave.  L stays in S (the caller stores it); inv(L) goes to Z and to Di
 // (zero outside the leading nb x nb block).
+// `during_first_panel` runs on waves 1..3 while wave 0 factors the first
+// panel (it may complete columns 16.. of S); with `fill` false the caller has
+// already made the rows >= nb identity rows.
+template <typename F>
 __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm)[16][17],
                                  double* rinv, double* lb, int nb, int k0, double* Di,
-                                 uint32_t* status) {
+                                 uint32_t* status, bool fill, F&& during_first_panel) {
   constexpr int PB = 16, NB = CB / 16;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  if (nb < CB) {   // the last, partial block only
+  if (fill && nb < CB) {   // the last, partial block only
     for (int e = tid; e < CB * CB; e += 256) {
       const int r = e / CB, c = e % CB;
       if (r >= nb && c <= r) S[r][c] = (r == c) ? 1.0 : 0.0;
@@ -897,6 +901,8 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
       }
 #pragma unroll
       for (int cc = 0; cc < PB; ++cc) S[lane][p0 + cc] = lane >= p0 + cc ? f[cc] : 0.0;
+    } else if (P == 0) {
+      during_first_panel();
     }
     __syncthreads();
     if (p1 < CB) {
@@ -1176,31 +1182,56 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
     __syncthreads();   // X, Y, yb are no longer read
     tile_to_lds(l, X);
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 4; ++c) td[c] = mm_nt<CB, true>(td[c], X, 16 * w, X, 16 * c, 0, lane);
+    // column block 0 of L L^T now; the other lower blocks while wave 0
+    // factors the first panel (L stays in X until then)
+    td[0] = mm_nt<CB, true>(td[0], X, 16 * w, X, 0, 0, lane);
     publish(&pflag[pi * nblk + pj]);
   }
 
-  // the diagonal block jd: factor, invert, and solve its block of L y = b
+  // the diagonal block jd: factor (in Y, the inverse in X), invert, and
+  // solve its block of L y = b; rows >= nb become identity rows as they are
+  // written
   const int kb0 = kbd;
   double* Di = reinterpret_cast<double*>(a.Dinv) + (size_t)jd * CB * CB;
-  __syncthreads();   // X is rewritten
-  tile_to_lds(td, X);
+  auto put_block = [&](const f64x4_t& t, int c) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + mrow(lane, v), col = 16 * c + (lane & 15);
+      Y[r][col] = r < nb ? t[v] : (r == col ? 1.0 : 0.0);
+    }
+  };
+  __syncthreads();   // Y is rewritten
+  if (has_panel) {
+    put_block(td[0], 0);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) put_block(td[c], c);
+  }
   if (tid < CB) {
     const double r = jd > 0 ? bpart - cown[tid] : bpart;
     yb[tid] = tid < nb ? r : 0.0;
   }
   __syncthreads();
-  factor_block_f64(X, Y, Tm, rinv, lb, nb, kb0, Di, a.status);
+  // waves 1..3: the rest of L L^T for their lower blocks (1 <= c <= w)
+  auto rest = [&]() {
+    if (!has_panel) return;
+#pragma unroll
+    for (int c = 1; c < 4; ++c)
+      if (c <= w) {
+        td[c] = mm_nt<CB, true>(td[c], X, 16 * w, X, 16 * c, 0, lane);
+        put_block(td[c], c);
+      }
+  };
+  factor_block_f64(Y, X, Tm, rinv, lb, nb, kb0, Di, a.status, false, rest);
   __syncthreads();
   {
     // y_jd = inv(L) yb: four threads per row, terms q = part, part + 4, ...
-    // up to the diagonal (Y above the diagonal blocks is not cleared)
+    // up to the diagonal (X above the diagonal blocks is not cleared)
     const int row = tid / 4, part = tid % 4;
     double zr[CB / 4], yq[CB / 4];
 #pragma unroll
     for (int u = 0; u < CB / 4; ++u) {
-      zr[u] = Y[row][part + 4 * u];
+      zr[u] = X[row][part + 4 * u];
       yq[u] = yb[part + 4 * u];
     }
     double s = 0.0;
@@ -1215,7 +1246,7 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
 #pragma unroll
   for (int q = 0; q < CB * CB / 256; ++q) {
     const int e = tid + 256 * q, i = e / CB, j = e % CB;
-    if (j <= i && i < nb) A[(size_t)(kb0 + i) * n + kb0 + j] = X[i][j];
+    if (j <= i && i < nb) A[(size_t)(kb0 + i) * n + kb0 + j] = Y[i][j];
   }
 }
 
