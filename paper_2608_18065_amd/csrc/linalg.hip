@@ -855,6 +855,60 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
     }
     __syncthreads();
   }
+  // the blockwise inverse, on the calling wave: Z_bb of diagonal block b
+  // (lane j: column j by forward substitution, the terms of each row taken in
+  // order of m, column by column so the dependent chain is one fma deep);
+  // Tm[slot] = sum_{P <= R < Q} L_QR Z_RP; Z_QP = -Z_QQ Tm[slot]
+  auto diag_inv = [&](int b) {
+    if (lane < 16) {
+      const int b0 = 16 * b, j = lane;
+      double z[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) z[i] = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        z[m] *= rinv[b0 + m];
+#pragma unroll
+        for (int i = m + 1; i < 16; ++i) z[i] = fma(-S[b0 + i][b0 + m], z[m], z[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Z[b0 + i][b0 + j] = z[i];
+    }
+  };
+  auto lprod = [&](int Q, int P, int slot) {
+    f64x4_t t = {0.0, 0.0, 0.0, 0.0};
+    for (int R = P; R < Q; ++R) {
+#pragma unroll
+      for (int s = 0; s < 16; s += 4) {
+        const double la = S[16 * Q + (lane & 15)][16 * R + s + (lane >> 4)];
+        const double zb = Z[16 * R + s + (lane >> 4)][16 * P + (lane & 15)];
+        t = __builtin_amdgcn_mfma_f64_16x16x4f64(la, zb, t, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Tm[slot][mrow(lane, v)][lane & 15] = t[v];
+  };
+  auto zprod = [&](int Q, int P, int slot) {
+    f64x4_t u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 16; s += 4) {
+      const double za = Z[16 * Q + (lane & 15)][16 * Q + s + (lane >> 4)];
+      const double tb = Tm[slot][s + (lane >> 4)][lane & 15];
+      u = __builtin_amdgcn_mfma_f64_16x16x4f64(-za, tb, u, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Z[16 * Q + mrow(lane, v)][16 * P + (lane & 15)] = u[v];
+  };
+  auto wave_fence = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+
+  // While wave 0 factors panel P, waves 1..3 form the parts of the inverse
+  // that blocks < P already fix: Z_00 under panel 1; Z_11 and L_10 Z_00
+  // under panel 2 (Z_10 after it); Z_22, L_20 Z_00 + L_21 Z_10 and L_21 Z_11
+  // under panel 3; the last row of blocks follows.
   bool bad = false;
   for (int P = 0; P < CB / PB; ++P) {
     const int p0 = PB * P, p1 = p0 + PB;
@@ -903,6 +957,15 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
       for (int cc = 0; cc < PB; ++cc) S[lane][p0 + cc] = lane >= p0 + cc ? f[cc] : 0.0;
     } else if (P == 0) {
       during_first_panel();
+    } else if (P == 1) {
+      if (w == 1) diag_inv(0);
+    } else if (P == 2) {
+      if (w == 1) diag_inv(1);
+      else if (w == 2) lprod(1, 0, 0);
+    } else {
+      if (w == 1) diag_inv(2);
+      else if (w == 2) lprod(2, 0, 1);
+      else lprod(2, 1, 2);
     }
     __syncthreads();
     if (p1 < CB) {
@@ -920,57 +983,29 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
         for (int v = 0; v < 4; ++v) S[16 * Q + mrow(lane, v)][16 * R + (lane & 15)] = t[v];
       }
     }
+    if (P == 2 && w == 1) zprod(1, 0, 0);   // the trailing update after panel 2 is wave 0's
     __syncthreads();
   }
   if (bad && lane == 0 && status) atomicOr(status, MINSR_ST_NOT_PD);
-  // diagonal blocks of the inverse
-  // (lane j: column j by forward substitution, the terms of each row taken
-  // in order of m, column by column so the dependent chain is one fma deep)
-  if (lane < 16) {
-    const int b0 = 16 * w, j = lane;
-    double z[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) z[i] = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      z[m] *= rinv[b0 + m];
-#pragma unroll
-      for (int i = m + 1; i < 16; ++i) z[i] = fma(-S[b0 + i][b0 + m], z[m], z[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) Z[b0 + i][b0 + j] = z[i];
+  // the last row of blocks: Z_33 with Z_20, Z_21 and L_32 Z_22, then
+  // Z_30, Z_31, Z_32
+  if (w == 0) diag_inv(3);
+  else if (w == 1) zprod(2, 0, 1);
+  else if (w == 2) zprod(2, 1, 2);
+  else lprod(3, 2, 3);
+  __syncthreads();
+  if (w == 1) {
+    lprod(3, 0, 0);
+    wave_fence();
+    zprod(3, 0, 0);
+  } else if (w == 2) {
+    lprod(3, 1, 1);
+    wave_fence();
+    zprod(3, 1, 1);
+  } else if (w == 3) {
+    zprod(3, 2, 3);
   }
   __syncthreads();
-  // blocks below the diagonal, level lv = Q - P, block P on wave P
-  for (int lv = 1; lv < NB; ++lv) {
-    const int P = w, Q = w + lv;
-    if (Q < NB) {
-      f64x4_t t = {0.0, 0.0, 0.0, 0.0};
-      for (int R = P; R < Q; ++R) {
-#pragma unroll
-        for (int s = 0; s < 16; s += 4) {
-          const double la = S[16 * Q + (lane & 15)][16 * R + s + (lane >> 4)];
-          const double zb = Z[16 * R + s + (lane >> 4)][16 * P + (lane & 15)];
-          t = __builtin_amdgcn_mfma_f64_16x16x4f64(la, zb, t, 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Tm[w][mrow(lane, v)][lane & 15] = t[v];
-    }
-    __syncthreads();
-    if (Q < NB) {
-      f64x4_t u = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 16; s += 4) {
-        const double za = Z[16 * Q + (lane & 15)][16 * Q + s + (lane >> 4)];
-        const double tb = Tm[w][s + (lane >> 4)][lane & 15];
-        u = __builtin_amdgcn_mfma_f64_16x16x4f64(-za, tb, u, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Z[16 * Q + mrow(lane, v)][16 * P + (lane & 15)] = u[v];
-    }
-    __syncthreads();
-  }
   {
     double zv[CB * CB / 256];
 #pragma unroll
