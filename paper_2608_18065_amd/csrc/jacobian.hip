@@ -180,6 +180,21 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
   const VT* b2 = reinterpret_cast<const VT*>(w.b2);
   const uint8_t* sig = a.sigma + (size_t)sid * N;
   const T* st = a.states + (size_t)sid * N * H;
+  // N <= 64: the sample's spins as the bits of one word, read once (all
+  // loads in flight together), so no site waits on a load for its spin
+  uint64_t smask = 0;
+  if (N <= 64) {
+#pragma unroll
+    for (int q0 = 0; q0 < 64; q0 += 16) {
+      uint8_t v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = sig[min(q0 + u, N - 1)];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (q0 + u < N) smask |= (uint64_t)(v[u] & 1) << (q0 + u);
+    }
+  }
+  auto spin = [&](int q) -> int { return N <= 64 ? (int)((smask >> q) & 1u) : (int)sig[q]; };
 
   const T bu = w.bias[j], br = w.bias[H + j], bh = w.bias[2 * H + j], bi = w.bias[3 * H + j];
   const T U0 = w.head[j], U1v = w.head[H + j];
@@ -241,7 +256,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
       // zero-magnetisation counts of sigma_{<ks}
       int nup = 0, ndn = 0;
       if (a.zero_mag)
-        for (int k = 0; k < ks; ++k) { nup += sig[k] == 0; ndn += sig[k] == 1; }
+        for (int k = 0; k < ks; ++k) { nup += spin(k) == 0; ndn += spin(k) == 1; }
 
       if (DIM == 1) {
         // ---- forward recompute of the segment from its checkpoint
@@ -254,7 +269,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
             u = gcur[0]; rr = gcur[1]; ag = gcur[2]; ht = gcur[3];
             hn = hcur;
           } else {
-            const int sprev = k > 0 ? sig[k - 1] : -1;
+            const int sprev = k > 0 ? spin(k - 1) : -1;
             T au = bu, ar = br, agg = bh, ai = bi;
             if (sprev >= 0) {
               au += w.xc[(0 * ds + sprev) * H + j];
@@ -316,7 +331,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
             thead[sg][kk][0] = p0; thead[sg][kk][1] = p1;
             thead[sg][kk][2] = q0 + cp0; thead[sg][kk][3] = q1 + cp1;
           }
-          nup += sig[k] == 0; ndn += sig[k] == 1;
+          nup += spin(k) == 0; ndn += spin(k) == 1;
           if (NW > 1) __syncthreads();
         }
         __syncthreads();
@@ -325,7 +340,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
       // ---- reverse through the segment
       for (int kk = len - 1; kk >= 0; --kk) {
         const int k = ks + kk;
-        const int sk = sig[k];
+        const int sk = spin(k);
         T u, rr, ag, ht, hprev, hk;
         int kh = -1, kv = -1, sh = -1, sv = -1;
         if (DIM == 1) {
@@ -336,8 +351,8 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
         } else {
           // recompute site k from its stored predecessors
           kh = a.nbr[2 * k]; kv = a.nbr[2 * k + 1];
-          sh = kh >= 0 ? sig[kh] : -1;
-          sv = kv >= 0 ? sig[kv] : -1;
+          sh = kh >= 0 ? spin(kh) : -1;
+          sv = kv >= 0 ? spin(kv) : -1;
           if (p == 0) {
             thh[sg][j] = kh >= 0 ? st[(size_t)kh * H + j] : (T)0;
             thv[sg][j] = kv >= 0 ? st[(size_t)kv * H + j] : (T)0;
@@ -409,7 +424,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
           }
           if (j == 0 && p == 0) {
             int cu = 0, cd = 0;
-            if (a.zero_mag) for (int q = 0; q < k; ++q) { cu += sig[q] == 0; cd += sig[q] == 1; }
+            if (a.zero_mag) for (int q = 0; q < k; ++q) { cu += spin(q) == 0; cd += spin(q) == 1; }
             const T zz0 = z0 + c0, zz1 = z1 + c1;
             const T mx = zz0 > zz1 ? zz0 : zz1;
             const T d = zz0 > zz1 ? zz1 - zz0 : zz0 - zz1;
@@ -463,7 +478,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
         gbu += dpu; gbr += dpr; gbh += dg; gbi += da;
         if (DIM == 1) {
           if (k > 0) {
-            const int sp = sig[k - 1];
+            const int sp = spin(k - 1);
             gxu[sp] += dpu; gxr[sp] += dpr; gxi[sp] += da;
           }
         } else {
