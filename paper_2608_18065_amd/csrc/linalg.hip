@@ -167,9 +167,15 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
   constexpr int NOP = SPLIT ? 2 : 1;
   __shared__ __align__(16) __hip_bfloat16 As[2][NOP][GT][GKP];
   __shared__ __align__(16) __hip_bfloat16 Bs[2][NOP][GT][GKP];
+  // workgroups are dealt to the eight XCDs in turn (linear id mod 8); each
+  // XCD takes a contiguous run of (split, pair) items, so the pairs that
+  // read the same rows over the same K range share that XCD's L2
+  const int npairs = gridDim.x, total = npairs * gridDim.y;
+  const int lin = blockIdx.x + blockIdx.y * npairs, xcd = lin % 8;
+  const int item = xcd * (total / 8) + min(xcd, total % 8) + lin / 8;
+  const int pair = item % npairs, split = item / npairs;
   int ti, tj;
-  pair_decode(blockIdx.x, ti, tj);
-  const int split = blockIdx.y;
+  pair_decode(pair, ti, tj);
   const size_t k0 = (size_t)split * kchunk;
   const size_t k1 = min(ld, k0 + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -258,7 +264,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
   flush();
   // write the partial tile: acc element e of lane l is row
   // (e / 4) * 8 + (l / 32) * 4 + e % 4, column l % 32 of its 32 x 32 block
-  double* out = part + ((size_t)split * gridDim.x + blockIdx.x) * GT * GT;
+  double* out = part + ((size_t)split * npairs + pair) * GT * GT;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
