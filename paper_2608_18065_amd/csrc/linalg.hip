@@ -1365,11 +1365,20 @@ __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const 
   }
   __syncthreads();
   // x_k[cc] = sum_{r >= cc} inv(L_kk)[r][cc] rb[r], four threads per cc
+  // (thread sb: rows cc + sb, cc + sb + 4, ... below nb; all sixteen reads
+  // issued together, rows past the block masked to zero terms)
   {
     const int cc = tid >> 2, sb = tid & 3;
+    TT dv[CB / 4], rv[CB / 4];
+#pragma unroll
+    for (int u = 0; u < CB / 4; ++u) {
+      const int r = min(cc + sb + 4 * u, CB - 1);
+      dv[u] = Dk[r][cc];
+      rv[u] = rb[r];
+    }
     TT v = (TT)0;
-    if (cc < nb)
-      for (int r = cc + sb; r < nb; r += 4) v = fma(Dk[r][cc], rb[r], v);
+#pragma unroll
+    for (int u = 0; u < CB / 4; ++u) v = fma(cc + sb + 4 * u < nb ? dv[u] : (TT)0, rv[u], v);
     v += __shfl_xor(v, 1, 4);
     v += __shfl_xor(v, 2, 4);
     if (sb == 0 && cc < nb) x[k0 + cc] = (double)v;
