@@ -952,8 +952,10 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
         const double lc1 = fma(-lc0, l10, f[cc + 1]) * inv1;   // lane c + 1: sqrt(det / d0)
         f[cc] = lc0;
         f[cc + 1] = lc1;
-        if (lane == c) rinv[c] = inv0;
-        if (lane == c + 1) rinv[c + 1] = inv1;
+        if (lane == 0) {   // inv0, inv1 are the same on every lane
+          rinv[c] = inv0;
+          rinv[c + 1] = inv1;
+        }
         // rank-2 update: the next pair's columns by readlane (short chain),
         // the others with the two columns broadcast through shared memory
         if (cc + 2 < PB) {
