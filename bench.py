@@ -42,14 +42,14 @@ PEAK_FP32_MFMA_TFLOPS = 157.3    # dense FP32 matrix cores (equal to the FP32 ve
 # scaled by the counter's reading on a plain copy of known size; None until
 # taken for the current kernel version
 TRAFFIC_BYTES = {
-    # k_eloc_mfma_w: 9971.5 KiB fetched x 2.000 + 1383.2 KiB written x 1.000
-    "eloc": 9971.5 * 1024 * 2.0 + 1383.2 * 1024,
+    # k_eloc_mfma_w: 9971.5 KiB fetched x 2.000 + 1379.9 KiB written x 1.000
+    "eloc": 9971.5 * 1024 * 2.0 + 1379.9 * 1024,
     # k_jacobian (gate-tape path, gate adjoints stored per site) + k_jac_wgrad:
-    # (41299.3 + 33944.3) KiB fetched x 2.000 + (55328.0 + 50235.5) KiB written x 1.000
-    "jacobian": (41299.3 + 33944.3) * 1024 * 2.0 + (55328.0 + 50235.5) * 1024,
+    # (41331.7 + 33968.4) KiB fetched x 2.000 + (55328.0 + 50234.5) KiB written x 1.000
+    "jacobian": (41331.7 + 33968.4) * 1024 * 2.0 + (55328.0 + 50234.5) * 1024,
     # k_gram_bf16 (split form, four products, 7-way split-K, FP64 partial tiles):
-    # 187089.5 KiB fetched x 2.000 + 32256.0 KiB written x 1.000
-    "gram": 187089.5 * 1024 * 2.0 + 32256.0 * 1024}
+    # 43368.0 KiB fetched x 2.000 + 32256.0 KiB written x 1.000
+    "gram": 43368.0 * 1024 * 2.0 + 32256.0 * 1024}
 
 
 def parse():
