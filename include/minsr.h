@@ -30,7 +30,9 @@
  *   - log Psi is complex: re = 0.5 log P(sigma), im = phase (Eqs. 2, 6, 8).
  *   - Identical inputs give bitwise identical outputs (no floating-point
  *     atomics anywhere).
- *   - A handle must not be used from two host threads at once.
+ *   - A handle must not be used from two host threads at once, and the
+ *     device work of its calls must not overlap (one stream, or streams
+ *     ordered by events): the calls share the handle's workspace.
  */
 #ifndef MINSR_H
 #define MINSR_H
