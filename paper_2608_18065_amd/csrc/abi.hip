@@ -37,16 +37,6 @@ size_t packed_elems(minsr_model* m);
 void bind_work(minsr_model* m);
 size_t gram_partial_bytes(int n, size_t Np, int dtype);
 
-__global__ void k_bump_counter(uint64_t* c) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) c[0] += 1;
-}
-
-// zero-fill by kernel (safe inside captured graphs)
-__global__ void k_zero_u32(uint32_t* p, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
 template <typename TO>
 __global__ void k_vjp(const TO* O, int Ns, int two, size_t Np, const double* g, double scale,
                       double* out) {
@@ -429,12 +419,11 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   };
 #define MINSR_PHASE(ph) do { int rc_ = mark(ph); if (rc_) return rc_; } while (0)
 
-  k_zero_u32<<<1, 64, 0, s>>>(out->dev_status, 1);
-  MINSR_CHECK_LAUNCH();
   MINSR_PHASE(0);
   // 1. exact autoregressive samples, hidden states, per-site conditionals
+  //    (the sampler also clears the status word)
   rc = launch_forward(m, 0, Ns, nullptr, st->key, st->counter, sigma, m->logpsi, m->states, 1,
-                      m->site, s, st->dev_counter, C == 1 ? m->gates : nullptr);
+                      m->site, s, st->dev_counter, C == 1 ? m->gates : nullptr, out->dev_status);
   if (rc) return rc;
   MINSR_PHASE(1);
   // 2. local energies, E, Var and eps'
@@ -478,9 +467,10 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   }
   if (rc) return rc;
   MINSR_PHASE(8);
-  // 5. dtheta = eta O' x, momentum, parameters, working copy
+  // 5. dtheta = eta O' x, momentum, parameters, working copy (the update
+  //    also advances the device-side Philox counter)
   rc = launch_update(n, Np, m->R, rdt, m->x, cfg->eta, cfg->mu, m->dpart, dth, st->dev_momentum,
-                     m->theta, out->dev_status, cfg->apply_update, s, Rlo);
+                     m->theta, out->dev_status, cfg->apply_update, s, Rlo, st->dev_counter);
   if (rc) return rc;
   MINSR_PHASE(9);
   if (cfg->apply_update) {
@@ -489,10 +479,6 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   }
   MINSR_PHASE(10);
 #undef MINSR_PHASE
-  if (st->dev_counter) {
-    k_bump_counter<<<1, 64, 0, s>>>(st->dev_counter);
-    MINSR_CHECK_LAUNCH();
-  }
   if (timing) m->t_slot++;
   m->last_n = n;
   m->last_form = cfg->form;

@@ -241,6 +241,7 @@ template <typename T> struct FwdArgs {
   const double* uniforms;
   uint64_t key, counter;
   const uint64_t* counter_ptr;   // if set, the counter is read from here
+  uint32_t* zero_word;           // if set, cleared by the first thread (a step's status word)
   // configurations and outputs
   uint8_t* sigma_out;        // mode 0
   const uint8_t* sigma_in;   // modes 1, 2
@@ -351,6 +352,7 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
   const T c0 = w.headb[0], c1 = w.headb[1], cp0 = w.headb[2], cp1 = w.headb[3];
   const T PI = (T)3.14159265358979323846;
   const uint64_t ctr = a.counter_ptr ? *a.counter_ptr : a.counter;
+  if (a.zero_word && blockIdx.x == 0 && threadIdx.x == 0) a.zero_word[0] = 0u;
 
   for (int item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     const int t = a.mode == MODE_ELOC ? item / a.nchunks : 0;
@@ -740,8 +742,9 @@ template <typename T>
 static int forward_t(minsr_model* m, const Work<T>& w, int mode, int Ns, const double* uniforms,
                      uint64_t key, uint64_t counter, const uint64_t* counter_ptr, uint8_t* sigma,
                      double* logpsi, void* states, int store_every, double* site, void* gates,
-                     hipStream_t s) {
+                     hipStream_t s, uint32_t* zero_word) {
   FwdArgs<T> a = base_args<T>(m, w);
+  a.zero_word = zero_word;
   a.Ns = Ns; a.mode = mode;
   a.uniforms = uniforms; a.key = key; a.counter = counter; a.counter_ptr = counter_ptr;
   if (mode == MODE_SAMPLE) a.sigma_out = sigma; else a.sigma_in = sigma;
@@ -760,13 +763,13 @@ static int forward_t(minsr_model* m, const Work<T>& w, int mode, int Ns, const d
 int launch_forward(minsr_model* m, int mode, int Ns, const double* uniforms, uint64_t key,
                    uint64_t counter, uint8_t* sigma, double* logpsi, void* states,
                    int store_every, double* site, hipStream_t s, const uint64_t* counter_ptr,
-                   void* gates) {
+                   void* gates, uint32_t* zero_word) {
   if (Ns == 0) return MINSR_OK;
   if (m->f64)
     return forward_t<double>(m, m->wd, mode, Ns, uniforms, key, counter, counter_ptr, sigma,
-                             logpsi, states, store_every, site, gates, s);
+                             logpsi, states, store_every, site, gates, s, zero_word);
   return forward_t<float>(m, m->wf, mode, Ns, uniforms, key, counter, counter_ptr, sigma, logpsi,
-                          states, store_every, site, gates, s);
+                          states, store_every, site, gates, s, zero_word);
 }
 
 // ------------------------------------------------------ local energies

@@ -1302,12 +1302,29 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
   }
 }
 
-// sync words and b -> y (one kernel, safe inside captured graphs)
+// sync words and b -> y (one kernel, safe inside captured graphs); if lam_out
+// is set, workgroup 0 also writes lambda_eff = max(lambda, rel * max_i T_ii):
+// the shift never falls below the accuracy to which a low-precision Gram is
+// computed
 template <typename TT>
-__global__ void k_chol_prep(uint32_t* sync, int nsync, const double* b, TT* y, int n) {
+__global__ __launch_bounds__(256) void k_chol_prep(uint32_t* sync, int nsync, const double* b,
+                                                   TT* y, int n, const double* T, double lambda,
+                                                   double rel, double* lam_out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nsync) sync[i] = 0u;
   if (i < n) y[i] = (TT)b[i];
+  if (lam_out && blockIdx.x == 0) {
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) mx = fmax(mx, T[(size_t)k * n + k]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) lam_out[0] = fmax(lambda, rel * red[0]);
+  }
 }
 
 // Backward substitution L^T x = y by one workgroup per block of 64:
@@ -1419,22 +1436,6 @@ size_t chol_vec_elems(int n) {
   return nblk * CB + nblk * nblk * CB + 1;   // + the shift actually used
 }
 
-// lambda_eff = max(lambda, rel * max_i T_ii): the shift never falls below the
-// accuracy to which a low-precision Gram is computed
-__global__ __launch_bounds__(256) void k_lambda_floor(const double* T, int n, double lambda,
-                                                      double rel, double* lam_out) {
-  __shared__ double red[256];
-  double mx = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) mx = fmax(mx, T[(size_t)i * n + i]);
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) lam_out[0] = fmax(lambda, rel * red[0]);
-}
-
 template <typename TT>
 static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, double lambda,
                   const double* b, double* x, uint32_t* status, hipStream_t s,
@@ -1442,16 +1443,20 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
   const int nblk = (n + CB - 1) / CB;
   const int nsync = (int)chol_sync_words(n);
   const int m = std::max(nsync, n);
-  k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n);
-  MINSR_CHECK_LAUNCH();
   CholArgs a{T, A, Dinv, yv, sync, status, lambda, nullptr, n, nblk};
+  const double* Tfloor = nullptr;
+  double* lam_slot = nullptr;
   if constexpr (std::is_same<TT, double>::value) {
     if (lam_floor_rel > 0.0) {
-      double* lam_slot = yv + chol_vec_elems(n) - 1;
-      k_lambda_floor<<<1, 256, 0, s>>>(T, n, lambda, lam_floor_rel, lam_slot);
-      MINSR_CHECK_LAUNCH();
+      Tfloor = T;
+      lam_slot = reinterpret_cast<double*>(yv) + chol_vec_elems(n) - 1;
       a.lam_dev = lam_slot;
     }
+  }
+  k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n, Tfloor, lambda,
+                                                  lam_floor_rel, lam_slot);
+  MINSR_CHECK_LAUNCH();
+  if constexpr (std::is_same<TT, double>::value) {
     k_chol_persist_f64<<<1 + nblk * (nblk - 1) / 2, 256, 0, s>>>(a, sync + chol_sync_one(nblk),
                                                              yv + (size_t)nblk * CB);
     MINSR_CHECK_LAUNCH();
@@ -1544,9 +1549,12 @@ __global__ void k_update_part<double>(const double* R, int n, size_t Np, size_t 
   part[(size_t)blockIdx.y * Np + col] = s;
 }
 
+// (bump, if set: the step's Philox counter, advanced once here since every
+// read of it this step has happened)
 __global__ void k_update_final(const double* part, int nrc, size_t Np, double eta, double* dtheta,
-                               uint32_t* status) {
+                               uint32_t* status, uint64_t* bump) {
   size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bump && col == 0) bump[0] += 1;
   if (col >= Np) return;
   double s = 0.0;
   for (int c = 0; c < nrc; ++c) s += part[(size_t)c * Np + col];
@@ -1567,7 +1575,7 @@ __global__ void k_apply(size_t Np, const double* dtheta, double mu, double* m, d
 
 int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, double eta,
                   double mu, double* dpart, double* dtheta, double* momentum, double* theta,
-                  uint32_t* status, int apply, hipStream_t s, const void* Rlo) {
+                  uint32_t* status, int apply, hipStream_t s, const void* Rlo, uint64_t* bump) {
   const int RC = 64;
   const int nrc = (n + RC - 1) / RC;
   dim3 grid((unsigned)((Np + 255) / 256), (unsigned)nrc);
@@ -1585,7 +1593,7 @@ int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, d
     k_update_part<double><<<grid, 256, 0, s>>>((const double*)R, n, Np, ld, RC, x, dpart, nullptr);
   MINSR_CHECK_LAUNCH();
   const unsigned g1 = (unsigned)((Np + 255) / 256);
-  k_update_final<<<g1, 256, 0, s>>>(dpart, nrc, Np, eta, dtheta, status);
+  k_update_final<<<g1, 256, 0, s>>>(dpart, nrc, Np, eta, dtheta, status, bump);
   MINSR_CHECK_LAUNCH();
   if (apply) {
     k_apply<<<g1, 256, 0, s>>>(Np, dtheta, mu, momentum, theta, status);

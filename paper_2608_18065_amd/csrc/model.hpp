@@ -84,7 +84,8 @@ int launch_pack(minsr_model* m, hipStream_t s);
 int launch_forward(minsr_model* m, int mode, int Ns, const double* uniforms, uint64_t key,
                    uint64_t counter, uint8_t* sigma, double* logpsi, void* states,
                    int store_every, double* site, hipStream_t s,
-                   const uint64_t* counter_ptr = nullptr, void* gates = nullptr);
+                   const uint64_t* counter_ptr = nullptr, void* gates = nullptr,
+                   uint32_t* zero_word = nullptr);
 // which: 1 = off-diagonal terms (the recurrence), 2 = diagonal + sum, 3 = both
 int launch_eloc(minsr_model* m, const minsr_hamiltonian* H, int Ns, const uint8_t* sigma,
                 const double* logpsi, const void* states, const double* site, double* eloc,
@@ -132,7 +133,8 @@ int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* 
 size_t pinv_workspace_doubles(int nmax);
 int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, double eta,
                   double mu, double* dpart, double* dtheta, double* momentum, double* theta,
-                  uint32_t* status, int apply, hipStream_t s, const void* Rlo = nullptr);
+                  uint32_t* status, int apply, hipStream_t s, const void* Rlo = nullptr,
+                  uint64_t* bump = nullptr);
 int launch_reduce_rows(int rows, size_t Np, const double* part, double* out, hipStream_t s);
 
 }  // namespace minsr
