@@ -606,7 +606,15 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
           }
         }
       }
-      __syncthreads();
+      if constexpr (DIM == 1 && NW == 1) {
+        // a group's lanes lie in one wavefront: its new state in xin only has
+        // to be visible to that wavefront's next site
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {
+        __syncthreads();
+      }
       if (NW > 1) {
         const int w0 = g * NW;
 #pragma unroll
