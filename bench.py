@@ -45,8 +45,8 @@ TRAFFIC_BYTES = {
     # k_eloc_mfma_w: 9971.5 KiB fetched x 2.000 + 1379.9 KiB written x 1.000
     "eloc": 9971.5 * 1024 * 2.0 + 1379.9 * 1024,
     # k_jacobian (gate-tape path, gate adjoints stored per site) + k_jac_wgrad:
-    # (41331.7 + 33968.4) KiB fetched x 2.000 + (55328.0 + 50234.5) KiB written x 1.000
-    "jacobian": (41331.7 + 33968.4) * 1024 * 2.0 + (55328.0 + 50234.5) * 1024,
+    # (41331.7 + 34102.5) KiB fetched x 2.000 + (55328.0 + 50235.8) KiB written x 1.000
+    "jacobian": (41331.7 + 34102.5) * 1024 * 2.0 + (55328.0 + 50235.8) * 1024,
     # k_gram_bf16 (split form, four products, 7-way split-K, FP64 partial tiles):
     # 43368.0 KiB fetched x 2.000 + 32256.0 KiB written x 1.000
     "gram": 43368.0 * 1024 * 2.0 + 32256.0 * 1024}
