@@ -36,14 +36,19 @@ if ROOT not in sys.path:
 METRIC = ("minSR steps/sec at fixed ΔE/N; Jacobian GB/s & Gram MFMA util vs peak")
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
-PEAK_FP32_MFMA_TFLOPS = 157.3    # dense FP32 matrix cores (equal to the FP32 vector peak)
+PEAK_FP16_TFLOPS = 2500.0
+PEAK_FP64_TFLOPS = 78.6         # dense FP64 matrix cores (equal to the FP64 vector peak)
 
 # traffic measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE) per launch,
 # scaled by the counter's reading on a plain copy of known size; None until
 # taken for the current kernel version
 TRAFFIC_BYTES = {
-    # k_eloc_mfma_w: 9971.5 KiB fetched x 2.000 + 1379.9 KiB written x 1.000
-    "eloc": 9971.5 * 1024 * 2.0 + 1379.9 * 1024,
+    # k_eloc_mfma_w (FP16 hi/lo split products): 9969.5 KiB fetched x 2.000 +
+    # 1330.8 KiB written x 1.000
+    "eloc": 9969.5 * 1024 * 2.0 + 1330.8 * 1024,
+    # k_chol_prep + k_chol_persist_f64 + k_trsv_back_mt:
+    # (76.5 + 9014.4 + 2241.5) KiB fetched x 2.000 + (9.3 + 4692.5 + 9.0) KiB written
+    "solve": (76.5 + 9014.4 + 2241.5) * 1024 * 2.0 + (9.3 + 4692.5 + 9.0) * 1024,
     # k_jacobian (gate-tape path, gate adjoints stored per site) + k_jac_wgrad:
     # (41331.7 + 34102.5) KiB fetched x 2.000 + (55328.0 + 50235.8) KiB written x 1.000
     "jacobian": (41331.7 + 34102.5) * 1024 * 2.0 + (55328.0 + 50235.8) * 1024,
@@ -83,6 +88,8 @@ def work_units(wl):
         jacobian_bytes=Ns * Np * 4 + Ns * N * 5 * H * 4,
         # useful flops of the symmetric Gram: n (n + 1) Np
         gram_flop=Ns * (Ns + 1) * Np,
+        # Cholesky of the n x n system (n^3 / 3) and its two triangular solves
+        solve_flop=Ns ** 3 / 3 + 2 * Ns * Ns,
     )
 
 
@@ -228,10 +235,18 @@ def roofline_entry(name, ms, units):
         ach = units["jacobian_bytes"] / (ms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": TRAFFIC_BYTES["jacobian"], "ms": ms}
-    # FP32 models evaluate the recurrence on v_mfma_f32_32x32x2_f32
+    if name == "solve":
+        # FP64 factorisation on the FP64 matrix cores; a chain of dependent
+        # 64 x 64 blocks, so latency rather than throughput sets its time
+        ach = units["solve_flop"] / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64_TFLOPS, "traffic": TRAFFIC_BYTES["solve"], "ms": ms}
+    # FP32 models evaluate the gate products on v_mfma_f32_32x32x16_f16 as
+    # three FP16 hi/lo products; the algorithmic flops are those of one
+    # product, priced against the FP16 peak
     ach = units["eloc_flop"] / (ms * 1e-3) / 1e12
-    return {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": TRAFFIC_BYTES["eloc"], "ms": ms}
+    return {"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP16_TFLOPS, "traffic": TRAFFIC_BYTES["eloc"], "ms": ms}
 
 
 def main():
@@ -277,8 +292,8 @@ def main():
         mu_, se = tail_mean(E)
         return mu_ - wl.E0 / N, se
 
-    graded = {k: roofline_entry(k, ph[k], units) for k in ("eloc", "jacobian", "gram")}
-    dom = max(("sample", "eloc", "jacobian", "gram"), key=lambda k: ph[k])
+    graded = {k: roofline_entry(k, ph[k], units) for k in ("eloc", "jacobian", "gram", "solve")}
+    dom = max(("sample", "eloc", "jacobian", "gram", "solve"), key=lambda k: ph[k])
     roof = graded.get(dom) or graded["eloc"]
 
     forms = {"bf16_fp64": {"steps_per_s": value, "ms_per_step": ms_step,

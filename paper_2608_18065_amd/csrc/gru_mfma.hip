@@ -73,6 +73,24 @@ __device__ inline f32x16_m mfma_f32(float a, float b, f32x16_m c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8_m;
+
+__device__ inline f32x16_m mfma_f16(f16x8_m a, f16x8_m b, f32x16_m c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// x = hi + lo with hi = fp16(x) and lo = fp16(x - hi), both rounded to
+// nearest; x - hi is exact in FP32, so |x - hi - lo| <= 2^-22 |x| for x in
+// the normal FP16 range (smaller values keep an absolute error of 2^-25)
+__device__ inline void split_f16(const float (&x)[8], f16x8_m& hi, f16x8_m& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const _Float16 h = (_Float16)x[e];
+    hi[e] = h;
+    lo[e] = (_Float16)(x[e] - (float)h);
+  }
+}
+
 // One connected configuration being re-evaluated: sample s with the flips of
 // Hamiltonian term t (sites f1 and, for an exchange, f2p > f1), restarted at
 // site k0 = f1 from the stored hidden state of the unflipped prefix.
@@ -363,10 +381,17 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
 
 // 1D models, d_h <= 64: each wave re-evaluates its own item (32 connected
 // configurations that share their first flipped site) over all d_h units,
-// so a wave never waits for another between sites.  The workgroup's eight
-// waves share one copy of the B-operand fragments of W_u, W_r, W_h and of
-// the one-hot columns in shared memory (four K-steps per 16-byte read);
-// each wave keeps the 32 x d_h state of its sequences in its own buffer,
+// so a wave never waits for another between sites.  The state products run
+// on v_mfma_f32_32x32x16_f16 with every FP32 operand split into an FP16
+// pair x = x_hi + x_lo (both rounded to nearest): the three terms
+// a_hi b_hi + a_hi b_lo + a_lo b_hi, accumulated in FP32, represent each
+// operand to 2^-22 of its size (the omitted a_lo b_lo is below 2^-22 of
+// the product), against 2^-24 for FP32 operands, at 3/16 of the matrix-core
+// cycles of the FP32 product.  The one-hot input step stays an FP32 product
+// (its operand is exactly 0 or 1).  The workgroup's eight waves share one
+// copy of the split B-operand fragments of W_u, W_r, W_h and of the one-hot
+// columns in shared memory (eight input units per 16-byte read); each wave
+// keeps the 32 x d_h state of its sequences in its own buffer,
 // updated in place (a wave reads all of it into the matrix products before
 // it writes the new state).  Items are dealt by position p: even positions
 // take items from the front of the list (term t restarts at site t, so the
@@ -386,7 +411,8 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
   constexpr int KS = H / 2;
   constexpr int NCB = H / 32;              // 32-unit column blocks
   constexpr int NSTEP = 3 * KS + 3;
-  __shared__ __align__(16) float4 Bh[NCB][3][KS / 4][64];   // u, r, h: K-steps 4j..4j+3
+  constexpr int KJ = H / 16;               // K-steps of the FP16 products
+  __shared__ __align__(16) f16x8_m Bh[NCB][3][KJ][2][64];   // u, r, h: hi and lo parts
   __shared__ __align__(16) float Bx[NCB][3][64];            // one-hot step of u, r, input
   __shared__ __align__(16) float hS[EW_WAVES][S][HP];
   __shared__ __align__(16) float hw[4][H];
@@ -398,11 +424,21 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
   if (lane == 0) simd_of[w] = (int)(__builtin_amdgcn_s_getreg(HWREG_SIMD_ID) & 3);
   const int half = lane >> 5, col = lane & 31;
   const int N = a.N;
-  for (int i = tid; i < NCB * 3 * KS * 64; i += 64 * EW_WAVES) {
-    const int l = i % 64, st = (i / 64) % KS, g = (i / (64 * KS)) % 3, cb = i / (64 * KS * 3);
-    const float* base = a.mw + (size_t)cb * NSTEP * 64 + l;
+  // B fragment of K-step j, lane l = n + 32 c, element e: input unit
+  // u = 16 j + 8 c + e, output unit 32 cb + n.  In the packed FP32 layout
+  // that entry sits at K-step u % KS in lane n + 32 (u / KS).
+  for (int i = tid; i < NCB * 3 * KJ * 64; i += 64 * EW_WAVES) {
+    const int l = i % 64, j = (i / 64) % KJ, g = (i / (64 * KJ)) % 3, cb = i / (64 * KJ * 3);
+    const int n = l & 31, c = l >> 5;
+    const float* base = a.mw + (size_t)cb * NSTEP * 64 + n;
     const int off = g == 0 ? 0 : g == 1 ? KS + 1 : 2 * (KS + 1);
-    reinterpret_cast<float*>(&Bh[cb][g][st / 4][l])[st % 4] = base[(size_t)(off + st) * 64];
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int u = 16 * j + 8 * c + e;
+      x[e] = base[(size_t)(off + u % KS) * 64 + 32 * (u / KS)];
+    }
+    split_f16(x, Bh[cb][g][j][0][l], Bh[cb][g][j][1][l]);
   }
   for (int i = tid; i < NCB * 3 * 64; i += 64 * EW_WAVES) {
     const int l = i % 64, g = (i / 64) % 3, cb = i / (64 * 3);
@@ -452,17 +488,21 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
         for (int q = 0; q < 16; ++q) { au[cb][q] = 0.f; ar[cb][q] = 0.f; ag[cb][q] = g0; ai[cb][q] = 0.f; }
       }
 #pragma unroll
-      for (int s4 = 0; s4 < KS; s4 += 4) {
-        const float4 av = *reinterpret_cast<const float4*>(&hA[col][s4 + half * KS]);
+      for (int j = 0; j < KJ; ++j) {
+        // A fragment: sequence col, input units 16 j + 8 half .. + 7
+        const float4 x0 = *reinterpret_cast<const float4*>(&hA[col][16 * j + 8 * half]);
+        const float4 x1 = *reinterpret_cast<const float4*>(&hA[col][16 * j + 8 * half + 4]);
+        const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        f16x8_m ahi, alo;
+        split_f16(x, ahi, alo);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
-          const float4 bu = Bh[cb][0][s4 / 4][lane];
-          const float4 br = Bh[cb][1][s4 / 4][lane];
-          const float4 bg = Bh[cb][2][s4 / 4][lane];
-          au[cb] = mfma_f32(av.x, bu.x, au[cb]); ar[cb] = mfma_f32(av.x, br.x, ar[cb]); ag[cb] = mfma_f32(av.x, bg.x, ag[cb]);
-          au[cb] = mfma_f32(av.y, bu.y, au[cb]); ar[cb] = mfma_f32(av.y, br.y, ar[cb]); ag[cb] = mfma_f32(av.y, bg.y, ag[cb]);
-          au[cb] = mfma_f32(av.z, bu.z, au[cb]); ar[cb] = mfma_f32(av.z, br.z, ar[cb]); ag[cb] = mfma_f32(av.z, bg.z, ag[cb]);
-          au[cb] = mfma_f32(av.w, bu.w, au[cb]); ar[cb] = mfma_f32(av.w, br.w, ar[cb]); ag[cb] = mfma_f32(av.w, bg.w, ag[cb]);
+          const f16x8_m uh = Bh[cb][0][j][0][lane], ul = Bh[cb][0][j][1][lane];
+          const f16x8_m rh = Bh[cb][1][j][0][lane], rl = Bh[cb][1][j][1][lane];
+          const f16x8_m gh = Bh[cb][2][j][0][lane], gl = Bh[cb][2][j][1][lane];
+          au[cb] = mfma_f16(alo, uh, au[cb]); ar[cb] = mfma_f16(alo, rh, ar[cb]); ag[cb] = mfma_f16(alo, gh, ag[cb]);
+          au[cb] = mfma_f16(ahi, ul, au[cb]); ar[cb] = mfma_f16(ahi, rl, ar[cb]); ag[cb] = mfma_f16(ahi, gl, ag[cb]);
+          au[cb] = mfma_f16(ahi, uh, au[cb]); ar[cb] = mfma_f16(ahi, rh, ar[cb]); ag[cb] = mfma_f16(ahi, gh, ag[cb]);
         }
       }
       {
