@@ -340,14 +340,16 @@ int minsr_jacobian(minsr_model* m, int Ns, const uint8_t* dev_sigma, int out_dty
   if (centered && !dev_colmean) return fail(MINSR_E_INVALID_ARG, "centred output needs dev_colmean");
   const int C = m->dim == 1 ? ckpt_every : 1;
   void* tape = C == 1 ? m->gates : nullptr;
+  double* site = m->site;   // the pass's per-site conditionals
   rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
-                      m->states, C, nullptr, s, nullptr, tape);
+                      m->states, C, site, s, nullptr, tape);
   if (rc) return rc;
   const int native = m->f64 ? MINSR_F64 : MINSR_F32;
   const int nb = m->cplx ? 2 : 1;
   if (!centered && out_dtype == native)
-    return launch_jacobian(m, Ns, dev_sigma, m->states, C, dev_O, nullptr, nullptr, s, tape);
-  rc = launch_jacobian(m, Ns, dev_sigma, m->states, C, m->O, nullptr, nullptr, s, tape);
+    return launch_jacobian(m, Ns, dev_sigma, m->states, C, dev_O, nullptr, nullptr, s, tape,
+                           site);
+  rc = launch_jacobian(m, Ns, dev_sigma, m->states, C, m->O, nullptr, nullptr, s, tape, site);
   if (rc) return rc;
   return launch_center(Ns, nb, m->L.Np, m->O, m->f64, dev_O, out_dtype, m->colpart,
                        centered ? dev_colmean : nullptr, m->L.Np, s);
@@ -363,9 +365,10 @@ int minsr_logpsi_vjp(minsr_model* m, int Ns, const uint8_t* dev_sigma, const dou
     return MINSR_OK;
   }
   rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
-                      m->states, 1, nullptr, s, nullptr, m->gates);
+                      m->states, 1, m->site, s, nullptr, m->gates);
   if (rc) return rc;
-  rc = launch_jacobian(m, Ns, dev_sigma, m->states, 1, m->O, nullptr, nullptr, s, m->gates);
+  rc = launch_jacobian(m, Ns, dev_sigma, m->states, 1, m->O, nullptr, nullptr, s, m->gates,
+                       m->site);
   if (rc) return rc;
   const size_t Np = m->L.Np;
   const double scale = std::sqrt((double)Ns);
@@ -437,7 +440,7 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   MINSR_PHASE(3);
   // 3. log-derivatives, centring and real form
   rc = launch_jacobian(m, Ns, sigma, m->states, C, m->O, nullptr, nullptr, s,
-                       C == 1 ? m->gates : nullptr);
+                       C == 1 ? m->gates : nullptr, m->site);
   if (rc) return rc;
   MINSR_PHASE(4);
   rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, padded_ld(Np), s,

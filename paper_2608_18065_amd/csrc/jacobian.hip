@@ -43,6 +43,9 @@ template <typename T> struct JacArgs {
   const T* states;       // [Ns][N][H]; 1D: rows k with (k+1) % C == 0 are read
   const T* gates;        // 1D, C == 1, optional: [Ns][N][4][H] u, r, g, ht of the sampler
   T* dp;                 // deferred gradients: [nseeds][Ns][N][3][H] gate adjoints
+  const double* site;    // 1D real FP32 models, optional: [Ns][N][4] the
+                         // forward pass's log p(0), log p(1) per site (the head's
+                         // conditionals, masked as in sampling)
   T* O;                  // [rows][Np]
   T scale;               // 1 / sqrt(Ns)
   int W2;                // 2D adjoint window
@@ -238,10 +241,15 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
     const bool tape = DIM == 1 && a.gates != nullptr;
     const T* gt = tape ? a.gates + (size_t)sid * N * 4 * H : nullptr;
     T gnx[4] = {(T)0, (T)0, (T)0, (T)0}, hnx = (T)0;
+    // the head's conditionals of the same pass: no reductions over the units
+    const bool hsite = DIM == 1 && a.site != nullptr && seed == 0;
+    const double* sit = hsite ? a.site + (size_t)sid * N * 4 : nullptr;
+    double lsn0 = 0.0, lsn1 = 0.0;
     auto tape_fetch = [&](int k) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) gnx[q] = gt[((size_t)k * 4 + q) * H + j];
       hnx = st[(size_t)k * H + j];
+      if (hsite) { lsn0 = sit[4 * k]; lsn1 = sit[4 * k + 1]; }
     };
     if (tape) tape_fetch(N - 1);
     for (int segi = nseg - 1; segi >= 0; --segi) {
@@ -251,6 +259,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
       if (DIM == 1 && p == 0) hnext = ckpt(segi - 1);
       T gcur[4] = {gnx[0], gnx[1], gnx[2], gnx[3]};
       const T hcur = hnx;
+      const double lsc0 = lsn0, lsc1 = lsn1;
       if (tape && segi > 0) tape_fetch(segi - 1);
 
       // zero-magnetisation counts of sigma_{<ks}
@@ -300,10 +309,12 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
             ht = j_tanh(rr * ag + ai);
             hn = ((T)1 - u) * hprev + u * ht;
           }
-          T z0 = JReduce<H>::run(U0 * hn), z1 = JReduce<H>::run(U1v * hn);
-          T q0 = (T)0, q1 = (T)0;
-          if (a.cplx) { q0 = JReduce<H>::run(P0 * hn); q1 = JReduce<H>::run(P1 * hn); }
-          if (NW > 1) {
+          T z0 = (T)0, z1 = (T)0, q0 = (T)0, q1 = (T)0;
+          if (!hsite) {
+            z0 = JReduce<H>::run(U0 * hn); z1 = JReduce<H>::run(U1v * hn);
+            if (a.cplx) { q0 = JReduce<H>::run(P0 * hn); q1 = JReduce<H>::run(P1 * hn); }
+          }
+          if (NW > 1 && !hsite) {
             if ((tid & 63) == 0) { red[wave][0] = z0; red[wave][1] = z1; red[wave][2] = q0; red[wave][3] = q1; }
           }
           if (p == 0) {
@@ -312,13 +323,13 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
             town[sg][kk][2][j] = ag; town[sg][kk][3][j] = ht;
           }
           __syncthreads();
-          if (NW > 1) {
+          if (NW > 1 && !hsite) {
             const int w0 = (tid / H) * NW;   // first wave of this p-subgroup
             T s0 = red[w0][0], s1 = red[w0][1], s2 = red[w0][2], s3 = red[w0][3];
             for (int i = 1; i < NW; ++i) { s0 += red[w0 + i][0]; s1 += red[w0 + i][1]; s2 += red[w0 + i][2]; s3 += red[w0 + i][3]; }
             z0 = s0; z1 = s1; q0 = s2; q1 = s3;
           }
-          if (j == 0 && p == 0) {
+          if (j == 0 && p == 0 && !hsite) {
             const T zz0 = z0 + c0, zz1 = z1 + c1;
             const T mx = zz0 > zz1 ? zz0 : zz1;
             const T d = zz0 > zz1 ? zz1 - zz0 : zz0 - zz1;
@@ -444,8 +455,16 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
         T dz0, dz1;
         T dh;
         if (seed == 0) {
-          dz0 = (T)0.5 * ((sk == 0 ? (T)1 : (T)0) - thead[sg][kt][0]);
-          dz1 = (T)0.5 * ((sk == 1 ? (T)1 : (T)0) - thead[sg][kt][1]);
+          T hp0, hp1;
+          if (hsite) {
+            hp0 = j_exp((T)(tape ? lsc0 : sit[4 * k]));
+            hp1 = j_exp((T)(tape ? lsc1 : sit[4 * k + 1]));
+          } else {
+            hp0 = thead[sg][kt][0];
+            hp1 = thead[sg][kt][1];
+          }
+          dz0 = (T)0.5 * ((sk == 0 ? (T)1 : (T)0) - hp0);
+          dz1 = (T)0.5 * ((sk == 1 ? (T)1 : (T)0) - hp1);
           dh = dz0 * U0 + dz1 * U1v;
         } else {
           const T a0 = thead[sg][kt][2], a1 = thead[sg][kt][3];
@@ -720,7 +739,8 @@ static int jac_dispatch(int H, int parts, const JacArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 static int jac_t(minsr_model* m, const Work<T>& w, int Ns, const uint8_t* sigma,
-                 const void* states, int C, void* O, const void* gates, hipStream_t s) {
+                 const void* states, int C, void* O, const void* gates, const double* site,
+                 hipStream_t s) {
   JacArgs<T> a{};
   a.w = w; a.L = m->L; a.N = m->N; a.Ns = Ns; a.C = C;
   a.zero_mag = m->d.zero_mag; a.cplx = m->cplx; a.nbr = m->nbr;
@@ -728,6 +748,7 @@ static int jac_t(minsr_model* m, const Work<T>& w, int Ns, const uint8_t* sigma,
   a.gates = (m->dim == 1 && C == 1) ? (const T*)gates : nullptr;
   // deferred weight gradients with the tape (FP32, 1D, d_h 32 or 64)
   a.dp = (a.gates && m->jdp && (m->H == 32 || m->H == 64)) ? (T*)m->jdp : nullptr;
+  a.site = (m->dim == 1 && !m->cplx && sizeof(T) == 4) ? site : nullptr;
   a.scale = (T)(1.0 / std::sqrt((double)Ns));
   a.W2 = 2 * m->d.Lx;
   if (m->dim == 1) return jac_dispatch<T, 1>(m->H, m->tune_jac_parts, a, s);
@@ -736,14 +757,14 @@ static int jac_t(minsr_model* m, const Work<T>& w, int Ns, const uint8_t* sigma,
 
 int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* states,
                     int ckpt_every, void* O, const double* g, double* vjp_part, hipStream_t s,
-                    const void* gates) {
+                    const void* gates, const double* site) {
   (void)g; (void)vjp_part;
   if (Ns == 0) return MINSR_OK;
   if (m->dim == 2 && 2 * m->d.Lx > 32) return fail(MINSR_E_UNSUPPORTED, "2D lattices need Lx <= 16");
   if (ckpt_every < 1 || ckpt_every > SEGMAX)
     return fail(MINSR_E_INVALID_ARG, "ckpt_every must be in [1, 16]");
-  if (m->f64) return jac_t<double>(m, m->wd, Ns, sigma, states, ckpt_every, O, gates, s);
-  return jac_t<float>(m, m->wf, Ns, sigma, states, ckpt_every, O, gates, s);
+  if (m->f64) return jac_t<double>(m, m->wd, Ns, sigma, states, ckpt_every, O, gates, site, s);
+  return jac_t<float>(m, m->wf, Ns, sigma, states, ckpt_every, O, gates, site, s);
 }
 
 }  // namespace minsr

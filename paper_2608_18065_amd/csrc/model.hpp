@@ -101,7 +101,8 @@ int launch_eloc_mfma(minsr_model* m, const minsr_hamiltonian* H, int Ns, const u
 // (used with ckpt_every == 1 only; may be null)
 int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* states,
                     int ckpt_every, void* O, const double* g, double* vjp_part,
-                    hipStream_t s, const void* gates = nullptr);
+                    hipStream_t s, const void* gates = nullptr,
+                    const double* site = nullptr);
 // linalg.hip
 // centred (colmean != null) or plain copy of O into R with row stride ldo
 // (ldo >= Np; columns Np..ldo-1 are written as zeros)
