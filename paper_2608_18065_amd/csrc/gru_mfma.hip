@@ -74,6 +74,8 @@ __device__ inline f32x16_m mfma_f32(float a, float b, f32x16_m c) {
 }
 
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8_m;
+typedef __attribute__((ext_vector_type(2))) _Float16 f16x2_m;
+typedef __attribute__((ext_vector_type(2))) float f32x2_m;
 
 __device__ inline f32x16_m mfma_f16(f16x8_m a, f16x8_m b, f32x16_m c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -84,10 +86,12 @@ __device__ inline f32x16_m mfma_f16(f16x8_m a, f16x8_m b, f32x16_m c) {
 // the normal FP16 range (smaller values keep an absolute error of 2^-25)
 __device__ inline void split_f16(const float (&x)[8], f16x8_m& hi, f16x8_m& lo) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const _Float16 h = (_Float16)x[e];
-    hi[e] = h;
-    lo[e] = (_Float16)(x[e] - (float)h);
+  for (int e = 0; e < 8; e += 2) {   // pairs: one packed conversion each way
+    const f32x2_m v = {x[e], x[e + 1]};
+    const f16x2_m h = __builtin_convertvector(v, f16x2_m);
+    const f16x2_m l = __builtin_convertvector(v - __builtin_convertvector(h, f32x2_m), f16x2_m);
+    hi[e] = h[0]; hi[e + 1] = h[1];
+    lo[e] = l[0]; lo[e + 1] = l[1];
   }
 }
 

@@ -1306,13 +1306,20 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
 // is set, workgroup 0 also writes lambda_eff = max(lambda, rel * max_i T_ii):
 // the shift never falls below the accuracy to which a low-precision Gram is
 // computed
+// x entries not yet computed by the backward substitution hold a signalling
+// NaN: arithmetic only ever yields quiet NaNs, so no computed x equals it,
+// and a waiting workgroup polls the entries themselves (one round trip for
+// flag and data)
+constexpr uint64_t X_UNSET = 0x7FF40000DEAD0001ull;
+
 template <typename TT>
 __global__ __launch_bounds__(256) void k_chol_prep(uint32_t* sync, int nsync, const double* b,
                                                    TT* y, int n, const double* T, double lambda,
-                                                   double rel, double* lam_out) {
+                                                   double rel, double* lam_out, uint64_t* xmark) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nsync) sync[i] = 0u;
   if (i < n) y[i] = (TT)b[i];
+  if (i < n) xmark[i] = X_UNSET;
   if (lam_out && blockIdx.x == 0) {
     __shared__ double red[256];
     double mx = 0.0;
@@ -1333,7 +1340,8 @@ __global__ __launch_bounds__(256) void k_chol_prep(uint32_t* sync, int nsync, co
 // for blocks whose workgroups started before it.  It keeps inv(L_kk) in
 // shared memory, adds the products L_jk^T x_j for j = nblk-1 down to k+1 in
 // that fixed order as the x_j are published (the tile of the next j is
-// requested before waiting), then publishes x_k through its flag.
+// requested before waiting), then publishes x_k: its entries are stored
+// atomically over the unset marks the waiting workgroups poll.
 template <typename TT>
 __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const TT* Dinv,
                                                       const TT* y, double* x, uint32_t* bsync,
@@ -1343,8 +1351,7 @@ __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const 
   __shared__ TT part[4][CB];
   __shared__ TT rb[CB];
   __shared__ int tk;
-  uint32_t* ticket_ctr = bsync;                      // then one flag per block
-  uint32_t* bflags = bsync + 1;
+  uint32_t* ticket_ctr = bsync;
   const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
   if (tid == 0)
     tk = (int)__hip_atomic_fetch_add(ticket_ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1372,13 +1379,17 @@ __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const 
   };
   if (kb + 1 < nblk) fetch(nblk - 1);
   for (int j = nblk - 1; j > kb; --j) {
-    if (tid == 0) {
-      while (__hip_atomic_load(&bflags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-        __builtin_amdgcn_s_sleep(1);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (tid < CB) {
+      TT v = (TT)0;
+      if (j * CB + tid < n) {
+        const uint64_t* xp = reinterpret_cast<const uint64_t*>(x) + j * CB + tid;
+        uint64_t bits;
+        while ((bits = __hip_atomic_load(xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == X_UNSET)
+          __builtin_amdgcn_s_sleep(1);
+        v = (TT)__longlong_as_double((long long)bits);
+      }
+      xj[tid] = v;
     }
-    __syncthreads();
-    if (tid < CB) xj[tid] = j * CB + tid < n ? (TT)x[j * CB + tid] : (TT)0;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc = fma(l[u], xj[16 * g + u], acc);
@@ -1409,12 +1420,10 @@ __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const 
     for (int u = 0; u < CB / 4; ++u) v = fma(cc + sb + 4 * u < nb ? dv[u] : (TT)0, rv[u], v);
     v += __shfl_xor(v, 1, 4);
     v += __shfl_xor(v, 2, 4);
-    if (sb == 0 && cc < nb) x[k0 + cc] = (double)v;
-  }
-  if (kb > 0) {
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&bflags[kb], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (sb == 0 && cc < nb)
+      __hip_atomic_store(reinterpret_cast<uint64_t*>(x) + k0 + cc,
+                         (uint64_t)__double_as_longlong((double)v), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1454,7 +1463,8 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
     }
   }
   k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n, Tfloor, lambda,
-                                                  lam_floor_rel, lam_slot);
+                                                  lam_floor_rel, lam_slot,
+                                                  reinterpret_cast<uint64_t*>(x));
   MINSR_CHECK_LAUNCH();
   if constexpr (std::is_same<TT, double>::value) {
     k_chol_persist_f64<<<1 + nblk * (nblk - 1) / 2, 256, 0, s>>>(a, sync + chol_sync_one(nblk),
