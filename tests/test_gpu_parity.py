@@ -359,6 +359,8 @@ def test_step_full_size_tfim64(form, tol):
 HAMS32 = [
     (dict(Lx=12, H=32), oham.Ham("tfim", J=1.0, h=0.9, pbc=True)),
     (dict(Lx=16, H=64), oham.Ham("tfim", J=1.0, h=1.0, pbc=True)),
+    # the benchmark's chain length: items restart at every site of 64
+    (dict(Lx=64, H=64), oham.Ham("tfim", J=1.0, h=1.0, pbc=True)),
     (dict(Lx=9, H=128, cplx=True), oham.Ham("cluster")),
     (dict(Lx=4, Ly=3, dim=2, H=32, marshall=True, zero_mag=True), oham.Ham("j1j2", J=1.0)),
     (dict(Lx=3, Ly=4, dim=2, H=64, cplx=True, marshall=True), oham.Ham("j1j2", J=1.0, J2=0.5)),
