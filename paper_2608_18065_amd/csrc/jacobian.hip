@@ -198,6 +198,18 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
     }
   }
   auto spin = [&](int q) -> int { return N <= 64 ? (int)((smask >> q) & 1u) : (int)sig[q]; };
+  // the per-site exchanges go through shared memory only; a workgroup of one
+  // wave orders them with a wavefront fence, which (unlike a workgroup
+  // barrier) does not also wait for its outstanding global loads and stores
+  auto site_sync = [&]() {
+    if constexpr (NT == 64) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  };
 
   const T bu = w.bias[j], br = w.bias[H + j], bh = w.bias[2 * H + j], bi = w.bias[3 * H + j];
   const T U0 = w.head[j], U1v = w.head[H + j];
@@ -270,7 +282,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
       if (DIM == 1) {
         // ---- forward recompute of the segment from its checkpoint
         if (p == 0) tx[sg][0][j] = hck;
-        __syncthreads();
+        site_sync();
         for (int kk = 0; kk < len; ++kk) {
           const int k = ks + kk;
           T u, rr, ag, ht, hn;
@@ -322,7 +334,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
             town[sg][kk][0][j] = u; town[sg][kk][1][j] = rr;
             town[sg][kk][2][j] = ag; town[sg][kk][3][j] = ht;
           }
-          __syncthreads();
+          site_sync();
           if (NW > 1 && !hsite) {
             const int w0 = (tid / H) * NW;   // first wave of this p-subgroup
             T s0 = red[w0][0], s1 = red[w0][1], s2 = red[w0][2], s3 = red[w0][3];
@@ -345,7 +357,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
           nup += spin(k) == 0; ndn += spin(k) == 1;
           if (NW > 1) __syncthreads();
         }
-        __syncthreads();
+        site_sync();
       }
 
       // ---- reverse through the segment
@@ -519,7 +531,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
             }
           }
         }
-        __syncthreads();
+        site_sync();
         // reverse product into the cell input: rows i of part p; four
         // partial sums so that several weight loads are in flight
         T partv[4] = {(T)0, (T)0, (T)0, (T)0};
@@ -608,7 +620,7 @@ __global__ __launch_bounds__((JShape<H, P, WL>::NT)) void k_jacobian(JacArgs<T> 
             if (kv >= 0) dacc[sg][kv % a.W2][j] += dhv;
           }
         }
-        __syncthreads();
+        site_sync();
       }
     }
 
