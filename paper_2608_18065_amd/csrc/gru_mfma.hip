@@ -423,11 +423,30 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
   __shared__ float hb[4];
   __shared__ float bgs_s[H];
   __shared__ int simd_of[EW_WAVES];
+  __shared__ unsigned wmax_bits;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (lane == 0) simd_of[w] = (int)(__builtin_amdgcn_s_getreg(HWREG_SIMD_ID) & 3);
   const int half = lane >> 5, col = lane & 31;
   const int N = a.N;
+  // FP16 holds magnitudes below 65504 (the state lies in [-1, 1]): when
+  // some weight reaches 2^14, all are staged as w 2^-s and the state
+  // products scaled back by 2^s, both exact powers of two
+  if (tid == 0) wmax_bits = 0u;
+  __syncthreads();
+  {
+    float mx = 0.f;
+    for (int i = tid; i < NCB * 3 * KS * 64; i += 64 * EW_WAVES) {
+      const int l = i % 64, st = (i / 64) % KS, g = (i / (64 * KS)) % 3, cb = i / (64 * KS * 3);
+      const int off = g == 0 ? 0 : g == 1 ? KS + 1 : 2 * (KS + 1);
+      mx = fmaxf(mx, fabsf(a.mw[(size_t)cb * NSTEP * 64 + (size_t)(off + st) * 64 + l]));
+    }
+    atomicMax(&wmax_bits, __float_as_uint(mx));   // non-negative floats order as their bits
+  }
+  __syncthreads();
+  const float wmax = __uint_as_float(wmax_bits);
+  const int sexp = wmax >= 16384.f ? min(ilogbf(wmax) - 13, 120) : 0;
+  const float sc_dn = ldexpf(1.f, -sexp), sc_up = ldexpf(1.f, sexp);
   // B fragment of K-step j, lane l = n + 32 c, element e: input unit
   // u = 16 j + 8 c + e, output unit 32 cb + n.  In the packed FP32 layout
   // that entry sits at K-step u % KS in lane n + 32 (u / KS).
@@ -440,7 +459,7 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int u = 16 * j + 8 * c + e;
-      x[e] = base[(size_t)(off + u % KS) * 64 + 32 * (u / KS)];
+      x[e] = base[(size_t)(off + u % KS) * 64 + 32 * (u / KS)] * sc_dn;
     }
     split_f16(x, Bh[cb][g][j][0][l], Bh[cb][g][j][1][l]);
   }
@@ -487,7 +506,7 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
       f32x16_m au[NCB], ar[NCB], ag[NCB], ai[NCB];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
-        const float g0 = bgs_s[32 * cb + col];
+        const float g0 = bgs_s[32 * cb + col] * sc_dn;
 #pragma unroll
         for (int q = 0; q < 16; ++q) { au[cb][q] = 0.f; ar[cb][q] = 0.f; ag[cb][q] = g0; ai[cb][q] = 0.f; }
       }
@@ -508,6 +527,12 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
           au[cb] = mfma_f16(ahi, ul, au[cb]); ar[cb] = mfma_f16(ahi, rl, ar[cb]); ag[cb] = mfma_f16(ahi, gl, ag[cb]);
           au[cb] = mfma_f16(ahi, uh, au[cb]); ar[cb] = mfma_f16(ahi, rh, ar[cb]); ag[cb] = mfma_f16(ahi, gh, ag[cb]);
         }
+      }
+      if (sexp) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) { au[cb][q] *= sc_up; ar[cb][q] *= sc_up; ag[cb][q] *= sc_up; }
       }
       {
         const float o = e.sprev == half ? 1.f : 0.f;

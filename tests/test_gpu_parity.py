@@ -384,6 +384,32 @@ def test_local_energy_fp32_model(arch, ham):
     assert rel_err(eloc.cpu().numpy(), ref) < 2e-4
 
 
+def test_local_energy_fp32_large_weights():
+    # gate weights beyond the FP16 range of the split state products (the
+    # kernel stages them scaled by a power of two): finite local energies
+    # within the FP32 bound of the FP64 oracle
+    spec, m = make_pair(Lx=16, H=64, dtype="f32")
+    th = scaled_theta(spec, 15, 1.0)
+    off = 0
+    for name, shape in omodel.layout(spec):
+        n = int(np.prod(shape))
+        if name in ("Wu", "Wr", "Wh"):
+            blk = th[off:off + n].reshape(shape)
+            blk[3, 5] = 1.0e5
+            blk[7, 1] = -4.0e4
+        off += n
+    m.set_params(to_dev(th))
+    ham = oham.Ham("tfim", J=1.0, h=1.0, pbc=True)
+    Ns = 45
+    sig, lp = omodel.sample(spec, th, philox.uniforms(79, 2, Ns, spec.N))
+    ref = oham.local_energy(spec, th, ham, sig, lp)
+    lp32 = m.logpsi(to_dev(sig.astype(np.uint8)))
+    eloc, _ = m.local_energy(_gpu_ham(ham), to_dev(sig.astype(np.uint8)), lp32)
+    eloc = eloc.cpu().numpy()
+    assert np.all(np.isfinite(eloc))
+    assert rel_err(eloc, ref) < 2e-4
+
+
 @pytest.mark.parametrize("arch", [dict(Lx=14, H=64), dict(Lx=9, H=128, cplx=True),
                                   dict(Lx=4, Ly=3, dim=2, H=64, marshall=True)], ids=_ids)
 def test_jacobian_fp32_model(arch):
