@@ -20,6 +20,8 @@
 // so that each nonlinearity is one hardware exp2 and one reciprocal.
 // 2D models form h' = U1 h_horizontal + U2 h_vertical with one more MFMA
 // product per site (B fragments streamed from L2) before the cell.
+#include <type_traits>
+
 #include "model.hpp"
 
 namespace minsr {
@@ -430,39 +432,33 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
   const int half = lane >> 5, col = lane & 31;
   const int N = a.N;
   // FP16 holds magnitudes below 65504 (the state lies in [-1, 1]): when
-  // some weight reaches 2^14, all are staged as w 2^-s and the state
+  // some weight reaches 2^14, all are staged again as w 2^-s and the state
   // products scaled back by 2^s, both exact powers of two
   if (tid == 0) wmax_bits = 0u;
   __syncthreads();
-  {
-    float mx = 0.f;
-    for (int i = tid; i < NCB * 3 * KS * 64; i += 64 * EW_WAVES) {
-      const int l = i % 64, st = (i / 64) % KS, g = (i / (64 * KS)) % 3, cb = i / (64 * KS * 3);
-      const int off = g == 0 ? 0 : g == 1 ? KS + 1 : 2 * (KS + 1);
-      mx = fmaxf(mx, fabsf(a.mw[(size_t)cb * NSTEP * 64 + (size_t)(off + st) * 64 + l]));
-    }
-    atomicMax(&wmax_bits, __float_as_uint(mx));   // non-negative floats order as their bits
-  }
-  __syncthreads();
-  const float wmax = __uint_as_float(wmax_bits);
-  const int sexp = wmax >= 16384.f ? min(ilogbf(wmax) - 13, 120) : 0;
-  const float sc_dn = ldexpf(1.f, -sexp), sc_up = ldexpf(1.f, sexp);
   // B fragment of K-step j, lane l = n + 32 c, element e: input unit
   // u = 16 j + 8 c + e, output unit 32 cb + n.  In the packed FP32 layout
   // that entry sits at K-step u % KS in lane n + 32 (u / KS).
-  for (int i = tid; i < NCB * 3 * KJ * 64; i += 64 * EW_WAVES) {
-    const int l = i % 64, j = (i / 64) % KJ, g = (i / (64 * KJ)) % 3, cb = i / (64 * KJ * 3);
-    const int n = l & 31, c = l >> 5;
-    const float* base = a.mw + (size_t)cb * NSTEP * 64 + n;
-    const int off = g == 0 ? 0 : g == 1 ? KS + 1 : 2 * (KS + 1);
-    float x[8];
+  auto stage = [&](float sc) -> float {
+    float mx = 0.f;
+    for (int i = tid; i < NCB * 3 * KJ * 64; i += 64 * EW_WAVES) {
+      const int l = i % 64, j = (i / 64) % KJ, g = (i / (64 * KJ)) % 3, cb = i / (64 * KJ * 3);
+      const int n = l & 31, c = l >> 5;
+      const float* base = a.mw + (size_t)cb * NSTEP * 64 + n;
+      const int off = g == 0 ? 0 : g == 1 ? KS + 1 : 2 * (KS + 1);
+      float x[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int u = 16 * j + 8 * c + e;
-      x[e] = base[(size_t)(off + u % KS) * 64 + 32 * (u / KS)] * sc_dn;
+      for (int e = 0; e < 8; ++e) {
+        const int u = 16 * j + 8 * c + e;
+        x[e] = base[(size_t)(off + u % KS) * 64 + 32 * (u / KS)];
+        mx = fmaxf(mx, fabsf(x[e]));
+        x[e] *= sc;
+      }
+      split_f16(x, Bh[cb][g][j][0][l], Bh[cb][g][j][1][l]);
     }
-    split_f16(x, Bh[cb][g][j][0][l], Bh[cb][g][j][1][l]);
-  }
+    return mx;
+  };
+  atomicMax(&wmax_bits, __float_as_uint(stage(1.f)));   // non-negative floats order as their bits
   for (int i = tid; i < NCB * 3 * 64; i += 64 * EW_WAVES) {
     const int l = i % 64, g = (i / 64) % 3, cb = i / (64 * 3);
     const float* base = a.mw + (size_t)cb * NSTEP * 64 + l;
@@ -473,6 +469,13 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
   for (int i = tid; i < H; i += 64 * EW_WAVES) bgs_s[i] = (float)(2.8853900817779268 * (double)a.bias[2 * H + i]);
   if (tid < 4) hb[tid] = a.headb[tid];
   __syncthreads();
+  const float wmax = __uint_as_float(wmax_bits);
+  const int sexp = wmax >= 16384.f ? min(ilogbf(wmax) - 13, 120) : 0;
+  const float sc_dn = ldexpf(1.f, -sexp), sc_up = ldexpf(1.f, sexp);
+  if (sexp) {
+    stage(sc_dn);
+    __syncthreads();
+  }
 
   float (*hA)[HP] = hS[w];
   // the wave's own shared-memory writes visible to all its lanes
@@ -490,6 +493,9 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
     for (int v = 0; v < EW_WAVES; ++v) rank += simd_of[v] < me || (simd_of[v] == me && v < w);
   }
   const int first_round = (int)gridDim.x * EW_WAVES;
+  // the site loop is instantiated with and without the weight scaling, so
+  // the unscaled case carries no branch between its products
+  auto items = [&](auto scaled) {
   for (int p = (int)blockIdx.x * EW_WAVES + rank; p < n_items;) {
     const int item = (p & 1) ? n_items - 1 - (p >> 1) : (p >> 1);
     ElocSeq e = eloc_begin(a, item, col);
@@ -528,7 +534,7 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
           au[cb] = mfma_f16(ahi, uh, au[cb]); ar[cb] = mfma_f16(ahi, rh, ar[cb]); ag[cb] = mfma_f16(ahi, gh, ag[cb]);
         }
       }
-      if (sexp) {
+      if constexpr (decltype(scaled)::value) {
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -568,6 +574,9 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
     if (lane == 0) next = (int)atomicAdd(&queue[0], 1u);
     p = first_round + __builtin_amdgcn_readfirstlane(next);
   }
+  };
+  if (sexp) items(std::true_type{});
+  else items(std::false_type{});
   // the last wave out resets the counter for the next launch
   if (lane == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
