@@ -43,18 +43,18 @@ PEAK_FP64_TFLOPS = 78.6         # dense FP64 matrix cores (equal to the FP64 vec
 # scaled by the counter's reading on a plain copy of known size; None until
 # taken for the current kernel version
 TRAFFIC_BYTES = {
-    # k_eloc_mfma_w (FP16 hi/lo split products): 9969.5 KiB fetched x 2.000 +
-    # 1330.8 KiB written x 1.000
-    "eloc": 9969.5 * 1024 * 2.0 + 1330.8 * 1024,
+    # k_eloc_mfma_w (FP16 hi/lo split products): 9984.8 KiB fetched x 2.000 +
+    # 1353.5 KiB written x 1.000
+    "eloc": 9984.8 * 1024 * 2.0 + 1353.5 * 1024,
     # k_chol_prep + k_chol_persist_f64 + k_trsv_back_mt:
-    # (76.5 + 9014.4 + 2241.5) KiB fetched x 2.000 + (9.3 + 4692.5 + 9.0) KiB written
-    "solve": (76.5 + 9014.4 + 2241.5) * 1024 * 2.0 + (9.3 + 4692.5 + 9.0) * 1024,
+    # (76.5 + 8995.1 + 2251.5) KiB fetched x 2.000 + (17.3 + 4692.5 + 8.5) KiB written
+    "solve": (76.5 + 8995.1 + 2251.5) * 1024 * 2.0 + (17.3 + 4692.5 + 8.5) * 1024,
     # k_jacobian (gate-tape path, gate adjoints stored per site) + k_jac_wgrad:
-    # (41331.7 + 34102.5) KiB fetched x 2.000 + (55328.0 + 50235.8) KiB written x 1.000
-    "jacobian": (41331.7 + 34102.5) * 1024 * 2.0 + (55328.0 + 50235.8) * 1024,
+    # (42362.2 + 33947.3) KiB fetched x 2.000 + (55328.0 + 50235.6) KiB written x 1.000
+    "jacobian": (42362.2 + 33947.3) * 1024 * 2.0 + (55328.0 + 50235.6) * 1024,
     # k_gram_bf16 (split form, four products, 7-way split-K, FP64 partial tiles):
-    # 43368.0 KiB fetched x 2.000 + 32256.0 KiB written x 1.000
-    "gram": 43368.0 * 1024 * 2.0 + 32256.0 * 1024}
+    # 43368.1 KiB fetched x 2.000 + 32256.0 KiB written x 1.000
+    "gram": 43368.1 * 1024 * 2.0 + 32256.0 * 1024}
 
 
 def parse():
