@@ -254,18 +254,70 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
   const int N = a.N;
   const int NT = blockDim.x;
 
-  float Wu[KS + KX], Wr[KS + KX], Wg[KS], Wi[KX];
+  // 2D: FP32 fragments.  1D: the state products as FP16 hi/lo fragments
+  // (the split described at k_eloc_mfma_w, same register footprint; the
+  // state lies in [-1, 1], while the 2D gate input U1 h_h + U2 h_v does not)
+  constexpr bool SPLIT = DIM == 1;
+  constexpr int KJ = H / 16;
+  float Wu[SPLIT ? KX : KS + KX], Wr[SPLIT ? KX : KS + KX], Wg[SPLIT ? 1 : KS], Wi[KX];
+  f16x8_m Wuh[SPLIT ? KJ : 1], Wul[SPLIT ? KJ : 1], Wrh[SPLIT ? KJ : 1], Wrl[SPLIT ? KJ : 1],
+      Wgh[SPLIT ? KJ : 1], Wgl[SPLIT ? KJ : 1];
+  __shared__ unsigned wmax_bits;
+  int sexp = 0;
+  float sc_dn = 1.f, sc_up = 1.f;
   {
     const float* base = a.mw + (size_t)w * NSTEP * 64 + lane;
+    if constexpr (SPLIT) {
+      const float* bw = a.mw + (size_t)w * NSTEP * 64;
+      // input unit u = 16 j + 8 half + e sits at K-step u % KS, lane half u / KS
+      auto wfrag = [&](int j, int e, int g) -> float {
+        const int u = 16 * j + 8 * half + e;
+        return bw[(size_t)(g * (KS + KX) + u % KS) * 64 + col + 32 * (u / KS)];
+      };
+      if (tid == 0) wmax_bits = 0u;
+      __syncthreads();
+      float mx = 0.f;
+      for (int j = 0; j < KJ; ++j)
+        for (int e = 0; e < 8; ++e)
+          for (int g = 0; g < 3; ++g) mx = fmaxf(mx, fabsf(wfrag(j, e, g)));
+      atomicMax(&wmax_bits, __float_as_uint(mx));   // non-negative floats order as their bits
+      __syncthreads();
+      // FP16 holds magnitudes below 65504: weights from 2^14 on are split
+      // as w 2^-s and the products scaled back by 2^s (exact)
+      const float wmax = __uint_as_float(wmax_bits);
+      sexp = wmax >= 16384.f ? min(ilogbf(wmax) - 13, 120) : 0;
+      sc_dn = ldexpf(1.f, -sexp);
+      sc_up = ldexpf(1.f, sexp);
 #pragma unroll
-    for (int s = 0; s < KS + KX; ++s) Wu[s] = base[(size_t)s * 64];
+      for (int j = 0; j < KJ; ++j) {
+        float xu[8], xr[8], xg[8];
 #pragma unroll
-    for (int s = 0; s < KS + KX; ++s) Wr[s] = base[(size_t)(KS + KX + s) * 64];
+        for (int e = 0; e < 8; ++e) {
+          xu[e] = wfrag(j, e, 0) * sc_dn;
+          xr[e] = wfrag(j, e, 1) * sc_dn;
+          xg[e] = wfrag(j, e, 2) * sc_dn;
+        }
+        split_f16(xu, Wuh[j], Wul[j]);
+        split_f16(xr, Wrh[j], Wrl[j]);
+        split_f16(xg, Wgh[j], Wgl[j]);
+      }
 #pragma unroll
-    for (int s = 0; s < KS; ++s) Wg[s] = base[(size_t)(2 * (KS + KX) + s) * 64];
+      for (int s = 0; s < KX; ++s) {
+        Wu[s] = base[(size_t)(KS + s) * 64];
+        Wr[s] = base[(size_t)(KS + KX + KS + s) * 64];
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS + KX; ++s) Wu[s] = base[(size_t)s * 64];
+#pragma unroll
+      for (int s = 0; s < KS + KX; ++s) Wr[s] = base[(size_t)(KS + KX + s) * 64];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) Wg[s] = base[(size_t)(2 * (KS + KX) + s) * 64];
+    }
 #pragma unroll
     for (int s = 0; s < KX; ++s) Wi[s] = base[(size_t)(2 * (KS + KX) + KS + s) * 64];
   }
+  constexpr int XO = SPLIT ? 0 : KS;   // index of the first one-hot fragment in Wu, Wr
   const float bu = a.bias[unit], br = a.bias[H + unit], bh = a.bias[2 * H + unit];
   const float bi = a.bias[3 * H + unit];
   const float bgs = (float)(2.8853900817779268 * (double)bh);   // 2 log2(e) b_h
@@ -274,6 +326,9 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
   __syncthreads();
 
   const int n_items = a.list ? a.count[a.M] : a.n_items;
+  // instantiated with and without the weight scaling (no branch between
+  // the products in the common case)
+  auto items = [&](auto scaled) {
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     ElocSeq e = eloc_begin(a, item, col);
     const int k0 = e.k0, f1 = e.f1, f2p = e.f2p;
@@ -331,28 +386,46 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
       f32x16_m au, ar, ag, ai;
       if (DIM == 1) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) { au[q] = 0.f; ar[q] = 0.f; ag[q] = bgs; ai[q] = 0.f; }
+        for (int q = 0; q < 16; ++q) { au[q] = 0.f; ar[q] = 0.f; ag[q] = bgs * sc_dn; ai[q] = 0.f; }
       } else {
 #pragma unroll
         for (int q = 0; q < 16; ++q) { au[q] = bu; ar[q] = br; ag[q] = bh; ai[q] = bi; }
       }
+      if constexpr (SPLIT) {
 #pragma unroll
-      for (int s4 = 0; s4 < KS; s4 += 4) {
-        const float4 av = *reinterpret_cast<const float4*>(&hA[cb][col][s4 + half * KS]);
-        au = mfma_f32(av.x, Wu[s4 + 0], au); ar = mfma_f32(av.x, Wr[s4 + 0], ar); ag = mfma_f32(av.x, Wg[s4 + 0], ag);
-        au = mfma_f32(av.y, Wu[s4 + 1], au); ar = mfma_f32(av.y, Wr[s4 + 1], ar); ag = mfma_f32(av.y, Wg[s4 + 1], ag);
-        au = mfma_f32(av.z, Wu[s4 + 2], au); ar = mfma_f32(av.z, Wr[s4 + 2], ar); ag = mfma_f32(av.z, Wg[s4 + 2], ag);
-        au = mfma_f32(av.w, Wu[s4 + 3], au); ar = mfma_f32(av.w, Wr[s4 + 3], ar); ag = mfma_f32(av.w, Wg[s4 + 3], ag);
+        for (int j = 0; j < KJ; ++j) {
+          const float4 x0 = *reinterpret_cast<const float4*>(&hA[cb][col][16 * j + 8 * half]);
+          const float4 x1 = *reinterpret_cast<const float4*>(&hA[cb][col][16 * j + 8 * half + 4]);
+          const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+          f16x8_m ahi, alo;
+          split_f16(x, ahi, alo);
+          au = mfma_f16(alo, Wuh[j], au); ar = mfma_f16(alo, Wrh[j], ar); ag = mfma_f16(alo, Wgh[j], ag);
+          au = mfma_f16(ahi, Wul[j], au); ar = mfma_f16(ahi, Wrl[j], ar); ag = mfma_f16(ahi, Wgl[j], ag);
+          au = mfma_f16(ahi, Wuh[j], au); ar = mfma_f16(ahi, Wrh[j], ar); ag = mfma_f16(ahi, Wgh[j], ag);
+        }
+        if constexpr (decltype(scaled)::value) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q) { au[q] *= sc_up; ar[q] *= sc_up; ag[q] *= sc_up; }
+        }
+      } else {
+#pragma unroll
+        for (int s4 = 0; s4 < KS; s4 += 4) {
+          const float4 av = *reinterpret_cast<const float4*>(&hA[cb][col][s4 + half * KS]);
+          au = mfma_f32(av.x, Wu[s4 + 0], au); ar = mfma_f32(av.x, Wr[s4 + 0], ar); ag = mfma_f32(av.x, Wg[s4 + 0], ag);
+          au = mfma_f32(av.y, Wu[s4 + 1], au); ar = mfma_f32(av.y, Wr[s4 + 1], ar); ag = mfma_f32(av.y, Wg[s4 + 1], ag);
+          au = mfma_f32(av.z, Wu[s4 + 2], au); ar = mfma_f32(av.z, Wr[s4 + 2], ar); ag = mfma_f32(av.z, Wg[s4 + 2], ag);
+          au = mfma_f32(av.w, Wu[s4 + 3], au); ar = mfma_f32(av.w, Wr[s4 + 3], ar); ag = mfma_f32(av.w, Wg[s4 + 3], ag);
+        }
       }
       // one-hot spin inputs: this lane supplies column c = 2x + half
       if (DIM == 1) {
         const float o = e.sprev == half ? 1.f : 0.f;
-        au = mfma_f32(o, Wu[KS], au); ar = mfma_f32(o, Wr[KS], ar); ai = mfma_f32(o, Wi[0], ai);
+        au = mfma_f32(o, Wu[XO], au); ar = mfma_f32(o, Wr[XO], ar); ai = mfma_f32(o, Wi[0], ai);
       } else {
         const float o0 = sh == half ? 1.f : 0.f;
         const float o1 = sv == half ? 1.f : 0.f;
-        au = mfma_f32(o0, Wu[KS], au); ar = mfma_f32(o0, Wr[KS], ar); ai = mfma_f32(o0, Wi[0], ai);
-        au = mfma_f32(o1, Wu[KS + 1], au); ar = mfma_f32(o1, Wr[KS + 1], ar); ai = mfma_f32(o1, Wi[1], ai);
+        au = mfma_f32(o0, Wu[XO], au); ar = mfma_f32(o0, Wr[XO], ar); ai = mfma_f32(o0, Wi[0], ai);
+        au = mfma_f32(o1, Wu[XO + 1], au); ar = mfma_f32(o1, Wr[XO + 1], ar); ai = mfma_f32(o1, Wi[1], ai);
       }
       // GRU update in the accumulator layout: element q is sequence
       // (q / 4) * 8 + half * 4 + q % 4, unit `unit`
@@ -383,6 +456,9 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
     if (w == 0 && half == 0 && e.act) eloc_end(a, e);
     __syncthreads();
   }
+  };
+  if (sexp) items(std::true_type{});
+  else items(std::false_type{});
 }
 
 // 1D models, d_h <= 64: each wave re-evaluates its own item (32 connected

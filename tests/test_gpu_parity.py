@@ -384,11 +384,12 @@ def test_local_energy_fp32_model(arch, ham):
     assert rel_err(eloc.cpu().numpy(), ref) < 2e-4
 
 
-def test_local_energy_fp32_large_weights():
+@pytest.mark.parametrize("arch", [dict(Lx=16, H=64), dict(Lx=9, H=128, cplx=True)], ids=_ids)
+def test_local_energy_fp32_large_weights(arch):
     # gate weights beyond the FP16 range of the split state products (the
-    # kernel stages them scaled by a power of two): finite local energies
+    # kernels stage them scaled by a power of two): finite local energies
     # within the FP32 bound of the FP64 oracle
-    spec, m = make_pair(Lx=16, H=64, dtype="f32")
+    spec, m = make_pair(**arch, dtype="f32")
     th = scaled_theta(spec, 15, 1.0)
     off = 0
     for name, shape in omodel.layout(spec):
@@ -399,7 +400,7 @@ def test_local_energy_fp32_large_weights():
             blk[7, 1] = -4.0e4
         off += n
     m.set_params(to_dev(th))
-    ham = oham.Ham("tfim", J=1.0, h=1.0, pbc=True)
+    ham = oham.Ham("cluster") if arch.get("cplx") else oham.Ham("tfim", J=1.0, h=1.0, pbc=True)
     Ns = 45
     sig, lp = omodel.sample(spec, th, philox.uniforms(79, 2, Ns, spec.N))
     ref = oham.local_energy(spec, th, ham, sig, lp)
