@@ -5,7 +5,10 @@
 // first flipped site (one term of the Hamiltonian for 32 samples), so all
 // 32 recurrences restart at the same site and advance in lockstep.  At
 // every site the gate pre-activations of the 32 sequences are one
-// [32 x (H + ds)] x [(H + ds) x 3H] product on v_mfma_f32_32x32x2_f32:
+// [32 x (H + ds)] x [(H + ds) x 3H] product on the matrix cores: the one-hot
+// input steps on v_mfma_f32_32x32x2_f32, the state term on the same FP32
+// instruction in 2D and, in 1D (state in [-1, 1]), as three FP16 hi/lo
+// products on v_mfma_f32_32x32x16_f16 (described at k_eloc_mfma_w):
 // wave w owns hidden units 32w..32w+31 and keeps its B-operand fragments of
 // W_u, W_r, W_h and of the one-hot input columns in registers for the whole
 // kernel, so the only per-site operand traffic is the 32 x H hidden state
