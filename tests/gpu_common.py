@@ -46,6 +46,8 @@ def to_dev(a, dtype=None):
 
 
 def rel_err(a, b):
+    """Largest entrywise difference relative to the largest entry of the
+    reference: max|a - b| / max|b| (the floor only avoids 0 / 0)."""
     a = np.asarray(a)
     b = np.asarray(b)
-    return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b)))))
+    return float(np.max(np.abs(a - b)) / max(1e-300, float(np.max(np.abs(b)))))

@@ -239,8 +239,14 @@ def test_step_fp64_config1():
     assert rel_err(T, ref["T"]) < 1e-10
     assert rel_err(it["x"].cpu().numpy(), ref["x"]) < 1e-10
     assert rel_err(o["dtheta"].cpu().numpy(), ref["dtheta"]) < 1e-10
-    assert rel_err(m.get_params().cpu().numpy(), ref["theta"]) < 1e-10
+    assert theta_err(m.get_params().cpu().numpy(), ref) < 1e-10
     assert rel_err(mom.cpu().numpy(), ref["m"]) < 1e-10
+
+
+def theta_err(theta, ref):
+    """theta = theta_0 - m (App. B): its error is that of the step, so it is
+    measured against the size of the applied step m, not of theta."""
+    return float(np.max(np.abs(theta - ref["theta"])) / np.max(np.abs(ref["m"])))
 
 
 @pytest.mark.parametrize("arch,ham,Ns", [
@@ -266,8 +272,32 @@ def test_step_fp64_ragged(arch, ham, Ns):
     assert rel_err(it["T"].cpu().numpy(), ref["T"]) < 1e-10
     assert rel_err(it["x"].cpu().numpy(), ref["x"]) < 1e-10
     assert rel_err(o["dtheta"].cpu().numpy(), ref["dtheta"]) < 1e-10
-    assert rel_err(m.get_params().cpu().numpy(), ref["theta"]) < 1e-10
+    assert theta_err(m.get_params().cpu().numpy(), ref) < 1e-10
     assert rel_err(mom.cpu().numpy(), ref["m"]) < 1e-10
+
+
+def test_step_fp64_two_steps_momentum():
+    # two consecutive steps at mu = 0.7 (App. B): the second step starts from
+    # the first step's theta and momentum on both sides, so the momentum
+    # recursion itself (not only m_1 = (1 - mu) dtheta_0) is compared
+    import paper_2608_18065_amd as pm
+    spec, m = make_pair(Lx=11, H=16, max_Ns=96)
+    th = scaled_theta(spec, 41, 1.0)
+    m.set_params(to_dev(th))
+    ham = oham.Ham("tfim", J=1.0, h=0.8, pbc=True)
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    th_ref, m_ref = th, np.zeros_like(th)
+    for t in range(2):
+        o = m.step(_gpu_ham(ham), 96, 0.03, 1e-3, 0.7, mom, 17, t, form=pm.FORM_FP64_REF)
+        torch.cuda.synchronize()
+        assert int(o["status"].item()) == 0
+        ref = ominsr.step(spec, th_ref, m_ref, ham, 96, 0.03, 1e-3, 0.7, 17, t)
+        assert np.array_equal(o["sigma"].cpu().numpy(), ref["sigma"].astype(np.uint8))
+        assert rel_err(o["dtheta"].cpu().numpy(), ref["dtheta"]) < 1e-10
+        assert rel_err(mom.cpu().numpy(), ref["m"]) < 1e-10
+        assert theta_err(m.get_params().cpu().numpy(), ref) < 1e-10
+        # continue both from their own states
+        th_ref, m_ref = ref["theta"], ref["m"]
 
 
 def test_step_fp64_pinv_heisenberg2d():
@@ -301,18 +331,57 @@ def test_step_fp64_pinv_heisenberg2d():
     assert np.linalg.norm(d - ref["dtheta"]) / np.linalg.norm(ref["dtheta"]) < tol
 
 
+def _draw_margins(spec, th, sigma, u):
+    """|u - p_i(0)| at every site of the given draws, with p_i(0) the
+    oracle's FP64 conditional along the drawn configuration."""
+    run = omodel.run(spec, th, sigma=sigma)
+    P = omodel.unpack(spec, th)
+    Ns, N = sigma.shape
+    nup = np.zeros(Ns, dtype=np.int64)
+    ndn = np.zeros(Ns, dtype=np.int64)
+    out = np.empty((Ns, N))
+    for k in range(N):
+        _, p, _ = omodel.conditional(spec, P, run["hs"][:, k], nup, ndn)
+        out[:, k] = np.abs(u[:, k] - p[:, 0])
+        nup += sigma[:, k] == 0
+        ndn += sigma[:, k] == 1
+    return out
+
+
+# an FP32 conditional is within a few FP32 ulps of the FP64 one; a draw
+# whose uniform lies closer than this to the conditional is a tie
+FP32_TIE = 1e-6
+
+
 def _low_precision_step(spec, m, ham, Ns, eta, lam, key, counter, form):
+    """One step of a low-precision form against the FP64 oracle.  The FP32
+    sampler may only differ from the FP64 draws where the uniform ties with
+    the conditional to FP32 resolution: then the first differing site of
+    each differing sample must be such a tie, and the oracle's downstream
+    stages are re-run on the GPU's samples.  Anything else fails."""
     mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
     th = m.get_params().cpu().numpy()
     o = m.step(_gpu_ham(ham), Ns, eta, lam, 0.0, mom, key, counter, form=form)
     torch.cuda.synchronize()
     assert int(o["status"].item()) == 0
     ref = ominsr.step(spec, th, np.zeros_like(th), ham, Ns, eta, lam, 0.0, key, counter)
-    same = o["sigma"].cpu().numpy() == ref["sigma"].astype(np.uint8)
-    if not same.all():
-        # an FP32 conditional can fall on the other side of u than the FP64
-        # one when |u - p| is below FP32 resolution; rare, not a defect
-        pytest.skip("FP32 sampling tie: %d of %d draws differ" % ((~same).sum(), same.size))
+    u = philox.uniforms(key, counter, Ns, spec.N)
+    sig = o["sigma"].cpu().numpy()
+    diff = sig != ref["sigma"].astype(np.uint8)
+    margin = _draw_margins(spec, th, ref["sigma"], u)
+    if not diff.any():
+        return o, ref
+    rows = np.nonzero(diff.any(axis=1))[0]
+    assert len(rows) <= max(2, Ns // 200), "%d samples differ" % len(rows)
+    for r in rows:
+        k = int(np.argmax(diff[r]))
+        assert margin[r, k] < FP32_TIE, (r, k, margin[r, k])
+    # the oracle's stages on the GPU's samples (same arithmetic as its step)
+    lp = omodel.log_psi(spec, th, sig.astype(np.int64))
+    eps = oham.local_energy(spec, th, ham, sig.astype(np.int64), lp)
+    D = ojac.log_derivatives(spec, th, sig.astype(np.int64))
+    ref = ominsr.update(D, eps, eta, lam)
+    ref.update(sigma=sig, eps=eps)
     return o, ref
 
 

@@ -470,3 +470,93 @@ def test_head_closed_forms():
     assert np.allclose(2 * lp.real, n0 * (0.3 - lse) + n1 * (-1.1 - lse), rtol=0, atol=1e-13)
     ph = n0 * math.pi * 0.7 / 1.7 + n1 * math.pi * (-2.0) / 3.0
     assert np.allclose(lp.imag, ph, rtol=0, atol=1e-13)
+
+
+def test_2d_log_p_matches_torch_recurrence():
+    # whole 2D recurrence (App. A, 2D cell; Sec. 2.1 zigzag path): torch
+    # GRUCell with h' = U1 h(i - (-1)^j, j) + U2 h(i, j - 1) and
+    # sigma' = [sigma(i - (-1)^j, j); sigma(i, j - 1)], zero states and zero
+    # one-hots outside the lattice.  The path, the neighbour coordinates and
+    # the hidden-state grid are built here from the paper's formulas, not
+    # from the oracle's path helpers; U1 and U2 are made very different so a
+    # swap (or a swapped sigma' order) shows.
+    import torch
+    Lx, Ly, H = 3, 4, 5
+    spec = model.Spec(Lx=Lx, Ly=Ly, dim=2, H=H)
+    th = scaled_theta(spec, 64, 2.0)
+    P = model.unpack(spec, th)
+    P["U1"][:] *= 3.0
+    P["U2"][:] *= 0.2
+    P["Wu"][:, H:H + 2] += 1.5      # horizontal spin columns differ from vertical
+    P["Win"][:, 0:2] -= 1.0
+    cell = _torch_cell_from_paper(P, H, 4)
+    U1, U2 = torch.from_numpy(P["U1"]), torch.from_numpy(P["U2"])
+    U, c = torch.from_numpy(P["U"]), torch.from_numpy(P["c"])
+    sig = refs.all_configs(Lx * Ly)[::97]
+    ns = len(sig)
+    order = []                                  # pi(k) = (i_k, j_k)
+    for k in range(Lx * Ly):
+        j = k // Lx
+        order.append((k % Lx if j % 2 == 0 else Lx - 1 - k % Lx, j))
+    pos = {ij: k for k, ij in enumerate(order)}
+    with torch.no_grad():
+        hgrid = {}
+        tot = torch.zeros(ns, dtype=torch.float64)
+        for k, (i, j) in enumerate(order):
+            ih = i - (1 if j % 2 == 0 else -1)
+            h_h = hgrid.get((ih, j), torch.zeros(ns, H, dtype=torch.float64))
+            h_v = hgrid.get((i, j - 1), torch.zeros(ns, H, dtype=torch.float64))
+
+            def onehot(ij):
+                if ij not in pos:
+                    return torch.zeros(ns, 2, dtype=torch.float64)
+                return torch.nn.functional.one_hot(torch.from_numpy(sig[:, pos[ij]]), 2).double()
+            x = torch.cat([onehot((ih, j)), onehot((i, j - 1))], dim=1)
+            hp = h_h @ U1.T + h_v @ U2.T
+            h = cell(x, hp)
+            hgrid[(i, j)] = h
+            lsm = torch.log_softmax(h @ U.T + c, dim=1)
+            tot += lsm[torch.arange(ns), torch.from_numpy(sig[:, k])]
+    lp = model.log_psi(spec, th, sig)
+    ref = tot.numpy()
+    assert np.max(np.abs(2 * lp.real - ref)) < 1e-13 * np.max(np.abs(ref))
+    # the same comparison fails for the swapped assembly (U1 <-> U2)
+    th2 = th.copy()
+    Q = model.unpack(spec, th2)
+    Q["U1"][:], Q["U2"][:] = P["U2"].copy(), P["U1"].copy()
+    lp2 = model.log_psi(spec, th2, sig)
+    assert np.max(np.abs(2 * lp2.real - ref)) > 1e-3
+    # ... and for sigma' = [sigma_v; sigma_h] (spin columns swapped)
+    th3 = th.copy()
+    R = model.unpack(spec, th3)
+    for name, c0 in (("Wu", H), ("Wr", H), ("Win", 0)):
+        a, b = R[name][:, c0:c0 + 2].copy(), R[name][:, c0 + 2:c0 + 4].copy()
+        R[name][:, c0:c0 + 2], R[name][:, c0 + 2:c0 + 4] = b, a
+    lp3 = model.log_psi(spec, th3, sig)
+    assert np.max(np.abs(2 * lp3.real - ref)) > 1e-3
+
+
+def test_momentum_by_hand():
+    # App. B: m_{t+1} = mu m_t + (1 - mu) dtheta_t, theta_{t+1} = theta_t -
+    # m_{t+1}; two steps at mu = 0.75 with dyadic values worked out by hand
+    th0 = np.array([1.0, -2.0])
+    m0 = np.zeros(2)
+    th1, m1 = minsr.momentum(th0, m0, np.array([0.5, 0.25]), 0.75)
+    assert np.array_equal(m1, [0.125, 0.0625])
+    assert np.array_equal(th1, [0.875, -2.0625])
+    th2, m2 = minsr.momentum(th1, m1, np.array([-1.0, 2.0]), 0.75)
+    assert np.array_equal(m2, [-0.15625, 0.546875])
+    assert np.array_equal(th2, [1.03125, -2.609375])
+
+
+def test_momentum_geometric_series():
+    # a constant direction d from m_0 = 0 gives m_t = (1 - mu^t) d (the
+    # geometric series of App. B's recursion); mu = 0.7 over 12 steps
+    d = np.array([0.3, -1.7, 2.5])
+    th, m = np.zeros(3), np.zeros(3)
+    mu = 0.7
+    for t in range(1, 13):
+        th, m = minsr.momentum(th, m, d, mu)
+        assert np.allclose(m, (1.0 - mu ** t) * d, rtol=1e-14, atol=0)
+    # theta_t = -sum_s m_s = -(t - mu (1 - mu^t) / (1 - mu)) d
+    assert np.allclose(th, -(12 - mu * (1 - mu ** 12) / (1 - mu)) * d, rtol=1e-13, atol=0)
