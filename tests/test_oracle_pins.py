@@ -560,3 +560,127 @@ def test_momentum_geometric_series():
         assert np.allclose(m, (1.0 - mu ** t) * d, rtol=1e-14, atol=0)
     # theta_t = -sum_s m_s = -(t - mu (1 - mu^t) / (1 - mu)) d
     assert np.allclose(th, -(12 - mu * (1 - mu ** 12) / (1 - mu)) * d, rtol=1e-13, atol=0)
+
+
+# ------------------------------------------------ adaptive regularisation
+
+from oracle import adaptive  # noqa: E402
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_tnorm_is_parameter_space_norm(cplx):
+    # ||T||_F = ||S||_F (T and S = O' O'^T share their non-zero spectrum) and
+    # equals the 2-norm of T's eigenvalues
+    _, _, D, eps = _config1_inputs(cplx)
+    r = minsr.update(D, eps, 0.01, 1e-3)
+    tn = adaptive.tnorm(r["T"])
+    S = r["Op"] @ r["Op"].T
+    assert abs(tn - np.linalg.norm(S, "fro")) < 1e-12 * tn
+    assert abs(tn - np.sqrt(np.sum(np.linalg.eigvalsh(r["T"]) ** 2))) < 1e-12 * tn
+
+
+def test_pow23_by_hand():
+    # ||diag(4, 4, 4, 4)||_F = 8, 8^{2/3} = 4: lambda = 3e-4 * 4 (Sec. 3.3)
+    T = np.diag([4.0, 4.0, 4.0, 4.0])
+    assert adaptive.tnorm(T) == 8.0
+    assert abs(adaptive.lambda_pow23(T, 3e-4) - 1.2e-3) < 1e-18
+
+
+@pytest.mark.parametrize("pinv", [False, True])
+def test_trust_region_saturates_constraint(pinv):
+    # App. F: the step eta_* O' x has dtheta^T S dtheta = eta^2 with the
+    # parameter-space metric S = O' O'^T formed densely (N_p = 962), and
+    # ||tau|| is the paper's ||(I - lambda (T + lambda I)^{-1}) e'|| with an
+    # explicit inverse (Cholesky) or ||T T^+ e'|| (pseudo-inverse)
+    _, _, D, eps = _config1_inputs(False)
+    eta = 0.07
+    lam, cut = (0.0, 1e-8) if pinv else (1e-3, 0.0)
+    r = minsr.update(D, eps, 1.0, lam, pinv_cutoff=cut)
+    T, ep, x, Op = r["T"], r["ep"], r["x"], r["Op"]
+    tau = adaptive.tau_vector(T, ep, x, lam, pinv)
+    n = T.shape[0]
+    if pinv:
+        ref = T @ (np.linalg.pinv(T, rcond=1e-8, hermitian=True) @ ep)
+    else:
+        ref = (np.eye(n) - lam * np.linalg.inv(T + lam * np.eye(n))) @ ep
+    assert np.max(np.abs(tau - ref)) < 1e-9 * np.max(np.abs(ref))
+    eta_s = eta / np.linalg.norm(tau)
+    dth = eta_s * (Op @ x)
+    S = Op @ Op.T
+    assert abs(dth @ S @ dth - eta ** 2) < 1e-9 * eta ** 2
+
+
+def test_lm_denominator_is_quadratic_model():
+    # App. G: g^T dtheta - dtheta^T S dtheta / 2 with g = O' e' and
+    # S = O' O'^T formed densely, for a plain and a trust-region rate
+    _, _, D, eps = _config1_inputs(True)
+    lam = 2e-3
+    r = minsr.update(D, eps, 1.0, lam)
+    T, ep, x, Op = r["T"], r["ep"], r["x"], r["Op"]
+    tau = adaptive.tau_vector(T, ep, x, lam, False)
+    g = Op @ ep
+    S = Op @ Op.T
+    for eta_used in (0.01, 0.05 / np.linalg.norm(tau)):
+        dth = eta_used * (Op @ x)
+        pred = g @ dth - 0.5 * dth @ S @ dth
+        assert abs(adaptive.predicted_decrease(eta_used, ep, tau) - pred) < 1e-10 * abs(pred)
+
+
+def test_lm_ratio_tends_to_one_with_exact_energies():
+    # On a wave function whose distribution is uniform (zero output weights
+    # and biases) the full enumeration of configurations is an exact
+    # "sample set": then g is the exact energy gradient, and with exact
+    # energies E(theta) and E(theta - dtheta) from the dense Hamiltonian the
+    # ratio is 1 + O(eta) (App. G's quadratic model to first order).
+    N = 6
+    spec = model.Spec(Lx=N, H=4, complex_head=True)
+    th = scaled_theta(spec, 71, 1.0)
+    P = model.unpack(spec, th)
+    P["U"][:] = 0.0
+    P["c"][:] = 0.0
+    s = refs.all_configs(N)
+    ham = ham_mod.Ham("tfim", J=1.0, h=0.7)
+    Hd = refs.dense_tfim(N, 1.0, 0.7, False)
+
+    def energy(t):
+        psi = np.exp(model.log_psi(spec, t, s))
+        return float((np.conj(psi) @ (Hd @ psi)).real / (np.conj(psi) @ psi).real)
+
+    lp = model.log_psi(spec, th, s)
+    assert np.allclose(np.exp(2 * lp.real), 1.0 / 2 ** N, rtol=1e-13)
+    eps = ham_mod.local_energy(spec, th, ham, s, lp)
+    D = jacobian.log_derivatives(spec, th, s)
+    lam = 1e-3
+    r = minsr.update(D, eps, 1.0, lam)
+    tau = adaptive.tau_vector(r["T"], r["ep"], r["x"], lam, False)
+    E0 = energy(th)
+    assert abs(E0 - r["E"].real) < 1e-12
+    dev = []
+    for eta in (1e-2, 1e-3):
+        rho = adaptive.lm_ratio(E0, energy(th - eta * r["dtheta"]), eta, r["ep"], tau)
+        dev.append(abs(rho - 1.0))
+    assert dev[1] < 0.02
+    assert dev[1] < 0.2 * dev[0]      # first order in eta
+
+
+def test_lm_lambda_rule_by_hand():
+    # App. G with omega = 3/2: strict inequalities at 1/4 and 3/4
+    assert adaptive.lm_next(1e-2, 0.1, 1.5) == 1.5e-2
+    assert adaptive.lm_next(1e-2, -3.0, 1.5) == 1.5e-2
+    assert adaptive.lm_next(1e-2, 0.9, 1.5) == 1e-2 / 1.5
+    assert adaptive.lm_next(1e-2, 0.5, 1.5) == 1e-2
+    assert adaptive.lm_next(1e-2, 0.25, 1.5) == 1e-2
+    assert adaptive.lm_next(1e-2, 0.75, 1.5) == 1e-2
+    assert adaptive.lm_next(1e-2, float("nan"), 1.5) == 1.5e-2
+
+
+def test_adaptive_step_reduces_to_plain_step():
+    # constant lambda without the trust region is Alg. 1's step
+    spec = model.Spec(Lx=8, H=8)
+    th = scaled_theta(spec, 72, 1.0)
+    ham = ham_mod.Ham("tfim", J=1.0, h=1.0, pbc=True)
+    a = adaptive.step(spec, th, np.zeros_like(th), ham, 40, 0.02, 1e-3, 0.3, 5, 2)
+    b = minsr.step(spec, th, np.zeros_like(th), ham, 40, 0.02, 1e-3, 0.3, 5, 2)
+    assert np.array_equal(a["dtheta"], b["dtheta"])
+    assert np.array_equal(a["theta"], b["theta"])
+    assert a["eta_used"] == 0.02 and a["lam_used"] == 1e-3
