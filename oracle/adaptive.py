@@ -28,14 +28,15 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
              lambda otherwise (App. G; omega = 3/2 there).  A ratio that is
              not a number (a failed trial) counts as rho < 1/4.
   E(theta - dtheta) is estimated from fresh samples of the trial
-  parameters (App. G's extra forward pass): Philox domain 2 of the step's
-  (key, counter), local energies, sample mean.
+  parameters (App. G's extra forward pass): Philox key `key`, counter
+  (counter XOR 2^63) -- a stream no step's own samples use -- then local
+  energies and their sample mean.
 """
 import numpy as np
 
 from . import hamiltonian, jacobian, minsr, model, philox
 
-LM_DOMAIN = 2
+TRIAL_COUNTER_BIT = 1 << 63
 
 
 def tnorm(T):
@@ -104,7 +105,7 @@ def step(spec, theta, m, ham, Ns, eta, lam, mu, key, counter, pinv_cutoff=0.0,
                ep_tau=float(ep @ tau))
     if lam_mode == "lm":
         trial = theta - dtheta
-        u1 = philox.uniforms(key, counter, Ns, spec.N, domain=LM_DOMAIN)
+        u1 = philox.uniforms(key, counter ^ TRIAL_COUNTER_BIT, Ns, spec.N)
         s1, lp1 = model.sample(spec, trial, u1)
         e1 = hamiltonian.local_energy(spec, trial, ham, s1, lp1)
         E1 = float(np.mean(e1).real)
