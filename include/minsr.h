@@ -248,6 +248,26 @@ int minsr_solve(minsr_model* m, int n, const double* dev_T, double lambda,
                 double pinv_cutoff, const double* dev_b, double* dev_x,
                 uint32_t* dev_status, hipStream_t s);
 
+/* ---- the Cholesky solve without device allocation --------------------------
+ * For callers that cannot allocate device memory (code under hip graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * solve as minsr_solve with pinv_cutoff == 0, (T + lambda I) x = b with
+ * lambda > 0 by tiled Cholesky (lower triangle of dev_T read, dev_T left
+ * unchanged; MINSR_ST_NOT_PD OR-ed into *dev_status on a pivot <= 0), with
+ * no model handle.  Its factor and solver workspace live in one static
+ * device array of 9 MiB per device, which the library holds until
+ * the process ends; it serves n <= 1024 (MINSR_E_SHAPE beyond).  The call
+ * allocates nothing.  Its first call on a device resolves that device's
+ * array address (a host-side lookup, no enqueued work): make it outside any
+ * stream capture, with n == 0 if nothing is to be solved yet.  Every call on
+ * one device uses the same array, so calls whose device work overlaps
+ * (different streams without ordering, or host threads) race; the array
+ * keeps the last call's contents and each call re-initialises what it
+ * reads.  dev_T [n x n], dev_b [n], dev_x [n], dev_status [1]: device,
+ * caller-owned.                                                            */
+int minsr_solve_noalloc(int n, const double* dev_T, double lambda, const double* dev_b,
+                        double* dev_x, uint32_t* dev_status, hipStream_t s);
+
 /* ---- many independent instances in one graph ------------------------------
  * A batch steps `count` independent minSR instances (each its own model,
  * Hamiltonian, step configuration, state and outputs; models may differ in

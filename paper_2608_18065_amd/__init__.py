@@ -26,7 +26,7 @@ SYMBOLS = (
     "minsr_local_energy", "minsr_jacobian", "minsr_logpsi_vjp", "minsr_step",
     "minsr_step_intermediates", "minsr_timing_begin", "minsr_timing_read",
     "minsr_batch_create", "minsr_batch_step", "minsr_batch_destroy", "minsr_set_tunable",
-    "minsr_get_tunable", "minsr_solve",
+    "minsr_get_tunable", "minsr_solve", "minsr_solve_noalloc",
 )
 OPT_PINV = 0x1
 PHASES = ("sample", "eloc", "eloc_sum_stats", "jacobian", "center", "gram", "gram_reduce",
@@ -98,6 +98,7 @@ def load_library(path=LIB_PATH):
         "minsr_get_tunable": [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)],
         "minsr_timing_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)],
         "minsr_solve": [vp, i32, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp],
+        "minsr_solve_noalloc": [i32, vp, ctypes.c_double, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -322,6 +323,23 @@ class Model:
         if form == FORM_BF16_FP64:   # low halves follow the high halves
             out["Oprime_lo"] = _from_ptr(O.value + n * Np * 2, (n, Np), odt)[:, :self.Np]
         return out
+
+
+def solve_noalloc(T, b, lam, x=None, status=None):
+    """(T + lam I) x = b by the allocation-free Cholesky entry point
+    (n <= 1024; device tensors; x and status may be given preallocated).
+    Returns (x, status word tensor)."""
+    n = b.shape[0]
+    assert T.shape == (n, n) and T.dtype == torch.float64 and b.dtype == torch.float64
+    T = T.contiguous()
+    b = b.contiguous()
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=b.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=b.device)
+    _check(lib().minsr_solve_noalloc(n, _ptr(T), float(lam), _ptr(b), _ptr(x), _ptr(status),
+                                     _stream()))
+    return x, status
 
 
 class Batch:
