@@ -76,12 +76,17 @@ extern "C" {
 #define MINSR_FORM_BF16_1PASS 3  /* as BF16_FP64 with O' a single BF16 array
                                     (one MFMA pass; larger Gram error)       */
 
-/* device status-word bits (minsr_step_out.dev_status) */
+/* device status-word bits (minsr_step_out.dev_status).  The bits in
+ * MINSR_ST_ERRORS are failures: a step that sets any of them leaves theta
+ * and the momentum unchanged.  MINSR_ST_SHIFT_FLOOR only reports that a
+ * BF16 form raised the shift to its floor (see minsr_step).              */
 #define MINSR_ST_NONFINITE_ELOC  0x1u
 #define MINSR_ST_NOT_PD          0x2u   /* Cholesky met a pivot <= 0 / NaN */
 #define MINSR_ST_NONFINITE_DTH   0x4u
 #define MINSR_ST_EIG_NOCONV      0x8u   /* pseudo-inverse met a non-finite
                                            tridiagonal entry                 */
+#define MINSR_ST_SHIFT_FLOOR     0x10u  /* informational, not a failure      */
+#define MINSR_ST_ERRORS          0x0Fu
 
 /* Architecture of one wave function (Sec. 2, Sec. 2.1 and App. A).
  *   Lx, Ly        lattice extent; a chain has Ly = 1 and dim = 1
@@ -198,9 +203,17 @@ int minsr_logpsi_vjp(minsr_model* m, int Ns, const uint8_t* dev_sigma,
  * lambda = 0, with the Moore-Penrose pseudo-inverse that drops eigenvalues
  * <= pinv_cutoff * lambda_max(T) (App. F), and sets
  *     dtheta = eta O' x;  m = mu m + (1 - mu) dtheta;  theta -= m.
- * theta and m change only if apply_update != 0 and the device status word
- * is zero.  The uniforms are Philox (key, counter) as in minsr_sample; the
- * caller advances counter between steps.                                   */
+ * theta and m change only if apply_update != 0 and no MINSR_ST_ERRORS bit
+ * is set.  The uniforms are Philox (key, counter) as in minsr_sample; the
+ * caller advances counter between steps.
+ * The shift: the FP64 and FP32 forms factor T + lambda I with lambda as
+ * given.  The BF16 forms use max(lambda, 2^-24 tr T): every entry of their
+ * Gram carries FP32 accumulation error of about 2^-24 sqrt(T_ii T_jj), whose
+ * spectral norm is below 2^-24 tr T, and a smaller shift can leave the
+ * computed T + lambda I indefinite; MINSR_ST_SHIFT_FLOOR is set when the
+ * floor is the larger.  The step reports the shift it used and the trace
+ * norm of T (tr T, the nuclear norm of the positive semidefinite T) through
+ * dev_lambda_used and dev_tnorm (the pseudo-inverse step reports shift 0).  */
 typedef struct {
   int32_t Ns;
   int32_t form;          /* MINSR_FORM_*                                    */
@@ -225,6 +238,8 @@ typedef struct {
   uint32_t* dev_status;  /* [1] MINSR_ST_* bits, written every step         */
   double* dev_eloc;      /* [Ns] complex, may be NULL                       */
   uint8_t* dev_sigma;    /* [Ns x N], may be NULL                           */
+  double* dev_tnorm;     /* [1] tr T (trace norm of T), may be NULL         */
+  double* dev_lambda_used; /* [1] the shift the solve used, may be NULL     */
 } minsr_step_out;
 
 int minsr_step(minsr_model* m, const minsr_hamiltonian* H,

@@ -18,6 +18,7 @@ F64, F32, BF16 = 0, 1, 2
 HAM_TFIM, HAM_CLUSTER, HAM_J1J2 = 0, 1, 2
 FORM_FP64_REF, FORM_BF16_FP64, FORM_FP32_PLAIN, FORM_BF16_1PASS = 0, 1, 2, 3
 ST_NONFINITE_ELOC, ST_NOT_PD, ST_NONFINITE_DTH, ST_EIG_NOCONV = 1, 2, 4, 8
+ST_SHIFT_FLOOR, ST_ERRORS = 0x10, 0x0F
 
 # every entry point of include/minsr.h
 SYMBOLS = (
@@ -61,7 +62,8 @@ class StepState(ctypes.Structure):
 class StepOut(ctypes.Structure):
     _fields_ = [("dev_energy", ctypes.c_void_p), ("dev_dtheta", ctypes.c_void_p),
                 ("dev_status", ctypes.c_void_p), ("dev_eloc", ctypes.c_void_p),
-                ("dev_sigma", ctypes.c_void_p)]
+                ("dev_sigma", ctypes.c_void_p), ("dev_tnorm", ctypes.c_void_p),
+                ("dev_lambda_used", ctypes.c_void_p)]
 
 
 def load_library(path=LIB_PATH):
@@ -253,7 +255,8 @@ class Model:
         """One minSR iteration (Alg. 1); returns the output tensors.
 
         `outputs` may hold preallocated tensors (energy, dtheta, status,
-        eloc, sigma) to avoid allocation, e.g. inside a timed loop.
+        eloc, sigma, tnorm, lambda_used) to avoid allocation, e.g. inside a
+        timed loop.
         `dev_counter` (int64 tensor of one element on the device) makes the
         step read its Philox counter from device memory and increment it,
         so a captured graph of the step can be replayed."""
@@ -261,7 +264,8 @@ class Model:
         cfg = StepCfg(Ns, form, eta, lam, mu, pinv_cutoff, ckpt_every, int(apply_update))
         st = StepState(ctypes.c_void_p(momentum.data_ptr()), key, counter, _ptr(dev_counter).value)
         out = StepOut(_ptr(o["energy"]).value, _ptr(o["dtheta"]).value, _ptr(o["status"]).value,
-                      _ptr(o.get("eloc")).value, _ptr(o.get("sigma")).value)
+                      _ptr(o.get("eloc")).value, _ptr(o.get("sigma")).value,
+                      _ptr(o.get("tnorm")).value, _ptr(o.get("lambda_used")).value)
         _check(lib().minsr_step(self.handle, ctypes.byref(ham), ctypes.byref(cfg),
                                 ctypes.byref(st), ctypes.byref(out), _stream()))
         return o
@@ -285,7 +289,9 @@ class Model:
                     dtheta=torch.empty(self.Np, dtype=torch.float64, device=dev),
                     status=torch.zeros(1, dtype=torch.int32, device=dev),
                     eloc=torch.empty((Ns, 2), dtype=torch.float64, device=dev),
-                    sigma=torch.empty((Ns, self.N), dtype=torch.uint8, device=dev))
+                    sigma=torch.empty((Ns, self.N), dtype=torch.uint8, device=dev),
+                    tnorm=torch.zeros(1, dtype=torch.float64, device=dev),
+                    lambda_used=torch.zeros(1, dtype=torch.float64, device=dev))
 
     def set_tunable(self, key, value):
         _check(lib().minsr_set_tunable(self.handle, key.encode(), int(value)))
@@ -374,7 +380,8 @@ class Batch:
                               inst.get("ckpt_every", 1), 1)
             states[i] = StepState(mom.data_ptr(), inst["key"], 0, ctr.data_ptr())
             outs[i] = StepOut(o["energy"].data_ptr(), o["dtheta"].data_ptr(),
-                              o["status"].data_ptr(), o["eloc"].data_ptr(), o["sigma"].data_ptr())
+                              o["status"].data_ptr(), o["eloc"].data_ptr(), o["sigma"].data_ptr(),
+                              o["tnorm"].data_ptr(), o["lambda_used"].data_ptr())
         h = ctypes.c_void_p()
         _check(lib().minsr_batch_create(models, hams, cfgs, states, outs, n, ctypes.byref(h)))
         self.handle = h

@@ -458,15 +458,21 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   MINSR_PHASE(7);
   if (cfg->pinv_cutoff > 0.0) {
     rc = ensure_pinv_ws(m, s);
+    if (!rc) rc = launch_report_trace(n, m->T, out->dev_tnorm, out->dev_lambda_used, s);
     if (!rc)
       rc = launch_pinv_solve(n, m->T, cfg->pinv_cutoff, m->epsp, m->x, m->eig, m->eig_elems,
                              m->eig_nmax, out->dev_status, s);
   } else {
-    // BF16 forms: T carries FP32 accumulation error of about 2^-22 of its
-    // largest diagonal entry, so the shift is kept at least 2^-21 of that
+    // BF16 forms: every entry of T carries FP32 accumulation error of at
+    // most about 2^-24 sqrt(T_ii T_jj) (flushes to FP64 every 128 inputs),
+    // so its spectral-norm error is below 2^-24 tr T: the shift is kept at
+    // least that (measured: a trajectory with tr T = 2.0e6 had a computed T
+    // with smallest eigenvalue -0.022, the exact Gram of its operand being
+    // positive semidefinite, against 2^-24 tr T = 0.12)
     rc = launch_cholesky_solve(n, m->T, m->Lf, m->Dinv, rdt == MINSR_F32, cfg->lambda, m->epsp,
                                m->x, m->vwork, m->csync, out->dev_status, s,
-                               rdt == MINSR_BF16 ? 0x1p-21 : 0.0);
+                               rdt == MINSR_BF16 ? 0x1p-24 : 0.0, out->dev_tnorm,
+                               out->dev_lambda_used);
   }
   if (rc) return rc;
   MINSR_PHASE(8);

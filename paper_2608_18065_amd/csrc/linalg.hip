@@ -1302,10 +1302,15 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
   }
 }
 
-// sync words and b -> y (one kernel, safe inside captured graphs); if lam_out
-// is set, workgroup 0 also writes lambda_eff = max(lambda, rel * max_i T_ii):
-// the shift never falls below the accuracy to which a low-precision Gram is
-// computed
+// sync words and b -> y (one kernel, safe inside captured graphs).  If
+// lam_out or a report pointer is set, workgroup 0 also sums the diagonal of
+// T (tr T, fixed order) and forms the shift
+//   lambda_eff = max(lambda, rel_tr * tr T)      (rel_tr = 0: lambda)
+// into lam_out, MINSR_ST_SHIFT_FLOOR in *status when the floor is the
+// larger, and tr T and lambda_eff into rep_tn / rep_lam.  The floor bounds
+// the accumulation error of a low-precision Gram: each entry of the
+// computed T is within gamma sqrt(T_ii T_jj) of the exact one, so its
+// spectral-norm error is at most gamma tr T.
 // x entries not yet computed by the backward substitution hold a signalling
 // NaN: arithmetic only ever yields quiet NaNs, so no computed x equals it,
 // and a waiting workgroup polls the entries themselves (one round trip for
@@ -1314,24 +1319,61 @@ constexpr uint64_t X_UNSET = 0x7FF40000DEAD0001ull;
 
 template <typename TT>
 __global__ __launch_bounds__(256) void k_chol_prep(uint32_t* sync, int nsync, const double* b,
-                                                   TT* y, int n, const double* T, double lambda,
-                                                   double rel, double* lam_out, uint64_t* xmark) {
+                                                   TT* y, int n, const TT* T, double lambda,
+                                                   double rel_tr, double* lam_out,
+                                                   uint64_t* xmark, double* rep_tn,
+                                                   double* rep_lam, uint32_t* status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nsync) sync[i] = 0u;
   if (i < n) y[i] = (TT)b[i];
   if (i < n) xmark[i] = X_UNSET;
-  if (lam_out && blockIdx.x == 0) {
+  if ((lam_out || rep_tn || rep_lam) && blockIdx.x == 0) {
     __shared__ double red[256];
-    double mx = 0.0;
-    for (int k = threadIdx.x; k < n; k += 256) mx = fmax(mx, T[(size_t)k * n + k]);
-    red[threadIdx.x] = mx;
+    double tr = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) tr += (double)T[(size_t)k * n + k];
+    red[threadIdx.x] = tr;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) lam_out[0] = fmax(lambda, rel * red[0]);
+    if (threadIdx.x == 0) {
+      const double fl = rel_tr * red[0];
+      double lam = lambda;
+      if (rel_tr > 0.0 && fl > lambda) {
+        lam = fl;
+        if (status) atomicOr(status, MINSR_ST_SHIFT_FLOOR);
+      }
+      if (lam_out) lam_out[0] = lam;
+      if (rep_tn) rep_tn[0] = red[0];
+      if (rep_lam) rep_lam[0] = lam;
+    }
   }
+}
+
+// the report of a pseudo-inverse step: tr T and the shift 0
+__global__ __launch_bounds__(256) void k_report_trace(const double* T, int n, double* rep_tn,
+                                                      double* rep_lam) {
+  __shared__ double red[256];
+  double tr = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) tr += T[(size_t)k * n + k];
+  red[threadIdx.x] = tr;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (rep_tn) rep_tn[0] = red[0];
+    if (rep_lam) rep_lam[0] = 0.0;
+  }
+}
+
+int launch_report_trace(int n, const double* T, double* rep_tn, double* rep_lam, hipStream_t s) {
+  if (n == 0 || (!rep_tn && !rep_lam)) return MINSR_OK;
+  k_report_trace<<<1, 256, 0, s>>>(T, n, rep_tn, rep_lam);
+  MINSR_CHECK_LAUNCH();
+  return MINSR_OK;
 }
 
 // Backward substitution L^T x = y by one workgroup per block of 64:
@@ -1448,23 +1490,22 @@ size_t chol_vec_elems(int n) {
 template <typename TT>
 static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, double lambda,
                   const double* b, double* x, uint32_t* status, hipStream_t s,
-                  double lam_floor_rel) {
+                  double lam_floor_rel, double* rep_tn, double* rep_lam) {
   const int nblk = (n + CB - 1) / CB;
   const int nsync = (int)chol_sync_words(n);
   const int m = std::max(nsync, n);
   CholArgs a{T, A, Dinv, yv, sync, status, lambda, nullptr, n, nblk};
-  const double* Tfloor = nullptr;
   double* lam_slot = nullptr;
   if constexpr (std::is_same<TT, double>::value) {
     if (lam_floor_rel > 0.0) {
-      Tfloor = T;
       lam_slot = reinterpret_cast<double*>(yv) + chol_vec_elems(n) - 1;
       a.lam_dev = lam_slot;
     }
   }
-  k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n, Tfloor, lambda,
-                                                  lam_floor_rel, lam_slot,
-                                                  reinterpret_cast<uint64_t*>(x));
+  k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n, T, lambda,
+                                                  lam_slot ? lam_floor_rel : 0.0, lam_slot,
+                                                  reinterpret_cast<uint64_t*>(x), rep_tn,
+                                                  rep_lam, status);
   MINSR_CHECK_LAUNCH();
   if constexpr (std::is_same<TT, double>::value) {
     k_chol_persist_f64<<<1 + nblk * (nblk - 1) / 2, 256, 0, s>>>(a, sync + chol_sync_one(nblk),
@@ -1485,13 +1526,15 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
 
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, double* yv, uint32_t* sync,
-                          uint32_t* status, hipStream_t s, double lam_floor_rel) {
+                          uint32_t* status, hipStream_t s, double lam_floor_rel, double* rep_tn,
+                          double* rep_lam) {
   if (n == 0) return MINSR_OK;
   if (f32)
     return chol_t<float>(n, reinterpret_cast<const float*>(T), reinterpret_cast<float*>(Lf),
                          reinterpret_cast<float*>(Dinv), reinterpret_cast<float*>(yv), sync,
-                         lambda, b, x, status, s, 0.0);
-  return chol_t<double>(n, T, Lf, Dinv, yv, sync, lambda, b, x, status, s, lam_floor_rel);
+                         lambda, b, x, status, s, 0.0, rep_tn, rep_lam);
+  return chol_t<double>(n, T, Lf, Dinv, yv, sync, lambda, b, x, status, s, lam_floor_rel, rep_tn,
+                        rep_lam);
 }
 
 // ================================================================ update
@@ -1577,7 +1620,7 @@ __global__ void k_apply(size_t Np, const double* dtheta, double mu, double* m, d
                         const uint32_t* status) {
   size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= Np) return;
-  if (status[0] != 0) return;
+  if (status[0] & MINSR_ST_ERRORS) return;
   const double mn = mu * m[col] + (1.0 - mu) * dtheta[col];
   m[col] = mn;
   theta[col] -= mn;

@@ -120,10 +120,15 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
 // factors T + lambda I into Lf (T is left unchanged) and solves for x
 // (yv: chol_vec_elems(n) elements of scratch; sync: chol_sync_words(n) words)
 // lam_floor_rel > 0 (FP64 solve of a low-precision Gram): the shift used is
-// max(lambda, lam_floor_rel * max_i T_ii)
+// max(lambda, lam_floor_rel * tr T), with MINSR_ST_SHIFT_FLOOR set in *status
+// when the floor is the larger; rep_tn / rep_lam (may be null) receive tr T
+// and the shift used
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, double* yv, uint32_t* sync,
-                          uint32_t* status, hipStream_t s, double lam_floor_rel = 0.0);
+                          uint32_t* status, hipStream_t s, double lam_floor_rel = 0.0,
+                          double* rep_tn = nullptr, double* rep_lam = nullptr);
+// tr T into rep_tn and 0 into rep_lam (the report of a pseudo-inverse step)
+int launch_report_trace(int n, const double* T, double* rep_tn, double* rep_lam, hipStream_t s);
 size_t chol_dinv_elems(int n);
 size_t chol_sync_words(int n);
 size_t chol_vec_elems(int n);

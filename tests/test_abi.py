@@ -50,3 +50,50 @@ def test_errors_without_device_calls():
     d = pm.ModelDesc(10, 1, 1, 48, 0, 0, 0, pm.F64, 1, 64, 0)
     assert lib.minsr_create_model(ctypes.byref(d), ctypes.byref(h)) == -6
     assert lib.minsr_destroy_model(None) == -1
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    # sizes and field offsets of the ctypes structures equal those of the C
+    # header, compiled here with the host C compiler
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("no host C compiler")
+    import paper_2608_18065_amd as pm
+    structs = {"minsr_model_desc": pm.ModelDesc, "minsr_hamiltonian": pm.Hamiltonian,
+               "minsr_step_cfg": pm.StepCfg, "minsr_step_state": pm.StepState,
+               "minsr_step_out": pm.StepOut}
+    cfields = {"minsr_model_desc": ["Lx", "Ly", "dim", "hidden", "complex_head", "marshall",
+                                    "zero_mag", "compute_dtype", "init_seed", "max_Ns", "options"],
+               "minsr_hamiltonian": ["kind", "pbc", "J", "h", "J2"],
+               "minsr_step_cfg": ["Ns", "form", "eta", "lambda", "mu", "pinv_cutoff",
+                                  "ckpt_every", "apply_update"],
+               "minsr_step_state": ["dev_momentum", "key", "counter", "dev_counter"],
+               "minsr_step_out": ["dev_energy", "dev_dtheta", "dev_status", "dev_eloc",
+                                  "dev_sigma", "dev_tnorm", "dev_lambda_used"]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", "#define __HIP_PLATFORM_AMD__ 1",
+             '#include "minsr.h"', "int main(void) {"]
+    for name, fields in cfields.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for f in fields:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    r = subprocess.run(["gcc", "-I", inc, "-I", "/opt/rocm/include", str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("header does not compile on the host: " + r.stderr[-300:])
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for name, S in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(S), name
+        cf = cfields[name]
+        pf = [f for f, _ in S._fields_]
+        assert len(cf) == len(pf), name
+        for c, p in zip(cf, pf):
+            assert got[(name, c)] == getattr(S, p).offset, (name, c)

@@ -43,7 +43,10 @@ def test_tfim64_training_steps_stay_positive_definite():
     st = status.cpu().numpy()
     E = hist.cpu().numpy()[:, 0] / (wl.Lx * wl.Ly)
     m.close()
-    assert np.count_nonzero(st) == 0, "steps with status bits: %s" % np.nonzero(st)[0][:10]
+    bad = np.nonzero(st & pm.ST_ERRORS)[0]
+    assert len(bad) == 0, "steps with failure bits: %s" % bad[:10]
+    print("steps whose shift was raised to the BF16 floor: %d" %
+          np.count_nonzero(st & pm.ST_SHIFT_FLOOR))
     # from about 0.25 per site above the ground energy to below 1e-2
     assert E[0] - wl.E0 / 64 > 0.1
     assert E[-20:].mean() - wl.E0 / 64 < 1e-2
