@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the short timings of the cluster100, heis10x10 and J1-J2 batch "
                          "systems")
+    ap.add_argument("--only-workload", default="", metavar="NAME",
+                    help="only time NAME (cluster100 or heis10x10: a few BF16 + FP64 steps "
+                         "with per-phase events; for profiler runs), print its JSON, exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (for scaling the HBM "
                          "traffic counters of a profiler run), then exit")
@@ -83,9 +86,12 @@ def work_units(wl):
         Np=Np,
         # GRU gate products (3 H x H) and the two logits per re-evaluated site
         eloc_flop=seq_sites * (6 * H * H + 4 * H),
-        # O written once in FP32 (Ns rows of Np); the sampler's gate tape
-        # (4 H per site) and hidden states (H per site) read once, FP32
-        jacobian_bytes=Ns * Np * 4 + Ns * N * 5 * H * 4,
+        # the Jacobian's algorithmic bytes: O written once in FP32 (Ns rows
+        # of Np) plus the stored hidden states read once (H per site, FP32)
+        jacobian_bytes=Ns * Np * 4 + Ns * N * H * 4,
+        # the same with the sampler's gate tape (4 H per site), which this
+        # implementation also reads back instead of recomputing the gates
+        jacobian_bytes_with_tape=Ns * Np * 4 + Ns * N * 5 * H * 4,
         # useful flops of the symmetric Gram: n (n + 1) Np
         gram_flop=Ns * (Ns + 1) * Np,
         # Cholesky of the n x n system (n^3 / 3) and its two triangular solves
@@ -141,6 +147,63 @@ def run_form(pm, wl, form, K, W, dtype="f32", graph=True, kernel_steps=20):
                 energy=E, status=st, kernel_steps=nrec)
 
 
+TARGET_DE = 1e-4      # |Delta E / N| of the metric
+WINDOW = 50           # steps averaged for the energy at a step
+
+
+def convergence_leg(pm, wl, form, K=500):
+    """K graph-replayed steps of the workload from the seeded init in one
+    form, with every step's energy, status word and shift kept on the
+    device.  Reports the first step at which the mean of E/N - E0/N over
+    the last WINDOW steps lies within TARGET_DE, the time to that step at
+    the leg's measured step time, the failure and shift-floor counts and
+    the mean over the last 100 steps with its standard error."""
+    import numpy as np
+    import torch
+    ham = pm.hamiltonian("tfim", J=wl.J, h=wl.h, pbc=wl.pbc)
+    m = pm.Model(wl.Lx, wl.Ly, wl.dim, wl.H, wl.complex_head, wl.marshall, wl.zero_mag,
+                 dtype="f32", seed=wl.seed, max_Ns=wl.Ns)
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    outs = m.step_outputs(wl.Ns)
+    g, _ = m.capture_step(ham, wl.Ns, wl.eta, wl.lam, wl.mu, mom, wl.key, ctr, form=form,
+                          ckpt_every=wl.ckpt_every, outputs=outs)
+    hist = torch.zeros((K, 3), dtype=torch.float64, device="cuda")
+    status = torch.zeros(K, dtype=torch.int32, device="cuda")
+    lam = torch.zeros(K, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        g.replay()
+        hist[i].copy_(outs["energy"], non_blocking=True)
+        status[i:i + 1].copy_(outs["status"], non_blocking=True)
+        lam[i:i + 1].copy_(outs["lambda_used"], non_blocking=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    tn = float(outs["tnorm"].item())
+    m.close()
+    del g
+    N = wl.Lx * wl.Ly
+    dE = hist.cpu().numpy()[:, 0] / N - wl.E0 / N
+    st = status.cpu().numpy()
+    lam = lam.cpu().numpy()
+    win = np.convolve(dE, np.ones(WINDOW) / WINDOW, mode="valid")
+    hit = np.nonzero(np.abs(win) <= TARGET_DE)[0]
+    steps_to = int(hit[0] + WINDOW) if len(hit) else None
+    ms = sec / K * 1e3
+    tail = dE[-100:]
+    return {"steps": K, "ms_per_step": ms,
+            "steps_to_target": steps_to,
+            "seconds_to_target": steps_to * ms * 1e-3 if steps_to else None,
+            "reached_target": steps_to is not None,
+            "dE_per_site_last100": [float(tail.mean()), float(tail.std() / math.sqrt(len(tail)))],
+            "failed_steps": int(np.count_nonzero(st & pm.ST_ERRORS)),
+            "not_pd_steps": int(np.count_nonzero(st & pm.ST_NOT_PD)),
+            "shift_floor_steps": int(np.count_nonzero(st & pm.ST_SHIFT_FLOOR)),
+            "lambda_used_min_max": [float(lam.min()), float(lam.max())],
+            "trace_norm_T_last": tn}
+
+
 def time_workload(pm, wl, steps=3):
     """One eager warmup step, then `steps` eager steps of one system in the
     BF16 + FP64 form with per-phase events; ms per step and phases."""
@@ -162,12 +225,12 @@ def time_workload(pm, wl, steps=3):
     t0 = time.perf_counter()
     for i in range(steps):
         st(1 + i)
-        bad += int(outs["status"].item() != 0)
+        bad += int(outs["status"].item() & pm.ST_ERRORS != 0)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     ph, n = m.timing_read()
     res = {"ms_per_step": dt * 1e3, "steps": steps, "Np": m.Np, "Ns": wl.Ns,
-           "N": wl.Lx * wl.Ly, "d_h": wl.H, "status_nonzero_steps": bad,
+           "N": wl.Lx * wl.Ly, "d_h": wl.H, "failed_steps": bad,
            "phase_ms": {k: v / max(n, 1) for k, v in ph.items()}}
     m.close()
     return res
@@ -195,16 +258,28 @@ def time_batch(pm, steps=2):
         b.step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    bad = sum(int(o["status"].item() != 0) for o in b.outputs)
+    bad = sum(int(o["status"].item() & pm.ST_ERRORS != 0) for o in b.outputs)
     b.close()
     for m in models:
         m.close()
     return {"ms_per_batch_step": dt * 1e3, "instance_steps_per_s": len(insts) / dt,
-            "instances": len(insts), "replays": steps, "status_nonzero_instances": bad}
+            "instances": len(insts), "replays": steps, "failed_instances": bad}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(wl):
-    """One full FP64 oracle step of the workload on the host cores."""
+    """One full FP64 oracle step of the workload on the host cores (all the
+    threads its numerical library uses), then one more with one thread."""
     import numpy as np
     from oracle import hamiltonian, minsr, model
     spec = model.Spec(Lx=wl.Lx, Ly=wl.Ly, dim=wl.dim, H=wl.H, complex_head=wl.complex_head,
@@ -212,17 +287,29 @@ def cpu_baseline(wl):
     th = model.glorot_init(spec, wl.seed)
     ham = hamiltonian.Ham("tfim", J=wl.J, h=wl.h, pbc=wl.pbc)
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    minsr.step(spec, th, np.zeros_like(th), ham, wl.Ns, wl.eta, wl.lam, wl.mu, wl.key, 0)
-    dt = time.perf_counter() - t0
+
+    def one():
+        t0 = time.perf_counter()
+        minsr.step(spec, th, np.zeros_like(th), ham, wl.Ns, wl.eta, wl.lam, wl.mu, wl.key, 0)
+        return time.perf_counter() - t0
+
+    dt = one()
+    dt1 = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            dt1 = one()
     return {"value": 1.0 / dt, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "value_1thread": (1.0 / dt1) if dt1 else None,
             "sample": "one full FP64 oracle step of the same workload (Ns=1024, N=64, d_h=64): "
                       "uniforms, sampling, local energies, Jacobian, Gram, Cholesky, update; "
-                      "%.1f s" % dt}
+                      "%.1f s with %d threads, %s s with one thread"
+                      % (dt, cores, "%.1f" % dt1 if dt1 else "n/a")}
 
 
 def roofline_entry(name, ms, units):
@@ -234,7 +321,9 @@ def roofline_entry(name, ms, units):
     if name == "jacobian":
         ach = units["jacobian_bytes"] / (ms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": TRAFFIC_BYTES["jacobian"], "ms": ms}
+                "frac": ach / PEAK_HBM_GBS, "traffic": TRAFFIC_BYTES["jacobian"], "ms": ms,
+                "bytes": units["jacobian_bytes"],
+                "achieved_with_gate_tape": units["jacobian_bytes_with_tape"] / (ms * 1e-3) / 1e9}
     if name == "solve":
         # FP64 factorisation on the FP64 matrix cores; a chain of dependent
         # 64 x 64 blocks, so latency rather than throughput sets its time
@@ -273,6 +362,10 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes,
                           "copies": 3}))
         return
+    if args.only_workload:
+        r = time_workload(pm, WORKLOADS[args.only_workload], steps=max(1, min(args.steps, 5)))
+        print(json.dumps({"workload": args.only_workload, **r}), flush=True)
+        return
     wl = WORKLOADS["tfim64"]
     K, W = args.steps, args.warmup
     units = work_units(wl)
@@ -298,19 +391,31 @@ def main():
 
     forms = {"bf16_fp64": {"steps_per_s": value, "ms_per_step": ms_step,
                            "dE_per_site_last100": dE(res["energy"]),
-                           "status_nonzero_steps": int(np.count_nonzero(res["status"]))}}
+                           "failed_steps": int(np.count_nonzero(res["status"] & pm.ST_ERRORS)),
+                           "shift_floor_steps": int(np.count_nonzero(res["status"]
+                                                                    & pm.ST_SHIFT_FLOOR))}}
     if not args.no_fp32:
         r32 = run_form(pm, wl, pm.FORM_FP32_PLAIN, K, W, graph=not args.eager)
         print("fp32_plain: %.3f s for %d steps" % (r32["seconds"], K), file=sys.stderr, flush=True)
         forms["fp32_plain"] = {"steps_per_s": K / r32["seconds"],
                                "ms_per_step": r32["seconds"] / K * 1e3,
                                "dE_per_site_last100": dE(r32["energy"]),
-                               "status_nonzero_steps": int(np.count_nonzero(r32["status"])),
+                               "failed_steps": int(np.count_nonzero(r32["status"] & pm.ST_ERRORS)),
                                "phase_ms": r32["phases"]}
 
     if "fp32_plain" in forms:
         (a, sa), (b, sb) = tail_mean(res["energy"]), tail_mean(r32["energy"])
         forms["dE_per_site_bf16_minus_fp32"] = [a - b, math.hypot(sa, sb)]
+
+    # the equal-energy condition of the metric, whatever --steps is: a
+    # training run of 500 steps per form from the seeded initialisation
+    conv = {"target_abs_dE_per_site": TARGET_DE, "window_steps": WINDOW}
+    for fname, fcode in (("bf16_fp64", pm.FORM_BF16_FP64), ("fp32_plain", pm.FORM_FP32_PLAIN)):
+        if fname == "fp32_plain" and args.no_fp32:
+            continue
+        conv[fname] = convergence_leg(pm, wl, fcode)
+        print("convergence %s: %s" % (fname, json.dumps(conv[fname])), file=sys.stderr,
+              flush=True)
 
     others = None
     if not args.no_workloads:
@@ -331,7 +436,11 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16-gram/f32-recurrence/f64-solve", "data": "synthetic",
+        "vs_baseline": None,
+        "dtype": "bf16 hi/lo O' and Gram (fp32 accumulate, fp64 flush); fp32 recurrence "
+                 "(local-energy state products as fp16 hi/lo pairs, fp32 accumulate); "
+                 "fp64 reductions, solve, update",
+        "data": "synthetic",
         "config": {"workload": "tfim64: 1D TFIM N=64 periodic J=h=1, 1D GRU pRNN d_h=64 "
                                "(13058 params), Ns=1024 (N+1 connected configs each), "
                                "BF16+FP64 form, lambda=1e-3, eta=0.05, mu=0.7, "
@@ -344,6 +453,7 @@ def main():
                    "step's stream over %d further eager steps of the same run"
                    % (K, "eager" if args.eager else "graph-replayed", res["kernel_steps"])),
         "forms": forms,
+        "convergence": conv,
         "E0_per_site": wl.E0 / N,
         "other_workloads": others,
         "cpu_baseline": cpu,
