@@ -684,3 +684,38 @@ def test_adaptive_step_reduces_to_plain_step():
     assert np.array_equal(a["dtheta"], b["dtheta"])
     assert np.array_equal(a["theta"], b["theta"])
     assert a["eta_used"] == 0.02 and a["lam_used"] == 1e-3
+
+
+# ------------------------------------------------ conditioning (App. E)
+
+from oracle import conditioning  # noqa: E402
+
+
+def test_condition_by_hand():
+    # diag(4, 1, 0), lambda = 1: kappa_2 = (4 + 1) / (0 + 1) = 5 and
+    # d = -log10(5 * 1e-7) = 7 - log10(5)
+    T = np.diag([4.0, 1.0, 0.0])
+    wmin, wmax, k, d = conditioning.condition(T, 1.0, 1e-7)
+    assert (wmin, wmax, k) == (0.0, 4.0, 5.0)
+    assert abs(d - (7.0 - math.log10(5.0))) < 1e-14
+    # no shift on a singular matrix: infinite condition, no reliable digit
+    assert conditioning.kappa2(np.array([0.0, 2.0]), 0.0) == math.inf
+    assert conditioning.digits(math.inf, 1e-16) == -math.inf
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_condition_matches_svd_condition_number(cplx):
+    # kappa_2 of T + lambda I from the spectrum equals the 2-norm condition
+    # number from the singular values (numpy's cond), and the spectrum has
+    # the trace and Frobenius norm of T
+    _, _, D, eps = _config1_inputs(cplx)
+    r = minsr.update(D, eps, 0.01, 1e-3)
+    T = r["T"]
+    for lam in (1e-3, 1e-1):
+        _, _, k, _ = conditioning.condition(T, lam, 2.0 ** -52)
+        ref = np.linalg.cond(T + lam * np.eye(T.shape[0]), 2)
+        assert abs(k - ref) < 1e-8 * ref
+    w = conditioning.spectrum(T)
+    assert abs(w.sum() - np.trace(T)) < 1e-10 * np.trace(T)
+    assert abs(np.sqrt((w * w).sum()) - np.linalg.norm(T)) < 1e-10 * np.linalg.norm(T)
+    assert np.all(np.diff(w) >= 0)
