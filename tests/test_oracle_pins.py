@@ -719,3 +719,42 @@ def test_condition_matches_svd_condition_number(cplx):
     assert abs(w.sum() - np.trace(T)) < 1e-10 * np.trace(T)
     assert abs(np.sqrt((w * w).sum()) - np.linalg.norm(T)) < 1e-10 * np.linalg.norm(T)
     assert np.all(np.diff(w) >= 0)
+
+
+# ------------------------------------------------ subsampled QGT (Prop. 3)
+
+from oracle import qgt  # noqa: E402
+
+
+def test_subsampled_S_is_real_part_of_empirical_qgt():
+    # Eq. SR: O' O'^T of the real form equals Re[(1/Ns) sum (O - Obar)(O - Obar)^dagger]
+    _, _, D, _ = _config1_inputs(True)
+    S = qgt.subsampled_S(D)
+    Xc = D - D.mean(axis=0)
+    ref = np.real(Xc.T @ np.conj(Xc)) / D.shape[0]
+    assert np.max(np.abs(S - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_qgt_estimator_mean_square_error_and_bound():
+    # i.i.d. draws from the exact Born distribution (N = 6 chain, cRNN):
+    # E ||Q - Q~||_F^2 = N_p^2 V_avg / N_s exactly (the identity behind
+    # Prop. 3), and the probability of exceeding the bound at epsilon stays
+    # below epsilon
+    spec = model.Spec(Lx=6, H=3, complex_head=True)
+    th = scaled_theta(spec, 73, 1.5)
+    pop = qgt.population(spec, th)
+    P = pop["P"]
+    assert abs(P.sum() - 1.0) < 1e-12
+    Np = pop["X"].shape[1]
+    rng = np.random.default_rng(5)
+    Ns, sets = 8, 3000
+    sq = np.empty(sets)
+    for t in range(sets):
+        idx = rng.choice(len(P), size=Ns, p=P)
+        sq[t] = np.linalg.norm(pop["Q"] - qgt.estimate(pop["X"][idx])) ** 2
+    expect = Np ** 2 * pop["V_avg"] / Ns
+    se = sq.std() / math.sqrt(sets)
+    assert abs(sq.mean() - expect) < 4 * se, (sq.mean(), expect, se)
+    for epsilon in (0.1, 0.3):
+        b = qgt.bound(Np, Ns, pop["V_avg"], epsilon)
+        assert np.mean(np.sqrt(sq) > b) <= epsilon
