@@ -263,6 +263,32 @@ int minsr_solve(minsr_model* m, int n, const double* dev_T, double lambda,
                 double pinv_cutoff, const double* dev_b, double* dev_x,
                 uint32_t* dev_status, hipStream_t s);
 
+/* ---- the parameter-space metric (Eq. SR; Prop. 3) -------------------------
+ * dev_S [Np x Np] FP64, row-major, exactly symmetric: S = O' O'^T with O'
+ * the centred real form of the log-derivatives of the Ns configurations
+ * dev_sigma (as minsr_jacobian with centred rows: Re rows then Im rows for
+ * a cRNN), i.e. S_ij = Re sum_s (O_si - mean_i)(O_sj - mean_j)^* / Ns, the
+ * subsampled SR metric of the samples.  Uses the handle's workspace.        */
+int minsr_param_gram(minsr_model* m, int Ns, const uint8_t* dev_sigma, double* dev_S,
+                     hipStream_t s);
+
+/* ---- spectrum and conditioning of T (App. E) ------------------------------
+ * The eigenvalues of the symmetric FP64 dev_T (n x n, row-major, read in
+ * full and left unchanged) in ascending order into dev_w [n], from the
+ * Householder tridiagonalisation and divide-and-conquer of the
+ * pseudo-inverse solve.  If dev_cond [4] is not NULL it receives
+ * (w_min, w_max, kappa_2(T + lambda I), d) with, for a positive
+ * semidefinite T, kappa_2 = (w_max + lambda) / (max(w_min, 0) + lambda) and
+ * the digit estimate d = -log10(kappa_2 eps) of App. E (eps: the machine
+ * epsilon of interest, e.g. 2^-52 for FP64, 2^-23 for FP32; an infinite
+ * kappa_2 gives d = -inf).  Uses the model's pseudo-inverse workspace
+ * (reserved with MINSR_OPT_PINV or by the first uncaptured call), so
+ * n <= min(max_Ns (2 max_Ns for a cRNN), 4096) and the call must not
+ * overlap other calls on the handle.  A non-finite entry of the
+ * tridiagonal form sets MINSR_ST_EIG_NOCONV in *dev_status.               */
+int minsr_spectrum(minsr_model* m, int n, const double* dev_T, double lambda, double eps,
+                   double* dev_w, double* dev_cond, uint32_t* dev_status, hipStream_t s);
+
 /* ---- the Cholesky solve without device allocation --------------------------
  * For callers that cannot allocate device memory (code under hip graph
  * capture, serving loops, harnesses that forbid hipMalloc): the same

@@ -27,7 +27,8 @@ SYMBOLS = (
     "minsr_local_energy", "minsr_jacobian", "minsr_logpsi_vjp", "minsr_step",
     "minsr_step_intermediates", "minsr_timing_begin", "minsr_timing_read",
     "minsr_batch_create", "minsr_batch_step", "minsr_batch_destroy", "minsr_set_tunable",
-    "minsr_get_tunable", "minsr_solve", "minsr_solve_noalloc",
+    "minsr_get_tunable", "minsr_solve", "minsr_solve_noalloc", "minsr_spectrum",
+    "minsr_param_gram",
 )
 OPT_PINV = 0x1
 PHASES = ("sample", "eloc", "eloc_sum_stats", "jacobian", "center", "gram", "gram_reduce",
@@ -101,6 +102,8 @@ def load_library(path=LIB_PATH):
         "minsr_timing_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)],
         "minsr_solve": [vp, i32, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp],
         "minsr_solve_noalloc": [i32, vp, ctypes.c_double, vp, vp, vp, vp],
+        "minsr_spectrum": [vp, i32, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp],
+        "minsr_param_gram": [vp, i32, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -248,6 +251,28 @@ class Model:
         _check(lib().minsr_solve(self.handle, n, _ptr(T), float(lam), float(pinv_cutoff), _ptr(b),
                                  _ptr(x), _ptr(status), _stream()))
         return x, status
+
+    def param_gram(self, sigma):
+        """S = O' O'^T (N_p x N_p): the SR metric of the configurations."""
+        sigma = sigma.to(device=self.device, dtype=torch.uint8).contiguous()
+        S = torch.empty((self.Np, self.Np), dtype=torch.float64, device=self.device)
+        _check(lib().minsr_param_gram(self.handle, sigma.shape[0], _ptr(sigma), _ptr(S),
+                                      _stream()))
+        return S
+
+    def spectrum(self, T, lam=0.0, eps=2.0 ** -52):
+        """Eigenvalues of the symmetric T (ascending) and (w_min, w_max,
+        kappa_2(T + lam I), -log10(kappa_2 eps)) as in App. E; returns
+        (w, cond, status)."""
+        T = T.to(device=self.device, dtype=torch.float64).contiguous()
+        n = T.shape[0]
+        assert T.shape == (n, n)
+        w = torch.empty(n, dtype=torch.float64, device=self.device)
+        cond = torch.empty(4, dtype=torch.float64, device=self.device)
+        status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _check(lib().minsr_spectrum(self.handle, n, _ptr(T), float(lam), float(eps), _ptr(w),
+                                    _ptr(cond), _ptr(status), _stream()))
+        return w, cond, status
 
     # ------------------------------------------------------------ one step
     def step(self, ham, Ns, eta, lam, mu, momentum, key, counter, form=FORM_FP64_REF,

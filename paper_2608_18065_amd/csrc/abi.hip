@@ -591,6 +591,43 @@ int minsr_solve(minsr_model* m, int n, const double* dev_T, double lambda, doubl
                                m->csync, dev_status, s);
 }
 
+int minsr_param_gram(minsr_model* m, int Ns, const uint8_t* dev_sigma, double* dev_S,
+                     hipStream_t s) {
+  int rc = check_ns(m, Ns);
+  if (rc) return rc;
+  if (!dev_sigma || !dev_S) return fail(MINSR_E_INVALID_ARG, "null argument");
+  if (Ns < 1) return fail(MINSR_E_SHAPE, "needs Ns >= 1");
+  const size_t Np = m->L.Np;
+  const int nb = m->cplx ? 2 : 1;
+  // log-derivative rows of the configurations (checkpoint stride 1),
+  // centred per block of Ns rows into the real form, then R^T R
+  void* tape = m->dim == 1 ? m->gates : nullptr;
+  rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
+                      m->states, 1, m->site, s, nullptr, tape);
+  if (rc) return rc;
+  rc = launch_jacobian(m, Ns, dev_sigma, m->states, 1, m->O, nullptr, nullptr, s, tape, m->site);
+  if (rc) return rc;
+  const int rdt = m->f64 ? MINSR_F64 : MINSR_F32;
+  rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, padded_ld(Np),
+                     s);
+  if (rc) return rc;
+  return launch_param_gram(m->R, m->f64, nb * Ns, (int)Np, padded_ld(Np), dev_S, s);
+}
+
+int minsr_spectrum(minsr_model* m, int n, const double* dev_T, double lambda, double eps,
+                   double* dev_w, double* dev_cond, uint32_t* dev_status, hipStream_t s) {
+  if (!m || !dev_T || !dev_w || !dev_status) return fail(MINSR_E_INVALID_ARG, "null argument");
+  const int rows_max = std::min((m->cplx ? 2 : 1) * m->d.max_Ns, 4096);
+  if (n < 0 || n > rows_max)
+    return fail(MINSR_E_SHAPE, "n = " + std::to_string(n) + " outside [0, " +
+                                   std::to_string(rows_max) + "]");
+  if (!(lambda >= 0.0) || !(eps > 0.0)) return fail(MINSR_E_INVALID_ARG, "lambda < 0 or eps <= 0");
+  const int rc = ensure_pinv_ws(m, s);
+  if (rc) return rc;
+  return launch_spectrum(n, dev_T, lambda, eps, dev_w, dev_cond, m->eig, m->eig_elems,
+                         m->eig_nmax, dev_status, s);
+}
+
 // ------------------------------------------------------------------ batch
 }  // extern "C"
 

@@ -783,15 +783,11 @@ __global__ __launch_bounds__(DCB) void k_dc_down_post(DcArgs a, int lev) {
 }
 
 // ================================================== driver
-int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* x, double* eig,
-                      size_t eig_elems, int nmax, uint32_t* status, hipStream_t s) {
-  if (n == 0) return MINSR_OK;
-  if (n > PINV_MAX_N)
-    return fail(MINSR_E_UNSUPPORTED, "pseudo-inverse solve: n = " + std::to_string(n) +
-                                         " above " + std::to_string(PINV_MAX_N));
-  if (!eig || eig_elems < pinv_workspace_doubles(nmax) || n > nmax)
-    return fail(MINSR_E_INVALID_ARG, "pseudo-inverse workspace missing or too small");
-  PinvWs w = carve(eig, n, nmax);
+// steps 1 and 2 (tridiagonalisation with b carried along, then the divide
+// and conquer merges up to the root), shared by the solve and the spectrum
+static int pinv_forward(int n, const double* T, const double* b, const PinvWs& w, int nmax,
+                        double cutoff, uint32_t* status, hipStream_t s, DcArgs& da,
+                        std::vector<size_t>& ubase) {
   TriArgs ta{w.A, w.V, w.W, w.tau, w.d, w.e, w.bq, w.g, w.s12, w.pc, w.pd, n};
   const size_t nn = (size_t)n * n;
   k_pinv_copy<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(T, w.A, nn, b, w.bq, n);
@@ -821,10 +817,10 @@ int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* 
   }
   // 2. divide and conquer, leaves at depth D
   const int D = depth_of(n);
-  DcArgs da{w, n, nmax, D, 0, 0, cutoff, status};
+  da = DcArgs{w, n, nmax, D, 0, 0, cutoff, status};
   k_dc_init<<<1, TBS, 0, s>>>(da);
   MINSR_CHECK_LAUNCH();
-  std::vector<size_t> ubase(D + 1, 0);
+  ubase.assign(D + 1, 0);
   {
     size_t u = 0;
     for (int l = 0; l <= D; ++l) { ubase[l] = u; u += u_level_elems(n, l); }
@@ -845,6 +841,78 @@ int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* 
     k_dc_ucols<<<dim3((unsigned)((mm + 3) / 4), nodes), 256, 0, s>>>(da, lev);
     MINSR_CHECK_LAUNCH();
   }
+  return MINSR_OK;
+}
+
+static int pinv_check(int n, const double* eig, size_t eig_elems, int nmax) {
+  if (n > PINV_MAX_N)
+    return fail(MINSR_E_UNSUPPORTED, "pseudo-inverse / spectrum: n = " + std::to_string(n) +
+                                         " above " + std::to_string(PINV_MAX_N));
+  if (!eig || eig_elems < pinv_workspace_doubles(nmax) || n > nmax)
+    return fail(MINSR_E_INVALID_ARG, "pseudo-inverse workspace missing or too small");
+  return MINSR_OK;
+}
+
+// the eigenvalues at the root (unscaled), in ascending order: position of
+// entry i = number of entries below it, ties broken by index
+__global__ __launch_bounds__(256) void k_eig_sorted(const double* ev, const double* scal, int n,
+                                                    double* w) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double v = ev[i];
+  int r = 0;
+  for (int j = 0; j < n; ++j) {
+    const double u = ev[j];
+    r += (u < v || (u == v && j < i)) ? 1 : 0;
+  }
+  w[r] = v * scal[0];
+}
+
+// App. E: (w_min, w_max, kappa_2(T + lambda I), d = -log10(kappa_2 eps)),
+// T positive semidefinite (w_min taken as max(w_min, 0))
+__global__ void k_condition(const double* w, int n, double lambda, double eps, double* cond) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double wmin = w[0], wmax = w[n - 1];
+  const double den = fmax(wmin, 0.0) + lambda;
+  const double k = den > 0.0 ? (wmax + lambda) / den : INFINITY;
+  cond[0] = wmin;
+  cond[1] = wmax;
+  cond[2] = k;
+  cond[3] = isfinite(k) ? -log10(k * eps) : -INFINITY;
+}
+
+int launch_spectrum(int n, const double* T, double lambda, double eps, double* w_out,
+                    double* cond, double* eig, size_t eig_elems, int nmax, uint32_t* status,
+                    hipStream_t s) {
+  if (n == 0) return MINSR_OK;
+  int rc = pinv_check(n, eig, eig_elems, nmax);
+  if (rc) return rc;
+  PinvWs w = carve(eig, n, nmax);
+  DcArgs da{};
+  std::vector<size_t> ubase;
+  // the carried vector plays no part in the eigenvalues: the first row of T
+  rc = pinv_forward(n, T, T, w, nmax, 0.0, status, s, da, ubase);
+  if (rc) return rc;
+  k_eig_sorted<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w.ev[0], w.scal, n, w_out);
+  MINSR_CHECK_LAUNCH();
+  if (cond) {
+    k_condition<<<1, 64, 0, s>>>(w_out, n, lambda, eps, cond);
+    MINSR_CHECK_LAUNCH();
+  }
+  return MINSR_OK;
+}
+
+int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* x, double* eig,
+                      size_t eig_elems, int nmax, uint32_t* status, hipStream_t s) {
+  if (n == 0) return MINSR_OK;
+  int rc = pinv_check(n, eig, eig_elems, nmax);
+  if (rc) return rc;
+  PinvWs w = carve(eig, n, nmax);
+  DcArgs da{};
+  std::vector<size_t> ubase;
+  rc = pinv_forward(n, T, b, w, nmax, cutoff, status, s, da, ubase);
+  if (rc) return rc;
+  const int D = da.D;
   // 3. weights at the root, then down the tree
   k_dc_root<<<1, TBS, 0, s>>>(da);
   MINSR_CHECK_LAUNCH();

@@ -137,6 +137,15 @@ size_t chol_vec_elems(int n);
 int launch_pinv_solve(int n, double* T, double cutoff, const double* b, double* x,
                       double* eig, size_t eig_elems, int nmax, uint32_t* status, hipStream_t s);
 size_t pinv_workspace_doubles(int nmax);
+// qgt.hip: S = R^T R over `rows` rows of R (row stride ld), N_p x N_p FP64
+int launch_param_gram(const void* R, int r_f64, int rows, int Np, size_t ld, double* S,
+                      hipStream_t s);
+// the eigenvalues of the symmetric T in ascending order into w_out (n <= 4096,
+// the pseudo-inverse workspace), and if cond is set (w_min, w_max,
+// kappa_2(T + lambda I), -log10(kappa_2 eps)) into cond[0..3]
+int launch_spectrum(int n, const double* T, double lambda, double eps, double* w_out,
+                    double* cond, double* eig, size_t eig_elems, int nmax, uint32_t* status,
+                    hipStream_t s);
 int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, double eta,
                   double mu, double* dpart, double* dtheta, double* momentum, double* theta,
                   uint32_t* status, int apply, hipStream_t s, const void* Rlo = nullptr,
