@@ -51,3 +51,67 @@ def rel_err(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.max(np.abs(a - b)) / max(1e-300, float(np.max(np.abs(b)))))
+
+
+def _draw_margins(spec, th, sigma, u):
+    """|u - p_i(0)| at every site of the given draws, with p_i(0) the
+    oracle's FP64 conditional along the drawn configuration."""
+    from oracle import model as omodel
+    run = omodel.run(spec, th, sigma=sigma)
+    P = omodel.unpack(spec, th)
+    Ns, N = sigma.shape
+    nup = np.zeros(Ns, dtype=np.int64)
+    ndn = np.zeros(Ns, dtype=np.int64)
+    out = np.empty((Ns, N))
+    for k in range(N):
+        _, p, _ = omodel.conditional(spec, P, run["hs"][:, k], nup, ndn)
+        out[:, k] = np.abs(u[:, k] - p[:, 0])
+        nup += sigma[:, k] == 0
+        ndn += sigma[:, k] == 1
+    return out
+
+
+# an FP32 conditional is within a few FP32 ulps of the FP64 one; a draw
+# whose uniform lies closer than this to the conditional is a tie
+FP32_TIE = 1e-6
+
+
+def low_precision_step(spec, m, gham, ham, Ns, eta, lam, key, counter, form, ckpt_every=1,
+                       pinv_cutoff=0.0):
+    """One step of a low-precision form against the FP64 oracle.  The FP32
+    sampler may only differ from the FP64 draws where the uniform ties with
+    the conditional to FP32 resolution: then the first differing site of
+    each differing sample must be such a tie, and the oracle's downstream
+    stages are re-run on the GPU's samples.  Anything else fails.
+    gham: the library's Hamiltonian; ham: the oracle's."""
+    import paper_2608_18065_amd as pm
+    from oracle import hamiltonian as oham
+    from oracle import jacobian as ojac
+    from oracle import minsr as ominsr
+    from oracle import philox
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    th = m.get_params().cpu().numpy()
+    o = m.step(gham, Ns, eta, lam, 0.0, mom, key, counter, form=form, ckpt_every=ckpt_every,
+               pinv_cutoff=pinv_cutoff)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) & pm.ST_ERRORS == 0
+    ref = ominsr.step(spec, th, np.zeros_like(th), ham, Ns, eta, lam, 0.0, key, counter,
+                      pinv_cutoff=pinv_cutoff)
+    u = philox.uniforms(key, counter, Ns, spec.N)
+    sig = o["sigma"].cpu().numpy()
+    diff = sig != ref["sigma"].astype(np.uint8)
+    margin = _draw_margins(spec, th, ref["sigma"], u)
+    if not diff.any():
+        return o, ref
+    rows = np.nonzero(diff.any(axis=1))[0]
+    assert len(rows) <= max(2, Ns // 200), "%d samples differ" % len(rows)
+    for r in rows:
+        k = int(np.argmax(diff[r]))
+        assert margin[r, k] < FP32_TIE, (r, k, margin[r, k])
+    # the oracle's stages on the GPU's samples (same arithmetic as its step)
+    lp = omodel.log_psi(spec, th, sig.astype(np.int64))
+    eps = oham.local_energy(spec, th, ham, sig.astype(np.int64), lp)
+    D = ojac.log_derivatives(spec, th, sig.astype(np.int64))
+    ref = ominsr.update(D, eps, eta, lam, pinv_cutoff)
+    ref.update(sigma=sig, eps=eps)
+    return o, ref

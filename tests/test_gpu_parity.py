@@ -10,7 +10,8 @@ from oracle import minsr as ominsr
 from oracle import model as omodel
 from oracle import philox
 from tests import refs
-from tests.gpu_common import gpu, make_pair, need_gpu, rel_err, scaled_theta, to_dev
+from tests.gpu_common import (gpu, low_precision_step, make_pair, need_gpu, rel_err,
+                              scaled_theta, to_dev)
 from workloads import random_configs
 
 pytestmark = gpu
@@ -331,58 +332,8 @@ def test_step_fp64_pinv_heisenberg2d():
     assert np.linalg.norm(d - ref["dtheta"]) / np.linalg.norm(ref["dtheta"]) < tol
 
 
-def _draw_margins(spec, th, sigma, u):
-    """|u - p_i(0)| at every site of the given draws, with p_i(0) the
-    oracle's FP64 conditional along the drawn configuration."""
-    run = omodel.run(spec, th, sigma=sigma)
-    P = omodel.unpack(spec, th)
-    Ns, N = sigma.shape
-    nup = np.zeros(Ns, dtype=np.int64)
-    ndn = np.zeros(Ns, dtype=np.int64)
-    out = np.empty((Ns, N))
-    for k in range(N):
-        _, p, _ = omodel.conditional(spec, P, run["hs"][:, k], nup, ndn)
-        out[:, k] = np.abs(u[:, k] - p[:, 0])
-        nup += sigma[:, k] == 0
-        ndn += sigma[:, k] == 1
-    return out
-
-
-# an FP32 conditional is within a few FP32 ulps of the FP64 one; a draw
-# whose uniform lies closer than this to the conditional is a tie
-FP32_TIE = 1e-6
-
-
 def _low_precision_step(spec, m, ham, Ns, eta, lam, key, counter, form):
-    """One step of a low-precision form against the FP64 oracle.  The FP32
-    sampler may only differ from the FP64 draws where the uniform ties with
-    the conditional to FP32 resolution: then the first differing site of
-    each differing sample must be such a tie, and the oracle's downstream
-    stages are re-run on the GPU's samples.  Anything else fails."""
-    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
-    th = m.get_params().cpu().numpy()
-    o = m.step(_gpu_ham(ham), Ns, eta, lam, 0.0, mom, key, counter, form=form)
-    torch.cuda.synchronize()
-    assert int(o["status"].item()) == 0
-    ref = ominsr.step(spec, th, np.zeros_like(th), ham, Ns, eta, lam, 0.0, key, counter)
-    u = philox.uniforms(key, counter, Ns, spec.N)
-    sig = o["sigma"].cpu().numpy()
-    diff = sig != ref["sigma"].astype(np.uint8)
-    margin = _draw_margins(spec, th, ref["sigma"], u)
-    if not diff.any():
-        return o, ref
-    rows = np.nonzero(diff.any(axis=1))[0]
-    assert len(rows) <= max(2, Ns // 200), "%d samples differ" % len(rows)
-    for r in rows:
-        k = int(np.argmax(diff[r]))
-        assert margin[r, k] < FP32_TIE, (r, k, margin[r, k])
-    # the oracle's stages on the GPU's samples (same arithmetic as its step)
-    lp = omodel.log_psi(spec, th, sig.astype(np.int64))
-    eps = oham.local_energy(spec, th, ham, sig.astype(np.int64), lp)
-    D = ojac.log_derivatives(spec, th, sig.astype(np.int64))
-    ref = ominsr.update(D, eps, eta, lam)
-    ref.update(sigma=sig, eps=eps)
-    return o, ref
+    return low_precision_step(spec, m, _gpu_ham(ham), ham, Ns, eta, lam, key, counter, form)
 
 
 @pytest.mark.parametrize("form,tol", [(1, 2e-2), (2, 2e-2), (3, 2e-2)],
