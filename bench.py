@@ -69,7 +69,7 @@ def parse():
                     help="skip the short timings of the cluster100, heis10x10 and J1-J2 batch "
                          "systems")
     ap.add_argument("--only-workload", default="", metavar="NAME",
-                    help="only time NAME (cluster100 or heis10x10: a few BF16 + FP64 steps "
+                    help="only time NAME (tfim64, cluster100 or heis10x10: a few BF16 + FP64 steps "
                          "with per-phase events; for profiler runs), print its JSON, exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (for scaling the HBM "

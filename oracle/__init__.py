@@ -20,6 +20,14 @@ Modules
                hand-written reverse pass through the GRU recurrence.
   minsr        centring, real form, T, regularised solve, update with
                momentum (Eqs. lstsq, real-valued, minsrR; Alg. 1; App. B).
+  adaptive     trust-region rate, lambda = c ||T||^(2/3) schedule and
+               Levenberg-Marquardt damping (Sec. 3.3; Apps. F, G).
+  conditioning spectrum of T, kappa_2(T + lambda I) and the digit estimate
+               of App. E.
+  qgt          population and subsampled QGT, the bound of Prop. 3 (App. H).
+  linear_rnn   the linear recurrent test model of App. C: forward, sampling,
+               log-derivatives, gauge directions (Prop. 1), population S
+               and the closed form of Prop. 2.
 
 Pins (tests marked "not gpu") tie every function to something other than
 itself: exact enumeration, dense exact diagonalisation, closed forms,
