@@ -102,7 +102,10 @@ extern "C" {
  *                 at creation (about 2.2 n^2 doubles for n = max_Ns, or
  *                 2 max_Ns for a cRNN; n <= 4096); without it the workspace
  *                 is allocated by the first pseudo-inverse call, which
- *                 therefore must not be captured into a graph             */
+ *                 therefore must not be captured into a graph.
+ *                 Bit MINSR_OPT_LINEAR makes the handle the linear
+ *                 recurrent test model of App. C instead of a GRU (see
+ *                 below)                                                  */
 typedef struct {
   int32_t Lx, Ly, dim, hidden;
   int32_t complex_head, marshall, zero_mag;
@@ -111,7 +114,23 @@ typedef struct {
   int32_t max_Ns;
   int32_t options;
 } minsr_model_desc;
-#define MINSR_OPT_PINV  0x1
+#define MINSR_OPT_PINV    0x1
+/* The linear recurrent test model of App. C (Eq. linear_rnn): a real,
+ * positive wave function over N = Lx sites with h_0 = 0,
+ *   z_i = U h_{i-1} + c,  p_i = softmax(z_i),
+ *   h_i = W h_{i-1} + V onehot(sigma_i) + b,
+ *   log Psi = (1/2) sum_i log p_i[sigma_i]   (re part; im part 0),
+ * theta = (W [H x H], V [H x 2], b [H], U [2 x H], c [2]) row-major in that
+ * order, N_p = H^2 + 5H + 2.  It needs dim = 1, Ly = 1, no complex head,
+ * Marshall sign or S^z mask, compute_dtype MINSR_F64 and hidden 8, 16, 32
+ * or 64; W, V and U start Glorot-uniform as above, b and c at zero.  Its
+ * exact gauge zero modes (Prop. 1) and closed-form bias element (Prop. 2)
+ * make it a check of the log-derivative, centring and Gram kernels that
+ * does not depend on the GRU.  Supported calls: minsr_num_params,
+ * minsr_num_sites, minsr_get/set_params, minsr_sample, minsr_logpsi,
+ * minsr_jacobian, minsr_param_gram, minsr_gram, minsr_solve and
+ * minsr_spectrum; the others return MINSR_E_UNSUPPORTED.                  */
+#define MINSR_OPT_LINEAR  0x2
 
 typedef struct {
   int32_t kind;      /* MINSR_HAM_*                                      */
@@ -271,6 +290,18 @@ int minsr_solve(minsr_model* m, int n, const double* dev_T, double lambda,
  * subsampled SR metric of the samples.  Uses the handle's workspace.        */
 int minsr_param_gram(minsr_model* m, int Ns, const uint8_t* dev_sigma, double* dev_S,
                      hipStream_t s);
+
+/* ---- the sample-space Gram matrix of one form (Alg. 1; Eq. real-valued) ---
+ * dev_T [n x n] FP64, n = Ns (2 Ns for a cRNN): T = O' O'^T of the centred
+ * real form O' of the log-derivatives of the configurations dev_sigma (as
+ * minsr_jacobian with centred rows, scaled by 1/sqrt(Ns)), formed with the
+ * arithmetic of `form` (MINSR_FORM_*): FP64 throughout; BF16 hi/lo split
+ * operands on BF16 MFMA (four products, or one for MINSR_FORM_BF16_1PASS)
+ * with FP32 accumulation flushed to FP64; or FP32 (MINSR_FORM_FP32_PLAIN,
+ * widened to FP64 on output) -- the T a minSR step of that form solves
+ * with.  FP64_REF needs an FP64 model.  Uses the handle's workspace.      */
+int minsr_gram(minsr_model* m, int Ns, const uint8_t* dev_sigma, int form, double* dev_T,
+               hipStream_t s);
 
 /* ---- spectrum and conditioning of T (App. E) ------------------------------
  * The eigenvalues of the symmetric FP64 dev_T (n x n, row-major, read in

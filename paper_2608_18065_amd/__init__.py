@@ -28,9 +28,10 @@ SYMBOLS = (
     "minsr_step_intermediates", "minsr_timing_begin", "minsr_timing_read",
     "minsr_batch_create", "minsr_batch_step", "minsr_batch_destroy", "minsr_set_tunable",
     "minsr_get_tunable", "minsr_solve", "minsr_solve_noalloc", "minsr_spectrum",
-    "minsr_param_gram",
+    "minsr_param_gram", "minsr_gram",
 )
 OPT_PINV = 0x1
+OPT_LINEAR = 0x2
 PHASES = ("sample", "eloc", "eloc_sum_stats", "jacobian", "center", "gram", "gram_reduce",
           "solve", "update", "repack")
 
@@ -104,6 +105,7 @@ def load_library(path=LIB_PATH):
         "minsr_solve_noalloc": [i32, vp, ctypes.c_double, vp, vp, vp, vp],
         "minsr_spectrum": [vp, i32, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp],
         "minsr_param_gram": [vp, i32, vp, vp, vp],
+        "minsr_gram": [vp, i32, vp, i32, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -149,10 +151,12 @@ class Model:
     """One GRU wave function on the current HIP device (Sec. 2, App. A)."""
 
     def __init__(self, Lx, Ly=1, dim=1, hidden=16, complex_head=False, marshall=False,
-                 zero_mag=False, dtype="f64", seed=0, max_Ns=1024, pinv=False):
+                 zero_mag=False, dtype="f64", seed=0, max_Ns=1024, pinv=False, linear=False):
+        """linear=True: the linear recurrent test model of App. C over Lx sites
+        (theta = W, V, b, U, c; FP64, 1D, real) instead of a GRU."""
+        opts = (OPT_PINV if pinv else 0) | (OPT_LINEAR if linear else 0)
         self.desc = ModelDesc(Lx, Ly, dim, hidden, int(complex_head), int(marshall),
-                              int(zero_mag), F64 if dtype == "f64" else F32, seed, max_Ns,
-                              OPT_PINV if pinv else 0)
+                              int(zero_mag), F64 if dtype == "f64" else F32, seed, max_Ns, opts)
         h = ctypes.c_void_p()
         _check(lib().minsr_create_model(ctypes.byref(self.desc), ctypes.byref(h)))
         self.handle = h
@@ -259,6 +263,16 @@ class Model:
         _check(lib().minsr_param_gram(self.handle, sigma.shape[0], _ptr(sigma), _ptr(S),
                                       _stream()))
         return S
+
+    def gram(self, sigma, form=FORM_FP64_REF):
+        """T = O' O'^T (rows x rows) of the configurations, formed with the
+        arithmetic of a minSR step of `form`, as FP64."""
+        sigma = sigma.to(device=self.device, dtype=torch.uint8).contiguous()
+        Ns = sigma.shape[0]
+        n = Ns * (2 if self.complex_head else 1)
+        T = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        _check(lib().minsr_gram(self.handle, Ns, _ptr(sigma), int(form), _ptr(T), _stream()))
+        return T
 
     def spectrum(self, T, lam=0.0, eps=2.0 ** -52):
         """Eigenvalues of the symmetric T (ascending) and (w_min, w_max,

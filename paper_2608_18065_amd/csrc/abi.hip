@@ -49,6 +49,11 @@ __global__ void k_vjp(const TO* O, int Ns, int two, size_t Np, const double* g, 
   out[col] = s * scale;
 }
 
+__global__ void k_widen(const float* a, size_t n, double* out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)a[i];
+}
+
 static int alloc(void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMalloc(p, bytes);
@@ -107,8 +112,17 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   *out = nullptr;
   if (d->dim != 1 && d->dim != 2) return fail(MINSR_E_INVALID_ARG, "dim must be 1 or 2");
   const int H = d->hidden;
+  const bool linear = (d->options & MINSR_OPT_LINEAR) != 0;
   if (H != 8 && H != 16 && H != 32 && H != 64 && H != 128)
     return fail(MINSR_E_UNSUPPORTED, "hidden width must be 8, 16, 32, 64 or 128");
+  if (linear) {
+    if (d->dim != 1 || d->Ly != 1 || d->complex_head || d->marshall || d->zero_mag)
+      return fail(MINSR_E_INVALID_ARG, "the linear test model is a real 1D chain without "
+                                       "phase head, Marshall sign or S^z mask");
+    if (d->compute_dtype != MINSR_F64)
+      return fail(MINSR_E_INVALID_ARG, "the linear test model computes in FP64");
+    if (H > 64) return fail(MINSR_E_UNSUPPORTED, "linear test model: hidden width at most 64");
+  }
   if (d->Lx < 2 || d->Ly < 1) return fail(MINSR_E_INVALID_ARG, "lattice too small");
   if (d->dim == 1 && d->Ly != 1) return fail(MINSR_E_INVALID_ARG, "1D models need Ly == 1");
   if (d->dim == 2 && (d->Ly < 2 || d->Lx > 16))
@@ -119,7 +133,8 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   if (d->compute_dtype != MINSR_F64 && d->compute_dtype != MINSR_F32)
     return fail(MINSR_E_INVALID_ARG, "compute_dtype must be MINSR_F64 or MINSR_F32");
   if (d->max_Ns < 1 || d->max_Ns > (1 << 16)) return fail(MINSR_E_INVALID_ARG, "max_Ns out of range");
-  if (d->options & ~MINSR_OPT_PINV) return fail(MINSR_E_INVALID_ARG, "unknown option bits");
+  if (d->options & ~(MINSR_OPT_PINV | MINSR_OPT_LINEAR))
+    return fail(MINSR_E_INVALID_ARG, "unknown option bits");
 
   minsr_model* m = new (std::nothrow) minsr_model();
   if (!m) return fail(MINSR_E_NOMEM, "host allocation failed");
@@ -127,7 +142,13 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   m->N = N; m->H = H; m->dim = d->dim; m->cplx = d->complex_head ? 1 : 0;
   m->ds = d->dim == 1 ? 2 : 4;
   m->f64 = d->compute_dtype == MINSR_F64;
+  m->linear = linear ? 1 : 0;
   m->L = make_layout(m->dim, H, m->cplx);
+  if (linear) {
+    m->L = Layout{};
+    m->L.H = H; m->L.ds = 2; m->L.dim = 1;
+    m->L.Np = linear_num_params(H);
+  }
   if (hipGetDevice(&m->device) != hipSuccess) { delete m; return fail(MINSR_E_DEVICE, "no HIP device"); }
 
   const size_t Np = m->L.Np, S = (size_t)d->max_Ns, Nz = (size_t)N, Hz = (size_t)H;
@@ -176,7 +197,7 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
 
   int rc = MINSR_OK;
   rc = rc ? rc : alloc((void**)&m->theta, Np * 8);
-  size_t pk = packed_elems(m);
+  size_t pk = linear ? 1 : packed_elems(m);
   m->work_elems = pk;
   rc = rc ? rc : alloc(&m->work, pk * sz);
   rc = rc ? rc : alloc((void**)&m->nbr, nbr.size() * sizeof(int));
@@ -229,9 +250,13 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
     e = hipMemcpy(m->bonds, bonds.data(), bonds.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(m->eloc_q, 0, 16);
   if (e != hipSuccess) { release(m); delete m; return fail(MINSR_E_DEVICE, hipGetErrorString(e)); }
-  bind_work(m);
-  rc = launch_init_theta(m, nullptr);
-  if (!rc) rc = launch_pack(m, nullptr);
+  if (linear) {
+    rc = launch_linear_init(m, nullptr);
+  } else {
+    bind_work(m);
+    rc = launch_init_theta(m, nullptr);
+    if (!rc) rc = launch_pack(m, nullptr);
+  }
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = fail(MINSR_E_DEVICE, "initialisation failed");
   if (rc) { release(m); delete m; return rc; }
   *out = m;
@@ -267,7 +292,7 @@ int minsr_get_params(minsr_model* m, double* dev_theta, hipStream_t s) {
 int minsr_set_params(minsr_model* m, const double* dev_theta, hipStream_t s) {
   if (!m || !dev_theta) return fail(MINSR_E_INVALID_ARG, "null argument");
   MINSR_HIP(hipMemcpyAsync(m->theta, dev_theta, m->L.Np * 8, hipMemcpyDeviceToDevice, s));
-  return launch_pack(m, s);
+  return m->linear ? MINSR_OK : launch_pack(m, s);   // the linear model reads theta itself
 }
 
 static int check_ns(minsr_model* m, int Ns) {
@@ -283,6 +308,8 @@ int minsr_sample(minsr_model* m, int Ns, const double* dev_uniforms, uint64_t ke
   int rc = check_ns(m, Ns);
   if (rc) return rc;
   if (!dev_sigma || !dev_logpsi) return fail(MINSR_E_INVALID_ARG, "null output");
+  if (m->linear)
+    return launch_linear_forward(m, 0, Ns, dev_uniforms, key, counter, dev_sigma, dev_logpsi, s);
   return launch_forward(m, 0, Ns, dev_uniforms, key, counter, dev_sigma, dev_logpsi, m->states, 1,
                         m->site, s);
 }
@@ -292,11 +319,15 @@ int minsr_logpsi(minsr_model* m, int Ns, const uint8_t* dev_sigma, double* dev_l
   int rc = check_ns(m, Ns);
   if (rc) return rc;
   if (!dev_sigma || !dev_logpsi) return fail(MINSR_E_INVALID_ARG, "null argument");
+  if (m->linear)
+    return launch_linear_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma),
+                                 dev_logpsi, s);
   return launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), dev_logpsi,
                         m->states, 1, m->site, s);
 }
 
 static int check_ham(minsr_model* m, const minsr_hamiltonian* H) {
+  if (m->linear) return fail(MINSR_E_UNSUPPORTED, "the linear test model has no local energies");
   if (!H) return fail(MINSR_E_INVALID_ARG, "null Hamiltonian");
   if (H->kind == MINSR_HAM_TFIM || H->kind == MINSR_HAM_CLUSTER) {
     if (m->dim != 1) return fail(MINSR_E_UNSUPPORTED, "TFIM / cluster need a 1D model");
@@ -338,6 +369,17 @@ int minsr_jacobian(minsr_model* m, int Ns, const uint8_t* dev_sigma, int out_dty
     return fail(MINSR_E_INVALID_ARG, "BF16 output requires centred rows");
   if (ckpt_every < 1 || ckpt_every > 16) return fail(MINSR_E_INVALID_ARG, "ckpt_every in [1, 16]");
   if (centered && !dev_colmean) return fail(MINSR_E_INVALID_ARG, "centred output needs dev_colmean");
+  if (m->linear) {
+    rc = launch_linear_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma),
+                               m->logpsi, s);
+    if (rc) return rc;
+    if (!centered && out_dtype == MINSR_F64)
+      return launch_linear_jacobian(m, Ns, dev_sigma, (double*)dev_O, s);
+    rc = launch_linear_jacobian(m, Ns, dev_sigma, (double*)m->O, s);
+    if (rc) return rc;
+    return launch_center(Ns, 1, m->L.Np, m->O, 1, dev_O, out_dtype, m->colpart,
+                         centered ? dev_colmean : nullptr, m->L.Np, s);
+  }
   const int C = m->dim == 1 ? ckpt_every : 1;
   void* tape = C == 1 ? m->gates : nullptr;
   double* site = m->site;   // the pass's per-site conditionals
@@ -360,6 +402,7 @@ int minsr_logpsi_vjp(minsr_model* m, int Ns, const uint8_t* dev_sigma, const dou
   int rc = check_ns(m, Ns);
   if (rc) return rc;
   if (!dev_sigma || !dev_g || !dev_grad_theta) return fail(MINSR_E_INVALID_ARG, "null argument");
+  if (m->linear) return fail(MINSR_E_UNSUPPORTED, "vjp: not for the linear test model");
   if (Ns == 0) {
     MINSR_HIP(hipMemsetAsync(dev_grad_theta, 0, m->L.Np * 8, s));
     return MINSR_OK;
@@ -591,6 +634,21 @@ int minsr_solve(minsr_model* m, int n, const double* dev_T, double lambda, doubl
                                m->csync, dev_status, s);
 }
 
+// raw log-derivative rows of the configurations into the handle's O
+// (checkpoint stride 1)
+static int raw_rows(minsr_model* m, int Ns, const uint8_t* dev_sigma, hipStream_t s) {
+  if (m->linear) {
+    int rc = launch_linear_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma),
+                                   m->logpsi, s);
+    return rc ? rc : launch_linear_jacobian(m, Ns, dev_sigma, (double*)m->O, s);
+  }
+  void* tape = m->dim == 1 ? m->gates : nullptr;
+  int rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
+                          m->states, 1, m->site, s, nullptr, tape);
+  if (rc) return rc;
+  return launch_jacobian(m, Ns, dev_sigma, m->states, 1, m->O, nullptr, nullptr, s, tape, m->site);
+}
+
 int minsr_param_gram(minsr_model* m, int Ns, const uint8_t* dev_sigma, double* dev_S,
                      hipStream_t s) {
   int rc = check_ns(m, Ns);
@@ -599,19 +657,48 @@ int minsr_param_gram(minsr_model* m, int Ns, const uint8_t* dev_sigma, double* d
   if (Ns < 1) return fail(MINSR_E_SHAPE, "needs Ns >= 1");
   const size_t Np = m->L.Np;
   const int nb = m->cplx ? 2 : 1;
-  // log-derivative rows of the configurations (checkpoint stride 1),
-  // centred per block of Ns rows into the real form, then R^T R
-  void* tape = m->dim == 1 ? m->gates : nullptr;
-  rc = launch_forward(m, 1, Ns, nullptr, 0, 0, const_cast<uint8_t*>(dev_sigma), m->logpsi,
-                      m->states, 1, m->site, s, nullptr, tape);
-  if (rc) return rc;
-  rc = launch_jacobian(m, Ns, dev_sigma, m->states, 1, m->O, nullptr, nullptr, s, tape, m->site);
+  // log-derivative rows, centred per block of Ns rows into the real form,
+  // then R^T R
+  rc = raw_rows(m, Ns, dev_sigma, s);
   if (rc) return rc;
   const int rdt = m->f64 ? MINSR_F64 : MINSR_F32;
   rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, padded_ld(Np),
                      s);
   if (rc) return rc;
   return launch_param_gram(m->R, m->f64, nb * Ns, (int)Np, padded_ld(Np), dev_S, s);
+}
+
+int minsr_gram(minsr_model* m, int Ns, const uint8_t* dev_sigma, int form, double* dev_T,
+               hipStream_t s) {
+  int rc = check_ns(m, Ns);
+  if (rc) return rc;
+  if (!dev_sigma || !dev_T) return fail(MINSR_E_INVALID_ARG, "null argument");
+  if (Ns < 1) return fail(MINSR_E_SHAPE, "needs Ns >= 1");
+  if (form < 0 || form > 3) return fail(MINSR_E_INVALID_ARG, "unknown form");
+  if (form == MINSR_FORM_FP64_REF && !m->f64)
+    return fail(MINSR_E_INVALID_ARG, "the FP64 reference form needs an FP64 model");
+  const size_t Np = m->L.Np;
+  const int nb = m->cplx ? 2 : 1;
+  const int n = nb * Ns;
+  const int rdt = form == MINSR_FORM_FP64_REF ? MINSR_F64
+                  : form == MINSR_FORM_FP32_PLAIN ? MINSR_F32 : MINSR_BF16;
+  void* Rlo = form == MINSR_FORM_BF16_FP64
+                  ? (void*)((__hip_bfloat16*)m->R + (size_t)n * padded_ld(Np))
+                  : nullptr;
+  rc = raw_rows(m, Ns, dev_sigma, s);
+  if (rc) return rc;
+  rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean, padded_ld(Np), s,
+                     Rlo);
+  if (rc) return rc;
+  // the FP32 form produces an FP32 T in the handle's buffer, widened here
+  double* Tout = rdt == MINSR_F32 ? m->T : dev_T;
+  rc = launch_gram(n, Np, m->R, rdt, Tout, m->gpart, m->gpart_elems, s, 3, Rlo,
+                   m->tune_gram_split);
+  if (rc || rdt != MINSR_F32) return rc;
+  const size_t nn = (size_t)n * n;
+  k_widen<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>((const float*)m->T, nn, dev_T);
+  MINSR_CHECK_LAUNCH();
+  return MINSR_OK;
 }
 
 int minsr_spectrum(minsr_model* m, int n, const double* dev_T, double lambda, double eps,
@@ -662,6 +749,8 @@ int minsr_batch_create(minsr_model* const* models, const minsr_hamiltonian* hams
   *out = nullptr;
   for (int i = 0; i < count; ++i) {
     if (!models[i]) return fail(MINSR_E_INVALID_ARG, "null model in batch");
+    if (models[i]->linear)
+      return fail(MINSR_E_UNSUPPORTED, "the linear test model has no minSR step");
     if (!states[i].dev_counter)
       return fail(MINSR_E_INVALID_ARG, "batch instances need a device-side Philox counter");
     for (int j = 0; j < i; ++j)

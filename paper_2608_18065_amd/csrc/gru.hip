@@ -28,12 +28,6 @@ __device__ inline double d_log1p(double x) { return log1p(x); }
 template <typename T> __device__ inline T d_sigmoid(T x) { return T(1) / (T(1) + d_exp(-x)); }
 
 // ------------------------------------------------------------------ init
-struct InitBlocks {
-  int n;
-  long long off[16], size[16];
-  double a[16];  // Glorot half-width, 0 for biases
-};
-
 __global__ void k_init_theta(double* theta, long long Np, InitBlocks b, uint64_t seed) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Np) return;
@@ -64,8 +58,12 @@ int launch_init_theta(minsr_model* m, hipStream_t s) {
   add(L.Wu, H, H + ds, true); add(L.Wr, H, H + ds, true); add(L.Wh, H, H, true);
   add(L.Win, H, ds, true); add(L.U, 2, H, true);
   if (L.cplx) add(L.Uphi, 2, H, true);
-  long long Np = (long long)L.Np;
-  k_init_theta<<<(unsigned)((Np + 255) / 256), 256, 0, s>>>(m->theta, Np, b, m->d.init_seed);
+  return launch_init_blocks(m->theta, (long long)L.Np, b, m->d.init_seed, s);
+}
+
+int launch_init_blocks(double* theta, long long Np, const InitBlocks& b, uint64_t seed,
+                       hipStream_t s) {
+  k_init_theta<<<(unsigned)((Np + 255) / 256), 256, 0, s>>>(theta, Np, b, seed);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
 }

@@ -7,6 +7,7 @@ struct minsr_model {
   minsr_model_desc d;
   int N, H, dim, cplx, ds;
   int f64;                 // compute precision: 1 double, 0 float
+  int linear = 0;          // the linear recurrent test model (MINSR_OPT_LINEAR)
   minsr::Layout L;
   int device;
 
@@ -76,6 +77,16 @@ struct minsr_model {
 namespace minsr {
 
 // gru.hip
+// parameter blocks of theta: Glorot-uniform a (2u - 1) with half-width a,
+// u the Philox4x64-10 uniform of (init seed, parameter index); zero where
+// a = 0 or outside every block
+struct InitBlocks {
+  int n;
+  long long off[16], size[16];
+  double a[16];  // Glorot half-width, 0 for biases
+};
+int launch_init_blocks(double* theta, long long Np, const InitBlocks& b, uint64_t seed,
+                       hipStream_t s);
 int launch_init_theta(minsr_model* m, hipStream_t s);
 int launch_pack(minsr_model* m, hipStream_t s);
 // mode 0: sample, 1: evaluate.  states/site may be null.
@@ -151,5 +162,18 @@ int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, d
                   uint32_t* status, int apply, hipStream_t s, const void* Rlo = nullptr,
                   uint64_t* bump = nullptr);
 int launch_reduce_rows(int rows, size_t Np, const double* part, double* out, hipStream_t s);
+// linear.hip: the linear recurrent test model (model option MINSR_OPT_LINEAR)
+size_t linear_num_params(int H);
+int launch_linear_init(minsr_model* m, hipStream_t s);
+// mode 0: sample (uniforms, or Philox(key, counter) if null), 1: evaluate;
+// stores the states h_{i-1} and log p_i(0), log p_i(1) into the model's
+// workspace for the Jacobian
+int launch_linear_forward(minsr_model* m, int mode, int Ns, const double* uniforms,
+                          uint64_t key, uint64_t counter, uint8_t* sigma, double* logpsi,
+                          hipStream_t s);
+// raw rows d log Psi / d theta / sqrt(Ns) (FP64) of the configurations the
+// last forward pass evaluated
+int launch_linear_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, double* O,
+                           hipStream_t s);
 
 }  // namespace minsr

@@ -21,18 +21,7 @@ import numpy as np
 import pytest
 
 from oracle import linear_rnn as lr
-
-
-def _theta(H, seed, scale=0.6, diag=None):
-    rng = np.random.default_rng(seed)
-    W = scale * rng.standard_normal((H, H)) / np.sqrt(H)
-    if diag is not None:
-        W = np.diag(np.asarray(diag, dtype=float))
-    V = rng.standard_normal((H, 2))
-    b = 0.3 * rng.standard_normal(H)
-    U = rng.standard_normal((2, H)) / np.sqrt(H)
-    c = 0.2 * rng.standard_normal(2)
-    return lr.pack(W, V, b, U, c)
+from tests.inputs import linear_theta as _theta
 
 
 def test_layout_order_and_size():
