@@ -458,8 +458,11 @@ __global__ __launch_bounds__(256) void k_forward(FwdArgs<T> a) {
             if (a.mode == MODE_ELOC && q <= k0) return a.states_in[((size_t)s * N + q) * H + j];
             return a.ring[(slot * a.W + (q % a.W)) * H + j];
           };
+          // an inactive sequence (sample index clamped to 0) takes no spin
+          // input: while sampling, row 0 of sigma_out may not be written yet,
+          // and a byte that is not 0 or 1 must never index the input columns
           auto spin = [&](int q) -> int {
-            if (q < 0) return -1;
+            if (q < 0 || !act[r]) return -1;
             int v = a.mode == MODE_SAMPLE ? a.sigma_out[(size_t)s * N + q]
                                           : a.sigma_in[(size_t)s * N + q];
             if (a.mode == MODE_ELOC && (q == f1 || q == f2p)) v ^= 1;

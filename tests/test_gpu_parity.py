@@ -65,6 +65,26 @@ def test_sample_bitexact_and_logpsi(arch):
     assert np.array_equal(lp2.cpu().numpy(), lp.cpu().numpy())
 
 
+@pytest.mark.parametrize("arch", [a for a in ARCHS if a.get("dim") == 2], ids=_ids)
+def test_sample_2d_ragged_tail_ignores_output_contents(arch):
+    # the inactive sequences of the last workgroup (Ns not a multiple of the
+    # sequences per workgroup) take no spin input from the output rows, whose
+    # bytes are not yet written: sampling into a buffer of 0xFF bytes gives
+    # the oracle's configurations
+    spec, m = make_pair(**arch)
+    th = scaled_theta(spec, 7, 2.0)
+    m.set_params(to_dev(th))
+    Ns = 37
+    u = philox.uniforms(1001, 3, Ns, spec.N)
+    sig_ref, lp_ref = omodel.sample(spec, th, u)
+    out = torch.full((Ns, spec.N), 255, dtype=torch.uint8, device="cuda")
+    sig, lp = m.sample(Ns, uniforms=to_dev(u), sigma_out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(sig.cpu().numpy(), sig_ref.astype(np.uint8))
+    assert rel_err(lp.cpu().numpy(), lp_ref) < 1e-12
+    m.close()
+
+
 @pytest.mark.parametrize("arch", ARCHS, ids=_ids)
 def test_logpsi_random_configs(arch):
     spec, m = make_pair(**arch)
