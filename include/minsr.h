@@ -320,6 +320,54 @@ int minsr_gram(minsr_model* m, int Ns, const uint8_t* dev_sigma, int form, doubl
 int minsr_spectrum(minsr_model* m, int n, const double* dev_T, double lambda, double eps,
                    double* dev_w, double* dev_cond, uint32_t* dev_status, hipStream_t s);
 
+/* ---- one minSR iteration with adaptive regularisation ---------------------
+ * (Sec. 3.3; Apps. F and G.)  The iteration of minsr_step with three
+ * optional changes, chosen by ad:
+ *   lambda_mode  MINSR_LAMBDA_CONST: the shift is cfg->lambda, as in
+ *                minsr_step.
+ *                MINSR_LAMBDA_POW23: the shift is cfg->lambda * ||T||_F^(2/3)
+ *                (Sec. 3.3 schedule; the paper's 2D runs take the
+ *                coefficient 3e-4), ||T||_F the Frobenius norm of the
+ *                step's T.
+ *                MINSR_LAMBDA_LM: the shift is *ad->dev_lambda, a damping
+ *                carried from step to step (cfg->lambda is not used).
+ *                After the update direction dtheta is formed, Ns fresh
+ *                samples of the trial parameters theta - dtheta (Philox key
+ *                st->key, counter st->counter XOR 2^63) give the trial
+ *                energy E_t, and App. G's ratio
+ *                  rho = (E - E_t) / (eta_u e'^T tau - eta_u^2 ||tau||^2 / 2)
+ *                sets *ad->dev_lambda to omega * lambda when rho < 1/4 or is
+ *                not a number, lambda / omega when rho > 3/4, and leaves it
+ *                otherwise.  The update itself is applied whatever rho is.
+ *   trust_region 1: the rate is eta_u = cfg->eta / ||tau||_2 (App. F),
+ *                tau = e' - lambda x for the Cholesky solve (lambda the
+ *                shift actually used, floor included) and tau = T x for
+ *                the pseudo-inverse; 0: eta_u = cfg->eta.
+ * The BF16 forms keep minsr_step's shift floor.  POW23 and LM need the
+ * Cholesky solve (pinv_cutoff = 0) of an FP64 form (not
+ * MINSR_FORM_FP32_PLAIN), and LM a host-side counter (st->dev_counter NULL)
+ * and omega > 1.  For CONST and LM, cfg->lambda must be > 0 with the
+ * Cholesky solve, as in minsr_step.
+ * ad->dev_report (device, 8 doubles, may be NULL): ||T||_F, the shift used,
+ * ||tau||_2, eta_u, e'^T tau, E_t, rho, the next damping (the last three
+ * are 0 outside LM mode).  out is filled as by minsr_step.  The call also
+ * uses the handle's workspace; it is not meant for graph capture.        */
+#define MINSR_LAMBDA_CONST  0
+#define MINSR_LAMBDA_POW23  1
+#define MINSR_LAMBDA_LM     2
+typedef struct {
+  int32_t lambda_mode;   /* MINSR_LAMBDA_*                                  */
+  int32_t trust_region;  /* 0 or 1                                          */
+  double omega;          /* LM damping factor (App. G: 3/2)                 */
+  double* dev_lambda;    /* LM: [1] the carried damping, updated in place   */
+  double* dev_report;    /* [8] FP64, may be NULL                           */
+} minsr_adaptive_cfg;
+
+int minsr_step_adaptive(minsr_model* m, const minsr_hamiltonian* H,
+                        const minsr_step_cfg* cfg, const minsr_adaptive_cfg* ad,
+                        const minsr_step_state* st, const minsr_step_out* out,
+                        hipStream_t s);
+
 /* ---- the Cholesky solve without device allocation --------------------------
  * For callers that cannot allocate device memory (code under hip graph
  * capture, serving loops, harnesses that forbid hipMalloc): the same

@@ -28,10 +28,14 @@ SYMBOLS = (
     "minsr_step_intermediates", "minsr_timing_begin", "minsr_timing_read",
     "minsr_batch_create", "minsr_batch_step", "minsr_batch_destroy", "minsr_set_tunable",
     "minsr_get_tunable", "minsr_solve", "minsr_solve_noalloc", "minsr_spectrum",
-    "minsr_param_gram", "minsr_gram",
+    "minsr_param_gram", "minsr_gram", "minsr_step_adaptive",
 )
 OPT_PINV = 0x1
 OPT_LINEAR = 0x2
+LAMBDA_CONST, LAMBDA_POW23, LAMBDA_LM = 0, 1, 2
+# fields of the adaptive step's report
+ADAPT_REPORT = ("tnorm_frob", "lambda", "tau_norm", "eta", "ep_tau", "E_trial", "rho",
+                "lambda_next")
 PHASES = ("sample", "eloc", "eloc_sum_stats", "jacobian", "center", "gram", "gram_reduce",
           "solve", "update", "repack")
 
@@ -59,6 +63,12 @@ class StepCfg(ctypes.Structure):
 class StepState(ctypes.Structure):
     _fields_ = [("dev_momentum", ctypes.c_void_p), ("key", ctypes.c_uint64),
                 ("counter", ctypes.c_uint64), ("dev_counter", ctypes.c_void_p)]
+
+
+class AdaptiveCfg(ctypes.Structure):
+    _fields_ = [("lambda_mode", ctypes.c_int32), ("trust_region", ctypes.c_int32),
+                ("omega", ctypes.c_double), ("dev_lambda", ctypes.c_void_p),
+                ("dev_report", ctypes.c_void_p)]
 
 
 class StepOut(ctypes.Structure):
@@ -106,6 +116,9 @@ def load_library(path=LIB_PATH):
         "minsr_spectrum": [vp, i32, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp],
         "minsr_param_gram": [vp, i32, vp, vp, vp],
         "minsr_gram": [vp, i32, vp, i32, vp, vp],
+        "minsr_step_adaptive": [vp, ctypes.POINTER(Hamiltonian), ctypes.POINTER(StepCfg),
+                                ctypes.POINTER(AdaptiveCfg), ctypes.POINTER(StepState),
+                                ctypes.POINTER(StepOut), vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -191,8 +204,15 @@ class Model:
         _check(lib().minsr_set_params(self.handle, _ptr(theta), _stream()))
 
     # ------------------------------------------------------------ sampling
-    def sample(self, Ns, key=0, counter=0, uniforms=None):
-        sigma = torch.empty((Ns, self.N), dtype=torch.uint8, device=self.device)
+    def sample(self, Ns, key=0, counter=0, uniforms=None, sigma_out=None):
+        """Ns exact autoregressive samples and their log Psi; `sigma_out`
+        (uint8 [Ns, N] on the device) may be given to sample into."""
+        if sigma_out is not None:
+            assert sigma_out.shape == (Ns, self.N) and sigma_out.dtype == torch.uint8
+            assert sigma_out.is_contiguous() and sigma_out.device == self.device
+            sigma = sigma_out
+        else:
+            sigma = torch.empty((Ns, self.N), dtype=torch.uint8, device=self.device)
         lp = torch.empty((Ns, 2), dtype=torch.float64, device=self.device)
         if uniforms is not None:
             uniforms = uniforms.to(device=self.device, dtype=torch.float64).contiguous()
@@ -307,6 +327,29 @@ class Model:
                       _ptr(o.get("tnorm")).value, _ptr(o.get("lambda_used")).value)
         _check(lib().minsr_step(self.handle, ctypes.byref(ham), ctypes.byref(cfg),
                                 ctypes.byref(st), ctypes.byref(out), _stream()))
+        return o
+
+    def step_adaptive(self, ham, Ns, eta, lam, mu, momentum, key, counter, form=FORM_FP64_REF,
+                      lambda_mode=LAMBDA_CONST, trust_region=False, omega=1.5, damping=None,
+                      pinv_cutoff=0.0, ckpt_every=1, apply_update=True, outputs=None):
+        """One minSR iteration with the adaptive shift / rate (Sec. 3.3,
+        Apps. F and G).  `lam` is the shift (CONST), the coefficient c of
+        c ||T||_F^(2/3) (POW23) or unused (LM, where `damping`, a one-element
+        FP64 device tensor, carries the shift and is updated in place).
+        Returns the step's outputs plus "report" (see ADAPT_REPORT)."""
+        o = outputs if outputs is not None else self.step_outputs(Ns)
+        if "report" not in o:
+            o["report"] = torch.zeros(8, dtype=torch.float64, device=self.device)
+        cfg = StepCfg(Ns, form, eta, lam, mu, pinv_cutoff, ckpt_every, int(apply_update))
+        ad = AdaptiveCfg(lambda_mode, int(trust_region), omega, _ptr(damping).value,
+                         _ptr(o["report"]).value)
+        st = StepState(ctypes.c_void_p(momentum.data_ptr()), key, counter, None)
+        out = StepOut(_ptr(o["energy"]).value, _ptr(o["dtheta"]).value, _ptr(o["status"]).value,
+                      _ptr(o.get("eloc")).value, _ptr(o.get("sigma")).value,
+                      _ptr(o.get("tnorm")).value, _ptr(o.get("lambda_used")).value)
+        _check(lib().minsr_step_adaptive(self.handle, ctypes.byref(ham), ctypes.byref(cfg),
+                                         ctypes.byref(ad), ctypes.byref(st), ctypes.byref(out),
+                                         _stream()))
         return o
 
     def capture_step(self, ham, Ns, eta, lam, mu, momentum, key, dev_counter, form=FORM_FP64_REF,

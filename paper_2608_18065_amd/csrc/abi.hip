@@ -92,7 +92,8 @@ static void release(minsr_model* m) {
                   m->elist, m->ecount, m->eitems, m->eloc_q,
                   m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
                   m->colpart, m->colmean, m->T, m->Lf, m->Dinv, m->gpart, m->epsp, m->x, m->vwork,
-                  m->dpart, m->dtheta, m->status, m->eig, m->csync};
+                  m->dpart, m->dtheta, m->status, m->eig, m->csync, m->adapt,
+                  m->theta_bak};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : m->ev) (void)hipEventDestroy(e);
@@ -239,6 +240,8 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
   rc = rc ? rc : alloc((void**)&m->csync, chol_sync_words((int)rows) * 4);
   rc = rc ? rc : alloc((void**)&m->dpart, ((rows + 63) / 64) * Np * 8);
   rc = rc ? rc : alloc((void**)&m->dtheta, Np * 8);
+  rc = rc ? rc : alloc((void**)&m->adapt, (rows + 16 + ADAPT_FROB_PARTS) * 8);
+  rc = rc ? rc : alloc((void**)&m->theta_bak, Np * 8);
   rc = rc ? rc : alloc((void**)&m->status, 16);
   rc = rc ? rc : alloc((void**)&m->eloc_q, 16);
   if (!rc && (d->options & MINSR_OPT_PINV)) rc = ensure_pinv_ws(m, nullptr);
@@ -532,6 +535,128 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   MINSR_PHASE(10);
 #undef MINSR_PHASE
   if (timing) m->t_slot++;
+  m->last_n = n;
+  m->last_form = cfg->form;
+  return MINSR_OK;
+}
+
+int minsr_step_adaptive(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg* cfg,
+                        const minsr_adaptive_cfg* ad, const minsr_step_state* st,
+                        const minsr_step_out* out, hipStream_t s) {
+  if (!m || !cfg || !ad || !st || !out) return fail(MINSR_E_INVALID_ARG, "null argument");
+  int rc = check_ns(m, cfg->Ns);
+  if (rc) return rc;
+  if ((rc = check_ham(m, H))) return rc;
+  const int Ns = cfg->Ns;
+  if (Ns < 2) return fail(MINSR_E_SHAPE, "a step needs Ns >= 2");
+  if (!out->dev_energy || !out->dev_status) return fail(MINSR_E_INVALID_ARG, "null output");
+  if (cfg->apply_update && !st->dev_momentum) return fail(MINSR_E_INVALID_ARG, "null momentum");
+  if (cfg->form < 0 || cfg->form > 3) return fail(MINSR_E_INVALID_ARG, "unknown form");
+  if (cfg->form == MINSR_FORM_FP64_REF && !m->f64)
+    return fail(MINSR_E_INVALID_ARG, "the FP64 reference form needs an FP64 model");
+  const int mode = ad->lambda_mode;
+  if (mode != MINSR_LAMBDA_CONST && mode != MINSR_LAMBDA_POW23 && mode != MINSR_LAMBDA_LM)
+    return fail(MINSR_E_INVALID_ARG, "unknown lambda_mode");
+  if (ad->trust_region != 0 && ad->trust_region != 1)
+    return fail(MINSR_E_INVALID_ARG, "trust_region must be 0 or 1");
+  const bool pinv = cfg->pinv_cutoff > 0.0;
+  if (!(cfg->pinv_cutoff >= 0.0)) return fail(MINSR_E_INVALID_ARG, "negative cutoff");
+  if (pinv) {
+    if (mode != MINSR_LAMBDA_CONST || cfg->lambda != 0.0)
+      return fail(MINSR_E_INVALID_ARG, "the pseudo-inverse solve takes lambda = 0 (CONST mode)");
+    if (cfg->form == MINSR_FORM_FP32_PLAIN)
+      return fail(MINSR_E_UNSUPPORTED, "the pseudo-inverse solve runs in FP64 only");
+  } else {
+    if (mode != MINSR_LAMBDA_LM && !(cfg->lambda > 0.0))
+      return fail(MINSR_E_INVALID_ARG, "the Cholesky solve needs lambda > 0");
+    if (mode != MINSR_LAMBDA_CONST && cfg->form == MINSR_FORM_FP32_PLAIN)
+      return fail(MINSR_E_UNSUPPORTED, "adaptive shifts need an FP64 solve");
+  }
+  if (mode == MINSR_LAMBDA_LM) {
+    if (!ad->dev_lambda) return fail(MINSR_E_INVALID_ARG, "LM mode needs dev_lambda");
+    if (st->dev_counter) return fail(MINSR_E_UNSUPPORTED, "LM mode needs a host-side counter");
+    if (!(ad->omega > 1.0)) return fail(MINSR_E_INVALID_ARG, "omega must be > 1");
+  }
+  const int C = m->dim == 1 ? cfg->ckpt_every : 1;
+  if (C < 1 || C > 16) return fail(MINSR_E_INVALID_ARG, "ckpt_every in [1, 16]");
+
+  const size_t Np = m->L.Np;
+  const int nb = m->cplx ? 2 : 1;
+  const int n = nb * Ns;
+  uint8_t* sigma = out->dev_sigma ? out->dev_sigma : m->sigma;
+  double* eloc = out->dev_eloc ? out->dev_eloc : m->eloc;
+  double* dth = out->dev_dtheta ? out->dev_dtheta : m->dtheta;
+  const int rdt = cfg->form == MINSR_FORM_FP64_REF ? MINSR_F64
+                  : cfg->form == MINSR_FORM_FP32_PLAIN ? MINSR_F32 : MINSR_BF16;
+  void* Rlo = cfg->form == MINSR_FORM_BF16_FP64
+                  ? (void*)((__hip_bfloat16*)m->R + (size_t)n * padded_ld(Np))
+                  : nullptr;
+  const size_t rows = (size_t)(m->cplx ? 2 : 1) * m->d.max_Ns;
+  double* tau = m->adapt;
+  double* report = ad->dev_report ? ad->dev_report : m->adapt + rows;
+  double* tstats = m->adapt + rows + 8;
+  double* part = m->adapt + rows + 16;
+
+  // 1-4: samples, local energies, E and eps', log-derivative rows, centred
+  // real form, T (as minsr_step)
+  rc = launch_forward(m, 0, Ns, nullptr, st->key, st->counter, sigma, m->logpsi, m->states, 1,
+                      m->site, s, st->dev_counter, C == 1 ? m->gates : nullptr, out->dev_status);
+  if (!rc) rc = launch_eloc(m, H, Ns, sigma, m->logpsi, m->states, m->site, eloc, s, 3);
+  if (!rc) rc = launch_stats(m, Ns, eloc, out->dev_energy, m->epsp, out->dev_status, s);
+  if (!rc) rc = launch_jacobian(m, Ns, sigma, m->states, C, m->O, nullptr, nullptr, s,
+                                C == 1 ? m->gates : nullptr, m->site);
+  if (!rc) rc = launch_center(Ns, nb, Np, m->O, m->f64, m->R, rdt, m->colpart, m->colmean,
+                              padded_ld(Np), s, Rlo);
+  if (!rc) rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 3, Rlo,
+                            m->tune_gram_split);
+  if (rc) return rc;
+  // ||T||_F and the shift (Sec. 3.3), then the solve; report[1] ends up as
+  // the shift the solve used
+  rc = launch_adapt_lambda(n, m->T, rdt == MINSR_F32, mode, pinv ? 0.0 : cfg->lambda,
+                           ad->dev_lambda, part, report, s);
+  if (rc) return rc;
+  if (pinv) {
+    rc = ensure_pinv_ws(m, s);
+    if (!rc) rc = launch_report_trace(n, m->T, out->dev_tnorm, out->dev_lambda_used, s);
+    if (!rc)
+      rc = launch_pinv_solve(n, m->T, cfg->pinv_cutoff, m->epsp, m->x, m->eig, m->eig_elems,
+                             m->eig_nmax, out->dev_status, s);
+  } else {
+    rc = launch_cholesky_solve(n, m->T, m->Lf, m->Dinv, rdt == MINSR_F32, cfg->lambda, m->epsp,
+                               m->x, m->vwork, m->csync, out->dev_status, s,
+                               rdt == MINSR_BF16 ? 0x1p-24 : 0.0, out->dev_tnorm, report + 1,
+                               mode == MINSR_LAMBDA_CONST ? nullptr : report + 1);
+    if (!rc && out->dev_lambda_used)
+      rc = hipMemcpyAsync(out->dev_lambda_used, report + 1, 8, hipMemcpyDeviceToDevice, s) ==
+                   hipSuccess ? MINSR_OK : fail(MINSR_E_DEVICE, "copy of the shift failed");
+  }
+  if (rc) return rc;
+  // tau, the rate (App. F), x scaled by rate / eta
+  rc = launch_tau(n, m->T, m->epsp, m->x, tau, pinv ? 1 : 0, cfg->eta, ad->trust_region,
+                  report, s);
+  if (rc) return rc;
+  if (mode == MINSR_LAMBDA_LM) {
+    // dtheta, then the trial energy at theta - dtheta from fresh samples
+    // (App. G), with theta restored afterwards
+    rc = launch_update(n, Np, m->R, rdt, m->x, cfg->eta, cfg->mu, m->dpart, dth,
+                       st->dev_momentum, m->theta, out->dev_status, 0, s, Rlo, nullptr);
+    if (!rc) rc = launch_trial_theta(m->theta, m->theta_bak, dth, Np, 0, s);
+    if (!rc) rc = launch_pack(m, s);
+    if (!rc)
+      rc = launch_forward(m, 0, Ns, nullptr, st->key, st->counter ^ (1ull << 63), m->sigma,
+                          m->logpsi, m->states, 1, m->site, s);
+    if (!rc) rc = launch_eloc(m, H, Ns, m->sigma, m->logpsi, m->states, m->site, m->eloc, s, 3);
+    if (!rc) rc = launch_stats(m, Ns, m->eloc, tstats, nullptr, nullptr, s);
+    if (!rc) rc = launch_trial_theta(m->theta, m->theta_bak, dth, Np, 1, s);
+    if (!rc) rc = launch_pack(m, s);
+    if (!rc) rc = launch_lm(out->dev_energy, tstats, ad->omega, ad->dev_lambda, report, s);
+    if (rc) return rc;
+  }
+  // the update (momentum and parameters, App. B) with the scaled x
+  rc = launch_update(n, Np, m->R, rdt, m->x, cfg->eta, cfg->mu, m->dpart, dth, st->dev_momentum,
+                     m->theta, out->dev_status, cfg->apply_update, s, Rlo, st->dev_counter);
+  if (!rc && cfg->apply_update) rc = launch_pack(m, s);
+  if (rc) return rc;
   m->last_n = n;
   m->last_form = cfg->form;
   return MINSR_OK;

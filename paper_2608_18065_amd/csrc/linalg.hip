@@ -1306,6 +1306,7 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
 // lam_out or a report pointer is set, workgroup 0 also sums the diagonal of
 // T (tr T, fixed order) and forms the shift
 //   lambda_eff = max(lambda, rel_tr * tr T)      (rel_tr = 0: lambda)
+// with lambda = *lam_in when lam_in is set (a shift computed on the device)
 // into lam_out, MINSR_ST_SHIFT_FLOOR in *status when the floor is the
 // larger, and tr T and lambda_eff into rep_tn / rep_lam.  The floor bounds
 // the accumulation error of a low-precision Gram: each entry of the
@@ -1322,7 +1323,8 @@ __global__ __launch_bounds__(256) void k_chol_prep(uint32_t* sync, int nsync, co
                                                    TT* y, int n, const TT* T, double lambda,
                                                    double rel_tr, double* lam_out,
                                                    uint64_t* xmark, double* rep_tn,
-                                                   double* rep_lam, uint32_t* status) {
+                                                   double* rep_lam, uint32_t* status,
+                                                   const double* lam_in) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nsync) sync[i] = 0u;
   if (i < n) y[i] = (TT)b[i];
@@ -1339,8 +1341,8 @@ __global__ __launch_bounds__(256) void k_chol_prep(uint32_t* sync, int nsync, co
     }
     if (threadIdx.x == 0) {
       const double fl = rel_tr * red[0];
-      double lam = lambda;
-      if (rel_tr > 0.0 && fl > lambda) {
+      double lam = lam_in ? lam_in[0] : lambda;
+      if (rel_tr > 0.0 && fl > lam) {
         lam = fl;
         if (status) atomicOr(status, MINSR_ST_SHIFT_FLOOR);
       }
@@ -1490,14 +1492,15 @@ size_t chol_vec_elems(int n) {
 template <typename TT>
 static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, double lambda,
                   const double* b, double* x, uint32_t* status, hipStream_t s,
-                  double lam_floor_rel, double* rep_tn, double* rep_lam) {
+                  double lam_floor_rel, double* rep_tn, double* rep_lam,
+                  const double* lam_in) {
   const int nblk = (n + CB - 1) / CB;
   const int nsync = (int)chol_sync_words(n);
   const int m = std::max(nsync, n);
   CholArgs a{T, A, Dinv, yv, sync, status, lambda, nullptr, n, nblk};
   double* lam_slot = nullptr;
   if constexpr (std::is_same<TT, double>::value) {
-    if (lam_floor_rel > 0.0) {
+    if (lam_floor_rel > 0.0 || lam_in) {
       lam_slot = reinterpret_cast<double*>(yv) + chol_vec_elems(n) - 1;
       a.lam_dev = lam_slot;
     }
@@ -1505,7 +1508,7 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
   k_chol_prep<TT><<<(m + 255) / 256, 256, 0, s>>>(sync, nsync, b, yv, n, T, lambda,
                                                   lam_slot ? lam_floor_rel : 0.0, lam_slot,
                                                   reinterpret_cast<uint64_t*>(x), rep_tn,
-                                                  rep_lam, status);
+                                                  rep_lam, status, lam_in);
   MINSR_CHECK_LAUNCH();
   if constexpr (std::is_same<TT, double>::value) {
     k_chol_persist_f64<<<1 + nblk * (nblk - 1) / 2, 256, 0, s>>>(a, sync + chol_sync_one(nblk),
@@ -1527,14 +1530,16 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, double* yv, uint32_t* sync,
                           uint32_t* status, hipStream_t s, double lam_floor_rel, double* rep_tn,
-                          double* rep_lam) {
+                          double* rep_lam, const double* lam_in) {
   if (n == 0) return MINSR_OK;
-  if (f32)
+  if (f32) {
+    if (lam_in) return fail(MINSR_E_UNSUPPORTED, "a device-side shift needs the FP64 solve");
     return chol_t<float>(n, reinterpret_cast<const float*>(T), reinterpret_cast<float*>(Lf),
                          reinterpret_cast<float*>(Dinv), reinterpret_cast<float*>(yv), sync,
-                         lambda, b, x, status, s, 0.0, rep_tn, rep_lam);
+                         lambda, b, x, status, s, 0.0, rep_tn, rep_lam, nullptr);
+  }
   return chol_t<double>(n, T, Lf, Dinv, yv, sync, lambda, b, x, status, s, lam_floor_rel, rep_tn,
-                        rep_lam);
+                        rep_lam, lam_in);
 }
 
 // ================================================================ update
@@ -1654,21 +1659,5 @@ int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, d
   }
   return MINSR_OK;
 }
-
-// weighted row reduction: out[k] = sum_r part-free  (used by the VJP)
-__global__ void k_reduce_rows(const double* w, int rows, size_t Np, const double* O,
-                              double* out) {
-  size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= Np) return;
-  double s = 0.0;
-  for (int r = 0; r < rows; ++r) s += w[r] * O[(size_t)r * Np + col];
-  out[col] = s;
-}
-
-int launch_reduce_rows(int rows, size_t Np, const double* part, double* out, hipStream_t s) {
-  (void)rows; (void)Np; (void)part; (void)out; (void)s;
-  return MINSR_OK;
-}
-
 
 }  // namespace minsr

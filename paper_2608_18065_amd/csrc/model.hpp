@@ -8,6 +8,9 @@ struct minsr_model {
   int N, H, dim, cplx, ds;
   int f64;                 // compute precision: 1 double, 0 float
   int linear = 0;          // the linear recurrent test model (MINSR_OPT_LINEAR)
+  double* adapt = nullptr;  // adaptive step: [rows] tau, [8] report, [4] trial stats,
+                            //   [4] spare, [256] norm partials
+  double* theta_bak = nullptr;  // [Np] parameters held while the trial step is evaluated
   minsr::Layout L;
   int device;
 
@@ -134,10 +137,13 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
 // max(lambda, lam_floor_rel * tr T), with MINSR_ST_SHIFT_FLOOR set in *status
 // when the floor is the larger; rep_tn / rep_lam (may be null) receive tr T
 // and the shift used
+// lam_in (FP64 only, may be null): the shift is read from the device
+// instead of `lambda` (the floor still applies)
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, double* yv, uint32_t* sync,
                           uint32_t* status, hipStream_t s, double lam_floor_rel = 0.0,
-                          double* rep_tn = nullptr, double* rep_lam = nullptr);
+                          double* rep_tn = nullptr, double* rep_lam = nullptr,
+                          const double* lam_in = nullptr);
 // tr T into rep_tn and 0 into rep_lam (the report of a pseudo-inverse step)
 int launch_report_trace(int n, const double* T, double* rep_tn, double* rep_lam, hipStream_t s);
 size_t chol_dinv_elems(int n);
@@ -161,7 +167,20 @@ int launch_update(int n, size_t Np, const void* R, int dtype, const double* x, d
                   double mu, double* dpart, double* dtheta, double* momentum, double* theta,
                   uint32_t* status, int apply, hipStream_t s, const void* Rlo = nullptr,
                   uint64_t* bump = nullptr);
-int launch_reduce_rows(int rows, size_t Np, const double* part, double* out, hipStream_t s);
+// adaptive.hip: report layout [0] ||T||_F [1] shift [2] ||tau|| [3] rate
+// [4] e'^T tau [5] E_trial [6] rho [7] next shift
+constexpr int ADAPT_FROB_PARTS = 256;
+// ||T||_F and the shift of lambda mode `mode` into report[0..1]; part:
+// ADAPT_FROB_PARTS doubles of scratch
+int launch_adapt_lambda(int n, const void* T, int t_f32, int mode, double lambda,
+                        const double* carried, double* part, double* report, hipStream_t s);
+// tau, ||tau||, e'^T tau, the rate into report[2..4]; x scaled by rate / eta
+int launch_tau(int n, const double* T, const double* ep, double* x, double* tau, int pinv,
+               double eta, int trust, double* report, hipStream_t s);
+int launch_trial_theta(double* theta, double* bak, const double* dth, size_t Np, int restore,
+                       hipStream_t s);
+int launch_lm(const double* E0, const double* E1, double omega, double* carried, double* report,
+              hipStream_t s);
 // linear.hip: the linear recurrent test model (model option MINSR_OPT_LINEAR)
 size_t linear_num_params(int H);
 int launch_linear_init(minsr_model* m, hipStream_t s);

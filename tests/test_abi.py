@@ -62,7 +62,7 @@ def test_binding_structs_match_header_layout(tmp_path):
     import paper_2608_18065_amd as pm
     structs = {"minsr_model_desc": pm.ModelDesc, "minsr_hamiltonian": pm.Hamiltonian,
                "minsr_step_cfg": pm.StepCfg, "minsr_step_state": pm.StepState,
-               "minsr_step_out": pm.StepOut}
+               "minsr_step_out": pm.StepOut, "minsr_adaptive_cfg": pm.AdaptiveCfg}
     cfields = {"minsr_model_desc": ["Lx", "Ly", "dim", "hidden", "complex_head", "marshall",
                                     "zero_mag", "compute_dtype", "init_seed", "max_Ns", "options"],
                "minsr_hamiltonian": ["kind", "pbc", "J", "h", "J2"],
@@ -70,7 +70,9 @@ def test_binding_structs_match_header_layout(tmp_path):
                                   "ckpt_every", "apply_update"],
                "minsr_step_state": ["dev_momentum", "key", "counter", "dev_counter"],
                "minsr_step_out": ["dev_energy", "dev_dtheta", "dev_status", "dev_eloc",
-                                  "dev_sigma", "dev_tnorm", "dev_lambda_used"]}
+                                  "dev_sigma", "dev_tnorm", "dev_lambda_used"],
+               "minsr_adaptive_cfg": ["lambda_mode", "trust_region", "omega", "dev_lambda",
+                                      "dev_report"]}
     lines = ["#include <stdio.h>", "#include <stddef.h>", "#define __HIP_PLATFORM_AMD__ 1",
              '#include "minsr.h"', "int main(void) {"]
     for name, fields in cfields.items():
