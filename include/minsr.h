@@ -86,7 +86,10 @@ extern "C" {
 #define MINSR_ST_EIG_NOCONV      0x8u   /* pseudo-inverse met a non-finite
                                            tridiagonal entry                 */
 #define MINSR_ST_SHIFT_FLOOR     0x10u  /* informational, not a failure      */
-#define MINSR_ST_ERRORS          0x0Fu
+#define MINSR_ST_SOLVE_TIMEOUT   0x20u  /* a wait between workgroups of the
+                                           Cholesky solve gave up (see the
+                                           tunable "solve_spin_limit")      */
+#define MINSR_ST_ERRORS          0x2Fu
 
 /* Architecture of one wave function (Sec. 2, Sec. 2.1 and App. A).
  *   Lx, Ly        lattice extent; a chain has Ly = 1 and dim = 1
@@ -413,7 +416,12 @@ int minsr_batch_destroy(minsr_batch* b);
  * (0 = one per work item up to the window limit);
  * key "sample_r": sequences per thread of the sampling recurrence (1 or 4);
  * key "jac_parts": threads per hidden unit of the Jacobian's reverse pass
- * (1, 2 or 4; d_h = 64 and 128 only; 0 = built-in choice).
+ * (1, 2 or 4; d_h = 64 and 128 only; 0 = built-in choice);
+ * key "solve_spin_limit": polls after which a wait of one workgroup of the
+ * Cholesky solve on another gives up (0 = built in, 2^22 polls, of the
+ * order of seconds).  A wait that gives up ends every wait of the launch,
+ * so the kernels exit, and sets MINSR_ST_SOLVE_TIMEOUT; the step then
+ * leaves theta unchanged.  Small values exist to test that path.
  * Values are validated; MINSR_E_INVALID_ARG for an unknown key.           */
 int minsr_set_tunable(minsr_model* m, const char* key, int value);
 int minsr_get_tunable(const minsr_model* m, const char* key, int* value);

@@ -18,7 +18,7 @@ F64, F32, BF16 = 0, 1, 2
 HAM_TFIM, HAM_CLUSTER, HAM_J1J2 = 0, 1, 2
 FORM_FP64_REF, FORM_BF16_FP64, FORM_FP32_PLAIN, FORM_BF16_1PASS = 0, 1, 2, 3
 ST_NONFINITE_ELOC, ST_NOT_PD, ST_NONFINITE_DTH, ST_EIG_NOCONV = 1, 2, 4, 8
-ST_SHIFT_FLOOR, ST_ERRORS = 0x10, 0x0F
+ST_SHIFT_FLOOR, ST_SOLVE_TIMEOUT, ST_ERRORS = 0x10, 0x20, 0x2F
 
 # every entry point of include/minsr.h
 SYMBOLS = (

@@ -518,7 +518,7 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
     rc = launch_cholesky_solve(n, m->T, m->Lf, m->Dinv, rdt == MINSR_F32, cfg->lambda, m->epsp,
                                m->x, m->vwork, m->csync, out->dev_status, s,
                                rdt == MINSR_BF16 ? 0x1p-24 : 0.0, out->dev_tnorm,
-                               out->dev_lambda_used);
+                               out->dev_lambda_used, nullptr, (uint32_t)m->tune_spin_limit);
   }
   if (rc) return rc;
   MINSR_PHASE(8);
@@ -625,7 +625,8 @@ int minsr_step_adaptive(minsr_model* m, const minsr_hamiltonian* H, const minsr_
     rc = launch_cholesky_solve(n, m->T, m->Lf, m->Dinv, rdt == MINSR_F32, cfg->lambda, m->epsp,
                                m->x, m->vwork, m->csync, out->dev_status, s,
                                rdt == MINSR_BF16 ? 0x1p-24 : 0.0, out->dev_tnorm, report + 1,
-                               mode == MINSR_LAMBDA_CONST ? nullptr : report + 1);
+                               mode == MINSR_LAMBDA_CONST ? nullptr : report + 1,
+                               (uint32_t)m->tune_spin_limit);
     if (!rc && out->dev_lambda_used)
       rc = hipMemcpyAsync(out->dev_lambda_used, report + 1, 8, hipMemcpyDeviceToDevice, s) ==
                    hipSuccess ? MINSR_OK : fail(MINSR_E_DEVICE, "copy of the shift failed");
@@ -709,6 +710,9 @@ int minsr_set_tunable(minsr_model* m, const char* key, int value) {
     if (value != 0 && value != 1 && value != 2 && value != 4)
       return fail(MINSR_E_INVALID_ARG, "jac_parts in {0, 1, 2, 4}");
     m->tune_jac_parts = value;
+  } else if (k == "solve_spin_limit") {
+    if (value < 0) return fail(MINSR_E_INVALID_ARG, "solve_spin_limit must be >= 0");
+    m->tune_spin_limit = value;
   } else {
     return fail(MINSR_E_INVALID_ARG, "unknown tunable " + k);
   }
@@ -722,6 +726,7 @@ int minsr_get_tunable(const minsr_model* m, const char* key, int* value) {
   else if (k == "eloc_grid") *value = m->tune_eloc_grid;
   else if (k == "sample_r") *value = m->tune_sample_r;
   else if (k == "jac_parts") *value = m->tune_jac_parts;
+  else if (k == "solve_spin_limit") *value = m->tune_spin_limit;
   else return fail(MINSR_E_INVALID_ARG, "unknown tunable " + k);
   return MINSR_OK;
 }
@@ -756,7 +761,8 @@ int minsr_solve(minsr_model* m, int n, const double* dev_T, double lambda, doubl
                              m->eig_elems, m->eig_nmax, dev_status, s);
   }
   return launch_cholesky_solve(n, dev_T, m->Lf, m->Dinv, 0, lambda, dev_b, dev_x, m->vwork,
-                               m->csync, dev_status, s);
+                               m->csync, dev_status, s, 0.0, nullptr, nullptr, nullptr,
+                               (uint32_t)m->tune_spin_limit);
 }
 
 // raw log-derivative rows of the configurations into the handle's O

@@ -266,8 +266,8 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
   f16x8_m Wuh[SPLIT ? KJ : 1], Wul[SPLIT ? KJ : 1], Wrh[SPLIT ? KJ : 1], Wrl[SPLIT ? KJ : 1],
       Wgh[SPLIT ? KJ : 1], Wgl[SPLIT ? KJ : 1];
   __shared__ unsigned wmax_bits;
-  int sexp = 0;
-  float sc_dn = 1.f, sc_up = 1.f;
+  int sexp = 0;                         // some column of the workgroup is scaled
+  float sdn[3] = {1.f, 1.f, 1.f}, sup[3] = {1.f, 1.f, 1.f};   // this lane's column, per gate
   {
     const float* base = a.mw + (size_t)w * NSTEP * 64 + lane;
     if constexpr (SPLIT) {
@@ -279,26 +279,33 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
       };
       if (tid == 0) wmax_bits = 0u;
       __syncthreads();
-      float mx = 0.f;
+      // FP16 holds magnitudes below 65504: the weights of an output column
+      // (one unit of one gate) whose largest magnitude reaches 2^14 are
+      // split as w 2^-s and that column's products scaled back by 2^s
+      // (exact); a column's inputs sit in this lane and in lane ^ 32
+      float mx[3] = {0.f, 0.f, 0.f};
       for (int j = 0; j < KJ; ++j)
         for (int e = 0; e < 8; ++e)
-          for (int g = 0; g < 3; ++g) mx = fmaxf(mx, fabsf(wfrag(j, e, g)));
-      atomicMax(&wmax_bits, __float_as_uint(mx));   // non-negative floats order as their bits
+          for (int g = 0; g < 3; ++g) mx[g] = fmaxf(mx[g], fabsf(wfrag(j, e, g)));
+#pragma unroll
+      for (int g = 0; g < 3; ++g) {
+        mx[g] = fmaxf(mx[g], __shfl_xor(mx[g], 32, 64));
+        const int se = mx[g] >= 16384.f ? min(ilogbf(mx[g]) - 13, 120) : 0;
+        sdn[g] = ldexpf(1.f, -se);
+        sup[g] = ldexpf(1.f, se);
+      }
+      // non-negative floats order as their bits
+      atomicMax(&wmax_bits, __float_as_uint(fmaxf(mx[0], fmaxf(mx[1], mx[2]))));
       __syncthreads();
-      // FP16 holds magnitudes below 65504: weights from 2^14 on are split
-      // as w 2^-s and the products scaled back by 2^s (exact)
-      const float wmax = __uint_as_float(wmax_bits);
-      sexp = wmax >= 16384.f ? min(ilogbf(wmax) - 13, 120) : 0;
-      sc_dn = ldexpf(1.f, -sexp);
-      sc_up = ldexpf(1.f, sexp);
+      sexp = __uint_as_float(wmax_bits) >= 16384.f ? 1 : 0;
 #pragma unroll
       for (int j = 0; j < KJ; ++j) {
         float xu[8], xr[8], xg[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          xu[e] = wfrag(j, e, 0) * sc_dn;
-          xr[e] = wfrag(j, e, 1) * sc_dn;
-          xg[e] = wfrag(j, e, 2) * sc_dn;
+          xu[e] = wfrag(j, e, 0) * sdn[0];
+          xr[e] = wfrag(j, e, 1) * sdn[1];
+          xg[e] = wfrag(j, e, 2) * sdn[2];
         }
         split_f16(xu, Wuh[j], Wul[j]);
         split_f16(xr, Wrh[j], Wrl[j]);
@@ -389,7 +396,7 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
       f32x16_m au, ar, ag, ai;
       if (DIM == 1) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) { au[q] = 0.f; ar[q] = 0.f; ag[q] = bgs * sc_dn; ai[q] = 0.f; }
+        for (int q = 0; q < 16; ++q) { au[q] = 0.f; ar[q] = 0.f; ag[q] = bgs * sdn[2]; ai[q] = 0.f; }
       } else {
 #pragma unroll
         for (int q = 0; q < 16; ++q) { au[q] = bu; ar[q] = br; ag[q] = bh; ai[q] = bi; }
@@ -408,7 +415,7 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
         }
         if constexpr (decltype(scaled)::value) {
 #pragma unroll
-          for (int q = 0; q < 16; ++q) { au[q] *= sc_up; ar[q] *= sc_up; ag[q] *= sc_up; }
+          for (int q = 0; q < 16; ++q) { au[q] *= sup[0]; ar[q] *= sup[1]; ag[q] *= sup[2]; }
         }
       } else {
 #pragma unroll
@@ -505,39 +512,48 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
   __shared__ float bgs_s[H];
   __shared__ int simd_of[EW_WAVES];
   __shared__ unsigned wmax_bits;
+  __shared__ unsigned colmax[NCB][3][32];   // largest |w| of each output column
+  __shared__ float csc[2][NCB][3][32];      // its scale 2^-s and 2^s
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (lane == 0) simd_of[w] = (int)(__builtin_amdgcn_s_getreg(HWREG_SIMD_ID) & 3);
   const int half = lane >> 5, col = lane & 31;
   const int N = a.N;
-  // FP16 holds magnitudes below 65504 (the state lies in [-1, 1]): when
-  // some weight reaches 2^14, all are staged again as w 2^-s and the state
-  // products scaled back by 2^s, both exact powers of two
+  // FP16 holds magnitudes below 65504 (the state lies in [-1, 1]): the
+  // weights of an output column (one unit of one gate) whose largest
+  // magnitude reaches 2^14 are staged again as w 2^-s and that column's
+  // state products scaled back by 2^s, both exact powers of two
   if (tid == 0) wmax_bits = 0u;
+  for (int i = tid; i < NCB * 3 * 32; i += 64 * EW_WAVES) (&colmax[0][0][0])[i] = 0u;
   __syncthreads();
   // B fragment of K-step j, lane l = n + 32 c, element e: input unit
   // u = 16 j + 8 c + e, output unit 32 cb + n.  In the packed FP32 layout
   // that entry sits at K-step u % KS in lane n + 32 (u / KS).
-  auto stage = [&](float sc) -> float {
+  // scaled == false: stage unscaled and record the column maxima
+  auto stage = [&](bool scaled) {
     float mx = 0.f;
     for (int i = tid; i < NCB * 3 * KJ * 64; i += 64 * EW_WAVES) {
       const int l = i % 64, j = (i / 64) % KJ, g = (i / (64 * KJ)) % 3, cb = i / (64 * KJ * 3);
       const int n = l & 31, c = l >> 5;
       const float* base = a.mw + (size_t)cb * NSTEP * 64 + n;
       const int off = g == 0 ? 0 : g == 1 ? KS + 1 : 2 * (KS + 1);
-      float x[8];
+      const float sc = scaled ? csc[0][cb][g][n] : 1.f;
+      float x[8], cm = 0.f;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int u = 16 * j + 8 * c + e;
         x[e] = base[(size_t)(off + u % KS) * 64 + 32 * (u / KS)];
-        mx = fmaxf(mx, fabsf(x[e]));
+        cm = fmaxf(cm, fabsf(x[e]));
         x[e] *= sc;
       }
+      // non-negative floats order as their bits
+      if (!scaled) atomicMax(&colmax[cb][g][n], __float_as_uint(cm));
+      mx = fmaxf(mx, cm);
       split_f16(x, Bh[cb][g][j][0][l], Bh[cb][g][j][1][l]);
     }
-    return mx;
+    if (!scaled) atomicMax(&wmax_bits, __float_as_uint(mx));
   };
-  atomicMax(&wmax_bits, __float_as_uint(stage(1.f)));   // non-negative floats order as their bits
+  stage(false);
   for (int i = tid; i < NCB * 3 * 64; i += 64 * EW_WAVES) {
     const int l = i % 64, g = (i / 64) % 3, cb = i / (64 * 3);
     const float* base = a.mw + (size_t)cb * NSTEP * 64 + l;
@@ -548,13 +564,27 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
   for (int i = tid; i < H; i += 64 * EW_WAVES) bgs_s[i] = (float)(2.8853900817779268 * (double)a.bias[2 * H + i]);
   if (tid < 4) hb[tid] = a.headb[tid];
   __syncthreads();
-  const float wmax = __uint_as_float(wmax_bits);
-  const int sexp = wmax >= 16384.f ? min(ilogbf(wmax) - 13, 120) : 0;
-  const float sc_dn = ldexpf(1.f, -sexp), sc_up = ldexpf(1.f, sexp);
+  for (int i = tid; i < NCB * 3 * 32; i += 64 * EW_WAVES) {
+    const float cm = __uint_as_float((&colmax[0][0][0])[i]);
+    const int se = cm >= 16384.f ? min(ilogbf(cm) - 13, 120) : 0;
+    (&csc[0][0][0][0])[i] = ldexpf(1.f, -se);
+    (&csc[1][0][0][0])[i] = ldexpf(1.f, se);
+  }
+  const int sexp = __uint_as_float(wmax_bits) >= 16384.f ? 1 : 0;   // some column is scaled
+  __syncthreads();
   if (sexp) {
-    stage(sc_dn);
+    stage(true);
     __syncthreads();
   }
+  // this lane's column scales of every block and gate
+  float sdn[NCB][3], sup[NCB][3];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      sdn[cb][g] = csc[0][cb][g][col];
+      sup[cb][g] = csc[1][cb][g][col];
+    }
 
   float (*hA)[HP] = hS[w];
   // the wave's own shared-memory writes visible to all its lanes
@@ -591,7 +621,7 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
       f32x16_m au[NCB], ar[NCB], ag[NCB], ai[NCB];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
-        const float g0 = bgs_s[32 * cb + col] * sc_dn;
+        const float g0 = bgs_s[32 * cb + col] * sdn[cb][2];
 #pragma unroll
         for (int q = 0; q < 16; ++q) { au[cb][q] = 0.f; ar[cb][q] = 0.f; ag[cb][q] = g0; ai[cb][q] = 0.f; }
       }
@@ -617,7 +647,9 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-          for (int q = 0; q < 16; ++q) { au[cb][q] *= sc_up; ar[cb][q] *= sc_up; ag[cb][q] *= sc_up; }
+          for (int q = 0; q < 16; ++q) {
+            au[cb][q] *= sup[cb][0]; ar[cb][q] *= sup[cb][1]; ag[cb][q] *= sup[cb][2];
+          }
       }
       {
         const float o = e.sprev == half ? 1.f : 0.f;

@@ -635,7 +635,34 @@ struct CholArgs {
   double lambda;
   const double* lam_dev;  // if set, the shift actually used (FP64 one-launch kernel)
   int n, nblk;
+  uint32_t* abort;        // set by the first wait that gives up
+  uint32_t spin_limit;    // polls before a wait gives up
 };
+
+// A wait on a flag another workgroup publishes, bounded: after `limit`
+// polls, or as soon as some wait of the launch has given up (the abort
+// word), it stops waiting, sets MINSR_ST_SOLVE_TIMEOUT and the abort word,
+// and returns false.  Every wait of the launch then ends, so the kernel
+// exits whatever happened to the publishing workgroup; the solve's result
+// is invalid and the status word says so.  Relaxed polls (an acquiring load
+// would invalidate this CU's caches at every poll); the caller fences once.
+__device__ inline bool bounded_wait(const uint32_t* f, uint32_t* abort, uint32_t limit,
+                                    uint32_t* status) {
+  uint32_t polls = 0;
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+    ++polls;
+    if (polls >= limit ||
+        ((polls & 63u) == 0u &&
+         __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+      if (status) atomicOr(status, MINSR_ST_SOLVE_TIMEOUT);
+      __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+constexpr uint32_t DEFAULT_SPIN_LIMIT = 1u << 22;
 
 // Block column k of the factorisation (k = -1: the first block column,
 // read straight from T).
@@ -764,10 +791,10 @@ __global__ __launch_bounds__(256) void k_chol_step(CholArgs a, int k) {
 
   // panel tile below the diagonal: wait for the factor of block kk
   if (tid == 0) {
-    while (__hip_atomic_load(&flags[kk], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-      __builtin_amdgcn_s_sleep(2);
+    bounded_wait(&flags[kk], a.abort, a.spin_limit, a.status);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
-  // the acquiring load invalidated this CU's L1 and its L2 for every wave
+  // the acquire invalidated this CU's L1 and its L2 for every wave
   __syncthreads();
 #pragma unroll
   for (int x = 0; x < 4; ++x)
@@ -1091,8 +1118,7 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
   // fence once the flag is seen
   auto wait_flag = [&](const uint32_t* f) {
     if (tid == 0) {
-      while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-        __builtin_amdgcn_s_sleep(2);
+      bounded_wait(f, a.abort, a.spin_limit, a.status);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
@@ -1389,7 +1415,8 @@ int launch_report_trace(int n, const double* T, double* rep_tn, double* rep_lam,
 template <typename TT>
 __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const TT* Dinv,
                                                       const TT* y, double* x, uint32_t* bsync,
-                                                      int nblk) {
+                                                      int nblk, uint32_t* abort,
+                                                      uint32_t spin_limit, uint32_t* status) {
   __shared__ TT Dk[CB][CB + 1];
   __shared__ TT xj[CB];
   __shared__ TT part[4][CB];
@@ -1428,8 +1455,20 @@ __global__ __launch_bounds__(256) void k_trsv_back_mt(const TT* A, int n, const 
       if (j * CB + tid < n) {
         const uint64_t* xp = reinterpret_cast<const uint64_t*>(x) + j * CB + tid;
         uint64_t bits;
-        while ((bits = __hip_atomic_load(xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == X_UNSET)
+        uint32_t polls = 0;
+        // bounded as in bounded_wait: a wait that gives up keeps the mark
+        // (a NaN) and flags the solve as failed
+        while ((bits = __hip_atomic_load(xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == X_UNSET) {
+          ++polls;
+          if (polls >= spin_limit ||
+              ((polls & 63u) == 0u &&
+               __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+            if (status) atomicOr(status, MINSR_ST_SOLVE_TIMEOUT);
+            __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
           __builtin_amdgcn_s_sleep(1);
+        }
         v = (TT)__longlong_as_double((long long)bits);
       }
       xj[tid] = v;
@@ -1475,12 +1514,12 @@ size_t chol_dinv_elems(int n) { return (size_t)((n + CB - 1) / CB) * CB * CB; }
 // sync words: [2 (nblk + 1)] tickets and flags of the launch-per-column
 // factorisation (FP32), [nblk + 1] ticket and flags of the backward pass,
 // [1 + nblk + nblk^2] ticket, diagonal and panel flags of the one-launch
-// factorisation (FP64)
+// factorisation (FP64), then the abort word of the bounded waits
 static size_t chol_sync_bwd(int nblk) { return 2 * (size_t)(nblk + 1); }
 static size_t chol_sync_one(int nblk) { return 3 * (size_t)(nblk + 1); }
 size_t chol_sync_words(int n) {
   const size_t nblk = (size_t)((n + CB - 1) / CB);
-  return chol_sync_one((int)nblk) + 1 + nblk + nblk * nblk;
+  return chol_sync_one((int)nblk) + 1 + nblk + nblk * nblk + 1;
 }
 // solver vector: y (n, rounded up to whole blocks), then the per-tile
 // contributions L_ij y_j of the one-launch factorisation ([nblk][nblk][64])
@@ -1493,11 +1532,13 @@ template <typename TT>
 static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, double lambda,
                   const double* b, double* x, uint32_t* status, hipStream_t s,
                   double lam_floor_rel, double* rep_tn, double* rep_lam,
-                  const double* lam_in) {
+                  const double* lam_in, uint32_t spin_limit) {
   const int nblk = (n + CB - 1) / CB;
   const int nsync = (int)chol_sync_words(n);
   const int m = std::max(nsync, n);
-  CholArgs a{T, A, Dinv, yv, sync, status, lambda, nullptr, n, nblk};
+  uint32_t* abort = sync + nsync - 1;   // cleared with the other sync words
+  const uint32_t lim = spin_limit ? spin_limit : DEFAULT_SPIN_LIMIT;
+  CholArgs a{T, A, Dinv, yv, sync, status, lambda, nullptr, n, nblk, abort, lim};
   double* lam_slot = nullptr;
   if constexpr (std::is_same<TT, double>::value) {
     if (lam_floor_rel > 0.0 || lam_in) {
@@ -1522,7 +1563,8 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
       MINSR_CHECK_LAUNCH();
     }
   }
-  k_trsv_back_mt<TT><<<nblk, 256, 0, s>>>(A, n, Dinv, yv, x, sync + chol_sync_bwd(nblk), nblk);
+  k_trsv_back_mt<TT><<<nblk, 256, 0, s>>>(A, n, Dinv, yv, x, sync + chol_sync_bwd(nblk), nblk,
+                                          abort, lim, status);
   MINSR_CHECK_LAUNCH();
   return MINSR_OK;
 }
@@ -1530,16 +1572,16 @@ static int chol_t(int n, const TT* T, TT* A, TT* Dinv, TT* yv, uint32_t* sync, d
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, double* yv, uint32_t* sync,
                           uint32_t* status, hipStream_t s, double lam_floor_rel, double* rep_tn,
-                          double* rep_lam, const double* lam_in) {
+                          double* rep_lam, const double* lam_in, uint32_t spin_limit) {
   if (n == 0) return MINSR_OK;
   if (f32) {
     if (lam_in) return fail(MINSR_E_UNSUPPORTED, "a device-side shift needs the FP64 solve");
     return chol_t<float>(n, reinterpret_cast<const float*>(T), reinterpret_cast<float*>(Lf),
                          reinterpret_cast<float*>(Dinv), reinterpret_cast<float*>(yv), sync,
-                         lambda, b, x, status, s, 0.0, rep_tn, rep_lam, nullptr);
+                         lambda, b, x, status, s, 0.0, rep_tn, rep_lam, nullptr, spin_limit);
   }
   return chol_t<double>(n, T, Lf, Dinv, yv, sync, lambda, b, x, status, s, lam_floor_rel, rep_tn,
-                        rep_lam, lam_in);
+                        rep_lam, lam_in, spin_limit);
 }
 
 // ================================================================ update

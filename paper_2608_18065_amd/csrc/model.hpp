@@ -71,6 +71,7 @@ struct minsr_model {
   int tune_eloc_grid = 0;
   int tune_sample_r = 0;
   int tune_jac_parts = 0;
+  int tune_spin_limit = 0;   // polls before a solver wait gives up (0: built in)
 
   // per-phase event timing of minsr_step (profiling only)
   std::vector<hipEvent_t> ev;   // [t_max][NPHASE + 1]
@@ -138,12 +139,14 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
 // when the floor is the larger; rep_tn / rep_lam (may be null) receive tr T
 // and the shift used
 // lam_in (FP64 only, may be null): the shift is read from the device
-// instead of `lambda` (the floor still applies)
+// instead of `lambda` (the floor still applies).  spin_limit: polls before
+// a wait between workgroups gives up (0: the built-in limit of about a
+// second or more)
 int launch_cholesky_solve(int n, const double* T, double* Lf, double* Dinv, int f32,
                           double lambda, const double* b, double* x, double* yv, uint32_t* sync,
                           uint32_t* status, hipStream_t s, double lam_floor_rel = 0.0,
                           double* rep_tn = nullptr, double* rep_lam = nullptr,
-                          const double* lam_in = nullptr);
+                          const double* lam_in = nullptr, uint32_t spin_limit = 0);
 // tr T into rep_tn and 0 into rep_lam (the report of a pseudo-inverse step)
 int launch_report_trace(int n, const double* T, double* rep_tn, double* rep_lam, hipStream_t s);
 size_t chol_dinv_elems(int n);

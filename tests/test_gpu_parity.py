@@ -451,6 +451,36 @@ def test_local_energy_fp32_large_weights(arch):
     assert rel_err(eloc, ref) < 2e-4
 
 
+@pytest.mark.parametrize("arch", [dict(Lx=16, H=64), dict(Lx=9, H=128, cplx=True)], ids=_ids)
+def test_local_energy_fp32_mixed_weight_magnitudes(arch):
+    # one output unit of each gate with a weight of 1e6 (its column staged
+    # scaled by a power of two) beside units whose weights are all of order
+    # 1e-3 (staged unscaled, so they keep their FP16 hi/lo precision)
+    spec, m = make_pair(**arch, dtype="f32")
+    th = scaled_theta(spec, 16, 1.0)
+    off = 0
+    for name, shape in omodel.layout(spec):
+        n = int(np.prod(shape))
+        if name in ("Wu", "Wr", "Wh"):
+            blk = th[off:off + n].reshape(shape)
+            blk *= 1e-3
+            blk[3, 5] = 1.0e6
+            blk[7, :] *= 1e3     # an ordinary unit beside them
+        off += n
+    m.set_params(to_dev(th))
+    ham = oham.Ham("cluster") if arch.get("cplx") else oham.Ham("tfim", J=1.0, h=1.0, pbc=True)
+    Ns = 45
+    sig, lp = omodel.sample(spec, th, philox.uniforms(80, 2, Ns, spec.N))
+    ref = oham.local_energy(spec, th, ham, sig, lp)
+    lp32 = m.logpsi(to_dev(sig.astype(np.uint8)))
+    eloc, _ = m.local_energy(_gpu_ham(ham), to_dev(sig.astype(np.uint8)), lp32)
+    eloc = eloc.cpu().numpy()
+    assert np.all(np.isfinite(eloc))
+    err = rel_err(eloc, ref)
+    print("mixed magnitudes %s: rel err %.2e" % (arch, err))
+    assert err < 2e-4
+
+
 @pytest.mark.parametrize("arch", [dict(Lx=14, H=64), dict(Lx=9, H=128, cplx=True),
                                   dict(Lx=4, Ly=3, dim=2, H=64, marshall=True)], ids=_ids)
 def test_jacobian_fp32_model(arch):

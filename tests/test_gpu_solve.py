@@ -66,6 +66,46 @@ def test_cholesky_reports_indefinite(model):
     assert int(st.item()) & 0x2   # MINSR_ST_NOT_PD
 
 
+def test_cholesky_waits_give_up_with_status():
+    # with a limit of one poll, waits between workgroups give up at once: the
+    # abort word ends every other wait, the kernels exit and the solve
+    # reports MINSR_ST_SOLVE_TIMEOUT (its x is not valid); at the built-in
+    # limit the same handle solves correctly again
+    import paper_2608_18065_amd as pm
+    n = 1024
+    m = pm.Model(16, hidden=8, dtype="f64", seed=2, max_Ns=n)
+    rng = np.random.default_rng(31)
+    T, _ = inputs.psd_matrix(inputs.spectrum_loguniform(n, 1e3, rng), seed=32)
+    b = inputs.rhs(n, seed=33)
+    m.set_tunable("solve_spin_limit", 1)
+    assert m.get_tunable("solve_spin_limit") == 1
+    x, st = m.solve(to_dev(T), to_dev(b), lam=1e-3)
+    torch.cuda.synchronize()
+    assert int(st.item()) & pm.ST_SOLVE_TIMEOUT
+    m.set_tunable("solve_spin_limit", 0)
+    x, st = m.solve(to_dev(T), to_dev(b), lam=1e-3)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert _rel(x.cpu().numpy(), ominsr.solve(T, b, 1e-3)) < 1e-10
+    m.close()
+
+
+def test_step_with_a_solve_that_gave_up_keeps_theta():
+    # a minSR step whose solve gave up leaves theta and the momentum as they
+    # were, with the failure in the status word
+    import paper_2608_18065_amd as pm
+    m = pm.Model(12, hidden=16, dtype="f64", seed=3, max_Ns=256)
+    th0 = m.get_params().clone()
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    m.set_tunable("solve_spin_limit", 1)
+    o = m.step(pm.hamiltonian("tfim", J=1.0, h=1.0), 256, 0.05, 1e-3, 0.5, mom, 5, 0,
+               form=pm.FORM_FP64_REF)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) & pm.ST_SOLVE_TIMEOUT
+    assert torch.equal(m.get_params(), th0) and not bool(mom.any())
+    m.close()
+
+
 def test_solve_rejects_bad_arguments(model):
     import paper_2608_18065_amd as pm
     T = torch.eye(4, dtype=torch.float64, device="cuda")
