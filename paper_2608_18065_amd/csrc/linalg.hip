@@ -947,14 +947,33 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
 
-  // While wave 0 factors panel P, waves 1..3 form the parts of the inverse
+  // block (Q, R) of S less the product of panel Pp's columns
+  auto trail = [&](int Q, int R, int Pp) {
+    f64x4_t t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = S[16 * Q + mrow(lane, v)][16 * R + (lane & 15)];
+    t = mm_nt<PB, true>(t, S, 16 * Q, S, 16 * R, PB * Pp, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[16 * Q + mrow(lane, v)][16 * R + (lane & 15)] = t[v];
+  };
+  // Panel P is factored by wave 0 after it has applied panel P - 1's
+  // product to its own column block; meanwhile waves 1..3 apply that
+  // product to the blocks right of it and form the parts of the inverse
   // that blocks < P already fix: Z_00 under panel 1; Z_11 and L_10 Z_00
-  // under panel 2 (Z_10 after it); Z_22, L_20 Z_00 + L_21 Z_10 and L_21 Z_11
-  // under panel 3; the last row of blocks follows.
+  // under panel 2; Z_22, Z_10 and L_21 Z_11 under panel 3; the last rows of
+  // blocks follow.  Every block receives the panel products in panel order,
+  // so the factor does not depend on which wave applies them.  One barrier
+  // per panel.  (The pivots of a pair form a dependent chain of about 580
+  // cycles, measured; taking the far columns' updates off wave 0 onto a
+  // helper wave did not shorten it.)
   bool bad = false;
   for (int P = 0; P < CB / PB; ++P) {
-    const int p0 = PB * P, p1 = p0 + PB;
+    const int p0 = PB * P;
     if (w == 0) {
+      if (P > 0) {
+        for (int Q = P; Q < NB; ++Q) trail(Q, P, P - 1);
+        wave_fence();   // the updated blocks are read back across lanes below
+      }
       double f[PB];
 #pragma unroll
       for (int cc = 0; cc < PB; ++cc) f[cc] = S[lane][p0 + cc];
@@ -965,12 +984,13 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
 #pragma unroll
       for (int cc = 0; cc < PB; cc += 2) {
         const int c = p0 + cc;
-        double d0 = lane_bcast(f[cc], c);
+        const double d0 = lane_bcast(f[cc], c);
         const double a10 = lane_bcast(f[cc], c + 1);
         const double d1 = lane_bcast(f[cc + 1], c + 1);
-        double det = fma(-a10, a10, d0 * d1);
-        if (!(d0 > 0.0)) { bad = true; d0 = 1.0; det = 1.0; }
-        if (!(det > 0.0)) { bad = true; det = 1.0; }
+        const double det = fma(-a10, a10, d0 * d1);
+        // a pivot <= 0 or NaN is recorded off the dependent chain; its NaNs
+        // then run through the factor, which the status word marks invalid
+        bad |= !(d0 > 0.0) || !(det > 0.0);
         const double inv0 = rsqrt_h(d0);
         const double invdet = rsqrt_h(det);
         const double inv1 = (d0 * inv0) * invdet;
@@ -999,44 +1019,48 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
       }
 #pragma unroll
       for (int cc = 0; cc < PB; ++cc) S[lane][p0 + cc] = lane >= p0 + cc ? f[cc] : 0.0;
-    } else if (P == 0) {
-      during_first_panel();
-    } else if (P == 1) {
-      if (w == 1) diag_inv(0);
-    } else if (P == 2) {
-      if (w == 1) diag_inv(1);
-      else if (w == 2) lprod(1, 0, 0);
     } else {
-      if (w == 1) diag_inv(2);
-      else if (w == 2) lprod(2, 0, 1);
-      else lprod(2, 1, 2);
-    }
-    __syncthreads();
-    if (p1 < CB) {
-      // blocks (Q, R), Q >= R >= p1 / 16 of the trailing lower triangle
-      const int R0 = p1 / 16, nr = NB - R0;
-      for (int pi = w; pi < nr * (nr + 1) / 2; pi += 4) {
-        int q = 0, rem = pi;
-        while (rem > q) { rem -= q + 1; ++q; }
-        const int Q = R0 + q, R = R0 + rem;
-        f64x4_t t;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) t[v] = S[16 * Q + mrow(lane, v)][16 * R + (lane & 15)];
-        t = mm_nt<PB, true>(t, S, 16 * Q, S, 16 * R, p0, lane);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) S[16 * Q + mrow(lane, v)][16 * R + (lane & 15)] = t[v];
+      if (P > 0) {
+        // blocks (Q, R), Q >= R >= P + 1, of panel P - 1's trailing update
+        const int R0 = P + 1, nr = NB - R0;
+        for (int pi = w - 1; pi < nr * (nr + 1) / 2; pi += 3) {
+          int q = 0, rem = pi;
+          while (rem > q) { rem -= q + 1; ++q; }
+          trail(R0 + q, R0 + rem, P - 1);
+        }
+      }
+      if (P == 0) {
+        during_first_panel();
+      } else if (P == 1) {
+        if (w == 1) diag_inv(0);
+      } else if (P == 2) {
+        if (w == 1) diag_inv(1);
+        else if (w == 2) lprod(1, 0, 0);
+      } else {
+        if (w == 1) {
+          diag_inv(2);
+          zprod(1, 0, 0);
+        } else if (w == 3) {
+          lprod(2, 1, 2);
+        }
       }
     }
-    if (P == 2 && w == 1) zprod(1, 0, 0);   // the trailing update after panel 2 is wave 0's
     __syncthreads();
   }
   if (bad && lane == 0 && status) atomicOr(status, MINSR_ST_NOT_PD);
-  // the last row of blocks: Z_33 with Z_20, Z_21 and L_32 Z_22, then
-  // Z_30, Z_31, Z_32
-  if (w == 0) diag_inv(3);
-  else if (w == 1) zprod(2, 0, 1);
-  else if (w == 2) zprod(2, 1, 2);
-  else lprod(3, 2, 3);
+  // the last rows of blocks: Z_33, Z_20 (L_20 Z_00 + L_21 Z_10 first),
+  // Z_21 and L_32 Z_22, then Z_30, Z_31, Z_32
+  if (w == 0) {
+    diag_inv(3);
+  } else if (w == 1) {
+    lprod(2, 0, 1);
+    wave_fence();
+    zprod(2, 0, 1);
+  } else if (w == 2) {
+    zprod(2, 1, 2);
+  } else {
+    lprod(3, 2, 3);
+  }
   __syncthreads();
   if (w == 1) {
     lprod(3, 0, 0);
