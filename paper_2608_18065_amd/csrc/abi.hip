@@ -87,7 +87,7 @@ static int ensure_pinv_ws(minsr_model* m, hipStream_t s) {
 }
 
 static void release(minsr_model* m) {
-  void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->gates, m->jdp, m->site,
+  void* ptrs[] = {m->theta, m->work, m->nbr, m->subA, m->bonds, m->states, m->gates, m->jdp, m->jtape, m->site,
                   m->contrib,
                   m->elist, m->ecount, m->eitems, m->eloc_q,
                   m->diag, m->ring, m->sigma, m->logpsi, m->eloc, m->stats, m->O, m->R,
@@ -211,6 +211,8 @@ int minsr_create_model(const minsr_model_desc* d, minsr_model** out) {
     rc = rc ? rc : alloc(&m->gates, S * Nz * 4 * Hz * sz);
     if (m->H >= 32) rc = rc ? rc : alloc(&m->jdp, (m->cplx ? 2 : 1) * S * Nz * 3 * Hz * sz);
   }
+  if (const size_t te = jac_mfma_tape_elems(m->dim, m->f64, m->H, m->N, m->cplx, S))
+    rc = rc ? rc : alloc(&m->jtape, te * sizeof(float));
   rc = rc ? rc : alloc((void**)&m->site, S * Nz * 4 * 8);
   rc = rc ? rc : alloc((void**)&m->contrib, (size_t)m->max_terms * S * 2 * 8);
   rc = rc ? rc : alloc((void**)&m->elist, (size_t)m->max_terms * S * 4);

@@ -776,6 +776,10 @@ int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* st
   if (ckpt_every < 1 || ckpt_every > SEGMAX)
     return fail(MINSR_E_INVALID_ARG, "ckpt_every must be in [1, 16]");
   if (m->f64) return jac_t<double>(m, m->wd, Ns, sigma, states, ckpt_every, O, gates, site, s);
+  // d_h = 128 chains: sample-batched reverse pass on the matrix cores
+  // (an explicit thread split selects the per-sample kernel below)
+  if (m->tune_jac_parts == 0 && site && states == m->states && jac_mfma_supported(m, ckpt_every))
+    return launch_jacobian_mfma(m, Ns, sigma, ckpt_every, O, site, s);
   return jac_t<float>(m, m->wf, Ns, sigma, states, ckpt_every, O, gates, site, s);
 }
 

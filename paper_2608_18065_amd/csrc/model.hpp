@@ -31,6 +31,8 @@ struct minsr_model {
   void* states = nullptr;   // [max_Ns][N][H] hidden states
   void* gates = nullptr;    // [max_Ns][N][4][H] gate tape (FP32 1D models, d_h <= 64)
   void* jdp = nullptr;      // [seeds][max_Ns][N][3][H] gate adjoints of the Jacobian (same models)
+  void* jtape = nullptr;    // FP32 1D d_h = 128: [seeds][max_Ns][N][4][H] gate adjoints, then
+                            //   [seeds][max_Ns][N][2] head adjoints (matrix-core Jacobian)
   double* site = nullptr;   // [max_Ns][N][4]: log p(0), log p(1), phi(0), phi(1)
   double* contrib = nullptr;// [max_terms][max_Ns][2]
   int* elist = nullptr;     // [max_terms][max_Ns] samples with a nonzero matrix element
@@ -118,6 +120,13 @@ int launch_jacobian(minsr_model* m, int Ns, const uint8_t* sigma, const void* st
                     int ckpt_every, void* O, const double* g, double* vjp_part,
                     hipStream_t s, const void* gates = nullptr,
                     const double* site = nullptr);
+// jac_mfma.hip: the Jacobian of FP32 1D models with d_h = 128 (N <= 128) on
+// the matrix cores; the tape it needs (elements of jtape, 0 if the path
+// does not apply) and whether checkpoint stride C fits its shared memory
+size_t jac_mfma_tape_elems(int dim, int f64, int H, int N, int cplx, size_t max_Ns);
+bool jac_mfma_supported(const minsr_model* m, int C);
+int launch_jacobian_mfma(minsr_model* m, int Ns, const uint8_t* sigma, int C, void* O,
+                         const double* site, hipStream_t s);
 // linalg.hip
 // centred (colmean != null) or plain copy of O into R with row stride ldo
 // (ldo >= Np; columns Np..ldo-1 are written as zeros)
