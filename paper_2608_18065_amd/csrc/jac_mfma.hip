@@ -71,6 +71,15 @@ __device__ __forceinline__ float jtanh(float y) {
   return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(2.8853900817779268f * y));
 }
 
+// workgroup barrier ordering shared-memory accesses only: unlike
+// lds_barrier() it does not wait for the wave's outstanding global stores
+// (these kernels never read back, within a launch, what they store)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // power-of-two exponent that brings a largest magnitude m into [2^14, 2^15)
 __device__ __forceinline__ int jexp_for(float m) {
   return m > 0.f ? min(max(14 - ilogbf(m), -120), 120) : 0;
@@ -94,30 +103,43 @@ struct JRevArgs {
   float* dzt;            // [rows][N][2]: adjoints of the two head outputs
 };
 
-template <bool CPLX>
+// NL: the last NL K-steps of the reverse product take their weight fragments
+// from shared memory instead of registers (as many as the segment length
+// leaves room for), so the fragments and the working set fit the register file
+template <bool CPLX, int NL>
 __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
   constexpr int H = JM_H, NW = H / 16, KF = H / 32, KR = 3 * H / 32;
+  constexpr int KRR = KR - NL;         // reverse K-steps with register fragments
   constexpr int S = CPLX ? 8 : 16;     // samples per workgroup (16 rows)
-  constexpr int HP = H + 4;            // state row pitch (floats)
-  constexpr int DP = 3 * H + 4;        // gate-adjoint row pitch
+  constexpr int HQ = H + 8;            // state row pitch (halves)
+  constexpr int DQ = 3 * H + 8;        // gate-adjoint row pitch (halves)
   constexpr int SGP = JM_SEG + 1;
   constexpr int NT = 64 * NW;
-  extern __shared__ __align__(16) float jsm[];
+  extern __shared__ __align__(16) unsigned char jsm[];
   const int C = a.C, N = a.N, Ns = a.Ns;
-  float* hs = jsm;                                 // [C + 1][S][HP]: h_{ks-1+kk}
-  float* dps = hs + (size_t)(C + 1) * S * HP;      // [2][16][DP] gate adjoints of a site
-  float* rmx = dps + 2 * 16 * DP;                  // [2][NW][16] their row maxima per wave
-  float* dzs = rmx + 2 * NW * 16;                  // [JM_SEG][16][2] head adjoints
-  float* cst = dzs + JM_SEG * 32;                  // [13][H] biases and one-hot columns
-  int* sgs = reinterpret_cast<int*>(cst + 13 * H); // [S][SGP] sigma_{ks-1+kk}, 2 before site 0
+  // states h_{ks-1+kk} and the scaled gate adjoints of a site, both as FP16
+  // hi/lo halves (the products' A operands, split once when written)
+  _Float16* hsh = reinterpret_cast<_Float16*>(jsm);     // [C + 1][S][HQ]
+  _Float16* hsl = hsh + (size_t)(C + 1) * S * HQ;
+  _Float16* dph = hsl + (size_t)(C + 1) * S * HQ;       // [16][DQ]
+  _Float16* dpl = dph + 16 * DQ;
+  jh8* rfr = reinterpret_cast<jh8*>(dpl + 16 * DQ);     // [NL][hi, lo][NW][64]
+  float* rmx = reinterpret_cast<float*>(rfr + NL * 2 * NW * 64);   // [16][NW] row maxima
+  float* dzs = rmx + 16 * NW;                      // [JM_SEG][16][2] head adjoints
+  float* cst = dzs + JM_SEG * 32;                  // [21][H] + 2, rows described below
+  int* sgs = reinterpret_cast<int*>(cst + 21 * H + 2); // [S][SGP] sigma_{ks-1+kk}, 2 before site 0
 
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int n = l & 15, kq = l >> 4;
   const int j = 16 * w + n;            // this lane's hidden unit (gate row / state column)
   const int s0 = blockIdx.x * S;
 
-  // cst rows: b_u, b_r, b_h, b_in, then for u, r, in the input columns of
-  // spin values 0, 1 and zeros (no input at site 0)
+  // cst rows: 0-3 b_u, b_r, b_h, b_in; 4-12 for u, r, in the input columns
+  // of spin values 0, 1 and zeros (no input at site 0); 13-15 the forward
+  // column scales of u, r, h; 16 the reverse column scales; 17-20 U, U_phi;
+  // then c_phi
+  for (int i = tid; i < 4 * H; i += NT) cst[17 * H + i] = a.head[i];
+  if (tid < 2) cst[21 * H + tid] = a.headb[2 + tid];
   for (int i = tid; i < H; i += NT) {
 #pragma unroll
     for (int g = 0; g < 4; ++g) cst[g * H + i] = a.bias[g * H + i];
@@ -129,15 +151,14 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
     }
   }
 
-  // ---- register-resident B fragments (lane: column n, inputs 8 kq .. 8 kq + 7)
+  // ---- B fragments (lane: column n, inputs 8 kq .. 8 kq + 7)
   auto fwv = [&](int g, int row, int i) -> float {   // W_g[row][i]
     return a.fw[((size_t)(i >> 2) * H + row) * 12 + g * 4 + (i & 3)];
   };
   auto bwv = [&](int g, int row, int col) -> float {   // W_g[row][col]
     return a.bw[((size_t)(row >> 2) * H + col) * 12 + g * 4 + (row & 3)];
   };
-  jh8 fh[3][KF], fl[3][KF], rh[KR], rl[KR];
-  float fup[3], rup;
+  jh8 fh[3][KF], fl[3][KF], rh[KRR], rl[KRR];
   {
     // forward: B[k][n] = W_g[j][32 t + 8 kq + e]
 #pragma unroll
@@ -152,7 +173,7 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
       // a weight column reaching 2^14 is split as w 2^-s, its products scaled back
       const int se = mx >= 16384.f ? min(ilogbf(mx) - 13, 120) : 0;
       const float dn = ldexpf(1.f, -se);
-      fup[g] = ldexpf(1.f, se);
+      if (kq == 0) cst[(13 + g) * H + j] = ldexpf(1.f, se);
 #pragma unroll
       for (int t = 0; t < KF; ++t) {
         float x[8];
@@ -171,54 +192,70 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
     mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
     const int se = mx >= 16384.f ? min(ilogbf(mx) - 13, 120) : 0;
     const float dn = ldexpf(1.f, -se);
-    rup = ldexpf(1.f, se);
+    if (kq == 0) cst[16 * H + j] = ldexpf(1.f, se);
 #pragma unroll
     for (int t = 0; t < KR; ++t) {
       float x[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) x[e] = bwv(t / KF, 32 * (t % KF) + 8 * kq + e, j) * dn;
-      jsplit(x, rh[t], rl[t]);
+      if (t < KRR) {
+        jsplit(x, rh[t < KRR ? t : 0], rl[t < KRR ? t : 0]);
+      } else {
+        jh8 hi, lo;
+        jsplit(x, hi, lo);
+        rfr[((t - KRR) * 2 + 0) * NW * 64 + w * 64 + l] = hi;
+        rfr[((t - KRR) * 2 + 1) * NW * 64 + w * 64 + l] = lo;
+      }
     }
   }
   // this lane's rows are 4 kq + e; with a cRNN rows 8..15 are the phase
   // outputs of the samples of rows 0..7, so a lane's four rows share a head
   const int seedL = CPLX ? (kq >> 1) : 0;
-  const float hd0 = a.head[(seedL ? 2 : 0) * H + j];
-  const float hd1 = a.head[(seedL ? 3 : 1) * H + j];
-  __syncthreads();
+  const float* hdw = cst + (17 + 2 * seedL) * H + j;   // this lane's head weights
+  lds_barrier();
 
-  // gate pre-activation products of the 16 rows from the states in hb (the
+  // state value of (buffer kk, sample s, unit u) and its split store
+  auto hget = [&](int kk, int s, int u) -> float {
+    const size_t o = ((size_t)kk * S + s) * HQ + u;
+    return (float)hsh[o] + (float)hsl[o];
+  };
+  auto hput = [&](int kk, int s, int u, float v) {
+    const size_t o = ((size_t)kk * S + s) * HQ + u;
+    const _Float16 hi = (_Float16)v;
+    hsh[o] = hi;
+    hsl[o] = (_Float16)(v - (float)hi);
+  };
+  // gate pre-activation products of the 16 rows from state buffer kk (the
   // A row of lane l is row n, i.e. sample n mod S)
-  auto gates = [&](const float* hb, jf4 (&acc)[3]) {
+  auto gates = [&](int kk, jf4 (&acc)[3]) {
 #pragma unroll
     for (int g = 0; g < 3; ++g) acc[g] = jf4{0.f, 0.f, 0.f, 0.f};
-    const float* src = hb + (n % S) * HP + 8 * kq;
+    const size_t o = ((size_t)kk * S + (n % S)) * HQ + 8 * kq;
 #pragma unroll
     for (int t = 0; t < KF; ++t) {
-      const float4 x0 = *reinterpret_cast<const float4*>(src + 32 * t);
-      const float4 x1 = *reinterpret_cast<const float4*>(src + 32 * t + 4);
-      const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-      jh8 ah, al;
-      jsplit(x, ah, al);
+      const jh8 ah = *reinterpret_cast<const jh8*>(hsh + o + 32 * t);
+      const jh8 al = *reinterpret_cast<const jh8*>(hsl + o + 32 * t);
 #pragma unroll
       for (int g = 0; g < 3; ++g) {
         acc[g] = jmma(al, fh[g][t], acc[g]);
         acc[g] = jmma(ah, fl[g][t], acc[g]);
         acc[g] = jmma(ah, fh[g][t], acc[g]);
       }
-      // keep the scheduler from hoisting every K-step's operand loads (the
-      // weight fragments leave few registers for them)
-      __builtin_amdgcn_sched_barrier(0);
     }
   };
   // the cell of row 4 kq + e, unit j, previous spin sp
   auto cell = [&](const jf4 (&acc)[3], int e, int sp, float& u, float& r, float& ag, float& ht) {
-    float au = fmaf(acc[0][e], fup[0], cst[j]);
-    float ar = fmaf(acc[1][e], fup[1], cst[H + j]);
-    ag = fmaf(acc[2][e], fup[2], cst[2 * H + j]);
-    const float ai = cst[3 * H + j] + cst[(10 + sp) * H + j];
-    au += cst[(4 + sp) * H + j];
-    ar += cst[(7 + sp) * H + j];
+    float au = fmaf(acc[0][e], cst[13 * H + j], cst[j]);
+    float ar = fmaf(acc[1][e], cst[14 * H + j], cst[H + j]);
+    ag = fmaf(acc[2][e], cst[15 * H + j], cst[2 * H + j]);
+    // input columns of both spin values read unconditionally (no shared-
+    // memory load waits on the spin), the one for sp selected
+    const float xu0 = cst[4 * H + j], xu1 = cst[5 * H + j];
+    const float xr0 = cst[7 * H + j], xr1 = cst[8 * H + j];
+    const float xi0 = cst[10 * H + j], xi1 = cst[11 * H + j];
+    const float ai = cst[3 * H + j] + (sp == 0 ? xi0 : sp == 1 ? xi1 : 0.f);
+    au += sp == 0 ? xu0 : sp == 1 ? xu1 : 0.f;
+    ar += sp == 0 ? xr0 : sp == 1 ? xr1 : 0.f;
     u = jsig(au);
     r = jsig(ar);
     ht = jtanh(fmaf(r, ag, ai));
@@ -232,23 +269,57 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
     const int len = min(C, N - ks);
     const bool last_ck = (ks + len) % C == 0;   // the segment's last state is stored
     const int nf = last_ck ? len - 1 : len;     // states recomputed forward
-    for (int i = tid; i < S * H; i += NT) {
-      const int s = i / H, u = i % H;
-      const size_t sg = (size_t)min(s0 + s, Ns - 1);
-      hs[s * HP + u] = ks > 0 ? a.states[(sg * N + ks - 1) * H + u] : 0.f;
-      if (last_ck) hs[((size_t)len * S + s) * HP + u] = a.states[(sg * N + ks + len - 1) * H + u];
-    }
-    for (int i = tid; i < S * (len + 1); i += NT) {
-      const int s = i / (len + 1), kk = i % (len + 1);
+    {
+      // every global load of the staging issued before any is used
+      constexpr int PT = S * H / NT;             // states per thread
+      float hv0[PT], hv1[PT];
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        const int i = tid + q * NT, s = i / H, u = i % H;
+        const size_t sg = (size_t)min(s0 + s, Ns - 1);
+        hv0[q] = ks > 0 ? a.states[(sg * N + ks - 1) * H + u] : 0.f;
+        hv1[q] = last_ck ? a.states[(sg * N + ks + len - 1) * H + u] : 0.f;
+      }
+      const bool sit = tid < S * (len + 1);
+      const int s = tid / (len + 1), kk = tid % (len + 1);
       const int k = ks - 1 + kk;
-      sgs[s * SGP + kk] = k >= 0 ? (int)(a.sigma[(size_t)min(s0 + s, Ns - 1) * N + k] & 1) : 2;
+      const size_t sg = (size_t)min(s0 + s, Ns - 1);
+      int sk = 2;
+      double l0 = 0.0, l1 = 0.0;
+      if (sit && k >= 0) sk = (int)(a.sigma[sg * N + k] & 1);
+      if (sit && k >= ks) {
+        const double* st = a.site + (sg * N + k) * 4;
+        l0 = st[0];
+        l1 = st[1];
+      }
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        const int i = tid + q * NT;
+        hput(0, i / H, i % H, hv0[q]);
+        if (last_ck) hput(len, i / H, i % H, hv1[q]);
+      }
+      if (sit) {
+        sgs[s * SGP + kk] = sk;
+        // log-modulus head adjoints of site k: (delta - p) / 2 from the
+        // forward pass's (masked) conditionals
+        if (k >= ks) {
+          const float z0 = 0.5f * ((sk == 0 ? 1.f : 0.f) - expf((float)l0));
+          const float z1 = 0.5f * ((sk == 1 ? 1.f : 0.f) - expf((float)l1));
+          dzs[((kk - 1) * 16 + s) * 2 + 0] = z0;
+          dzs[((kk - 1) * 16 + s) * 2 + 1] = z1;
+          if (s0 + s < Ns) {
+            float* d0 = a.dzt + ((size_t)(s0 + s) * N + k) * 2;
+            d0[0] = z0; d0[1] = z1;
+          }
+        }
+      }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ---- forward recomputation of the segment's states
     for (int kk = 0; kk < nf; ++kk) {
       jf4 acc[3];
-      gates(hs + (size_t)kk * S * HP, acc);
+      gates(kk, acc);
       if (!CPLX || kq < 2) {
         const int k = ks + kk;
 #pragma unroll
@@ -256,85 +327,68 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
           const int sm = 4 * kq + e;
           float u, r, ag, ht;
           cell(acc, e, sgs[sm * SGP + kk], u, r, ag, ht);
-          const float hp = hs[((size_t)kk * S + sm) * HP + j];
+          const float hp = hget(kk, sm, j);
           const float hn = fmaf(u, ht - hp, hp);
-          hs[((size_t)(kk + 1) * S + sm) * HP + j] = hn;
+          hput(kk + 1, sm, j, hn);
           if (s0 + sm < Ns) a.states[((unsigned)(s0 + sm) * N + k) * H + j] = hn;
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
 
-    // ---- head adjoints of the segment's sites
+    // ---- phase-head adjoints of the segment's sites (cRNN; the log-modulus
+    // ones come from the forward pass's conditionals, staged above)
     if constexpr (CPLX) {
-      for (int p = w; p < len * S; p += NW) {
-        const int kk = p / S, s = p % S;
-        const float* hr = hs + ((size_t)(kk + 1) * S + s) * HP;
-        float v0 = hr[l] * a.head[2 * H + l];
-        float v1 = hr[l] * a.head[3 * H + l];
-        v0 = fmaf(hr[l + 64], a.head[2 * H + l + 64], v0);
-        v1 = fmaf(hr[l + 64], a.head[3 * H + l + 64], v1);
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-          v0 += __shfl_xor(v0, o, 64);
-          v1 += __shfl_xor(v1, o, 64);
-        }
-        if (l == 0) {
-          const int k = ks + kk;
-          const int sk = sgs[s * SGP + kk + 1];
-          const double* st = a.site + ((size_t)min(s0 + s, Ns - 1) * N + k) * 4;
-          const float z0 = 0.5f * ((sk == 0 ? 1.f : 0.f) - expf((float)st[0]));
-          const float z1 = 0.5f * ((sk == 1 ? 1.f : 0.f) - expf((float)st[1]));
-          const float e0 = 1.f + fabsf(v0 + a.headb[2]), e1 = 1.f + fabsf(v1 + a.headb[3]);
-          const float PI = 3.14159265358979323846f;
-          const float q0 = sk == 0 ? PI / (e0 * e0) : 0.f;
-          const float q1 = sk == 1 ? PI / (e1 * e1) : 0.f;
-          dzs[(kk * 16 + s) * 2 + 0] = z0;
-          dzs[(kk * 16 + s) * 2 + 1] = z1;
-          dzs[(kk * 16 + 8 + s) * 2 + 0] = q0;
-          dzs[(kk * 16 + 8 + s) * 2 + 1] = q1;
-          if (s0 + s < Ns) {
-            float* d0 = a.dzt + ((size_t)(s0 + s) * N + k) * 2;
-            float* d1 = a.dzt + ((size_t)(Ns + s0 + s) * N + k) * 2;
-            d0[0] = z0; d0[1] = z1; d1[0] = q0; d1[1] = q1;
-          }
-        }
+      // four lanes per (site, sample), 32 units each
+      const int p = tid >> 2, qd = tid & 3;
+      const bool on = p < len * S;     // len * S <= 128: one pass
+      const int kk = on ? p / S : 0, s = p % S;
+      const float* hph = cst + 19 * H;
+      float v0 = 0.f, v1 = 0.f;
+#pragma unroll 8
+      for (int u = 32 * qd; u < 32 * qd + 32; ++u) {
+        const float hv = hget(kk + 1, s, u);
+        v0 = fmaf(hv, hph[u], v0);
+        v1 = fmaf(hv, hph[H + u], v1);
       }
-    } else {
-      for (int p = tid; p < len * S; p += NT) {
-        const int kk = p / S, s = p % S;
+      v0 += __shfl_xor(v0, 1, 64);
+      v1 += __shfl_xor(v1, 1, 64);
+      v0 += __shfl_xor(v0, 2, 64);
+      v1 += __shfl_xor(v1, 2, 64);
+      if (on && qd == 0) {
         const int k = ks + kk;
         const int sk = sgs[s * SGP + kk + 1];
-        const double* st = a.site + ((size_t)min(s0 + s, Ns - 1) * N + k) * 4;
-        const float z0 = 0.5f * ((sk == 0 ? 1.f : 0.f) - expf((float)st[0]));
-        const float z1 = 0.5f * ((sk == 1 ? 1.f : 0.f) - expf((float)st[1]));
-        dzs[(kk * 16 + s) * 2 + 0] = z0;
-        dzs[(kk * 16 + s) * 2 + 1] = z1;
+        const float e0 = 1.f + fabsf(v0 + cst[21 * H]), e1 = 1.f + fabsf(v1 + cst[21 * H + 1]);
+        const float PI = 3.14159265358979323846f;
+        const float q0 = sk == 0 ? PI / (e0 * e0) : 0.f;
+        const float q1 = sk == 1 ? PI / (e1 * e1) : 0.f;
+        dzs[(kk * 16 + 8 + s) * 2 + 0] = q0;
+        dzs[(kk * 16 + 8 + s) * 2 + 1] = q1;
         if (s0 + s < Ns) {
-          float* d0 = a.dzt + ((size_t)(s0 + s) * N + k) * 2;
-          d0[0] = z0; d0[1] = z1;
+          float* d1 = a.dzt + ((size_t)(Ns + s0 + s) * N + k) * 2;
+          d1[0] = q0; d1[1] = q1;
         }
       }
+      lds_barrier();
     }
-    __syncthreads();
 
     // ---- reverse through the segment
+    // the gate products of site k - 1 are issued together with the reverse
+    // product of site k (independent work for the matrix cores)
+    jf4 acc[3];
+    gates(len - 1, acc);
     for (int kk = len - 1; kk >= 0; --kk) {
-      const int k = ks + kk, buf = k & 1;
-      jf4 acc[3];
-      gates(hs + (size_t)kk * S * HP, acc);
-      float* db = dps + (size_t)buf * 16 * DP;
-      float dhd[4];
-      float mloc[4];
+      const int k = ks + kk;
+      float dp[4][3], dhd[4], mloc[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int rr = 4 * kq + e;
         const int sm = rr % S;
         float u, r, ag, ht;
         cell(acc, e, sgs[sm * SGP + kk], u, r, ag, ht);
-        const float hp = hs[((size_t)kk * S + sm) * HP + j];
+        const float hp = hget(kk, sm, j);
         const float dz0 = dzs[(kk * 16 + rr) * 2 + 0], dz1 = dzs[(kk * 16 + rr) * 2 + 1];
-        const float dh = fmaf(dz1, hd1, fmaf(dz0, hd0, carry[e]));
+        const float dh = fmaf(dz1, hdw[H], fmaf(dz0, hdw[0], carry[e]));
         const float dht = dh * u;
         const float du = dh * (ht - hp);
         dhd[e] = dh * (1.f - u);
@@ -343,9 +397,7 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
         const float dg = da * r;
         const float dpu = du * u * (1.f - u);
         const float dpr = dr * r * (1.f - r);
-        db[rr * DP + j] = dpu;
-        db[rr * DP + H + j] = dpr;
-        db[rr * DP + 2 * H + j] = dg;
+        dp[e][0] = dpu; dp[e][1] = dpr; dp[e][2] = dg;
         mloc[e] = fmaxf(fabsf(dpu), fmaxf(fabsf(dpr), fabsf(dg)));
         if (s0 + sm < Ns) {
           const unsigned grow = (CPLX ? (rr >> 3) * Ns : 0) + s0 + sm;
@@ -359,36 +411,56 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
         for (int o = 1; o < 16; o <<= 1) mloc[e] = fmaxf(mloc[e], __shfl_xor(mloc[e], o, 16));
       if (n == 0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) rmx[(buf * NW + w) * 16 + 4 * kq + e] = mloc[e];
+        for (int e = 0; e < 4; ++e) rmx[(4 * kq + e) * NW + w] = mloc[e];
       }
-      __syncthreads();
-
-      // adjoint of h_{k-1}: [16 x 3 d_h] x [3 d_h x d_h] with row n scaled by 2^ex
-      float mx = 0.f;
-#pragma unroll
-      for (int v = 0; v < NW; ++v) mx = fmaxf(mx, rmx[(buf * NW + v) * 16 + n]);
-      const int ex = jexp_for(mx);
-      const float sc = ldexpf(1.f, ex);
-      jf4 racc = {0.f, 0.f, 0.f, 0.f};
-      const float* arow = db + n * DP + 8 * kq;
-#pragma unroll
-      for (int t = 0; t < KR; ++t) {
-        const float4 x0 = *reinterpret_cast<const float4*>(arow + 32 * t);
-        const float4 x1 = *reinterpret_cast<const float4*>(arow + 32 * t + 4);
-        const float x[8] = {x0.x * sc, x0.y * sc, x0.z * sc, x0.w * sc,
-                            x1.x * sc, x1.y * sc, x1.z * sc, x1.w * sc};
-        jh8 ah, al;
-        jsplit(x, ah, al);
-        racc = jmma(al, rh[t], racc);
-        racc = jmma(ah, rl[t], racc);
-        racc = jmma(ah, rh[t], racc);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      lds_barrier();
+      // each row scaled by a power of two from its largest gate adjoint,
+      // then split into the A operand of the reverse product
+      int ex[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float inv = ldexpf(1.f, -__shfl(ex, 4 * kq + e, 64));
-        carry[e] = fmaf(racc[e] * rup, inv, dhd[e]);
+        const float4 m0 = *reinterpret_cast<const float4*>(rmx + (4 * kq + e) * NW);
+        const float4 m1 = *reinterpret_cast<const float4*>(rmx + (4 * kq + e) * NW + 4);
+        const float mx = fmaxf(fmaxf(fmaxf(m0.x, m0.y), fmaxf(m0.z, m0.w)),
+                               fmaxf(fmaxf(m1.x, m1.y), fmaxf(m1.z, m1.w)));
+        ex[e] = jexp_for(mx);
+        const float sc = ldexpf(1.f, ex[e]);
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+          const float v = dp[e][g] * sc;
+          const _Float16 hi = (_Float16)v;
+          dph[(4 * kq + e) * DQ + g * H + j] = hi;
+          dpl[(4 * kq + e) * DQ + g * H + j] = (_Float16)(v - (float)hi);
+        }
       }
+      lds_barrier();
+
+      if (kk > 0) gates(kk - 1, acc);
+      // adjoint of h_{k-1}: [16 x 3 d_h] x [3 d_h x d_h]; three independent
+      // accumulation chains, one per split product
+      jf4 rc0 = {0.f, 0.f, 0.f, 0.f}, rc1 = rc0, rc2 = rc0;
+      const _Float16* ahp = dph + n * DQ + 8 * kq;
+      const _Float16* alp = dpl + n * DQ + 8 * kq;
+#pragma unroll
+      for (int t = 0; t < KR; ++t) {
+        const jh8 ah = *reinterpret_cast<const jh8*>(ahp + 32 * t);
+        const jh8 al = *reinterpret_cast<const jh8*>(alp + 32 * t);
+        jh8 bh, bl;
+        if (t < KRR) {
+          bh = rh[t < KRR ? t : 0];
+          bl = rl[t < KRR ? t : 0];
+        } else {
+          bh = rfr[((t - KRR) * 2 + 0) * NW * 64 + w * 64 + l];
+          bl = rfr[((t - KRR) * 2 + 1) * NW * 64 + w * 64 + l];
+        }
+        rc0 = jmma(al, bh, rc0);
+        rc1 = jmma(ah, bl, rc1);
+        rc2 = jmma(ah, bh, rc2);
+      }
+      const jf4 racc = (rc0 + rc1) + rc2;
+      const float rs = cst[16 * H + j];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) carry[e] = fmaf(racc[e] * rs, ldexpf(1.f, -ex[e]), dhd[e]);
     }
   }
 }
@@ -411,6 +483,7 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
   __shared__ float xch[4][H];      // the upper half's max, sum, one-hot sums
   __shared__ float exs[H];         // 2^-E of gate row j
   __shared__ int sgl[KM];
+  __shared__ float dzl[2][KM][2];  // head adjoints of both outputs
   const int N = a.N, Ns = a.Ns;
   const int s = blockIdx.x;
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
@@ -441,6 +514,72 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
   // staging thread: gate row j, sites [64 kb, 64 kb + 64)
   const int jr = tid & (H - 1), kb = tid >> 7;
   const int nseed = CPLX ? 2 : 1;
+
+  // output head: d/dU[c][j] = sum_k dz_k[c] h_k[j], d/dc[c] = sum_k dz_k[c]
+  // (each output's own head; the other head of a cRNN row is zero)
+  for (int i = tid; i < nseed * KM * 2; i += 256) {
+    const int sd = i / (KM * 2), r = i % (KM * 2);
+    dzl[sd][r >> 1][r & 1] = (r >> 1) < N ? a.dzt[((size_t)sd * Ns + s) * N * 2 + r] : 0.f;
+  }
+  lds_barrier();
+  {
+    float hv[64];
+#pragma unroll
+    for (int m = 0; m < 64; ++m) {
+      const int k = 64 * kb + m;
+      hv[m] = k < N ? hst[(size_t)k * H + jr] : 0.f;
+    }
+    float g[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+#pragma unroll
+    for (int m = 0; m < 64; ++m)
+#pragma unroll
+      for (int sd = 0; sd < (CPLX ? 2 : 1); ++sd) {
+        g[sd][0] = fmaf(dzl[sd][64 * kb + m][0], hv[m], g[sd][0]);
+        g[sd][1] = fmaf(dzl[sd][64 * kb + m][1], hv[m], g[sd][1]);
+      }
+    if (kb == 1) {
+      xch[0][jr] = g[0][0]; xch[1][jr] = g[0][1]; xch[2][jr] = g[1][0]; xch[3][jr] = g[1][1];
+    }
+    lds_barrier();
+    if (kb == 0) {
+      float* o0 = a.O + (size_t)s * L.Np;
+      o0[L.U + jr] = (g[0][0] + xch[0][jr]) * sc;
+      o0[L.U + H + jr] = (g[0][1] + xch[1][jr]) * sc;
+      if (CPLX) {
+        float* o1 = a.O + ((size_t)Ns + s) * L.Np;
+        o0[L.Uphi + jr] = 0.f;
+        o0[L.Uphi + H + jr] = 0.f;
+        o1[L.Uphi + jr] = (g[1][0] + xch[2][jr]) * sc;
+        o1[L.Uphi + H + jr] = (g[1][1] + xch[3][jr]) * sc;
+        o1[L.U + jr] = 0.f;
+        o1[L.U + H + jr] = 0.f;
+      }
+    }
+    if (w == 0) {
+      float c[2][2];
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          float v = sd < nseed ? dzl[sd][l][q] + dzl[sd][l + 64][q] : 0.f;
+#pragma unroll
+          for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+          c[sd][q] = v;
+        }
+      if (l == 0) {
+        float* o0 = a.O + (size_t)s * L.Np;
+        o0[L.c] = c[0][0] * sc;
+        o0[L.c + 1] = c[0][1] * sc;
+        if (CPLX) {
+          float* o1 = a.O + ((size_t)Ns + s) * L.Np;
+          o0[L.cphi] = 0.f; o0[L.cphi + 1] = 0.f;
+          o1[L.cphi] = c[1][0] * sc; o1[L.cphi + 1] = c[1][1] * sc;
+          o1[L.c] = 0.f; o1[L.c + 1] = 0.f;
+        }
+      }
+    }
+    lds_barrier();
+  }
   for (int seed = 0; seed < nseed; ++seed) {
     const size_t row = (size_t)seed * Ns + s;
     float* o = a.O + row * L.Np;
@@ -467,7 +606,7 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
       if (kb == 1) {
         xch[0][jr] = mx; xch[1][jr] = sa; xch[2][jr] = s0v; xch[3][jr] = s1v;
       }
-      __syncthreads();
+      lds_barrier();
       if (kb == 0) {
         mx = fmaxf(mx, xch[0][jr]);
         sa += xch[1][jr]; s0v += xch[2][jr]; s1v += xch[3][jr];
@@ -490,10 +629,10 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
         xch[0][jr] = mx;
       }
       if (q == 3) {
-        __syncthreads();
+        lds_barrier();
         break;
       }
-      __syncthreads();
+      lds_barrier();
       // scaled split into the A tile (rows j, sites k)
       const int E = jexp_for(xch[0][jr]);
       const float up = ldexpf(1.f, E);
@@ -508,7 +647,7 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
         *reinterpret_cast<jh8*>(&ahi[jr][64 * kb + 8 * c8]) = hi;
         *reinterpret_cast<jh8*>(&alo[jr][64 * kb + 8 * c8]) = lo;
       }
-      __syncthreads();
+      lds_barrier();
 
       // W_q block: D[j][i] = sum_k A[j][k] B[k][i]; wave w takes columns
       // 32 w .. 32 w + 31, all rows in tiles of 16
@@ -539,24 +678,7 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
             o[off + (size_t)j * ldq + 32 * w + 16 * ut + n] = acc[ut][e] * f;
         }
       }
-      __syncthreads();
-    }
-
-    // output head: d/dU[c][j] = sum_k dz_k[c] h_k[j], d/dc[c] = sum_k dz_k[c]
-    {
-      const float* dz = a.dzt + row * N * 2;
-      const int c = kb, j = jr;
-      float gh = 0.f;
-      for (int k = 0; k < N; ++k) gh = fmaf(dz[2 * k + c], hst[(size_t)k * H + j], gh);
-      const size_t hU = seed == 0 ? L.U : L.Uphi;
-      o[hU + (size_t)c * H + j] = gh * sc;
-      if (CPLX) o[(seed == 0 ? L.Uphi : L.U) + (size_t)c * H + j] = 0.f;
-      if (tid < 2) {
-        float gc = 0.f;
-        for (int k = 0; k < N; ++k) gc += dz[2 * k + tid];
-        o[(seed == 0 ? L.c : L.cphi) + tid] = gc * sc;
-        if (CPLX) o[(seed == 0 ? L.cphi : L.c) + tid] = 0.f;
-      }
+      lds_barrier();
     }
   }
 }
@@ -569,11 +691,21 @@ size_t jac_mfma_tape_elems(int dim, int f64, int H, int N, int cplx, size_t max_
   return rows * (size_t)N * 4 * H + rows * (size_t)N * 2;
 }
 
-static size_t rev_smem(int C, bool cplx) {
-  const int S = cplx ? 8 : 16;
-  return sizeof(float) * ((size_t)(C + 1) * S * (JM_H + 4) + 2 * 16 * (3 * JM_H + 4) +
-                          2 * (JM_H / 16) * 16 + JM_SEG * 32 + 13 * JM_H) +
+static size_t rev_smem(int C, bool cplx, int NL) {
+  const int S = cplx ? 8 : 16, NW = JM_H / 16;
+  return 2 * sizeof(_Float16) * ((size_t)(C + 1) * S * (JM_H + 8) + 16 * (3 * JM_H + 8)) +
+         (size_t)NL * 2 * NW * 64 * 16 +
+         sizeof(float) * ((size_t)16 * NW + JM_SEG * 32 + 21 * JM_H + 2) +
          sizeof(int) * (size_t)S * (JM_SEG + 1);
+}
+
+constexpr size_t JM_LDS = 160 * 1024;
+
+// register fragments moved to shared memory: as many as fit (at most 4)
+static int rev_nl(int C, bool cplx) {
+  for (int NL = 4; NL > 0; --NL)
+    if (rev_smem(C, cplx, NL) <= JM_LDS) return NL;
+  return 0;
 }
 
 bool jac_mfma_supported(const minsr_model* m, int C) {
@@ -581,13 +713,29 @@ bool jac_mfma_supported(const minsr_model* m, int C) {
   // the reverse kernel addresses the tape and the states with 32-bit offsets
   if ((size_t)2 * m->d.max_Ns * m->N * 4 * JM_H >= ((size_t)1 << 32)) return false;
   if (C < 1 || C > JM_SEG) return false;
-  return rev_smem(C, m->cplx != 0) <= 160 * 1024;
+  return rev_smem(C, m->cplx != 0, 0) <= JM_LDS;
+}
+
+template <bool CPLX, int NL>
+static int launch_rev(const JRevArgs& r, int Ns, hipStream_t s) {
+  const int S = CPLX ? 8 : 16;
+  // more than 64 KiB of dynamic shared memory: allowed once per process,
+  // before the first launch (outside any stream capture of later calls)
+  static std::once_flag once;
+  hipError_t attr = hipSuccess;
+  std::call_once(once, [&] {
+    attr = hipFuncSetAttribute((const void*)k_jac_rev<CPLX, NL>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)JM_LDS);
+  });
+  MINSR_HIP(attr);
+  k_jac_rev<CPLX, NL><<<(unsigned)((Ns + S - 1) / S), 512, rev_smem(r.C, CPLX, NL), s>>>(r);
+  MINSR_CHECK_LAUNCH();
+  return MINSR_OK;
 }
 
 template <bool CPLX>
 static int launch_rev_rows(minsr_model* m, int Ns, const uint8_t* sigma, int C, float* O,
                            const double* site, hipStream_t s) {
-  const int S = CPLX ? 8 : 16;
   const int N = m->N, H = JM_H;
   const size_t rows = (size_t)(CPLX ? 2 : 1) * Ns;
   float* dpt = (float*)m->jtape;
@@ -598,18 +746,15 @@ static int launch_rev_rows(minsr_model* m, int Ns, const uint8_t* sigma, int C, 
   r.N = N; r.Ns = Ns; r.C = C;
   r.sigma = sigma; r.states = (float*)m->states; r.site = site;
   r.dpt = dpt; r.dzt = dzt;
-  const size_t sm = rev_smem(C, CPLX);
-  // more than 64 KiB of dynamic shared memory: allowed once per process,
-  // before the first launch (outside any stream capture of later calls)
-  static std::once_flag once;
-  hipError_t attr = hipSuccess;
-  std::call_once(once, [&] {
-    attr = hipFuncSetAttribute((const void*)k_jac_rev<CPLX>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  });
-  MINSR_HIP(attr);
-  k_jac_rev<CPLX><<<(unsigned)((Ns + S - 1) / S), 512, sm, s>>>(r);
-  MINSR_CHECK_LAUNCH();
+  int rc = MINSR_OK;
+  switch (rev_nl(C, CPLX)) {
+    case 4: rc = launch_rev<CPLX, 4>(r, Ns, s); break;
+    case 3: rc = launch_rev<CPLX, 3>(r, Ns, s); break;
+    case 2: rc = launch_rev<CPLX, 2>(r, Ns, s); break;
+    case 1: rc = launch_rev<CPLX, 1>(r, Ns, s); break;
+    default: rc = launch_rev<CPLX, 0>(r, Ns, s); break;
+  }
+  if (rc) return rc;
   JRowsArgs q{};
   q.L = m->L; q.N = N; q.Ns = Ns; q.sigma = sigma; q.states = (const float*)m->states;
   q.dpt = dpt; q.dzt = dzt; q.O = O;
