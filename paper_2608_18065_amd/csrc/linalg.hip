@@ -141,8 +141,9 @@ __device__ inline void pair_decode(int p, int& ti, int& tj) {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(16))) float f32x16_t;
 
-// BF16 MFMA tile kernel: 128 x 128 output tile per workgroup (4 waves,
-// 64 x 64 each as 2 x 2 blocks of v_mfma_f32_32x32x16_bf16), K staged
+// BF16 MFMA tile kernel: 128 x 128 output tile per workgroup (8 waves,
+// 32 x 64 each as 1 x 2 blocks of v_mfma_f32_32x32x16_bf16, so two waves
+// share each SIMD and hide each other's latency), K staged
 // through two LDS buffers: the next stage's global loads are in flight
 // while the current stage feeds the matrix cores.  Rows of R have a stride
 // ld that is a multiple of 64, zero-padded past Np.
@@ -159,8 +160,10 @@ typedef __attribute__((ext_vector_type(16))) float f32x16_t;
 constexpr int GT = 128;
 constexpr int GFLUSH = 4;
 
+constexpr int GNT = 512;
+
 template <bool SPLIT>
-__global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
+__global__ __launch_bounds__(GNT) void k_gram_bf16(const __hip_bfloat16* R,
                                                    const __hip_bfloat16* Rlo, int n, size_t ld,
                                                    size_t kchunk, double* part) {
   constexpr int GK = SPLIT ? 32 : 64, GKP = GK + 8;
@@ -179,18 +182,18 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
   const size_t k0 = (size_t)split * kchunk;
   const size_t k1 = min(ld, k0 + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  f32x16_t acc[2][2];
-  double accd[2][2][16];
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+  f32x16_t acc[1][2];
+  double accd[1][2][16];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 1; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int e = 0; e < 16; ++e) { acc[a][b][e] = 0.f; accd[a][b][e] = 0.0; }
   auto flush = [&]() {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 1; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
   };
 
   const int arow0 = ti * GT, brow0 = tj * GT;
-  constexpr int CPT = GT * (GK / 8) / 256;
+  constexpr int CPT = GT * (GK / 8) / GNT;
   uint4 ra[NOP][CPT], rb[NOP][CPT];
   auto load = [&](size_t kk) {
 #pragma unroll
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
       const __hip_bfloat16* M = o == 0 ? R : Rlo;
 #pragma unroll
       for (int i = 0; i < CPT; ++i) {
-        const int c = tid + 256 * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
+        const int c = tid + GNT * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
         const int xa = arow0 + r, xb = brow0 + r;
         ra[o][i] = xa < n ? *reinterpret_cast<const uint4*>(M + (size_t)xa * ld + kk + q) : make_uint4(0, 0, 0, 0);
         rb[o][i] = xb < n ? *reinterpret_cast<const uint4*>(M + (size_t)xb * ld + kk + q) : make_uint4(0, 0, 0, 0);
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
     for (int o = 0; o < NOP; ++o)
 #pragma unroll
       for (int i = 0; i < CPT; ++i) {
-        const int c = tid + 256 * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
+        const int c = tid + GNT * i, r = c / (GK / 8), q = (c % (GK / 8)) * 8;
         *reinterpret_cast<uint4*>(&As[buf][o][r][q]) = ra[o][i];
         *reinterpret_cast<uint4*>(&Bs[buf][o][r][q]) = rb[o][i];
       }
@@ -234,18 +237,18 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
     if (more) load(kk + GK);
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 16) {
-      bf16x8_t fa[NOP][2], fb[NOP][2];
+      bf16x8_t fa[NOP][1], fb[NOP][2];
 #pragma unroll
       for (int o = 0; o < NOP; ++o) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 1; ++a)
           fa[o][a] = *reinterpret_cast<const bf16x8_t*>(&As[cur][o][wm + a * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           fb[o][b] = *reinterpret_cast<const bf16x8_t*>(&Bs[cur][o][wn + b * 32 + (lane & 31)][ks + (lane >> 5) * 8]);
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 1; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][a], fb[0][b], acc[a][b], 0, 0, 0);
@@ -266,7 +269,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const __hip_bfloat16* R,
   // (e / 4) * 8 + (l / 32) * 4 + e % 4, column l % 32 of its 32 x 32 block
   double* out = part + ((size_t)split * npairs + pair) * GT * GT;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 1; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -431,10 +434,10 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
     double* dp = reinterpret_cast<double*>(gpart);
     if (which & 1) {
       if (Rlo)
-        k_gram_bf16<true><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R,
+        k_gram_bf16<true><<<grid, GNT, 0, s>>>((const __hip_bfloat16*)R,
                                                (const __hip_bfloat16*)Rlo, n, ld, kchunk, dp);
       else
-        k_gram_bf16<false><<<grid, 256, 0, s>>>((const __hip_bfloat16*)R, nullptr, n, ld, kchunk,
+        k_gram_bf16<false><<<grid, GNT, 0, s>>>((const __hip_bfloat16*)R, nullptr, n, ld, kchunk,
                                                 dp);
       MINSR_CHECK_LAUNCH();
     }
