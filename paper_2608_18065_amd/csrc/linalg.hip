@@ -138,6 +138,37 @@ __device__ inline void pair_decode(int p, int& ti, int& tj) {
   tj = p - t * (t + 1) / 2;
 }
 
+// Work order of the Gram's tile pairs: blocks of GB x GB tiles (lower-
+// triangular blocks, each block's pairs row by row), so the workgroups that
+// run together on one XCD read few distinct row tiles of R and share them
+// in that XCD's L2.  Work item q -> tile pair (ti, tj), ti >= tj.
+constexpr int GB = 8;
+__device__ inline void pair_blocked(int q, int nt, int& ti, int& tj) {
+  const int nb = (nt + GB - 1) / GB;
+  for (int I = 0; I < nb; ++I) {
+    const int rows = min(GB, nt - GB * I);
+    for (int J = 0; J <= I; ++J) {
+      const int cols = min(GB, nt - GB * J);
+      const int cnt = I == J ? rows * (rows + 1) / 2 : rows * cols;
+      if (q < cnt) {
+        if (I == J) {
+          int r = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+          while ((r + 1) * (r + 2) / 2 <= q) ++r;
+          while (r * (r + 1) / 2 > q) --r;
+          ti = GB * I + r;
+          tj = GB * J + (q - r * (r + 1) / 2);
+        } else {
+          ti = GB * I + q / cols;
+          tj = GB * J + q % cols;
+        }
+        return;
+      }
+      q -= cnt;
+    }
+  }
+  ti = tj = 0;
+}
+
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(16))) float f32x16_t;
 
@@ -153,12 +184,12 @@ typedef __attribute__((ext_vector_type(16))) float f32x16_t;
 // about 2^-8 of it, so lo lo^T is about 2^-16 of T: leaving it out subtracts
 // a positive semidefinite matrix of that size, which made T + lambda I
 // indefinite for lambda = 1e-3 once |T| grew to a few hundred.)
-// The FP32 accumulators are added into FP64 ones every GFLUSH stages and
-// restarted, so no FP32 sum runs over more than 128 (split) or 256 inputs;
+// The FP32 accumulators are added into FP64 ones every 128 (split) or 256
+// (one product) input columns and restarted, so no FP32 sum runs longer;
 // the partial tiles are written in FP64 (rounding them to FP32 put an error
 // of about 2^-24 |T| on every element, whose 2-norm reached 6e-7 |T|_max).
 constexpr int GT = 128;
-constexpr int GFLUSH = 4;
+constexpr int GFLUSH = 4;   // stages of 64 columns per flush (one product)
 
 constexpr int GNT = 512;
 
@@ -166,7 +197,10 @@ template <bool SPLIT>
 __global__ __launch_bounds__(GNT) void k_gram_bf16(const __hip_bfloat16* R,
                                                    const __hip_bfloat16* Rlo, int n, size_t ld,
                                                    size_t kchunk, double* part) {
-  constexpr int GK = SPLIT ? 32 : 64, GKP = GK + 8;
+  // 64 columns per stage: the next stage's loads have a whole stage of
+  // products (about 2000 matrix-core cycles per SIMD) to arrive in
+  constexpr int GK = 64, GKP = GK + 8;
+  constexpr int FLUSH = SPLIT ? GFLUSH / 2 : GFLUSH;
   constexpr int NOP = SPLIT ? 2 : 1;
   __shared__ __align__(16) __hip_bfloat16 As[2][NOP][GT][GKP];
   __shared__ __align__(16) __hip_bfloat16 Bs[2][NOP][GT][GKP];
@@ -176,9 +210,10 @@ __global__ __launch_bounds__(GNT) void k_gram_bf16(const __hip_bfloat16* R,
   const int npairs = gridDim.x, total = npairs * gridDim.y;
   const int lin = blockIdx.x + blockIdx.y * npairs, xcd = lin % 8;
   const int item = xcd * (total / 8) + min(xcd, total % 8) + lin / 8;
-  const int pair = item % npairs, split = item / npairs;
+  const int split = item / npairs;
   int ti, tj;
-  pair_decode(pair, ti, tj);
+  pair_blocked(item % npairs, (n + GT - 1) / GT, ti, tj);
+  const int pair = ti * (ti + 1) / 2 + tj;   // the partial tile's slot
   const size_t k0 = (size_t)split * kchunk;
   const size_t k1 = min(ld, k0 + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -259,7 +294,7 @@ __global__ __launch_bounds__(GNT) void k_gram_bf16(const __hip_bfloat16* R,
           }
         }
     }
-    if (++stages == GFLUSH) { flush(); stages = 0; }
+    if (++stages == FLUSH) { flush(); stages = 0; }
     if (more) store(cur ^ 1);
     __syncthreads();
     cur ^= 1;
