@@ -315,6 +315,100 @@ __global__ __launch_bounds__(GNT) void k_gram_bf16(const __hip_bfloat16* R,
       }
 }
 
+// FP32 MFMA tile kernel (the FP32 form): 128 x 128 output tile per
+// workgroup (4 waves, 64 x 64 each as 2 x 2 blocks of
+// v_mfma_f32_32x32x2_f32, lane l supplying A[l % 32][l / 32] and
+// B[l / 32][l % 32]), FP32 accumulation over the workgroup's K range like
+// the form's other arithmetic, K staged 32 columns at a time through two
+// shared-memory buffers while the next stage's loads are in flight.
+constexpr int FK = 32, FKP = FK + 1;
+
+__global__ __launch_bounds__(256, 2) void k_gram_f32(const float* R, int n, size_t ld,
+                                                     size_t kchunk, float* part) {
+  __shared__ float As[2][GT][FKP];
+  __shared__ float Bs[2][GT][FKP];
+  const int npairs = gridDim.x, total = npairs * gridDim.y;
+  const int lin = blockIdx.x + blockIdx.y * npairs, xcd = lin % 8;
+  const int item = xcd * (total / 8) + min(xcd, total % 8) + lin / 8;
+  const int split = item / npairs;
+  int ti, tj;
+  pair_blocked(item % npairs, (n + GT - 1) / GT, ti, tj);
+  const int pair = ti * (ti + 1) / 2 + tj;
+  const size_t k0 = (size_t)split * kchunk;
+  const size_t k1 = min(ld, k0 + kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x16_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
+  const int arow0 = ti * GT, brow0 = tj * GT;
+  constexpr int CPT = GT * (FK / 4) / 256;   // float4 per thread and operand
+  float4 ra[CPT], rb[CPT];
+  auto load = [&](size_t kk) {
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int c = tid + 256 * i, r = c / (FK / 4), q = (c % (FK / 4)) * 4;
+      const int xa = arow0 + r, xb = brow0 + r;
+      ra[i] = xa < n ? *reinterpret_cast<const float4*>(R + (size_t)xa * ld + kk + q) : make_float4(0, 0, 0, 0);
+      rb[i] = xb < n ? *reinterpret_cast<const float4*>(R + (size_t)xb * ld + kk + q) : make_float4(0, 0, 0, 0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int c = tid + 256 * i, r = c / (FK / 4), q = (c % (FK / 4)) * 4;
+      As[buf][r][q] = ra[i].x; As[buf][r][q + 1] = ra[i].y;
+      As[buf][r][q + 2] = ra[i].z; As[buf][r][q + 3] = ra[i].w;
+      Bs[buf][r][q] = rb[i].x; Bs[buf][r][q + 1] = rb[i].y;
+      Bs[buf][r][q + 2] = rb[i].z; Bs[buf][r][q + 3] = rb[i].w;
+    }
+  };
+  if (k0 < k1) {
+    load(k0);
+    store(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  const int lr = lane & 31, lk = lane >> 5;
+  for (size_t kk = k0; kk < k1; kk += FK) {
+    const bool more = kk + FK < k1;
+    if (more) load(kk + FK);
+#pragma unroll
+    for (int ks = 0; ks < FK; ks += 2) {
+      float fa[2], fb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) fa[a] = As[cur][wm + a * 32 + lr][ks + lk];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) fb[b] = Bs[cur][wn + b * 32 + lr][ks + lk];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  // acc element e of lane l is row (e / 4) * 8 + (l / 32) * 4 + e % 4,
+  // column l % 32 of its 32 x 32 block
+  float* out = part + ((size_t)split * npairs + pair) * GT * GT;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int r = wm + a * 32 + (e / 4) * 8 + (lane >> 5) * 4 + (e % 4);
+        const int c = wn + b * 32 + (lane & 31);
+        out[r * GT + c] = acc[a][b][e];
+      }
+}
+
 // Vector SYRK tile kernel for FP32 / FP64 inputs: 64 x 64 tile, 256
 // threads with 4 x 4 outputs each, K staged 16 at a time.
 constexpr int VT_ = 64, VK = 16;
@@ -421,7 +515,7 @@ static int pick_split(int npairs, size_t Np, int want) {
 
 // workspace for the largest split any setting may request
 size_t gram_partial_bytes(int n, size_t Np, int dtype) {
-  const int tile = dtype == MINSR_BF16 ? GT : VT_;
+  const int tile = dtype == MINSR_F64 ? VT_ : GT;
   const int nt = (n + tile - 1) / tile;
   const int npairs = nt * (nt + 1) / 2;
   const int S = std::max(pick_split(npairs, Np, 0), pick_split(npairs, Np, MAX_SPLIT));
@@ -434,7 +528,7 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
   // R rows have the padded stride ld = round_up(Np, 64); the padding is zero
   const size_t ld = (Np + 63) / 64 * 64;
   if (n == 0) return MINSR_OK;
-  const int tile = dtype == MINSR_BF16 ? GT : VT_;
+  const int tile = dtype == MINSR_F64 ? VT_ : GT;
   const int nt = (n + tile - 1) / tile;
   const int npairs = nt * (nt + 1) / 2;
   // the MFMA tile kernel holds one workgroup per CU (FP64 accumulators):
@@ -458,7 +552,7 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
     }
   }
   const int S = pick_split(npairs, Np, want);
-  const size_t kgran = dtype == MINSR_BF16 ? 64 : VK;
+  const size_t kgran = dtype == MINSR_BF16 ? 64 : dtype == MINSR_F32 ? FK : VK;
   size_t kchunk = (ld + S - 1) / S;
   kchunk = (kchunk + kgran - 1) / kgran * kgran;
   const size_t need = (size_t)S * npairs * tile * tile * (dtype == MINSR_F32 ? 4 : 8);
@@ -479,7 +573,7 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
     if (which & 2) k_gram_reduce<double, double><<<rgrid, 256, 0, s>>>(dp, npairs, S, tile, n, T);
   } else if (dtype == MINSR_F32) {
     if (which & 1) {
-      k_gram_vec<float, float><<<grid, 256, 0, s>>>((const float*)R, n, ld, kchunk, gpart);
+      k_gram_f32<<<grid, 256, 0, s>>>((const float*)R, n, ld, kchunk, gpart);
       MINSR_CHECK_LAUNCH();
     }
     if (which & 2) k_gram_reduce<float, float><<<rgrid, 256, 0, s>>>(gpart, npairs, S, tile, n, (float*)T);
