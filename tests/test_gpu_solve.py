@@ -218,3 +218,31 @@ def test_pinv_zero_matrix(pmodel):
     torch.cuda.synchronize()
     assert int(st.item()) == 0
     assert float(x.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("Ns", [300, 512], ids=["n600_ragged", "n1024"])
+def test_fp32_form_solve_matches_its_system(Ns):
+    # the FP32 form solves (T + lambda I) x = eps' in FP32 with the same
+    # one-launch factorisation (FP32 matrix cores): x against the FP64 oracle
+    # solve of the same FP32 T, within the FP32 forward-error bound
+    # 4 n u cond(T + lambda I), u = 2^-24
+    import paper_2608_18065_amd as pm
+    from oracle import hamiltonian as oham
+    from tests.gpu_common import make_pair
+    spec, m = make_pair(Lx=20, H=32, cplx=True, dtype="f32", max_Ns=Ns)
+    ham = pm.hamiltonian("cluster", J=1.0, h=0.0, J2=0.0, pbc=True)
+    mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
+    lam = 0.1
+    o = m.step(ham, Ns, 0.01, lam, 0.0, mom, 7, 0, form=pm.FORM_FP32_PLAIN)
+    it = m.intermediates(pm.FORM_FP32_PLAIN)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) & pm.ST_ERRORS == 0
+    T = it["T"].double().cpu().numpy()
+    ep = it["eps_prime"].cpu().numpy()
+    x = it["x"].cpu().numpy()
+    n = T.shape[0]
+    ref = ominsr.solve(T, ep, lam)
+    kappa = np.linalg.cond(T + lam * np.eye(n))
+    err = _rel(x, ref)
+    print("FP32 solve n=%d: rel err %.2e, cond %.1e" % (n, err, kappa))
+    assert err < 4 * n * 2.0 ** -24 * kappa
