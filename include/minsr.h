@@ -397,7 +397,12 @@ int minsr_solve_noalloc(int n, const double* dev_T, double lambda, const double*
  * lattice, N_s and architecture).  The first minsr_batch_step captures one
  * step of every instance into a single hip graph, each instance on its own
  * stream forked from and joined back into a library-owned origin stream, so
- * the instances' kernels run concurrently; that call and every later one
+ * the instances' kernels run concurrently.  The Grams of the instances in
+ * MINSR_FORM_BF16_FP64 run as one grouped launch between their sampling and
+ * their solve (each with the split-K of its own step, so T and every output
+ * equal those of single-instance steps bitwise); the first minsr_batch_step
+ * copies that launch's job table to device memory the batch owns (one
+ * synchronous copy, before the capture).  That call and every later one
  * launch the graph on `s` (which may be the null stream).  Every state must
  * carry a dev_counter (the Philox counter advances on the device at each
  * replay); all pointers in the descriptors must stay valid for the batch's

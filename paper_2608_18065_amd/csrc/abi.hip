@@ -427,8 +427,12 @@ int minsr_logpsi_vjp(minsr_model* m, int Ns, const uint8_t* dev_sigma, const dou
   return MINSR_OK;
 }
 
-int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg* cfg,
-               const minsr_step_state* st, const minsr_step_out* out, hipStream_t s) {
+// the step in three stages (bits of `stages`): 1 = sampling through the
+// real form O', 2 = the Gram, 4 = the solve and the update; a batch runs the
+// Grams of its instances in one grouped launch between stages 1 and 4
+static int step_stages(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg* cfg,
+                       const minsr_step_state* st, const minsr_step_out* out, hipStream_t s,
+                       int stages) {
   if (!m || !cfg || !st || !out) return fail(MINSR_E_INVALID_ARG, "null argument");
   int rc = check_ns(m, cfg->Ns);
   if (rc) return rc;
@@ -470,6 +474,7 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
   };
 #define MINSR_PHASE(ph) do { int rc_ = mark(ph); if (rc_) return rc_; } while (0)
 
+  if (stages & 1) {
   MINSR_PHASE(0);
   // 1. exact autoregressive samples, hidden states, per-site conditionals
   //    (the sampler also clears the status word)
@@ -495,7 +500,9 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
                      Rlo);
   if (rc) return rc;
   MINSR_PHASE(5);
+  }
   // 4. Gram and regularised solve
+  if (stages & 2) {
   rc = launch_gram(n, Np, m->R, rdt, m->T, m->gpart, m->gpart_elems, s, 1, Rlo,
                    m->tune_gram_split);
   if (rc) return rc;
@@ -504,6 +511,8 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
                    m->tune_gram_split);
   if (rc) return rc;
   MINSR_PHASE(7);
+  }
+  if (stages & 4) {
   if (cfg->pinv_cutoff > 0.0) {
     rc = ensure_pinv_ws(m, s);
     if (!rc) rc = launch_report_trace(n, m->T, out->dev_tnorm, out->dev_lambda_used, s);
@@ -535,12 +544,20 @@ int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg*
     if (rc) return rc;
   }
   MINSR_PHASE(10);
-#undef MINSR_PHASE
   if (timing) m->t_slot++;
   m->last_n = n;
   m->last_form = cfg->form;
+  }
+#undef MINSR_PHASE
   return MINSR_OK;
 }
+
+int minsr_step(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg* cfg,
+               const minsr_step_state* st, const minsr_step_out* out, hipStream_t s) {
+  return step_stages(m, H, cfg, st, out, s, 7);
+}
+
+
 
 int minsr_step_adaptive(minsr_model* m, const minsr_hamiltonian* H, const minsr_step_cfg* cfg,
                         const minsr_adaptive_cfg* ad, const minsr_step_state* st,
@@ -858,7 +875,10 @@ struct minsr_batch {
   std::vector<minsr_step_state> states;
   std::vector<minsr_step_out> outs;
   std::vector<hipStream_t> streams;  // [i] instance i, [count] capture origin
-  std::vector<hipEvent_t> events;   // [0] fork, [1 + i] join of instance i
+  // [0] fork, [1 + i] join of instance i's first stage; [count + 1] fork of
+  // the last stages, [count + 2 + i] their joins
+  std::vector<hipEvent_t> events;
+  minsr::GramJob* jobs = nullptr;   // device copy of the grouped Gram's job table
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -868,6 +888,8 @@ static void batch_release(minsr_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
   for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+  if (b->jobs) (void)hipFree(b->jobs);
+  b->jobs = nullptr;
   b->exec = nullptr; b->graph = nullptr;
   b->events.clear(); b->streams.clear();
 }
@@ -907,7 +929,7 @@ int minsr_batch_create(minsr_model* const* models, const minsr_hamiltonian* hams
     }
     b->streams.push_back(st);
   }
-  for (int i = 0; i <= count; ++i) {
+  for (int i = 0; i < 2 * (count + 1); ++i) {
     hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       batch_release(b); delete b;
@@ -919,23 +941,68 @@ int minsr_batch_create(minsr_model* const* models, const minsr_hamiltonian* hams
   return MINSR_OK;
 }
 
+// Phase-major capture: every instance's first stage on its own stream, then
+// the Grams of the BF16 split-form instances in one grouped launch (each
+// instance keeps the split its own step would use, so T is the same), then
+// every instance's solve and update on its stream again.
 static int batch_capture(minsr_batch* b) {
+  const int count = (int)b->models.size();
+  std::vector<minsr::GramJob> jobs;
+  std::vector<int> grouped(count, 0);
+  int items = 0, ritems = 0;
+  for (int i = 0; i < count; ++i) {
+    minsr_model* m = b->models[i];
+    const minsr_step_cfg& c = b->cfgs[i];
+    // an instance whose shape the step would reject runs the whole step
+    // alone, which reports the error
+    if (c.form != MINSR_FORM_BF16_FP64 || c.Ns < 2 || c.Ns > m->d.max_Ns) continue;
+    const int n = (m->cplx ? 2 : 1) * c.Ns;
+    const size_t Np = m->L.Np;
+    const void* R = m->R;
+    const void* Rlo = (const void*)((const __hip_bfloat16*)m->R + (size_t)n * padded_ld(Np));
+    minsr::GramJob g{};
+    int rc = gram_job(n, Np, R, Rlo, m->T, m->gpart, m->gpart_elems, m->tune_gram_split, &g);
+    if (rc) return rc;
+    g.item0 = items;
+    g.ritem0 = ritems;
+    items += g.npairs * g.S;
+    ritems += g.npairs * minsr::GRAM_SUBTILES;
+    jobs.push_back(g);
+    grouped[i] = 1;
+  }
+  if (!jobs.empty()) {
+    if (!b->jobs) MINSR_HIP(hipMalloc(&b->jobs, sizeof(minsr::GramJob) * count));
+    MINSR_HIP(hipMemcpy(b->jobs, jobs.data(), sizeof(minsr::GramJob) * jobs.size(),
+                        hipMemcpyHostToDevice));
+  }
   hipStream_t s = b->streams.back();
   MINSR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   int rc = MINSR_OK;
-  if (hipEventRecord(b->events[0], s) != hipSuccess) rc = fail(MINSR_E_DEVICE, "fork record failed");
-  for (size_t i = 0; i < b->models.size() && !rc; ++i) {
+  // stages of instance i on its stream, between a wait on `fork` and a
+  // record of `join` that the origin stream waits for
+  auto run = [&](int i, int stages, hipEvent_t fork, hipEvent_t join) {
     minsr_model* m = b->models[i];
     const int t_max = m->t_max;
     m->t_max = 0;   // no event timing inside the graph
-    if (hipStreamWaitEvent(b->streams[i], b->events[0], 0) != hipSuccess)
+    if (hipStreamWaitEvent(b->streams[i], fork, 0) != hipSuccess)
       rc = fail(MINSR_E_DEVICE, "fork wait failed");
-    if (!rc) rc = minsr_step(m, &b->hams[i], &b->cfgs[i], &b->states[i], &b->outs[i], b->streams[i]);
+    if (!rc) rc = step_stages(m, &b->hams[i], &b->cfgs[i], &b->states[i], &b->outs[i],
+                              b->streams[i], stages);
     m->t_max = t_max;
-    if (!rc && hipEventRecord(b->events[1 + i], b->streams[i]) != hipSuccess)
+    if (!rc && hipEventRecord(join, b->streams[i]) != hipSuccess)
       rc = fail(MINSR_E_DEVICE, "join record failed");
-    if (!rc && hipStreamWaitEvent(s, b->events[1 + i], 0) != hipSuccess)
+    if (!rc && hipStreamWaitEvent(s, join, 0) != hipSuccess)
       rc = fail(MINSR_E_DEVICE, "join wait failed");
+  };
+  if (hipEventRecord(b->events[0], s) != hipSuccess) rc = fail(MINSR_E_DEVICE, "fork record failed");
+  for (int i = 0; i < count && !rc; ++i)
+    run(i, grouped[i] ? 1 : 7, b->events[0], b->events[1 + i]);
+  if (!rc && !jobs.empty()) {
+    rc = launch_gram_grouped(b->jobs, (int)jobs.size(), items, ritems, s);
+    if (!rc && hipEventRecord(b->events[count + 1], s) != hipSuccess)
+      rc = fail(MINSR_E_DEVICE, "fork record failed");
+    for (int i = 0; i < count && !rc; ++i)
+      if (grouped[i]) run(i, 4, b->events[count + 1], b->events[count + 2 + i]);
   }
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);

@@ -193,10 +193,12 @@ constexpr int GFLUSH = 4;   // stages of 64 columns per flush (one product)
 
 constexpr int GNT = 512;
 
+// one tile pair over one K range: work item `item` of a Gram with npairs
+// tile pairs (item = split * npairs + position in the blocked pair order)
 template <bool SPLIT>
-__global__ __launch_bounds__(GNT) void k_gram_bf16(const __hip_bfloat16* R,
-                                                   const __hip_bfloat16* Rlo, int n, size_t ld,
-                                                   size_t kchunk, double* part) {
+__device__ __forceinline__ void gram_tile(const __hip_bfloat16* R, const __hip_bfloat16* Rlo,
+                                          int n, size_t ld, size_t kchunk, double* part,
+                                          int npairs, int item) {
   // 64 columns per stage: the next stage's loads have a whole stage of
   // products (about 2000 matrix-core cycles per SIMD) to arrive in
   constexpr int GK = 64, GKP = GK + 8;
@@ -204,12 +206,6 @@ __global__ __launch_bounds__(GNT) void k_gram_bf16(const __hip_bfloat16* R,
   constexpr int NOP = SPLIT ? 2 : 1;
   __shared__ __align__(16) __hip_bfloat16 As[2][NOP][GT][GKP];
   __shared__ __align__(16) __hip_bfloat16 Bs[2][NOP][GT][GKP];
-  // workgroups are dealt to the eight XCDs in turn (linear id mod 8); each
-  // XCD takes a contiguous run of (split, pair) items, so the pairs that
-  // read the same rows over the same K range share that XCD's L2
-  const int npairs = gridDim.x, total = npairs * gridDim.y;
-  const int lin = blockIdx.x + blockIdx.y * npairs, xcd = lin % 8;
-  const int item = xcd * (total / 8) + min(xcd, total % 8) + lin / 8;
   const int split = item / npairs;
   int ti, tj;
   pair_blocked(item % npairs, (n + GT - 1) / GT, ti, tj);
@@ -313,6 +309,38 @@ __global__ __launch_bounds__(GNT) void k_gram_bf16(const __hip_bfloat16* R,
         const int c = wn + b * 32 + (lane & 31);
         out[r * GT + c] = accd[a][b][e];
       }
+}
+
+// workgroups are dealt to the eight XCDs in turn (linear id mod 8); each
+// XCD takes a contiguous run of work items, so the pairs that read the same
+// rows over the same K range share that XCD's L2
+__device__ __forceinline__ int xcd_item(int lin, int total) {
+  const int xcd = lin % 8;
+  return xcd * (total / 8) + min(xcd, total % 8) + lin / 8;
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(GNT) void k_gram_bf16(const __hip_bfloat16* R,
+                                                   const __hip_bfloat16* Rlo, int n, size_t ld,
+                                                   size_t kchunk, double* part) {
+  const int npairs = gridDim.x, total = npairs * gridDim.y;
+  gram_tile<SPLIT>(R, Rlo, n, ld, kchunk, part, npairs,
+                   xcd_item(blockIdx.x + blockIdx.y * npairs, total));
+}
+
+// the Grams of several instances (BF16 split form) in one launch: the work
+// items of instance j are [item0, item0 + npairs S) of the grid, each
+// instance with its own split, so every partial tile equals the one of the
+// instance's own launch; the reduction likewise over (instance, pair,
+// 32 x 32 sub-tile)
+__global__ __launch_bounds__(GNT) void k_gram_bf16_grouped(const GramJob* jobs, int njobs,
+                                                           int total) {
+  const int item = xcd_item(blockIdx.x, total);
+  int j = 0;
+  while (j + 1 < njobs && item >= jobs[j + 1].item0) ++j;
+  const GramJob& g = jobs[j];
+  gram_tile<true>(static_cast<const __hip_bfloat16*>(g.R), static_cast<const __hip_bfloat16*>(g.Rlo),
+                  g.n, g.ld, g.kchunk, g.part, g.npairs, item - g.item0);
 }
 
 // FP32 MFMA tile kernel (the FP32 form): 128 x 128 output tile per
@@ -471,14 +499,14 @@ __global__ __launch_bounds__(256) void k_gram_vec(const TI* R, int n, size_t Np,
 
 // sum the split-K partials in split order; write T (lower and mirror)
 template <typename TA, typename TT>
-__global__ __launch_bounds__(256) void k_gram_reduce(const TA* part, int npairs, int nsplit,
-                                                     int tile, int n, TT* T) {
+__device__ __forceinline__ void gram_reduce_tile(const TA* part, int npairs, int nsplit,
+                                                 int tile, int n, TT* T, int pair, int sub) {
   // one 32 x 32 sub-tile per workgroup: partials summed in split order, the
   // tile written row-wise and its mirror through a shared-memory transpose,
   // so both stores are coalesced rows
   __shared__ TT sh[32][33];
-  const int pair = blockIdx.y, nsub = tile / 32;
-  const int sr = blockIdx.x / nsub, sc = blockIdx.x % nsub;
+  const int nsub = tile / 32;
+  const int sr = sub / nsub, sc = sub % nsub;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   int ti, tj;
   pair_decode(pair, ti, tj);
@@ -498,6 +526,22 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const TA* part, int npairs,
     const int r = ti * tile + lr, c = tj * tile + lc;
     if (r < n && c < n && (ti != tj || c <= r)) T[(size_t)c * n + r] = sh[tx][ty + 8 * q];
   }
+}
+
+template <typename TA, typename TT>
+__global__ __launch_bounds__(256) void k_gram_reduce(const TA* part, int npairs, int nsplit,
+                                                     int tile, int n, TT* T) {
+  gram_reduce_tile<TA, TT>(part, npairs, nsplit, tile, n, T, blockIdx.y, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce_grouped(const GramJob* jobs, int njobs) {
+  constexpr int SUB = GRAM_SUBTILES;
+  static_assert(SUB == (GT / 32) * (GT / 32), "sub-tiles of a Gram tile");
+  int j = 0;
+  while (j + 1 < njobs && (int)blockIdx.x >= jobs[j + 1].ritem0) ++j;
+  const GramJob& g = jobs[j];
+  const int r = blockIdx.x - g.ritem0;
+  gram_reduce_tile<double, double>(g.part, g.npairs, g.S, GT, g.n, g.T, r / SUB, r % SUB);
 }
 
 constexpr int MAX_SPLIT = 64;
@@ -523,17 +567,12 @@ size_t gram_partial_bytes(int n, size_t Np, int dtype) {
   return (size_t)S * npairs * tile * tile * el;
 }
 
-int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gpart,
-                size_t gpart_elems, hipStream_t s, int which, const void* Rlo, int want_split) {
-  // R rows have the padded stride ld = round_up(Np, 64); the padding is zero
-  const size_t ld = (Np + 63) / 64 * 64;
-  if (n == 0) return MINSR_OK;
-  const int tile = dtype == MINSR_F64 ? VT_ : GT;
-  const int nt = (n + tile - 1) / tile;
-  const int npairs = nt * (nt + 1) / 2;
-  // the MFMA tile kernel holds one workgroup per CU (FP64 accumulators):
-  // by default the split (1..8) minimises rounds of the grid over the CUs
-  // times the K range of one workgroup
+// split-K factor and K range per workgroup: the MFMA tile kernel holds one
+// workgroup per CU (FP64 accumulators), so by default the split (1..8)
+// minimises rounds of the grid over the CUs times the K range of one
+// workgroup
+static void gram_plan(int npairs, size_t Np, size_t ld, int dtype, int want_split, int& S,
+                      size_t& kchunk) {
   int want = want_split;
   if (dtype == MINSR_BF16 && want_split <= 0) {
     static int ncu = 0;
@@ -546,15 +585,52 @@ int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gp
         ncu = 256;
     }
     double best = 1e300;
-    for (int S = 1; S <= 8; ++S) {
-      const double cost = (double)((npairs * S + ncu - 1) / ncu) / S;
-      if (cost < best * (1.0 - 1e-9)) { best = cost; want = S; }
+    for (int q = 1; q <= 8; ++q) {
+      const double cost = (double)((npairs * q + ncu - 1) / ncu) / q;
+      if (cost < best * (1.0 - 1e-9)) { best = cost; want = q; }
     }
   }
-  const int S = pick_split(npairs, Np, want);
+  S = pick_split(npairs, Np, want);
   const size_t kgran = dtype == MINSR_BF16 ? 64 : dtype == MINSR_F32 ? FK : VK;
-  size_t kchunk = (ld + S - 1) / S;
+  kchunk = (ld + S - 1) / S;
   kchunk = (kchunk + kgran - 1) / kgran * kgran;
+}
+
+int gram_job(int n, size_t Np, const void* R, const void* Rlo, double* T, float* gpart,
+             size_t gpart_elems, int want_split, GramJob* job) {
+  const size_t ld = (Np + 63) / 64 * 64;
+  const int nt = (n + GT - 1) / GT;
+  const int npairs = nt * (nt + 1) / 2;
+  int S = 0;
+  size_t kchunk = 0;
+  gram_plan(npairs, Np, ld, MINSR_BF16, want_split, S, kchunk);
+  if ((size_t)S * npairs * GT * GT * 8 > gpart_elems * sizeof(float))
+    return fail(MINSR_E_SHAPE, "Gram workspace too small");
+  *job = GramJob{R, Rlo, reinterpret_cast<double*>(gpart), T, ld, kchunk, n, npairs, S, 0, 0, 0};
+  return MINSR_OK;
+}
+
+int launch_gram_grouped(const GramJob* dev_jobs, int njobs, int items, int ritems,
+                        hipStream_t s) {
+  if (njobs == 0 || items == 0) return MINSR_OK;
+  k_gram_bf16_grouped<<<(unsigned)items, GNT, 0, s>>>(dev_jobs, njobs, items);
+  MINSR_CHECK_LAUNCH();
+  k_gram_reduce_grouped<<<(unsigned)ritems, 256, 0, s>>>(dev_jobs, njobs);
+  MINSR_CHECK_LAUNCH();
+  return MINSR_OK;
+}
+
+int launch_gram(int n, size_t Np, const void* R, int dtype, double* T, float* gpart,
+                size_t gpart_elems, hipStream_t s, int which, const void* Rlo, int want_split) {
+  // R rows have the padded stride ld = round_up(Np, 64); the padding is zero
+  const size_t ld = (Np + 63) / 64 * 64;
+  if (n == 0) return MINSR_OK;
+  const int tile = dtype == MINSR_F64 ? VT_ : GT;
+  const int nt = (n + tile - 1) / tile;
+  const int npairs = nt * (nt + 1) / 2;
+  int S = 0;
+  size_t kchunk = 0;
+  gram_plan(npairs, Np, ld, dtype, want_split, S, kchunk);
   const size_t need = (size_t)S * npairs * tile * tile * (dtype == MINSR_F32 ? 4 : 8);
   if (need > gpart_elems * sizeof(float)) return fail(MINSR_E_SHAPE, "Gram workspace too small");
   dim3 grid((unsigned)npairs, (unsigned)S);

@@ -135,6 +135,27 @@ int launch_center(int rows_per_block, int nblocks, size_t Np, const void* O, int
                   hipStream_t s, void* Rlo = nullptr);
 // the step keeps O' with rows padded to a multiple of 64 columns
 inline size_t padded_ld(size_t Np) { return (Np + 63) / 64 * 64; }
+// one instance's Gram in a grouped launch (BF16 split form): its work items
+// are [item0, item0 + npairs S) of the tile kernel's grid and
+// [ritem0, ritem0 + 16 npairs) of the reduction's
+// 32 x 32 sub-tiles of one 128 x 128 Gram tile: the reduction's work items per pair
+constexpr int GRAM_SUBTILES = 16;
+struct GramJob {
+  const void* R;      // BF16 hi rows, stride ld
+  const void* Rlo;    // BF16 lo rows
+  double* part;       // FP64 partial tiles [S][npairs][128][128]
+  double* T;          // [n][n]
+  size_t ld, kchunk;
+  int n, npairs, S, item0, ritem0, pad;
+};
+// fills the split, K range and item counts of a job (the same choice as
+// launch_gram for the instance); returns an error if its workspace is short
+int gram_job(int n, size_t Np, const void* R, const void* Rlo, double* T, float* gpart,
+             size_t gpart_elems, int want_split, GramJob* job);
+// one launch of tile products and one of reductions over all jobs (a device
+// copy of the job table, item0 / ritem0 prefix sums filled in)
+int launch_gram_grouped(const GramJob* dev_jobs, int njobs, int items, int ritems,
+                        hipStream_t s);
 // which: 1 = tile products, 2 = split-K reduction and mirror, 3 = both
 // Rlo (BF16 only, may be null): low parts of a hi/lo split of R
 // split: split-K factor (0 = heuristic)

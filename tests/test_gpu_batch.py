@@ -1,6 +1,7 @@
 """Many independent instances in one captured graph: every replay equals
 eager single-instance steps bitwise, for instances of different lattices,
-sample counts, architectures and forms."""
+sample counts, architectures and forms (the BF16 split-form instances with
+their Grams in one grouped launch)."""
 import pytest
 import torch
 
@@ -18,6 +19,12 @@ def _instances(pm, tag):
          pm.hamiltonian("j1j2", J=1.0, J2=0.0), 130, 1),
         (dict(Lx=3, Ly=4, dim=2, hidden=64, complex_head=True, marshall=True, dtype="f32", seed=4),
          pm.hamiltonian("j1j2", J=1.0, J2=0.5), 70, 2),
+        # two BF16 split-form instances: their Grams run in one grouped
+        # launch (3 and 10 tile pairs, ragged last tiles)
+        (dict(Lx=14, Ly=1, dim=1, hidden=32, dtype="f32", seed=5), pm.hamiltonian("tfim", pbc=True),
+         200, 1),
+        (dict(Lx=11, Ly=1, dim=1, hidden=16, complex_head=True, dtype="f32", seed=6),
+         pm.hamiltonian("cluster"), 230, 1),
     ]
     out = []
     for k, (margs, ham, Ns, form) in enumerate(specs):
