@@ -84,16 +84,23 @@ def low_precision_step(spec, m, gham, ham, Ns, eta, lam, key, counter, form, ckp
     each differing sample must be such a tie, and the oracle's downstream
     stages are re-run on the GPU's samples.  Anything else fails.
     gham: the library's Hamiltonian; ham: the oracle's."""
-    import paper_2608_18065_amd as pm
-    from oracle import hamiltonian as oham
-    from oracle import jacobian as ojac
-    from oracle import minsr as ominsr
-    from oracle import philox
     mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
     th = m.get_params().cpu().numpy()
     o = m.step(gham, Ns, eta, lam, 0.0, mom, key, counter, form=form, ckpt_every=ckpt_every,
                pinv_cutoff=pinv_cutoff)
     torch.cuda.synchronize()
+    return o, low_precision_ref(spec, th, ham, Ns, eta, lam, key, counter, o, pinv_cutoff)
+
+
+def low_precision_ref(spec, th, ham, Ns, eta, lam, key, counter, o, pinv_cutoff=0.0):
+    """The oracle's step (momentum 0) from parameters th for the outputs o
+    of a low-precision step already taken on the GPU, with the tie rule of
+    low_precision_step for samples that differ."""
+    import paper_2608_18065_amd as pm
+    from oracle import hamiltonian as oham
+    from oracle import jacobian as ojac
+    from oracle import minsr as ominsr
+    from oracle import philox
     assert int(o["status"].item()) & pm.ST_ERRORS == 0
     ref = ominsr.step(spec, th, np.zeros_like(th), ham, Ns, eta, lam, 0.0, key, counter,
                       pinv_cutoff=pinv_cutoff)
@@ -102,7 +109,7 @@ def low_precision_step(spec, m, gham, ham, Ns, eta, lam, key, counter, form, ckp
     diff = sig != ref["sigma"].astype(np.uint8)
     margin = _draw_margins(spec, th, ref["sigma"], u)
     if not diff.any():
-        return o, ref
+        return ref
     rows = np.nonzero(diff.any(axis=1))[0]
     assert len(rows) <= max(2, Ns // 200), "%d samples differ" % len(rows)
     for r in rows:
@@ -114,4 +121,4 @@ def low_precision_step(spec, m, gham, ham, Ns, eta, lam, key, counter, form, ckp
     D = ojac.log_derivatives(spec, th, sig.astype(np.int64))
     ref = ominsr.update(D, eps, eta, lam, pinv_cutoff)
     ref.update(sigma=sig, eps=eps)
-    return o, ref
+    return ref

@@ -3,8 +3,9 @@ architecture, so every kernel takes the path it takes there; fewer samples so
 the FP64 oracle stays tractable): the cluster chain (N = 100, d_h = 128 cRNN,
 checkpoints every 10 sites), the 10 x 10 Heisenberg lattice (2D pRNN,
 Marshall sign, S^z = 0 mask, pseudo-inverse), one 12 x 12 J1-J2 instance of
-the batched workload, a batch replay against the oracle, and the
-pseudo-inverse at n = 4096."""
+the batched workload, batch replays against the oracle (FP64 instances, and
+BF16 instances of the batched workload's architecture whose Grams run in one
+grouped launch), and the pseudo-inverse at n = 4096."""
 import numpy as np
 import pytest
 import torch
@@ -13,7 +14,8 @@ from oracle import hamiltonian as oham
 from oracle import minsr as ominsr
 from oracle import model as omodel
 from tests import inputs
-from tests.gpu_common import gpu, low_precision_step, make_pair, need_gpu, rel_err, to_dev
+from tests.gpu_common import (gpu, low_precision_ref, low_precision_step, make_pair, need_gpu,
+                              rel_err, to_dev)
 
 pytestmark = gpu
 
@@ -151,6 +153,35 @@ def test_batch_replay_matches_oracle():
         assert np.array_equal(ob["sigma"].cpu().numpy(), ref["sigma"].astype(np.uint8))
         assert rel_err(ob["dtheta"].cpu().numpy(), ref["dtheta"]) < 1e-10
         assert rel_err(b.momentum[k].cpu().numpy(), ref["m"]) < 1e-10
+    b.close()
+
+
+def test_batch_grouped_gram_matches_oracle():
+    # one replay of a batch of three instances of the batched J1-J2
+    # workload's architecture (2D cRNN d_h = 128, Marshall sign, J2 = 0.5) on
+    # 6 x 6, 7 x 7 and 5 x 5 lattices with uneven N_s, all in the BF16 split
+    # form: their Grams run as one grouped launch.  Every instance's T,
+    # eps', O' and dtheta against the oracle's step
+    import paper_2608_18065_amd as pm
+    ham = oham.Ham("j1j2", J=1.0, J2=0.5)
+    cases = [(6, 128, 701), (7, 96, 702), (5, 150, 703)]
+    insts, pairs = [], []
+    for L, Ns, key in cases:
+        print("grouped batch instance %dx%d Ns=%d" % (L, L, Ns), flush=True)
+        spec, m = make_pair(Lx=L, Ly=L, dim=2, H=128, cplx=True, marshall=True, dtype="f32",
+                            seed=key, max_Ns=Ns)
+        pairs.append((spec, m, Ns, key))
+        insts.append(dict(model=m, ham=_gham(ham), Ns=Ns, eta=0.1, lam=0.1, mu=0.0, key=key,
+                          form=pm.FORM_BF16_FP64))
+    th0 = [m.get_params().cpu().numpy() for _, m, _, _ in pairs]
+    b = pm.Batch(insts)
+    b.step()
+    torch.cuda.synchronize()
+    for k, (spec, m, Ns, key) in enumerate(pairs):
+        ref = low_precision_ref(spec, th0[k], ham, Ns, 0.1, 0.1, key, 0, b.outputs[k])
+        it = m.intermediates(pm.FORM_BF16_FP64)
+        print("instance %d: errors T %.2e  O' %.2e  dtheta %.2e" % ((k,) + _compare_low_precision(
+            b.outputs[k], ref, it, pm.FORM_BF16_FP64)), flush=True)
     b.close()
 
 
