@@ -774,6 +774,12 @@ int launch_forward(minsr_model* m, int mode, int Ns, const double* uniforms, uin
                    int store_every, double* site, hipStream_t s, const uint64_t* counter_ptr,
                    void* gates, uint32_t* zero_word) {
   if (Ns == 0) return MINSR_OK;
+  // FP32 chains of 64 or 128 units sample on the matrix cores; evaluation
+  // keeps the vector recurrence, whose arithmetic the Jacobian's checkpoint
+  // recomputation repeats exactly
+  if (mode == MODE_SAMPLE && sample_mfma_supported(m))
+    return launch_sample_mfma(m, Ns, uniforms, key, counter, counter_ptr, sigma, logpsi, states,
+                              store_every, site, m->dim == 1 ? gates : nullptr, zero_word, s);
   if (m->f64)
     return forward_t<double>(m, m->wd, mode, Ns, uniforms, key, counter, counter_ptr, sigma,
                              logpsi, states, store_every, site, gates, s, zero_word);

@@ -33,57 +33,17 @@
 #include <mutex>
 
 #include "model.hpp"
+#include "mfma16.hpp"
 
 namespace minsr {
 
 namespace {
 
-typedef __attribute__((ext_vector_type(8))) _Float16 jh8;
-typedef __attribute__((ext_vector_type(2))) _Float16 jh2;
-typedef __attribute__((ext_vector_type(2))) float jf2;
-typedef __attribute__((ext_vector_type(4))) float jf4;
+using namespace mf16;
 
 constexpr int JM_H = 128;       // hidden width of this path
 constexpr int JM_SEG = 16;      // longest checkpoint segment
 constexpr int JM_KMAX = 128;    // longest chain of the row assembly
-
-__device__ __forceinline__ jf4 jmma(jh8 a, jh8 b, jf4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-}
-
-// x = hi + lo, both rounded to nearest FP16; x - hi is exact in FP32
-__device__ __forceinline__ void jsplit(const float (&x)[8], jh8& hi, jh8& lo) {
-#pragma unroll
-  for (int e = 0; e < 8; e += 2) {
-    const jf2 v = {x[e], x[e + 1]};
-    const jh2 h = __builtin_convertvector(v, jh2);
-    const jh2 l = __builtin_convertvector(v - __builtin_convertvector(h, jf2), jh2);
-    hi[e] = h[0]; hi[e + 1] = h[1];
-    lo[e] = l[0]; lo[e + 1] = l[1];
-  }
-}
-
-// hardware exp2 and reciprocal (about 1 ulp each)
-__device__ __forceinline__ float jsig(float x) {
-  return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-1.4426950408889634f * x));
-}
-__device__ __forceinline__ float jtanh(float y) {
-  return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(2.8853900817779268f * y));
-}
-
-// workgroup barrier ordering shared-memory accesses only: unlike
-// lds_barrier() it does not wait for the wave's outstanding global stores
-// (these kernels never read back, within a launch, what they store)
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// power-of-two exponent that brings a largest magnitude m into [2^14, 2^15)
-__device__ __forceinline__ int jexp_for(float m) {
-  return m > 0.f ? min(max(14 - ilogbf(m), -120), 120) : 0;
-}
 
 }  // namespace
 
@@ -123,7 +83,7 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
   _Float16* hsl = hsh + (size_t)(C + 1) * S * HQ;
   _Float16* dph = hsl + (size_t)(C + 1) * S * HQ;       // [16][DQ]
   _Float16* dpl = dph + 16 * DQ;
-  jh8* rfr = reinterpret_cast<jh8*>(dpl + 16 * DQ);     // [NL][hi, lo][NW][64]
+  h16x8* rfr = reinterpret_cast<h16x8*>(dpl + 16 * DQ);     // [NL][hi, lo][NW][64]
   float* rmx = reinterpret_cast<float*>(rfr + NL * 2 * NW * 64);   // [16][NW] row maxima
   float* dzs = rmx + 16 * NW;                      // [JM_SEG][16][2] head adjoints
   float* cst = dzs + JM_SEG * 32;                  // [21][H] + 2, rows described below
@@ -158,7 +118,7 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
   auto bwv = [&](int g, int row, int col) -> float {   // W_g[row][col]
     return a.bw[((size_t)(row >> 2) * H + col) * 12 + g * 4 + (row & 3)];
   };
-  jh8 fh[3][KF], fl[3][KF], rh[KRR], rl[KRR];
+  h16x8 fh[3][KF], fl[3][KF], rh[KRR], rl[KRR];
   {
     // forward: B[k][n] = W_g[j][32 t + 8 kq + e]
 #pragma unroll
@@ -179,7 +139,7 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
         float x[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = fwv(g, j, 32 * t + 8 * kq + e) * dn;
-        jsplit(x, fh[g][t], fl[g][t]);
+        split16(x, fh[g][t], fl[g][t]);
       }
     }
     // reverse: B[k][n] = W_g[32 (t % KF) + 8 kq + e][j], g = t / KF
@@ -199,10 +159,10 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) x[e] = bwv(t / KF, 32 * (t % KF) + 8 * kq + e, j) * dn;
       if (t < KRR) {
-        jsplit(x, rh[t < KRR ? t : 0], rl[t < KRR ? t : 0]);
+        split16(x, rh[t < KRR ? t : 0], rl[t < KRR ? t : 0]);
       } else {
-        jh8 hi, lo;
-        jsplit(x, hi, lo);
+        h16x8 hi, lo;
+        split16(x, hi, lo);
         rfr[((t - KRR) * 2 + 0) * NW * 64 + w * 64 + l] = hi;
         rfr[((t - KRR) * 2 + 1) * NW * 64 + w * 64 + l] = lo;
       }
@@ -227,24 +187,24 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
   };
   // gate pre-activation products of the 16 rows from state buffer kk (the
   // A row of lane l is row n, i.e. sample n mod S)
-  auto gates = [&](int kk, jf4 (&acc)[3]) {
+  auto gates = [&](int kk, f32x4v (&acc)[3]) {
 #pragma unroll
-    for (int g = 0; g < 3; ++g) acc[g] = jf4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < 3; ++g) acc[g] = f32x4v{0.f, 0.f, 0.f, 0.f};
     const size_t o = ((size_t)kk * S + (n % S)) * HQ + 8 * kq;
 #pragma unroll
     for (int t = 0; t < KF; ++t) {
-      const jh8 ah = *reinterpret_cast<const jh8*>(hsh + o + 32 * t);
-      const jh8 al = *reinterpret_cast<const jh8*>(hsl + o + 32 * t);
+      const h16x8 ah = *reinterpret_cast<const h16x8*>(hsh + o + 32 * t);
+      const h16x8 al = *reinterpret_cast<const h16x8*>(hsl + o + 32 * t);
 #pragma unroll
       for (int g = 0; g < 3; ++g) {
-        acc[g] = jmma(al, fh[g][t], acc[g]);
-        acc[g] = jmma(ah, fl[g][t], acc[g]);
-        acc[g] = jmma(ah, fh[g][t], acc[g]);
+        acc[g] = mma16(al, fh[g][t], acc[g]);
+        acc[g] = mma16(ah, fl[g][t], acc[g]);
+        acc[g] = mma16(ah, fh[g][t], acc[g]);
       }
     }
   };
   // the cell of row 4 kq + e, unit j, previous spin sp
-  auto cell = [&](const jf4 (&acc)[3], int e, int sp, float& u, float& r, float& ag, float& ht) {
+  auto cell = [&](const f32x4v (&acc)[3], int e, int sp, float& u, float& r, float& ag, float& ht) {
     float au = fmaf(acc[0][e], cst[13 * H + j], cst[j]);
     float ar = fmaf(acc[1][e], cst[14 * H + j], cst[H + j]);
     ag = fmaf(acc[2][e], cst[15 * H + j], cst[2 * H + j]);
@@ -256,9 +216,9 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
     const float ai = cst[3 * H + j] + (sp == 0 ? xi0 : sp == 1 ? xi1 : 0.f);
     au += sp == 0 ? xu0 : sp == 1 ? xu1 : 0.f;
     ar += sp == 0 ? xr0 : sp == 1 ? xr1 : 0.f;
-    u = jsig(au);
-    r = jsig(ar);
-    ht = jtanh(fmaf(r, ag, ai));
+    u = sigm_hw(au);
+    r = sigm_hw(ar);
+    ht = tanh_hw(fmaf(r, ag, ai));
   };
 
   float carry[4] = {0.f, 0.f, 0.f, 0.f};   // adjoint of h_k arriving from site k + 1
@@ -318,7 +278,7 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
 
     // ---- forward recomputation of the segment's states
     for (int kk = 0; kk < nf; ++kk) {
-      jf4 acc[3];
+      f32x4v acc[3];
       gates(kk, acc);
       if (!CPLX || kq < 2) {
         const int k = ks + kk;
@@ -375,7 +335,7 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
     // ---- reverse through the segment
     // the gate products of site k - 1 are issued together with the reverse
     // product of site k (independent work for the matrix cores)
-    jf4 acc[3];
+    f32x4v acc[3];
     gates(len - 1, acc);
     for (int kk = len - 1; kk >= 0; --kk) {
       const int k = ks + kk;
@@ -423,7 +383,7 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
         const float4 m1 = *reinterpret_cast<const float4*>(rmx + (4 * kq + e) * NW + 4);
         const float mx = fmaxf(fmaxf(fmaxf(m0.x, m0.y), fmaxf(m0.z, m0.w)),
                                fmaxf(fmaxf(m1.x, m1.y), fmaxf(m1.z, m1.w)));
-        ex[e] = jexp_for(mx);
+        ex[e] = pow2_exp_for(mx);
         const float sc = ldexpf(1.f, ex[e]);
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
@@ -438,14 +398,14 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
       if (kk > 0) gates(kk - 1, acc);
       // adjoint of h_{k-1}: [16 x 3 d_h] x [3 d_h x d_h]; three independent
       // accumulation chains, one per split product
-      jf4 rc0 = {0.f, 0.f, 0.f, 0.f}, rc1 = rc0, rc2 = rc0;
+      f32x4v rc0 = {0.f, 0.f, 0.f, 0.f}, rc1 = rc0, rc2 = rc0;
       const _Float16* ahp = dph + n * DQ + 8 * kq;
       const _Float16* alp = dpl + n * DQ + 8 * kq;
 #pragma unroll
       for (int t = 0; t < KR; ++t) {
-        const jh8 ah = *reinterpret_cast<const jh8*>(ahp + 32 * t);
-        const jh8 al = *reinterpret_cast<const jh8*>(alp + 32 * t);
-        jh8 bh, bl;
+        const h16x8 ah = *reinterpret_cast<const h16x8*>(ahp + 32 * t);
+        const h16x8 al = *reinterpret_cast<const h16x8*>(alp + 32 * t);
+        h16x8 bh, bl;
         if (t < KRR) {
           bh = rh[t < KRR ? t : 0];
           bl = rl[t < KRR ? t : 0];
@@ -453,11 +413,11 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
           bh = rfr[((t - KRR) * 2 + 0) * NW * 64 + w * 64 + l];
           bl = rfr[((t - KRR) * 2 + 1) * NW * 64 + w * 64 + l];
         }
-        rc0 = jmma(al, bh, rc0);
-        rc1 = jmma(ah, bl, rc1);
-        rc2 = jmma(ah, bh, rc2);
+        rc0 = mma16(al, bh, rc0);
+        rc1 = mma16(ah, bl, rc1);
+        rc2 = mma16(ah, bh, rc2);
       }
-      const jf4 racc = (rc0 + rc1) + rc2;
+      const f32x4v racc = (rc0 + rc1) + rc2;
       const float rs = cst[16 * H + j];
 #pragma unroll
       for (int e = 0; e < 4; ++e) carry[e] = fmaf(racc[e] * rs, ldexpf(1.f, -ex[e]), dhd[e]);
@@ -497,7 +457,7 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
   // B fragments: B[k][i] = h_{k-1}[i] (zero for k = 0 and k >= N),
   // k = 32 t + 8 kq + e, i = 32 w + 16 ut + n
   const float* hst = a.states + (size_t)s * N * H;
-  jh8 bh[2][KM / 32], bl[2][KM / 32];
+  h16x8 bh[2][KM / 32], bl[2][KM / 32];
 #pragma unroll
   for (int ut = 0; ut < 2; ++ut)
 #pragma unroll
@@ -508,7 +468,7 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
         const int k = 32 * t + 8 * kq + e;
         x[e] = (k >= 1 && k < N) ? hst[(size_t)(k - 1) * H + 32 * w + 16 * ut + n] : 0.f;
       }
-      jsplit(x, bh[ut][t], bl[ut][t]);
+      split16(x, bh[ut][t], bl[ut][t]);
     }
 
   // staging thread: gate row j, sites [64 kb, 64 kb + 64)
@@ -634,7 +594,7 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
       }
       lds_barrier();
       // scaled split into the A tile (rows j, sites k)
-      const int E = jexp_for(xch[0][jr]);
+      const int E = pow2_exp_for(xch[0][jr]);
       const float up = ldexpf(1.f, E);
       if (kb == 0) exs[jr] = ldexpf(1.f, -E);
 #pragma unroll
@@ -642,10 +602,10 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
         float x[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = v[8 * c8 + e] * up;
-        jh8 hi, lo;
-        jsplit(x, hi, lo);
-        *reinterpret_cast<jh8*>(&ahi[jr][64 * kb + 8 * c8]) = hi;
-        *reinterpret_cast<jh8*>(&alo[jr][64 * kb + 8 * c8]) = lo;
+        h16x8 hi, lo;
+        split16(x, hi, lo);
+        *reinterpret_cast<h16x8*>(&ahi[jr][64 * kb + 8 * c8]) = hi;
+        *reinterpret_cast<h16x8*>(&alo[jr][64 * kb + 8 * c8]) = lo;
       }
       lds_barrier();
 
@@ -655,17 +615,17 @@ __global__ __launch_bounds__(256, 2) void k_jac_rows(JRowsArgs a) {
       const int ldq = q < 2 ? H + 2 : H;
 #pragma unroll 1
       for (int mt = 0; mt < H / 16; ++mt) {
-        jf4 acc[2] = {jf4{0.f, 0.f, 0.f, 0.f}, jf4{0.f, 0.f, 0.f, 0.f}};
+        f32x4v acc[2] = {f32x4v{0.f, 0.f, 0.f, 0.f}, f32x4v{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
         for (int t = 0; t < KM / 32; ++t) {
           if (t < KT) {
-            const jh8 ah = *reinterpret_cast<const jh8*>(&ahi[16 * mt + n][32 * t + 8 * kq]);
-            const jh8 al = *reinterpret_cast<const jh8*>(&alo[16 * mt + n][32 * t + 8 * kq]);
+            const h16x8 ah = *reinterpret_cast<const h16x8*>(&ahi[16 * mt + n][32 * t + 8 * kq]);
+            const h16x8 al = *reinterpret_cast<const h16x8*>(&alo[16 * mt + n][32 * t + 8 * kq]);
 #pragma unroll
             for (int ut = 0; ut < 2; ++ut) {
-              acc[ut] = jmma(al, bh[ut][t], acc[ut]);
-              acc[ut] = jmma(ah, bl[ut][t], acc[ut]);
-              acc[ut] = jmma(ah, bh[ut][t], acc[ut]);
+              acc[ut] = mma16(al, bh[ut][t], acc[ut]);
+              acc[ut] = mma16(ah, bl[ut][t], acc[ut]);
+              acc[ut] = mma16(ah, bh[ut][t], acc[ut]);
             }
           }
         }

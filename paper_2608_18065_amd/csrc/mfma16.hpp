@@ -1,0 +1,74 @@
+// Helpers of the 16 x 16 x 32 FP16 matrix-core kernels of FP32 recurrences
+// (the Jacobian's reverse pass and row assembly, the sampler): FP32
+// operands enter v_mfma_f32_16x16x32_f16 as pairs x = hi + lo of FP16
+// values, products a_lo b_hi + a_hi b_lo + a_hi b_hi accumulate in FP32.
+//
+// Lane layouts of v_mfma_f32_16x16x32_f16 (64 lanes, l = lane):
+//   A (16 x 32): lane l holds A[l % 16][8 (l / 16) + e], e = 0..7;
+//   B (32 x 16): lane l holds B[8 (l / 16) + e][l % 16], e = 0..7;
+//   D (16 x 16): lane l holds D[4 (l / 16) + v][l % 16], v = 0..3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace minsr {
+namespace mf16 {
+
+typedef __attribute__((ext_vector_type(8))) _Float16 h16x8;
+typedef __attribute__((ext_vector_type(4))) _Float16 h16x4;
+typedef __attribute__((ext_vector_type(2))) _Float16 h16x2;
+typedef __attribute__((ext_vector_type(2))) float f32x2v;
+typedef __attribute__((ext_vector_type(4))) float f32x4v;
+
+__device__ __forceinline__ f32x4v mma16(h16x8 a, h16x8 b, f32x4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// x = hi + lo, both rounded to nearest FP16; x - hi is exact in FP32, so
+// |x - hi - lo| <= 2^-22 |x| while lo stays in FP16's normal range
+__device__ __forceinline__ void split16(const float (&x)[8], h16x8& hi, h16x8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    const f32x2v v = {x[e], x[e + 1]};
+    const h16x2 h = __builtin_convertvector(v, h16x2);
+    const h16x2 l = __builtin_convertvector(v - __builtin_convertvector(h, f32x2v), h16x2);
+    hi[e] = h[0]; hi[e + 1] = h[1];
+    lo[e] = l[0]; lo[e + 1] = l[1];
+  }
+}
+__device__ __forceinline__ void split16(const float (&x)[4], h16x4& hi, h16x4& lo) {
+#pragma unroll
+  for (int e = 0; e < 4; e += 2) {
+    const f32x2v v = {x[e], x[e + 1]};
+    const h16x2 h = __builtin_convertvector(v, h16x2);
+    const h16x2 l = __builtin_convertvector(v - __builtin_convertvector(h, f32x2v), h16x2);
+    hi[e] = h[0]; hi[e + 1] = h[1];
+    lo[e] = l[0]; lo[e + 1] = l[1];
+  }
+}
+
+// logistic function and tanh from the hardware exp2 and reciprocal (about
+// 1 ulp each); both saturate correctly
+__device__ __forceinline__ float sigm_hw(float x) {
+  return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-1.4426950408889634f * x));
+}
+__device__ __forceinline__ float tanh_hw(float y) {
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(2.8853900817779268f * y));
+}
+
+// workgroup barrier ordering shared-memory accesses only: unlike
+// __syncthreads() it does not wait for the wave's outstanding global stores
+// (these kernels never read back, within a launch, what they store)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// power-of-two exponent that brings a largest magnitude m into [2^14, 2^15)
+__device__ __forceinline__ int pow2_exp_for(float m) {
+  return m > 0.f ? min(max(14 - ilogbf(m), -120), 120) : 0;
+}
+
+}  // namespace mf16
+}  // namespace minsr

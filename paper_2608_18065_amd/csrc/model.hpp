@@ -98,6 +98,13 @@ int launch_pack(minsr_model* m, hipStream_t s);
 // mode 0: sample, 1: evaluate.  states/site may be null.
 // gates (1D, store_every == 1, may be null): [Ns][N][4][H] gate values u, r,
 // candidate pre-activation and candidate of every site, for the Jacobian.
+// sample_mfma.hip: sampling of 1D FP32 models with d_h = 64 or 128 (N <= 256)
+// on the matrix cores; launch_forward takes it for mode 0 where it applies
+bool sample_mfma_supported(const minsr_model* m);
+int launch_sample_mfma(minsr_model* m, int Ns, const double* uniforms, uint64_t key,
+                       uint64_t counter, const uint64_t* counter_ptr, uint8_t* sigma,
+                       double* logpsi, void* states, int store_every, double* site, void* gates,
+                       uint32_t* zero_word, hipStream_t s);
 int launch_forward(minsr_model* m, int mode, int Ns, const double* uniforms, uint64_t key,
                    uint64_t counter, uint8_t* sigma, double* logpsi, void* states,
                    int store_every, double* site, hipStream_t s,
