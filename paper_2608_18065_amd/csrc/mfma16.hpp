@@ -65,6 +65,18 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// v[l] + v[l ^ 16] and v[l] + v[l ^ 32]: both lanes of a pair add the same
+// two values in the same order (lower row or half first), so they end with
+// equal sums; the exchanges are VALU lane swaps, not shared-memory traffic
+__device__ __forceinline__ float sum_xor16(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float sum_xor32(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // power-of-two exponent that brings a largest magnitude m into [2^14, 2^15)
 __device__ __forceinline__ int pow2_exp_for(float m) {
   return m > 0.f ? min(max(14 - ilogbf(m), -120), 120) : 0;

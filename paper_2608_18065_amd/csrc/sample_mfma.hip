@@ -17,11 +17,12 @@
 // share of the output head (the two logits and, for a complex head, the two
 // phase pre-activations) is summed over the four lanes of its sequence by
 // cross-lane exchanges and over the waves through shared memory in a fixed
-// order.  After the single barrier of a site every lane holds the
-// conditional of its sequence and draws its spin with the uniform of
-// (sequence, site), generated into shared memory before the site loop from
-// the same Philox4x64-10 stream as every other sampler.  The drawn spin
-// selects the input columns of the next site.
+// order.  After the single barrier of a site the next site's products are
+// issued first; while they run, every lane forms the conditional of its
+// sequence and draws its spin with the uniform of (sequence, site),
+// generated into shared memory before the site loop from the same
+// Philox4x64-10 stream as every other sampler.  The drawn spin then
+// selects the input columns the next cell adds to the products.
 #include "model.hpp"
 #include "mfma16.hpp"
 
@@ -63,6 +64,7 @@ __global__ __launch_bounds__(4 * H) void k_sample_mfma(SampMArgs a) {
   __shared__ __align__(16) _Float16 hsl[2][SM_SEQ][HP];
   __shared__ __align__(16) float4 part[2][NW][SM_SEQ];
   __shared__ double uni[SM_SEQ][SM_NMAX];
+  __shared__ uint8_t subA[SM_NMAX];
 
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int col = l & 15, grp = l >> 4;
@@ -87,6 +89,7 @@ __global__ __launch_bounds__(4 * H) void k_sample_mfma(SampMArgs a) {
       for (int e = 0; e < 4 && 4 * b + e < N; ++e) uni[c][4 * b + e] = u01(r.w[e]);
     }
   }
+  for (int i = tid; i < N; i += 4 * H) subA[i] = a.marshall ? a.subA[i] : 0;
   for (int i = tid; i < SM_SEQ * HP; i += 4 * H) {
     (&hsh[0][0][0])[i] = (_Float16)0.f;
     (&hsl[0][0][0])[i] = (_Float16)0.f;
@@ -146,13 +149,62 @@ __global__ __launch_bounds__(4 * H) void k_sample_mfma(SampMArgs a) {
   const float PI = 3.14159265358979323846f;
   const bool cplx = a.cplx != 0;
   const bool wr = w == 0 && grp == 0 && act;   // the lane that writes its sequence's outputs
+  // every load of the set-up complete before the site loop: the loop's
+  // global accesses are stores only, and no wait inside it may then count
+  // the stores still in flight (vmcnt covers loads and stores alike)
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
   __syncthreads();
 
   float h[4] = {0.f, 0.f, 0.f, 0.f};
   double lp = 0.0, ph = 0.0;
   int nup = 0, ndn = 0, nA = 0, sp = -1;
+  // conditional of site k - 1 from the head sums the waves left in part[],
+  // and the draw of its spin (every lane of the sequence draws the same)
+  auto draw = [&](int k) {
+    const int pb = k & 1;
+    float4 zs = part[pb][0][col];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+      const float4 t = part[pb][i][col];
+      zs.x += t.x; zs.y += t.y; zs.z += t.z; zs.w += t.w;
+    }
+    const float zz0 = zs.x + c0, zz1 = zs.y + c1;
+    const float mxz = fmaxf(zz0, zz1);
+    const float d = -fabsf(zz0 - zz1);
+    const float lse = mxz + 0.6931471805599453f *
+                                __builtin_amdgcn_logf(1.f + __builtin_amdgcn_exp2f(1.4426950408889634f * d));
+    float lp0 = zz0 - lse, lp1 = zz1 - lse;
+    if (a.zero_mag) {
+      const int half = N / 2;
+      if (nup >= half) { lp0 = -INFINITY; lp1 = 0.f; }
+      else if (ndn >= half) { lp0 = 0.f; lp1 = -INFINITY; }
+    }
+    float ph0 = 0.f, ph1 = 0.f;
+    if (cplx) {
+      const float aa0 = zs.z + cp0, aa1 = zs.w + cp1;
+      ph0 = PI * aa0 * __builtin_amdgcn_rcpf(1.f + fabsf(aa0));
+      ph1 = PI * aa1 * __builtin_amdgcn_rcpf(1.f + fabsf(aa1));
+    }
+    const double p0 = (double)__builtin_amdgcn_exp2f(1.4426950408889634f * lp0);
+    const int v = uni[col][k] < p0 ? 0 : 1;
+    lp += (double)(v == 0 ? lp0 : lp1);
+    ph += (double)(v == 0 ? ph0 : ph1);
+    nup += v == 0;
+    ndn += v == 1;
+    nA += subA[k] ? v : 0;
+    sp = v;
+    if (wr) {
+      a.sigma[(size_t)s * N + k] = (uint8_t)v;
+      if (a.site) {
+        double* st = a.site + ((size_t)s * N + k) * 4;
+        st[0] = (double)lp0; st[1] = (double)lp1; st[2] = (double)ph0; st[3] = (double)ph1;
+      }
+    }
+  };
   for (int k = 0; k < N; ++k) {
     const int cb = k & 1, nb = cb ^ 1;
+    // gate products of site k on h_k, issued before the spin of site k - 1
+    // is drawn: the matrix cores run while the draw takes the vector units
     h16x8 bhi[KB], blo[KB];
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
@@ -170,6 +222,7 @@ __global__ __launch_bounds__(4 * H) void k_sample_mfma(SampMArgs a) {
         acc[q] = mma16(wah[q][kb], bhi[kb], acc[q]);
       }
     }
+    if (k > 0) draw(k - 1);
     // the cell for units j0 + v of this lane's sequence
     float hn[4], gu[4], gr[4], ag[4], gt[4];
 #pragma unroll
@@ -194,21 +247,8 @@ __global__ __launch_bounds__(4 * H) void k_sample_mfma(SampMArgs a) {
       *reinterpret_cast<h16x4*>(&hsh[nb][col][j0]) = hi;
       *reinterpret_cast<h16x4*>(&hsl[nb][col][j0]) = lo;
     }
-    if (act) {
-      const size_t row = (size_t)s * N + k;
-      if (a.states && (k + 1) % a.store_every == 0)
-        *reinterpret_cast<float4*>(a.states + row * H + j0) = make_float4(hn[0], hn[1], hn[2], hn[3]);
-      if (a.gates) {
-        float* g = a.gates + row * 4 * H + j0;
-        *reinterpret_cast<float4*>(g) = make_float4(gu[0], gu[1], gu[2], gu[3]);
-        *reinterpret_cast<float4*>(g + H) = make_float4(gr[0], gr[1], gr[2], gr[3]);
-        *reinterpret_cast<float4*>(g + 2 * H) = make_float4(ag[0], ag[1], ag[2], ag[3]);
-        *reinterpret_cast<float4*>(g + 3 * H) = make_float4(gt[0], gt[1], gt[2], gt[3]);
-      }
-    }
     // output head: this lane's four units, then the four lanes of the
-    // sequence (exchanges are symmetric, so every lane ends with the same
-    // sum), then the waves in order
+    // sequence, then (after the barrier) the waves in order
     float z0 = U0[0] * hn[0], z1 = U1[0] * hn[0], q0 = 0.f, q1 = 0.f;
 #pragma unroll
     for (int v = 1; v < 4; ++v) {
@@ -224,56 +264,30 @@ __global__ __launch_bounds__(4 * H) void k_sample_mfma(SampMArgs a) {
         q1 = fmaf(P1[v], hn[v], q1);
       }
     }
-    z0 += __shfl_xor(z0, 16); z1 += __shfl_xor(z1, 16);
-    z0 += __shfl_xor(z0, 32); z1 += __shfl_xor(z1, 32);
+    z0 = sum_xor32(sum_xor16(z0));
+    z1 = sum_xor32(sum_xor16(z1));
     if (cplx) {
-      q0 += __shfl_xor(q0, 16); q1 += __shfl_xor(q1, 16);
-      q0 += __shfl_xor(q0, 32); q1 += __shfl_xor(q1, 32);
+      q0 = sum_xor32(sum_xor16(q0));
+      q1 = sum_xor32(sum_xor16(q1));
     }
     if (grp == 0) part[cb][w][col] = make_float4(z0, z1, q0, q1);
-    lds_barrier();
-    float4 zs = part[cb][0][col];
-#pragma unroll
-    for (int i = 1; i < NW; ++i) {
-      const float4 t = part[cb][i][col];
-      zs.x += t.x; zs.y += t.y; zs.z += t.z; zs.w += t.w;
-    }
-    // conditional of site k and the draw
-    const float zz0 = zs.x + c0, zz1 = zs.y + c1;
-    const float mxz = fmaxf(zz0, zz1);
-    const float d = -fabsf(zz0 - zz1);
-    const float lse = mxz + 0.6931471805599453f *
-                                __builtin_amdgcn_logf(1.f + __builtin_amdgcn_exp2f(1.4426950408889634f * d));
-    float lp0 = zz0 - lse, lp1 = zz1 - lse;
-    if (a.zero_mag) {
-      const int half = N / 2;
-      if (nup >= half) { lp0 = -INFINITY; lp1 = 0.f; }
-      else if (ndn >= half) { lp0 = 0.f; lp1 = -INFINITY; }
-    }
-    float ph0 = 0.f, ph1 = 0.f;
-    if (cplx) {
-      const float aa0 = zs.z + cp0, aa1 = zs.w + cp1;
-      ph0 = PI * aa0 / (1.f + fabsf(aa0));
-      ph1 = PI * aa1 / (1.f + fabsf(aa1));
-    }
-    const double p0 = (double)__builtin_amdgcn_exp2f(1.4426950408889634f * lp0);
-    const int v = uni[col][k] < p0 ? 0 : 1;
-    lp += (double)(v == 0 ? lp0 : lp1);
-    ph += (double)(v == 0 ? ph0 : ph1);
-    nup += v == 0;
-    ndn += v == 1;
-    if (a.marshall) nA += a.subA[k] ? v : 0;
-    sp = v;
-    if (wr) {
-      a.sigma[(size_t)s * N + k] = (uint8_t)v;
-      if (a.site) {
-        double* st = a.site + ((size_t)s * N + k) * 4;
-        st[0] = (double)lp0; st[1] = (double)lp1; st[2] = (double)ph0; st[3] = (double)ph1;
+    if (act) {
+      const size_t row = (size_t)s * N + k;
+      if (a.states && (k + 1) % a.store_every == 0)
+        *reinterpret_cast<float4*>(a.states + row * H + j0) = make_float4(hn[0], hn[1], hn[2], hn[3]);
+      if (a.gates) {
+        float* g = a.gates + row * 4 * H + j0;
+        *reinterpret_cast<float4*>(g) = make_float4(gu[0], gu[1], gu[2], gu[3]);
+        *reinterpret_cast<float4*>(g + H) = make_float4(gr[0], gr[1], gr[2], gr[3]);
+        *reinterpret_cast<float4*>(g + 2 * H) = make_float4(ag[0], ag[1], ag[2], ag[3]);
+        *reinterpret_cast<float4*>(g + 3 * H) = make_float4(gt[0], gt[1], gt[2], gt[3]);
       }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) h[i] = hn[i];
+    lds_barrier();
   }
+  draw(N - 1);
   if (wr) {
     a.logpsi[2 * s] = 0.5 * lp;
     a.logpsi[2 * s + 1] = ph + 3.14159265358979323846 * (double)nA;
