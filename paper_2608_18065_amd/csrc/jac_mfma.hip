@@ -311,10 +311,8 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
         v0 = fmaf(hv, hph[u], v0);
         v1 = fmaf(hv, hph[H + u], v1);
       }
-      v0 += __shfl_xor(v0, 1, 64);
-      v1 += __shfl_xor(v1, 1, 64);
-      v0 += __shfl_xor(v0, 2, 64);
-      v1 += __shfl_xor(v1, 2, 64);
+      v0 = quad_sum(v0);
+      v1 = quad_sum(v1);
       if (on && qd == 0) {
         const int k = ks + kk;
         const int sk = sgs[s * SGP + kk + 1];
@@ -366,9 +364,7 @@ __global__ __launch_bounds__(512, 1) void k_jac_rev(JRevArgs a) {
         }
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) mloc[e] = fmaxf(mloc[e], __shfl_xor(mloc[e], o, 16));
+      for (int e = 0; e < 4; ++e) mloc[e] = row16_max(mloc[e]);
       if (n == 0) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) rmx[(4 * kq + e) * NW + w] = mloc[e];

@@ -77,6 +77,26 @@ __device__ __forceinline__ float sum_xor32(float v) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// lane exchanges inside rows of 16 lanes by DPP (no shared-memory crossbar
+// round trip): quad_sum adds the partners at distance 1, then 2, exactly as
+// an xor butterfly over those distances does; row16_max takes the maximum
+// over each row of 16 lanes
+template <int CTRL> __device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_sum(float v) {
+  v += dpp_f<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  return v;
+}
+__device__ __forceinline__ float row16_max(float v) {
+  v = fmaxf(v, dpp_f<0xB1>(v));
+  v = fmaxf(v, dpp_f<0x4E>(v));
+  v = fmaxf(v, dpp_f<0x141>(v));   // row_half_mirror
+  v = fmaxf(v, dpp_f<0x140>(v));   // row_mirror
+  return v;
+}
+
 // power-of-two exponent that brings a largest magnitude m into [2^14, 2^15)
 __device__ __forceinline__ int pow2_exp_for(float m) {
   return m > 0.f ? min(max(14 - ilogbf(m), -120), 120) : 0;
