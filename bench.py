@@ -43,18 +43,18 @@ PEAK_FP64_TFLOPS = 78.6         # dense FP64 matrix cores (equal to the FP64 vec
 # scaled by the counter's reading on a plain copy of known size; None until
 # taken for the current kernel version
 TRAFFIC_BYTES = {
-    # k_eloc_mfma_w (FP16 hi/lo split products): 9984.8 KiB fetched x 2.000 +
-    # 1353.5 KiB written x 1.000
-    "eloc": 9984.8 * 1024 * 2.0 + 1353.5 * 1024,
+    # k_eloc_mfma_w (FP16 hi/lo split products): 9995.0 KiB fetched x 2.000 +
+    # 1336.2 KiB written x 1.000
+    "eloc": 9995.0 * 1024 * 2.0 + 1336.2 * 1024,
     # k_chol_prep + k_chol_persist_f64 + k_trsv_back_mt:
-    # (76.5 + 8995.1 + 2251.5) KiB fetched x 2.000 + (17.3 + 4692.5 + 8.5) KiB written
-    "solve": (76.5 + 8995.1 + 2251.5) * 1024 * 2.0 + (17.3 + 4692.5 + 8.5) * 1024,
+    # (76.9 + 8961.1 + 2254.6) KiB fetched x 2.000 + (17.4 + 4692.5 + 8.5) KiB written
+    "solve": (76.9 + 8961.1 + 2254.6) * 1024 * 2.0 + (17.4 + 4692.5 + 8.5) * 1024,
     # k_jacobian (gate-tape path, gate adjoints stored per site) + k_jac_wgrad:
-    # (42362.2 + 33947.3) KiB fetched x 2.000 + (55328.0 + 50235.6) KiB written x 1.000
-    "jacobian": (42362.2 + 33947.3) * 1024 * 2.0 + (55328.0 + 50235.6) * 1024,
-    # k_gram_bf16 (split form, four products, 7-way split-K, FP64 partial tiles):
-    # 43368.1 KiB fetched x 2.000 + 32256.0 KiB written x 1.000
-    "gram": 43368.1 * 1024 * 2.0 + 32256.0 * 1024}
+    # (42362.9 + 33943.5) KiB fetched x 2.000 + (55328.0 + 50235.2) KiB written x 1.000
+    "jacobian": (42362.9 + 33943.5) * 1024 * 2.0 + (55328.0 + 50235.2) * 1024,
+    # k_gram_bf16 (split form, four products, eight-wave 128 x 128 tiles, FP64
+    # partial tiles): 43333.2 KiB fetched x 2.000 + 32256.0 KiB written x 1.000
+    "gram": 43333.2 * 1024 * 2.0 + 32256.0 * 1024}
 
 
 def parse():
