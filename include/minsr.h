@@ -419,7 +419,9 @@ int minsr_batch_destroy(minsr_batch* b);
  * key "gram_split": split-K factor of the Gram (0 = built-in heuristic);
  * key "eloc_grid": workgroups of the persistent local-energy launch
  * (0 = one per work item up to the window limit);
- * key "sample_r": sequences per thread of the sampling recurrence (1 or 4);
+ * key "sample_r": sequences per thread of the vector sampling recurrence
+ * (1 or 4; FP32 1D chains with d_h = 64 or 128 and N <= 256 sample on the
+ * matrix cores, which this key does not affect);
  * key "jac_parts": threads per hidden unit of the Jacobian's reverse pass
  * (1, 2 or 4; d_h = 64 and 128 only; 0 = built-in choice);
  * key "solve_spin_limit": polls after which a wait of one workgroup of the

@@ -11,7 +11,7 @@ this way.
     tunable      phase timed                  candidates
     gram_split   Gram tiles + reduction       0 (heuristic), 1, 2, 4, 8, 16, 32
     eloc_grid    local-energy recurrence      0 (one per item), 256, 512, 1024, 2048
-    sample_r     sampling recurrence          1, 4
+    sample_r     vector sampling recurrence   1, 4 (no effect on the matrix-core sampler)
     jac_parts    Jacobian reverse pass        0 (built-in), 1, 2, 4
 """
 import json
