@@ -26,6 +26,7 @@
 #include <type_traits>
 
 #include "model.hpp"
+#include "mfma16.hpp"
 
 namespace minsr {
 
@@ -238,9 +239,10 @@ __device__ inline void eloc_end(const ElocMArgs& a, const ElocSeq& e) {
 }
 
 template <int H, int DIM>
-// d_h <= 64: two waves per SIMD (at most 256 registers each), so one wave's
-// elementwise update overlaps the other's matrix products
-__global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(ElocMArgs a) {
+// 1D d_h <= 64: two waves per SIMD (at most 256 registers each); 2D keeps
+// the whole register file for one wave (its split weight fragments, the
+// gate-input product and the window of neighbour states)
+__global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void k_eloc_mfma(ElocMArgs a) {
   constexpr int S = 32;
   constexpr int HP = H + 4;
   constexpr int KS = H / 2;
@@ -250,6 +252,7 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
   __shared__ __align__(16) float hx[DIM == 2 ? S : 1][2 * H + 4];
   __shared__ __align__(16) float hw[4][H];
   __shared__ float hb[4];
+  __shared__ float hmx[2][H / 32];   // 2D: largest |h'| of each wave at a site
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
@@ -257,10 +260,12 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
   const int N = a.N;
   const int NT = blockDim.x;
 
-  // 2D: FP32 fragments.  1D: the state products as FP16 hi/lo fragments
-  // (the split described at k_eloc_mfma_w, same register footprint; the
-  // state lies in [-1, 1], while the 2D gate input U1 h_h + U2 h_v does not)
-  constexpr bool SPLIT = DIM == 1;
+  // the gate products as FP16 hi/lo fragments (the split described at
+  // k_eloc_mfma_w, same register footprint).  The 1D state lies in
+  // [-1, 1]; the 2D gate input h' = U1 h_h + U2 h_v does not, so in 2D the
+  // split operand is h' 2^-t with t from the site's largest |h'| over the
+  // workgroup (t = 0 below 2^14) and the products are scaled back by 2^t
+  constexpr bool SPLIT = true;
   constexpr int KJ = H / 16;
   float Wu[SPLIT ? KX : KS + KX], Wr[SPLIT ? KX : KS + KX], Wg[SPLIT ? 1 : KS], Wi[KX];
   f16x8_m Wuh[SPLIT ? KJ : 1], Wul[SPLIT ? KJ : 1], Wrh[SPLIT ? KJ : 1], Wrl[SPLIT ? KJ : 1],
@@ -386,34 +391,66 @@ __global__ __launch_bounds__(64 * (H / 32), H <= 64 ? 2 : 1) void k_eloc_mfma(El
           acc = mfma_f32(av.w, m2[(size_t)(s4 + 3) * 64], acc);
         }
         hin = acc;
+        float m = 0.f;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) hA[cb][(q / 4) * 8 + half * 4 + (q % 4)][unit] = hin[q];
+        for (int q = 0; q < 16; ++q) {
+          hA[cb][(q / 4) * 8 + half * 4 + (q % 4)][unit] = hin[q];
+          m = fmaxf(m, fabsf(hin[q]));
+        }
+        m = mf16::row16_max(m);
+        if (lane == 0) {
+          const float m1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 16));
+          const float m2v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 32));
+          const float m3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 48));
+          hmx[cb][w] = fmaxf(fmaxf(m, m1), fmaxf(m2v, m3));
+        }
         __syncthreads();
       }
       // gate pre-activations of the 32 sequences for this wave's units (1D:
       // scaled for exp2, biases of u, r and the input term in the one-hot
       // fragments, so those accumulators start from zero)
       f32x16_m au, ar, ag, ai;
+      // 2D: the split operand's power-of-two scale at this site
+      float hdn = 1.f, hup = 1.f;
+      if (DIM == 2) {
+        float mx = hmx[cb][0];
+#pragma unroll
+        for (int v = 1; v < H / 32; ++v) mx = fmaxf(mx, hmx[cb][v]);
+        const int t = mx >= 16384.f ? min(ilogbf(mx) - 13, 120) : 0;
+        hdn = ldexpf(1.f, -t);
+        hup = ldexpf(1.f, t);
+      }
       if (DIM == 1) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) { au[q] = 0.f; ar[q] = 0.f; ag[q] = bgs * sdn[2]; ai[q] = 0.f; }
       } else {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) { au[q] = bu; ar[q] = br; ag[q] = bh; ai[q] = bi; }
+        for (int q = 0; q < 16; ++q) { au[q] = 0.f; ar[q] = 0.f; ag[q] = 0.f; ai[q] = bi; }
       }
       if constexpr (SPLIT) {
 #pragma unroll
         for (int j = 0; j < KJ; ++j) {
           const float4 x0 = *reinterpret_cast<const float4*>(&hA[cb][col][16 * j + 8 * half]);
           const float4 x1 = *reinterpret_cast<const float4*>(&hA[cb][col][16 * j + 8 * half + 4]);
-          const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+          float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+          if (DIM == 2) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] *= hdn;
+          }
           f16x8_m ahi, alo;
           split_f16(x, ahi, alo);
           au = mfma_f16(alo, Wuh[j], au); ar = mfma_f16(alo, Wrh[j], ar); ag = mfma_f16(alo, Wgh[j], ag);
           au = mfma_f16(ahi, Wul[j], au); ar = mfma_f16(ahi, Wrl[j], ar); ag = mfma_f16(ahi, Wgl[j], ag);
           au = mfma_f16(ahi, Wuh[j], au); ar = mfma_f16(ahi, Wrh[j], ar); ag = mfma_f16(ahi, Wgh[j], ag);
         }
-        if constexpr (decltype(scaled)::value) {
+        if (DIM == 2) {
+          // back to the unscaled products, then the biases
+          const float su = sup[0] * hup, sr = sup[1] * hup, sgs = sup[2] * hup;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            au[q] = fmaf(au[q], su, bu); ar[q] = fmaf(ar[q], sr, br); ag[q] = fmaf(ag[q], sgs, bh);
+          }
+        } else if constexpr (decltype(scaled)::value) {
 #pragma unroll
           for (int q = 0; q < 16; ++q) { au[q] *= sup[0]; ar[q] *= sup[1]; ag[q] *= sup[2]; }
         }

@@ -451,6 +451,43 @@ def test_local_energy_fp32_large_weights(arch):
     assert rel_err(eloc, ref) < 2e-4
 
 
+@pytest.mark.parametrize("arch", [dict(Lx=4, Ly=4, dim=2, H=64, marshall=True, zero_mag=True),
+                                  dict(Lx=3, Ly=4, dim=2, H=128, cplx=True, marshall=True)], ids=_ids)
+def test_local_energy_fp32_2d_large_gate_input(arch):
+    # 2D gate input h' = U1 h_h + U2 h_v beyond 2^14 (one column of U1 of
+    # 2e4), which the split products take scaled by a power of two per
+    # site; the update gate is held at 1 (bias 40, small W_u, W_r) so the
+    # states stay in [-1, 1], and W_h has a weight of 1e5 (its column staged
+    # scaled); finite local energies within the FP32 bound of the oracle
+    spec, m = make_pair(**arch, dtype="f32")
+    th = scaled_theta(spec, 18, 1.0)
+    off = 0
+    for name, shape in omodel.layout(spec):
+        n = int(np.prod(shape))
+        blk = th[off:off + n].reshape(shape)
+        if name == "U1":
+            blk[:, 3] = 2.0e4
+        elif name in ("Wu", "Wr"):
+            blk *= 1e-6
+        elif name == "bu":
+            blk[:] = 40.0
+        elif name == "Wh":
+            blk[5, 2] = 1.0e5
+        off += n
+    m.set_params(to_dev(th))
+    ham = oham.Ham("j1j2", J=1.0, J2=0.5)
+    Ns = 40
+    sig, lp = omodel.sample(spec, th, philox.uniforms(81, 2, Ns, spec.N))
+    ref = oham.local_energy(spec, th, ham, sig, lp)
+    lp32 = m.logpsi(to_dev(sig.astype(np.uint8)))
+    eloc, _ = m.local_energy(_gpu_ham(ham), to_dev(sig.astype(np.uint8)), lp32)
+    eloc = eloc.cpu().numpy()
+    assert np.all(np.isfinite(eloc))
+    err = rel_err(eloc, ref)
+    print("2D large gate input: rel err %.2e" % err)
+    assert err < 2e-4
+
+
 @pytest.mark.parametrize("arch", [dict(Lx=16, H=64), dict(Lx=9, H=128, cplx=True)], ids=_ids)
 def test_local_energy_fp32_mixed_weight_magnitudes(arch):
     # one output unit of each gate with a weight of 1e6 (its column staged
