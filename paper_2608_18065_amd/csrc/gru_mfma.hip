@@ -348,7 +348,9 @@ __global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void 
     ElocSeq e = eloc_begin(a, item, col);
     const int k0 = e.k0, f1 = e.f1, f2p = e.f2p;
     const uint8_t* sg = e.sg;
-    if (DIM == 1 && k0 + 1 < N) {
+    // the state of the last unflipped site (2D: the horizontal predecessor
+    // of site k0 + 1 unless that site starts a row)
+    if (k0 + 1 < N) {
       for (int i = tid; i < S * H; i += NT) {
         const int q = i / H, u = i % H;
         const int sq = eloc_row_sample(a, e, q);
@@ -365,12 +367,17 @@ __global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void 
         const int kh = a.nbr[2 * k], kv = a.nbr[2 * k + 1];
         if (kh >= 0) { sh = sg[kh]; if (kh == f1 || kh == f2p) sh ^= 1; }
         if (kv >= 0) { sv = sg[kv]; if (kv == f1 || kv == f2p) sv ^= 1; }
+        // a predecessor at site k - 1 is the state this workgroup wrote to
+        // shared memory at the last site (or loaded above for k0 + 1); older
+        // ones come from the stored states (at or before k0) or the window
         for (int i = tid; i < S * 2 * H; i += NT) {
           const int q = i / (2 * H), r = i % (2 * H);
           const int pos = r < H ? kh : kv;
           const int u = r < H ? r : r - H;
           float v = 0.f;
-          if (pos >= 0) {
+          if (pos == k - 1) {
+            v = hA[cb][q][u];
+          } else if (pos >= 0) {
             const int sq = eloc_row_sample(a, e, q);
             if (pos <= k0) v = a.states[((size_t)sq * N + pos) * H + u];
             else v = a.ring[(((size_t)blockIdx.x * S + q) * a.W + pos % a.W) * H + u];
