@@ -253,6 +253,7 @@ __global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void 
   __shared__ __align__(16) float hw[4][H];
   __shared__ float hb[4];
   __shared__ float hmx[2][H / 32];   // 2D: largest |h'| of each wave at a site
+  __shared__ int sqs[DIM == 2 ? S : 1];   // 2D: the item's sample of each sequence
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
@@ -348,6 +349,30 @@ __global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void 
     ElocSeq e = eloc_begin(a, item, col);
     const int k0 = e.k0, f1 = e.f1, f2p = e.f2p;
     const uint8_t* sg = e.sg;
+    // 2D: this thread's share (sequence i / H, unit i % H for i = tid +
+    // 2H m; the block has 2H threads) of the vertical predecessor of site
+    // k2, requested a site ahead, unless that predecessor is site k2 - 1
+    // (then the state is in shared memory)
+    // (four units per request: thread tid takes sequence i / (H / 4), units
+    // 4 (i % (H / 4)) .. + 3 for i = tid + 2H m)
+    constexpr int PFN = DIM == 2 ? S / 8 : 1;
+    float4 pf[PFN];
+    if (DIM == 2) {
+      if (tid < S) sqs[tid] = eloc_row_sample(a, e, tid);
+      __syncthreads();
+    }
+    auto prefetch_v = [&](int k2) {
+      const int kv2 = a.nbr[2 * k2 + 1];
+      if (kv2 < 0 || kv2 == k2 - 1) return;
+#pragma unroll
+      for (int mm = 0; mm < PFN; ++mm) {
+        const int i = tid + 2 * H * mm;
+        const int q = i / (H / 4), u = 4 * (i % (H / 4));
+        const float* src = kv2 <= k0 ? a.states + ((size_t)sqs[q] * N + kv2) * H + u
+                                     : a.ring + (((size_t)blockIdx.x * S + q) * a.W + kv2 % a.W) * H + u;
+        pf[mm] = *reinterpret_cast<const float4*>(src);
+      }
+    };
     // the state of the last unflipped site (2D: the horizontal predecessor
     // of site k0 + 1 unless that site starts a row)
     if (k0 + 1 < N) {
@@ -356,6 +381,7 @@ __global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void 
         const int sq = eloc_row_sample(a, e, q);
         hA[(k0 + 1) & 1][q][u] = a.states[((size_t)sq * N + k0) * H + u];
       }
+      if (DIM == 2) prefetch_v(k0 + 1);
     }
     __syncthreads();
 
@@ -370,21 +396,26 @@ __global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void 
         // a predecessor at site k - 1 is the state this workgroup wrote to
         // shared memory at the last site (or loaded above for k0 + 1); older
         // ones come from the stored states (at or before k0) or the window
-        for (int i = tid; i < S * 2 * H; i += NT) {
-          const int q = i / (2 * H), r = i % (2 * H);
-          const int pos = r < H ? kh : kv;
-          const int u = r < H ? r : r - H;
-          float v = 0.f;
-          if (pos == k - 1) {
-            v = hA[cb][q][u];
-          } else if (pos >= 0) {
-            const int sq = eloc_row_sample(a, e, q);
-            if (pos <= k0) v = a.states[((size_t)sq * N + pos) * H + u];
-            else v = a.ring[(((size_t)blockIdx.x * S + q) * a.W + pos % a.W) * H + u];
+        // (the vertical one, when older, was requested at the last site)
+#pragma unroll
+        for (int mm = 0; mm < PFN; ++mm) {
+          const int i = tid + 2 * H * mm;
+          const int q = i / (H / 4), u = 4 * (i % (H / 4));
+          const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+          float4 vh = z, vv = z;
+          if (kh == k - 1) {
+            vh = *reinterpret_cast<const float4*>(&hA[cb][q][u]);
+          } else if (kh >= 0) {
+            const float* src = kh <= k0 ? a.states + ((size_t)sqs[q] * N + kh) * H + u
+                                        : a.ring + (((size_t)blockIdx.x * S + q) * a.W + kh % a.W) * H + u;
+            vh = *reinterpret_cast<const float4*>(src);
           }
-          hx[q][r] = v;
+          if (kv == k - 1) vv = *reinterpret_cast<const float4*>(&hA[cb][q][u]);
+          else if (kv >= 0) vv = pf[mm];
+          *reinterpret_cast<float4*>(&hx[q][u]) = vh;
+          *reinterpret_cast<float4*>(&hx[q][H + u]) = vv;
         }
-        __syncthreads();
+        mf16::lds_barrier();
         f32x16_m acc;
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[q] = 0.f;
@@ -398,6 +429,10 @@ __global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void 
           acc = mfma_f32(av.w, m2[(size_t)(s4 + 3) * 64], acc);
         }
         hin = acc;
+        // the next site's vertical predecessor is requested now, after this
+        // site's streamed weight loads, so no wait for those also waits for
+        // it; it arrives while the gate products and the cell run
+        if (k + 1 < N) prefetch_v(k + 1);
         float m = 0.f;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -411,7 +446,7 @@ __global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void 
           const float m3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 48));
           hmx[cb][w] = fmaxf(fmaxf(m, m1), fmaxf(m2v, m3));
         }
-        __syncthreads();
+        mf16::lds_barrier();
       }
       // gate pre-activations of the 32 sequences for this wave's units (1D:
       // scaled for exp2, biases of u, r and the input term in the one-hot
