@@ -22,7 +22,10 @@
 
 namespace minsr {
 
-constexpr int TNB = 16;        // panel width of the tridiagonalisation
+// panel width of the tridiagonalisation: the single-workgroup column
+// kernel's dot products with the panel grow with it, the number of
+// trailing rank-2 TNB updates with its inverse (8 beat 16 at n = 4096)
+constexpr int TNB = 8;
 constexpr int PINV_MAX_N = 4096;
 
 // ------------------------------------------------------------ workspace
