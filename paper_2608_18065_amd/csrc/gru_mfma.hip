@@ -95,7 +95,7 @@ __device__ inline void split_f16(const float (&x)[8], f16x8_m& hi, f16x8_m& lo) 
   for (int e = 0; e < 8; e += 2) {   // pairs: one packed conversion each way
     const f32x2_m v = {x[e], x[e + 1]};
     const f16x2_m h = __builtin_convertvector(v, f16x2_m);
-    const f16x2_m l = __builtin_convertvector(v - __builtin_convertvector(h, f32x2_m), f16x2_m);
+    const f16x2_m l = mf16::lo_pair(h, x[e], x[e + 1]);
     hi[e] = h[0]; hi[e + 1] = h[1];
     lo[e] = l[0]; lo[e + 1] = l[1];
   }
