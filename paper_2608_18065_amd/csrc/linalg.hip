@@ -6,6 +6,7 @@
 //   dtheta = eta O'^T x, momentum and the parameter update.
 // Every reduction runs in a fixed order: results are bitwise reproducible.
 #include "model.hpp"
+#include "mfma16.hpp"
 #include <algorithm>
 #include <type_traits>
 #include <cmath>
@@ -1091,11 +1092,15 @@ __device__ __forceinline__ f64x4_t mm_nt(f64x4_t acc, const double (*X)[LDT], in
 // (zero outside the leading nb x nb block).
 // `during_first_panel` runs on waves 1..3 while wave 0 factors the first
 // panel (it may complete columns 16.. of S); with `fill` false the caller has
-// already made the rows >= nb identity rows.
+// already made the rows >= nb identity rows.  `pub` (may be null) is
+// released once the barrier after the first panel has seen every wave's
+// earlier global stores complete: the caller's stores are published off
+// wave 0's path.
 template <typename F>
 __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm)[16][17],
                                  double* rinv, double* lb, int nb, int k0, double* Di,
-                                 uint32_t* status, bool fill, F&& during_first_panel) {
+                                 uint32_t* status, bool fill, F&& during_first_panel,
+                                 uint32_t* pub) {
   constexpr int PB = 16, NB = CB / 16;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   if (fill && nb < CB) {   // the last, partial block only
@@ -1228,6 +1233,8 @@ __device__ void factor_block_f64(double (*S)[LDT], double (*Z)[LDT], double (*Tm
 #pragma unroll
       for (int cc = 0; cc < PB; ++cc) S[lane][p0 + cc] = lane >= p0 + cc ? f[cc] : 0.0;
     } else {
+      if (P == 1 && pub && tid == 192)
+        __hip_atomic_store(pub, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (P > 0) {
         // blocks (Q, R), Q >= R >= P + 1, of panel P - 1's trailing update
         const int R0 = P + 1, nr = NB - R0;
@@ -1484,18 +1491,19 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
       return;
     }
     // the pair workgroup: keep the contribution, subtract L L^T from the
-    // diagonal tile (rows beyond n of L are zero), then publish L
+    // diagonal tile (rows beyond n of L are zero); L is published during the
+    // factorisation's first panel, so the barriers up to there order shared
+    // memory only and do not wait for its stores
     if ((lane & 15) == 0) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) cown[16 * w + mrow(lane, v)] = s[v];
     }
-    __syncthreads();   // X, Y, yb are no longer read
+    mf16::lds_barrier();   // X, Y, yb are no longer read
     tile_to_lds(l, X);
-    __syncthreads();
+    mf16::lds_barrier();
     // column block 0 of L L^T now; the other lower blocks while wave 0
     // factors the first panel (L stays in X until then)
     td[0] = mm_nt<CB, true>(td[0], X, 16 * w, X, 0, 0, lane);
-    publish(&pflag[pi * nblk + pj]);
   }
 
   // the diagonal block jd: factor (in Y, the inverse in X), invert, and
@@ -1510,7 +1518,7 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
       Y[r][col] = r < nb ? t[v] : (r == col ? 1.0 : 0.0);
     }
   };
-  __syncthreads();   // Y is rewritten
+  mf16::lds_barrier();   // Y is rewritten
   if (has_panel) {
     put_block(td[0], 0);
   } else {
@@ -1521,7 +1529,7 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
     const double r = jd > 0 ? bpart - cown[tid] : bpart;
     yb[tid] = tid < nb ? r : 0.0;
   }
-  __syncthreads();
+  mf16::lds_barrier();
   // waves 1..3: the rest of L L^T for their lower blocks (1 <= c <= w)
   auto rest = [&]() {
     if (!has_panel) return;
@@ -1532,8 +1540,9 @@ __global__ __launch_bounds__(256) void k_chol_persist_f64(CholArgs a, uint32_t* 
         put_block(td[c], c);
       }
   };
-  factor_block_f64(Y, X, Tm, rinv, lb, nb, kb0, Di, a.status, false, rest);
-  __syncthreads();
+  factor_block_f64(Y, X, Tm, rinv, lb, nb, kb0, Di, a.status, false, rest,
+                   has_panel ? &pflag[pi * nblk + pj] : nullptr);
+  mf16::lds_barrier();   // the inverse's stores complete under the solve below
   {
     // y_jd = inv(L) yb: four threads per row, terms q = part, part + 4, ...
     // up to the diagonal (X above the diagonal blocks is not cleared)
