@@ -24,8 +24,16 @@ __global__ void k_colsum_part(const TI* O, int rows_per_block, int nrc, int RC, 
   const int r0 = chunk * RC;
   const int r1 = min(rows_per_block, r0 + RC);
   const TI* base = O + ((size_t)blk * rows_per_block) * Np + col;
+  // eight rows' loads in flight, then summed in row order
   double s = 0.0;
-  for (int r = r0; r < r1; ++r) s += (double)base[(size_t)r * Np];
+  for (int r = r0; r < r1; r += 8) {
+    TI v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = base[(size_t)min(r + u, r1 - 1) * Np];   // tail rows repeat, unused
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (r + u < r1) s += (double)v[u];
+  }
   part[((size_t)blk * nrc + chunk) * Np + col] = s;
 }
 
@@ -37,6 +45,13 @@ __global__ void k_colmean(const double* part, int nrc, int rows_per_block, int n
     // four partial sums so that several loads are in flight
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
     int c = 0;
+    for (; c + 8 <= nrc; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[((size_t)b * nrc + c + u) * Np + col];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s4[u & 3] += v[u];
+    }
     for (; c + 4 <= nrc; c += 4) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) s4[u] += part[((size_t)b * nrc + c + u) * Np + col];
@@ -75,11 +90,18 @@ __global__ void k_center(const TI* O, int rows_per_block, int RC, size_t Np, con
   }
   const TI mu = mean ? (TI)mean[(size_t)blk * Np + col] : (TI)0;
   const size_t off = ((size_t)blk * rows_per_block) * Np + col;
-  for (int r = r0; r < r1; ++r) {
-    const TI v = O[off + (size_t)r * Np] - mu;
-    const TO hi = cvt_out<TO>((double)v);
-    R[oo + (size_t)r * ldo] = hi;
-    if (Rlo) Rlo[oo + (size_t)r * ldo] = cvt_out<TO>((double)v - (double)(float)hi);
+  for (int r = r0; r < r1; r += 8) {   // eight rows' loads in flight
+    TI x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = O[off + (size_t)min(r + u, r1 - 1) * Np];   // tail rows repeat, unused
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (r + u >= r1) break;
+      const TI v = x[u] - mu;
+      const TO hi = cvt_out<TO>((double)v);
+      R[oo + (size_t)(r + u) * ldo] = hi;
+      if (Rlo) Rlo[oo + (size_t)(r + u) * ldo] = cvt_out<TO>((double)v - (double)(float)hi);
+    }
   }
 }
 
@@ -511,14 +533,30 @@ __device__ __forceinline__ void gram_reduce_tile(const TA* part, int npairs, int
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   int ti, tj;
   pair_decode(pair, ti, tj);
+  // partials summed in split order, eight splits' loads in flight
+  TA s[4] = {(TA)0, (TA)0, (TA)0, (TA)0};
+  for (int k0 = 0; k0 < nsplit; k0 += 8) {
+    TA v[4][8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int lr = sr * 32 + ty + 8 * q, lc = sc * 32 + tx;
+        const int k = min(k0 + u, nsplit - 1);   // tail splits repeat, unused
+        v[q][u] = part[((size_t)k * npairs + pair) * tile * tile + lr * tile + lc];
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u < nsplit) s[q] += v[q][u];
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int lr = sr * 32 + ty + 8 * q, lc = sc * 32 + tx;
     const int r = ti * tile + lr, c = tj * tile + lc;
-    TA s = (TA)0;
-    for (int k = 0; k < nsplit; ++k) s += part[((size_t)k * npairs + pair) * tile * tile + lr * tile + lc];
-    sh[ty + 8 * q][tx] = (TT)s;
-    if (r < n && c < n && (ti != tj || c <= r)) T[(size_t)r * n + c] = (TT)s;
+    sh[ty + 8 * q][tx] = (TT)s[q];
+    if (r < n && c < n && (ti != tj || c <= r)) T[(size_t)r * n + c] = (TT)s[q];
   }
   __syncthreads();
 #pragma unroll
@@ -1898,7 +1936,14 @@ __global__ void k_update_final(const double* part, int nrc, size_t Np, double et
   if (bump && col == 0) bump[0] += 1;
   if (col >= Np) return;
   double s = 0.0;
-  for (int c = 0; c < nrc; ++c) s += part[(size_t)c * Np + col];
+  for (int c0 = 0; c0 < nrc; c0 += 8) {   // eight partials in flight, summed in order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)min(c0 + u, nrc - 1) * Np + col];   // tail repeats, unused
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c0 + u < nrc) s += v[u];
+  }
   const double d = eta * s;
   dtheta[col] = d;
   if (!isfinite(d)) atomicOr(status, MINSR_ST_NONFINITE_DTH);
