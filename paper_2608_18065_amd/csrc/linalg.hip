@@ -1637,7 +1637,17 @@ __global__ __launch_bounds__(256) void k_chol_prep(uint32_t* sync, int nsync, co
   if ((lam_out || rep_tn || rep_lam) && blockIdx.x == 0) {
     __shared__ double red[256];
     double tr = 0.0;
-    for (int k = threadIdx.x; k < n; k += 256) tr += (double)T[(size_t)k * n + k];
+    for (int k0 = threadIdx.x; k0 < n; k0 += 256 * 8) {   // eight loads in flight
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = min(k0 + 256 * u, n - 1);
+        v[u] = (double)T[(size_t)k * n + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + 256 * u < n) tr += v[u];
+    }
     red[threadIdx.x] = tr;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
