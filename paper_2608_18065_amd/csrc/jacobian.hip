@@ -90,32 +90,50 @@ __device__ void wgrad_row(const JacArgs<float>& a, int row, int s, int lane, int
   const float* st = a.states + (size_t)s * N * H;
   float* o = a.O + (size_t)row * a.L.Np;
   const int kl = lane >> 5, cl = lane & 31;
-  for (int b = w; b < NBLK; b += nw) {
+  // items (block of this wave, group of 64 sites) in order; the operands of
+  // the next item (clamped addresses, masked values) are requested before
+  // the current item's 32 products, so a wave waits for memory about once
+  // per row rather than once per 16 sites
+  const int ng = (N + 63) / 64;
+  const int nblk = w < NBLK ? (NBLK - 1 - w) / nw + 1 : 0;
+  const int nitem = nblk * ng;
+  auto load = [&](int item, float (&av)[32], float (&bv)[32]) {
+    const int b = w + (item / ng) * nw, k64 = 64 * (item % ng);
     const int q = b / (NB * NB), jb = (b / NB) % NB, cb = b % NB;
-    f32x16_j acc;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = 0.f;
-    // sites in groups of 16: the group's operand loads (clamped addresses,
-    // masked values) are issued before its eight products
-    for (int k16 = 0; k16 < N; k16 += 16) {
-      float av[8], bv[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k16 + 2 * u + kl;
-        const float x = dp[((size_t)min(k, N - 1) * 3 + q) * H + jb * 32 + cl];
-        const float y = st[(size_t)max(min(k, N) - 1, 0) * H + cb * 32 + cl];
-        av[u] = k < N ? x : 0.f;
-        bv[u] = (k >= 1 && k < N) ? y : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+    for (int u = 0; u < 32; ++u) {
+      const int k = k64 + 2 * u + kl;
+      const float x = dp[((size_t)min(k, N - 1) * 3 + q) * H + jb * 32 + cl];
+      const float y = st[(size_t)max(min(k, N) - 1, 0) * H + cb * 32 + cl];
+      av[u] = k < N ? x : 0.f;
+      bv[u] = (k >= 1 && k < N) ? y : 0.f;
     }
-    const size_t off = q == 0 ? a.L.Wu : q == 1 ? a.L.Wr : a.L.Wh;
-    const int ldq = q < 2 ? H + ds : H;
+  };
+  float av[32], bv[32], an[32], bn[32];
+  if (nitem > 0) load(0, av, bv);
+  f32x16_j acc;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int jr = jb * 32 + 8 * (e / 4) + 4 * kl + e % 4;
-      o[off + (size_t)jr * ldq + cb * 32 + cl] = acc[e] * a.scale;
+  for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+  for (int it = 0; it < nitem; ++it) {
+    const bool more = it + 1 < nitem;
+    if (more) load(it + 1, an, bn);
+#pragma unroll
+    for (int u = 0; u < 32; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+    if (it % ng == ng - 1) {
+      const int b = w + (it / ng) * nw;
+      const int q = b / (NB * NB), jb = (b / NB) % NB, cb = b % NB;
+      const size_t off = q == 0 ? a.L.Wu : q == 1 ? a.L.Wr : a.L.Wh;
+      const int ldq = q < 2 ? H + ds : H;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int jr = jb * 32 + 8 * (e / 4) + 4 * kl + e % 4;
+        o[off + (size_t)jr * ldq + cb * 32 + cl] = acc[e] * a.scale;
+        acc[e] = 0.f;
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < 32; ++u) { av[u] = an[u]; bv[u] = bn[u]; }
     }
   }
 }
