@@ -147,19 +147,39 @@ __device__ inline ElocSeq eloc_begin(const ElocMArgs& a, int item, int col) {
   const double* st = a.site + (size_t)e.s * N * 4;
   e.nup = 0; e.ndn = 0; e.dA = 0;
   e.oldlp = 0.0; e.oldph = 0.0;
-  for (int k = 0; k <= e.k0; ++k) {
-    int v = sg[k];
-    if (k == e.f1) v ^= 1;
-    e.nup += v == 0; e.ndn += v == 1;
-  }
-  for (int k = e.k0; k < N; ++k) {
-    const int v = sg[k];
-    e.oldlp += st[4 * k + v];
-    e.oldph += st[4 * k + 2 + v];
-  }
   e.smask = 0;
-  if (N <= 64)
-    for (int k = e.k0 + 1; k < N; ++k) e.smask |= (uint64_t)(sg[k] & 1) << k;
+  // spins and site terms requested eight sites at a time (clamped
+  // addresses, the values beyond the range unused), then taken in site order
+  for (int k = 0; k <= e.k0; k += 8) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = sg[min(k + u, N - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k + u <= e.k0) {
+        const int vv = v[u] ^ (k + u == e.f1 ? 1 : 0);
+        e.nup += vv == 0; e.ndn += vv == 1;
+      }
+  }
+  for (int k = e.k0; k < N; k += 8) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = sg[min(k + u, N - 1)];
+    double lv[8], pv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int kk = min(k + u, N - 1);
+      lv[u] = st[4 * kk + v[u]];
+      pv[u] = st[4 * kk + 2 + v[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k + u < N) {
+        e.oldlp += lv[u];
+        e.oldph += pv[u];
+        if (N <= 64 && k + u > e.k0) e.smask |= (uint64_t)(v[u] & 1) << (k + u);
+      }
+  }
   const int vflip = sg[e.k0] ^ 1;
   e.lp = st[4 * e.k0 + vflip];
   e.ph = st[4 * e.k0 + 2 + vflip];
@@ -376,10 +396,19 @@ __global__ __launch_bounds__(64 * (H / 32), (H <= 64 && DIM == 1) ? 2 : 1) void 
     // the state of the last unflipped site (2D: the horizontal predecessor
     // of site k0 + 1 unless that site starts a row)
     if (k0 + 1 < N) {
-      for (int i = tid; i < S * H; i += NT) {
-        const int q = i / H, u = i % H;
+      // four units per request, all requested before any is stored
+      constexpr int NTL = 64 * (H / 32), PV = S * H / 4 / NTL;   // NTL: the launch's block size
+      float4 pv[PV];
+#pragma unroll
+      for (int m = 0; m < PV; ++m) {
+        const int i = tid + NTL * m, q = i / (H / 4), u = 4 * (i % (H / 4));
         const int sq = eloc_row_sample(a, e, q);
-        hA[(k0 + 1) & 1][q][u] = a.states[((size_t)sq * N + k0) * H + u];
+        pv[m] = *reinterpret_cast<const float4*>(&a.states[((size_t)sq * N + k0) * H + u]);
+      }
+#pragma unroll
+      for (int m = 0; m < PV; ++m) {
+        const int i = tid + NTL * m, q = i / (H / 4), u = 4 * (i % (H / 4));
+        *reinterpret_cast<float4*>(&hA[(k0 + 1) & 1][q][u]) = pv[m];
       }
       if (DIM == 2) prefetch_v(k0 + 1);
     }
@@ -689,10 +718,20 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
     ElocSeq e = eloc_begin(a, item, col);
     const int k0 = e.k0;
     if (k0 + 1 < N) {
-      for (int i = lane; i < S * H; i += 64) {
-        const int q = i / H, u = i % H;
+      // the prefix states, four units per request, all requested before
+      // any is stored
+      constexpr int PV = S * H / 4 / 64;
+      float4 pv[PV];
+#pragma unroll
+      for (int m = 0; m < PV; ++m) {
+        const int i = lane + 64 * m, q = i / (H / 4), u = 4 * (i % (H / 4));
         const int sq = eloc_row_sample(a, e, q);
-        hA[q][u] = a.states[((size_t)sq * N + k0) * H + u];
+        pv[m] = *reinterpret_cast<const float4*>(&a.states[((size_t)sq * N + k0) * H + u]);
+      }
+#pragma unroll
+      for (int m = 0; m < PV; ++m) {
+        const int i = lane + 64 * m, q = i / (H / 4), u = 4 * (i % (H / 4));
+        *reinterpret_cast<float4*>(&hA[q][u]) = pv[m];
       }
     }
     wave_sync();
