@@ -148,8 +148,9 @@ __device__ inline ElocSeq eloc_begin(const ElocMArgs& a, int item, int col) {
   e.nup = 0; e.ndn = 0; e.dA = 0;
   e.oldlp = 0.0; e.oldph = 0.0;
   e.smask = 0;
-  // spins and site terms requested eight sites at a time (clamped
-  // addresses, the values beyond the range unused), then taken in site order
+  // spins (eight sites at a time) and site terms (four) requested before
+  // use (clamped addresses, the values beyond the range unused), then taken
+  // in site order
   for (int k = 0; k <= e.k0; k += 8) {
     int v[8];
 #pragma unroll
@@ -161,19 +162,19 @@ __device__ inline ElocSeq eloc_begin(const ElocMArgs& a, int item, int col) {
         e.nup += vv == 0; e.ndn += vv == 1;
       }
   }
-  for (int k = e.k0; k < N; k += 8) {
-    int v[8];
+  for (int k = e.k0; k < N; k += 4) {
+    int v[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = sg[min(k + u, N - 1)];
-    double lv[8], pv[8];
+    for (int u = 0; u < 4; ++u) v[u] = sg[min(k + u, N - 1)];
+    double lv[4], pv[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 4; ++u) {
       const int kk = min(k + u, N - 1);
       lv[u] = st[4 * kk + v[u]];
       pv[u] = st[4 * kk + 2 + v[u]];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 4; ++u)
       if (k + u < N) {
         e.oldlp += lv[u];
         e.oldph += pv[u];
@@ -619,6 +620,7 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
   __shared__ float hb[4];
   __shared__ float bgs_s[H];
   __shared__ int simd_of[EW_WAVES];
+  __shared__ int sqw[EW_WAVES][S];          // samples of the rows of each wave's item
   __shared__ unsigned wmax_bits;
   __shared__ unsigned colmax[NCB][3][32];   // largest |w| of each output column
   __shared__ float csc[2][NCB][3][32];      // its scale 2^-s and 2^s
@@ -718,20 +720,27 @@ __global__ __launch_bounds__(64 * EW_WAVES, 2) void k_eloc_mfma_w(ElocMArgs a, u
     ElocSeq e = eloc_begin(a, item, col);
     const int k0 = e.k0;
     if (k0 + 1 < N) {
-      // the prefix states, four units per request, all requested before
-      // any is stored
+      // the prefix states, four units per request: the rows' samples go
+      // through shared memory first, then four requests are made before any
+      // of them is stored (named values, so they stay in registers)
+      if (lane < S) sqw[w][lane] = eloc_row_sample(a, e, lane);
+      wave_sync();
       constexpr int PV = S * H / 4 / 64;
-      float4 pv[PV];
-#pragma unroll
-      for (int m = 0; m < PV; ++m) {
+      auto ld = [&](int m) {
         const int i = lane + 64 * m, q = i / (H / 4), u = 4 * (i % (H / 4));
-        const int sq = eloc_row_sample(a, e, q);
-        pv[m] = *reinterpret_cast<const float4*>(&a.states[((size_t)sq * N + k0) * H + u]);
-      }
-#pragma unroll
-      for (int m = 0; m < PV; ++m) {
+        return *reinterpret_cast<const float4*>(&a.states[((size_t)sqw[w][q] * N + k0) * H + u]);
+      };
+      auto stv = [&](int m, float4 v) {
         const int i = lane + 64 * m, q = i / (H / 4), u = 4 * (i % (H / 4));
-        *reinterpret_cast<float4*>(&hA[q][u]) = pv[m];
+        *reinterpret_cast<float4*>(&hA[q][u]) = v;
+      };
+#pragma unroll
+      for (int m0 = 0; m0 < PV; m0 += 4) {
+        const float4 p0 = ld(m0), p1 = ld(m0 + 1), p2 = ld(m0 + 2), p3 = ld(m0 + 3);
+        stv(m0, p0);
+        stv(m0 + 1, p1);
+        stv(m0 + 2, p2);
+        stv(m0 + 3, p3);
       }
     }
     wave_sync();
