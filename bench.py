@@ -43,18 +43,18 @@ PEAK_FP64_TFLOPS = 78.6         # dense FP64 matrix cores (equal to the FP64 vec
 # scaled by the counter's reading on a plain copy of known size; None until
 # taken for the current kernel version
 TRAFFIC_BYTES = {
-    # k_eloc_mfma_w (FP16 hi/lo split products): 9995.0 KiB fetched x 2.000 +
-    # 1336.2 KiB written x 1.000
-    "eloc": 9995.0 * 1024 * 2.0 + 1336.2 * 1024,
+    # k_eloc_mfma_w (FP16 hi/lo split products): 10006.6 KiB fetched x 2.000 +
+    # 1371.7 KiB written x 1.000
+    "eloc": 10006.6 * 1024 * 2.0 + 1371.7 * 1024,
     # k_chol_prep + k_chol_persist_f64 + k_trsv_back_mt:
-    # (76.9 + 8961.1 + 2254.6) KiB fetched x 2.000 + (17.4 + 4692.5 + 8.5) KiB written
-    "solve": (76.9 + 8961.1 + 2254.6) * 1024 * 2.0 + (17.4 + 4692.5 + 8.5) * 1024,
+    # (78.2 + 9287.3 + 2254.3) KiB fetched x 2.000 + (17.4 + 4692.5 + 8.5) KiB written
+    "solve": (78.2 + 9287.3 + 2254.3) * 1024 * 2.0 + (17.4 + 4692.5 + 8.5) * 1024,
     # k_jacobian (gate-tape path, gate adjoints stored per site) + k_jac_wgrad:
-    # (42362.9 + 33943.5) KiB fetched x 2.000 + (55328.0 + 50235.2) KiB written x 1.000
-    "jacobian": (42362.9 + 33943.5) * 1024 * 2.0 + (55328.0 + 50235.2) * 1024,
+    # (42359.0 + 33373.7) KiB fetched x 2.000 + (55328.0 + 50254.2) KiB written x 1.000
+    "jacobian": (42359.0 + 33373.7) * 1024 * 2.0 + (55328.0 + 50254.2) * 1024,
     # k_gram_bf16 (split form, four products, eight-wave 128 x 128 tiles, FP64
-    # partial tiles): 43333.2 KiB fetched x 2.000 + 32256.0 KiB written x 1.000
-    "gram": 43333.2 * 1024 * 2.0 + 32256.0 * 1024}
+    # partial tiles): 43333.6 KiB fetched x 2.000 + 32256.0 KiB written x 1.000
+    "gram": 43333.6 * 1024 * 2.0 + 32256.0 * 1024}
 
 
 def parse():
@@ -103,14 +103,19 @@ def run_form(pm, wl, form, K, W, dtype="f32", graph=True, kernel_steps=20):
     """W warmup steps, then the timed run of K steps (replays of a captured
     graph of the step, or eager steps), then `kernel_steps` eager steps with
     per-phase HIP events for the kernel breakdown."""
+    import numpy as np
     import torch
     ham = pm.hamiltonian("tfim", J=wl.J, h=wl.h, pbc=wl.pbc)
     m = pm.Model(wl.Lx, wl.Ly, wl.dim, wl.H, wl.complex_head, wl.marshall, wl.zero_mag,
                  dtype=dtype, seed=wl.seed, max_Ns=wl.Ns)
     mom = torch.zeros(m.Np, dtype=torch.float64, device="cuda")
     outs = m.step_outputs(wl.Ns)
-    hist = torch.zeros((max(K, 1), 3), dtype=torch.float64, device="cuda")
-    status = torch.zeros(max(K, 1), dtype=torch.int32, device="cuda")
+    # E, Var, the third energy slot and the status word side by side, so one
+    # copy per step records them
+    rec = torch.zeros(4, dtype=torch.float64, device="cuda")
+    outs["energy"] = rec[0:3]
+    outs["status"] = rec[3:4].view(torch.int32)[0:1]
+    hist = torch.zeros((max(K, 1), 4), dtype=torch.float64, device="cuda")
     ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
 
     def eager():
@@ -130,8 +135,7 @@ def run_form(pm, wl, form, K, W, dtype="f32", graph=True, kernel_steps=20):
             g.replay()
         else:
             eager()
-        hist[i].copy_(outs["energy"], non_blocking=True)
-        status[i:i + 1].copy_(outs["status"], non_blocking=True)
+        hist[i].copy_(rec, non_blocking=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # kernel breakdown: eager steps with events on the step's stream
@@ -140,8 +144,9 @@ def run_form(pm, wl, form, K, W, dtype="f32", graph=True, kernel_steps=20):
         eager()
     torch.cuda.synchronize()
     phases, nrec = m.timing_read()
-    E = hist.cpu().numpy()
-    st = status.cpu().numpy()
+    hr = hist.cpu().numpy()
+    E = hr[:, :3].copy()
+    st = hr[:, 3].copy().view(np.int32)[0::2]   # the status word is the low half of its slot
     m.close()
     return dict(seconds=t1 - t0, phases={k: v / max(nrec, 1) for k, v in phases.items()},
                 energy=E, status=st, kernel_steps=nrec)
