@@ -305,6 +305,19 @@ __global__ __launch_bounds__(256) void k_tri_gemv(TriArgs a, int j, int p, int w
     const double* row = a.A + (size_t)i * n;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int c = j + 1 + lane;
+    // sixteen loads in flight per step, then eight, four, one; element t of
+    // this lane goes to accumulator t % 4 in every wide step, so the sums
+    // are those of the narrower steps alone
+    for (; c + 960 < n; c += 1024) {
+      double r[16], x[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) { r[q] = row[c + 64 * q]; x[q] = v[c + 64 * q]; }
+#pragma unroll
+      for (int q = 0; q < 16; q += 4) {
+        s0 = fma(r[q], x[q], s0); s1 = fma(r[q + 1], x[q + 1], s1);
+        s2 = fma(r[q + 2], x[q + 2], s2); s3 = fma(r[q + 3], x[q + 3], s3);
+      }
+    }
     for (; c + 448 < n; c += 512) {
       double r[8], x[8];
 #pragma unroll
