@@ -363,11 +363,18 @@ __global__ __launch_bounds__(TBS) void k_tri_fin(TriArgs a, int jp, int pp, int 
   for (int i = jp + 1 + tid; i < n; i += TBS) a.W[(size_t)pp * n + i] = tp * a.g[i] + alpha * v[i];
 }
 
-// A[i][c] -= sum_q V[q][i] W[q][c] + W[q][i] V[q][c], i, c >= j1: 64 x 64 tiles
+// A[i][c] -= sum_q V[q][i] W[q][c] + W[q][i] V[q][c], i, c >= j1: 64 x 64
+// tiles on the FP64 matrix cores.  Wave w takes rows 16 w .. 16 w + 15 of
+// the tile as four 16 x 16 blocks; the product's K index runs over the 2 TNB
+// panel columns [V W] against [W V] (zero beyond nb and beyond n).  Lane l
+// of v_mfma_f64_16x16x4 supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and holds D[l / 16 + 4 e][l % 16] in element e.
+typedef double f64x4_e __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_tri_syr2k(double* A, const double* V, const double* W,
                                                    int n, int j1, int nb) {
   __shared__ double Vi[TNB][64], Wi[TNB][64], Vc[TNB][64], Wc[TNB][64];
   const int r0 = j1 + blockIdx.y * 64, c0 = j1 + blockIdx.x * 64, tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
   for (int e = tid; e < TNB * 64; e += 256) {
     const int q = e / 64, k = e % 64;
     const bool okq = q < nb;
@@ -376,22 +383,34 @@ __global__ __launch_bounds__(256) void k_tri_syr2k(double* A, const double* V, c
     Vc[q][k] = (okq && c0 + k < n) ? V[(size_t)q * n + c0 + k] : 0.0;
     Wc[q][k] = (okq && c0 + k < n) ? W[(size_t)q * n + c0 + k] : 0.0;
   }
+  // this lane's 16 elements of the tile, requested before the barrier
+  f64x4_e acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = r0 + 16 * w + (lane >> 4) + 4 * e, c = c0 + 16 * cb + (lane & 15);
+      acc[cb][e] = (r < n && c < n) ? A[(size_t)r * n + c] : 0.0;
+    }
   __syncthreads();
-  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
-  double acc[4][4] = {};
-  for (int q = 0; q < nb; ++q) {
+  const int i = 16 * w + (lane & 15);
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+  for (int ks = 0; ks < 2 * TNB; ks += 4) {
+    const int k = ks + (lane >> 4);
+    const double a = k < TNB ? Vi[k][i] : Wi[k - TNB][i];
 #pragma unroll
-      for (int z = 0; z < 4; ++z)
-        acc[x][z] += Vi[q][tr + x] * Wc[q][tc + z] + Wi[q][tr + x] * Vc[q][tc + z];
+    for (int cb = 0; cb < 4; ++cb) {
+      const int c = 16 * cb + (lane & 15);
+      const double b = k < TNB ? Wc[k][c] : Vc[k - TNB][c];
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, b, acc[cb], 0, 0, 0);
+    }
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-    for (int z = 0; z < 4; ++z) {
-      const int r = r0 + tr + x, c = c0 + tc + z;
-      if (r < n && c < n) A[(size_t)r * n + c] -= acc[x][z];
+    for (int e = 0; e < 4; ++e) {
+      const int r = r0 + 16 * w + (lane >> 4) + 4 * e, c = c0 + 16 * cb + (lane & 15);
+      if (r < n && c < n) A[(size_t)r * n + c] = acc[cb][e];
     }
 }
 
