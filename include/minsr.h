@@ -52,7 +52,7 @@ extern "C" {
 #define MINSR_E_DEVICE       -3   /* a HIP runtime call failed             */
 #define MINSR_E_NUMERIC      -4   /* reserved: host-visible numeric error  */
 #define MINSR_E_NOMEM        -5   /* device allocation failed              */
-#define MINSR_E_UNSUPPORTED  -6   /* option not available in this build    */
+#define MINSR_E_UNSUPPORTED  -6   /* option not available in this library  */
 
 /* floating-point formats */
 #define MINSR_F64   0
